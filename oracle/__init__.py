@@ -1,0 +1,225 @@
+"""FV3 acoustic-substep ORACLE: test infrastructure only.
+
+A plain FP64 CPU implementation (C, built with ``-O2 -ffp-contract=off``)
+of the acoustic substep loop, the tracer transport and the global mass sums,
+wrapped with ctypes over numpy arrays in the oracle's own unpadded layout
+``f[t][k][j+3][i+3]``.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the HIP library
+never does, and the two share no code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_SRCS = ["grid.c", "halo.c", "ppm.c", "column.c", "dyn.c", "api.c"]
+
+ST = {"C": 0, "X": 1, "Y": 2, "B": 3}
+MODE = {"x": 0, "y": 1}
+PAIR = {"signed": 0, "abs": 1, "cos": 2}
+METRICS = ["dx", "dy", "dxc", "dyc", "dxa", "dya", "area", "area_c", "fC", "fB", "sin_u",
+           "cos_u", "sin_v", "cos_v", "sin_a", "cos_a", "cx", "cy", "cz", "bx", "by", "bz"]
+H = 3
+OMEGA = 7.2921e-5
+RADIUS = 6.3712e6
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with gcc (no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-o", _LIB] + [os.path.join(_HERE, s) for s in _SRCS] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        L.orc_grid_new.restype = C.c_void_p
+        L.orc_grid_new.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, C.c_char_p, C.c_int]
+        L.orc_grid_free.argtypes = [C.c_void_p]
+        L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
+        L.orc_grid_conn.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_halo_fill.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, C.c_int]
+        L.orc_halo_fill_pair.argtypes = [C.c_void_p, dp, C.c_int, dp, C.c_int, C.c_int, C.c_int]
+        L.orc_corner_view.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, dp]
+        L.orc_corner_view_pair.argtypes = [C.c_void_p, dp, C.c_int, dp, C.c_int, C.c_int, dp, dp]
+        L.orc_ppm_face.restype = C.c_double
+        L.orc_ppm_face.argtypes = [dp, C.c_double]
+        L.orc_fv_tp_2d.argtypes = [C.c_void_p, C.c_int] + [dp] * 9
+        L.orc_sim1.restype = C.c_double
+        L.orc_sim1.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double] + [dp] * 8
+        L.orc_pgf.restype = C.c_double
+        L.orc_pgf.argtypes = [C.c_double] * 12
+        L.orc_acoustic_substeps.argtypes = [C.c_void_p] + [dp] * 16 + [C.c_double, C.c_int,
+                                                                      C.c_int, C.POINTER(dp)]
+        L.orc_tracer_transport.argtypes = [C.c_void_p, C.POINTER(dp), C.c_int] + [dp] * 5 + [
+            C.c_int, C.POINTER(C.c_int)]
+        L.orc_mass_sums.argtypes = [C.c_void_p, dp, dp, C.POINTER(dp), C.c_int, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "oracle wants C-contiguous float64"
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+class Grid:
+    """Oracle grid: kind 0 = doubly periodic (one tile), 1 = cubed sphere (6 tiles)."""
+
+    def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
+                 radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0):
+        err = C.create_string_buffer(256)
+        h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
+        if not h:
+            raise RuntimeError("oracle grid: " + err.value.decode())
+        self._h = h
+        self.kind, self.n, self.nz = kind, n, nz
+        self.T = 6 if kind == 1 else 1
+        self.N = n + 2 * H + 1
+        self.ptop = ptop
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_grid_free(h)
+            self._h = None
+
+    def metric(self, name: str) -> np.ndarray:
+        out = np.zeros((self.T, self.N, self.N))
+        if lib().orc_grid_metric(self._h, METRICS.index(name), _p(out)) != 0:
+            raise KeyError(name)
+        return out
+
+    def connectivity(self):
+        nbr = np.zeros(24, dtype=np.int32)
+        rot = np.zeros(96, dtype=np.int32)
+        lib().orc_grid_conn(self._h, nbr.ctypes.data_as(C.POINTER(C.c_int)),
+                            rot.ctypes.data_as(C.POINTER(C.c_int)))
+        return nbr.reshape(6, 4), rot.reshape(6, 4, 2, 2)
+
+    def field(self, nlev: int) -> np.ndarray:
+        return np.zeros((self.T, nlev, self.N, self.N))
+
+
+def halo_fill(g: Grid, f: np.ndarray, stagger: str = "C", coslike: bool = False) -> None:
+    lib().orc_halo_fill(g._h, _p(f), f.shape[1] if f.ndim == 4 else 1, ST[stagger], int(coslike))
+
+
+def halo_fill_pair(g: Grid, fx, stx, fy, sty, kind="signed") -> None:
+    nlev = fx.shape[1] if fx.ndim == 4 else 1
+    lib().orc_halo_fill_pair(g._h, _p(fx), ST[stx], _p(fy), ST[sty], nlev, PAIR[kind])
+
+
+def corner_view(g: Grid, plane: np.ndarray, stagger: str, mode: str) -> np.ndarray:
+    plane = np.ascontiguousarray(plane)
+    out = np.zeros_like(plane)
+    lib().orc_corner_view(g._h, _p(plane), ST[stagger], MODE[mode], _p(out))
+    return out
+
+
+def corner_view_pair(g: Grid, px, stx, py, sty, mode):
+    px = np.ascontiguousarray(px)
+    py = np.ascontiguousarray(py)
+    ox, oy = np.zeros_like(px), np.zeros_like(py)
+    lib().orc_corner_view_pair(g._h, _p(px), ST[stx], _p(py), ST[sty], MODE[mode], _p(ox), _p(oy))
+    return ox, oy
+
+
+def ppm_face(q6, c: float) -> float:
+    q = np.ascontiguousarray(q6, dtype=np.float64)
+    assert q.shape == (6,)
+    return lib().orc_ppm_face(_p(q), float(c))
+
+
+def fv_tp_2d(g: Grid, t: int, q, crx, cry, xfx, yfx, mx=None, my=None):
+    args = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+            for a in (q, crx, cry, xfx, yfx, mx, my)]
+    FX = np.zeros((g.N, g.N))
+    FY = np.zeros((g.N, g.N))
+    lib().orc_fv_tp_2d(g._h, t, *[_p(a) for a in args], _p(FX), _p(FY))
+    return FX, FY
+
+
+def sim1(dt, ptop, zs, dpi, theta, delz, w):
+    nz = len(dpi)
+    ins = [np.ascontiguousarray(a, dtype=np.float64) for a in (dpi, theta, delz, w)]
+    wo, dzo = np.zeros(nz), np.zeros(nz)
+    pf, ph = np.zeros(nz + 1), np.zeros(nz + 1)
+    minpiv = lib().orc_sim1(nz, dt, ptop, zs, *[_p(a) for a in ins], _p(wo), _p(dzo), _p(pf), _p(ph))
+    return dict(w=wo, delz=dzo, pfull=pf, phi=ph, min_pivot=minpiv)
+
+
+def pgf(dt, L, dpiW, dpiE, phW0, phW1, phE0, phE1, pW0, pW1, pE0, pE1) -> float:
+    return lib().orc_pgf(dt, L, dpiW, dpiE, phW0, phW1, phE0, phE1, pW0, pW1, pE0, pE1)
+
+
+STATE_FIELDS = ["u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "cx", "cy",
+                "dp0", "pfull", "phi"]
+DEBUG_FIELDS = ["delpc", "ptc", "wc", "ax", "ay", "crx", "cry", "xfx", "yfx", "pkc", "gz"]
+
+
+def new_state(g: Grid, init: dict) -> dict:
+    """Copy an input state (from fv3_inputs) into a full oracle state."""
+    s = {}
+    for k in ("u", "v", "w", "delp", "pt", "delz"):
+        s[k] = np.ascontiguousarray(init[k], dtype=np.float64).copy()
+    for k in ("uc", "vc", "mfx", "mfy", "cx", "cy", "dp0"):
+        s[k] = g.field(g.nz)
+    s["pfull"] = g.field(g.nz + 1)
+    s["phi"] = g.field(g.nz + 1)
+    s["phis"] = np.ascontiguousarray(init.get("phis", np.zeros((g.T, g.N, g.N))), dtype=np.float64)
+    return s
+
+
+def acoustic_substeps(g: Grid, s: dict, dt: float, n_split: int, stop_stage: int = 0,
+                      debug: bool = False):
+    """Run n_split substeps in place.  Returns the status (0 ok, -6 Courant > 1,
+    -7 non-finite) and, with debug=True, the intermediate fields of the last
+    substep."""
+    dbg = None
+    dbg_arr = None
+    if debug:
+        dbg = {k: g.field(g.nz + (1 if k in ("pkc", "gz") else 0)) for k in DEBUG_FIELDS}
+        dbg_arr = (C.POINTER(C.c_double) * len(DEBUG_FIELDS))(*[_p(dbg[k]) for k in DEBUG_FIELDS])
+    st = lib().orc_acoustic_substeps(g._h, *[_p(s[k]) for k in STATE_FIELDS], _p(s["phis"]),
+                                     float(dt), int(n_split), int(stop_stage), dbg_arr)
+    return (st, dbg) if debug else st
+
+
+def tracer_transport(g: Grid, qs, dp0, mfx, mfy, cx, cy, nsplt: int = 0) -> int:
+    arr = (C.POINTER(C.c_double) * len(qs))(*[_p(q) for q in qs])
+    used = C.c_int(0)
+    lib().orc_tracer_transport(g._h, arr, len(qs), _p(dp0), _p(mfx), _p(mfy), _p(cx), _p(cy),
+                               int(nsplt), C.byref(used))
+    return used.value
+
+
+def mass_sums(g: Grid, delp, pt, qs=()) -> np.ndarray:
+    out = np.zeros(2 + len(qs))
+    arr = (C.POINTER(C.c_double) * max(1, len(qs)))(*[_p(q) for q in qs])
+    lib().orc_mass_sums(g._h, _p(delp), _p(pt), arr, len(qs), _p(out))
+    return out

@@ -1,0 +1,93 @@
+/*
+ * FV3 acoustic-substep ORACLE -- test infrastructure only.
+ *
+ * A plain, slow, FP64 CPU implementation of the nonhydrostatic acoustic
+ * substep loop and tracer transport of the FV3 dynamical core (the innermost
+ * and middle loops of the three-level substepping, paper Sec. II), written to
+ * be checked by eye against the method.  Only the test suite, the smoke entry
+ * point and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or helper with the HIP library; the two are compared
+ * element by element on the same seeded inputs.
+ *
+ * Layout used throughout the oracle (deliberately unpadded and simple):
+ *   3-D field  f[t][k][jj][ii],  jj = j + H, ii = i + H,  N = n + 2H + 1
+ *   2-D metric m[t][jj][ii]
+ * with H = 3 halo points on every side.  Staggerings share the N x N plane:
+ *   C  cell centre   (i+1/2, j+1/2)     interior i,j in [0,n-1]
+ *   X  x-face        (i,     j+1/2)     interior i in [0,n], j in [0,n-1]
+ *   Y  y-face        (i+1/2, j    )     interior i in [0,n-1], j in [0,n]
+ *   B  cell corner   (i,     j    )     interior i,j in [0,n]
+ * (coordinates in units of the grid spacing, corner (0,0) at the tile's SW
+ * vertex).  D-grid winds: u on Y, v on X.  C-grid winds: uc on X, vc on Y.
+ */
+#ifndef FV3_ORACLE_ORC_H
+#define FV3_ORACLE_ORC_H
+
+#include <stddef.h>
+
+#define H 3
+
+enum { ST_C = 0, ST_X = 1, ST_Y = 2, ST_B = 3 };
+enum { MODE_X = 0, MODE_Y = 1 };
+/* how a pair of components transforms when copied across a rotated edge */
+enum { PAIR_SIGNED = 0, PAIR_ABS = 1, PAIR_COS = 2 };
+
+/* physical constants of the dry nonhydrostatic system (reading R3) */
+#define O_GRAV 9.80665
+#define O_RDGAS 287.05
+#define O_CP 1004.6
+#define O_P0 1.0e5
+
+typedef struct {
+    int kind;              /* 0 doubly periodic, 1 cubed sphere */
+    int n, nz, T, N;
+    double delta, f0, radius, omega, ptop;
+    /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
+    int nbr[6][4];
+    int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
+    int P0[6][4][2];       /* edge start point on this tile (lattice units)      */
+    int Q0[6][4][2];       /* the same point on the neighbour tile               */
+    /* metrics [T][N][N]; halos hold the neighbour's values */
+    double *dx, *dy, *dxc, *dyc, *dxa, *dya, *area, *area_c, *fC, *fB;
+    double *sin_u, *cos_u, *sin_v, *cos_v, *sin_a, *cos_a;
+    /* unit-sphere positions (cube only): cell centres and cell corners */
+    double *cpos[3], *bpos[3];
+} OGrid;
+
+static inline size_t o_plane(const OGrid *g) { return (size_t)g->N * g->N; }
+#define IX(g, i, j) ((size_t)((j) + H) * (size_t)(g)->N + (size_t)((i) + H))
+
+/* caller-owned state arrays of the substep loop */
+typedef struct {
+    double *u, *v, *w, *delp, *pt, *delz, *uc, *vc, *mfx, *mfy, *cx, *cy, *dp0, *pfull, *phi;
+    const double *phis;
+} OState;
+
+/* grid.c */
+OGrid *og_new(int kind, int n, int nz, double delta, double f0, double radius,
+              double omega, double ptop, char *err, size_t errlen);
+void og_free(OGrid *g);
+
+/* halo.c */
+int og_region(const OGrid *g, int st, int i, int j);   /* 0 interior, 1 edge halo, 2 corner block */
+void og_fill_scalar(const OGrid *g, double *f, int nlev, int st, int coslike);
+void og_fill_pair(const OGrid *g, double *fx, int stx, double *fy, int sty, int nlev, int kind);
+void og_view_scalar(const OGrid *g, const double *plane, int st, int mode, int coslike, double *out);
+void og_view_pair(const OGrid *g, const double *px, int stx, const double *py, int sty,
+                  int mode, int kind, double *ox, double *oy);
+int og_is_vertex(const OGrid *g, int i, int j);
+
+/* ppm.c */
+double o_ppm_face(const double q[6], double c);
+void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const double *qy,
+                const double *crx, const double *cry, const double *xfx, const double *yfx,
+                const double *mx, const double *my, double *FX, double *FY);
+
+/* column.c */
+double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, const double *theta,
+              const double *delz, const double *w, double *w_out, double *delz_out,
+              double *pfull, double *phi);
+double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
+             double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
+
+#endif

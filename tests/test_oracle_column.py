@@ -1,0 +1,177 @@
+"""Pins of the oracle's semi-implicit vertical solve (riem_solver_c /
+riem_solver3, Sec. IX-B: nonhydrostatic w and pressure perturbation through a
+tridiagonal solver) and of the finite-volume pressure-gradient force.
+
+Pins: the Thomas elimination equals a dense LU solve of the same system; the
+closed-form single-layer solution; a column at hydrostatic rest stays at rest;
+the top-down scan of the new perturbation equals the implicitly linearised
+interface pressure (so the returned w solves the discrete momentum equation);
+the thickness inversion reproduces the new pressure through the equation of
+state; all pivots positive; the pressure gradient is zero for identical
+columns, equals -dt*dp/(rho*L) for a uniform offset, and is antisymmetric."""
+import math
+
+import numpy as np
+import pytest
+
+G, RD, CP, P0 = 9.80665, 287.05, 1004.6, 1.0e5
+KAPPA = RD / CP
+GAM = 1.0 / (1.0 - KAPPA)
+
+
+def _column(nz, rng, perturb=0.02):
+    pi = np.linspace(100.0, 1.0e5, nz + 1)
+    dpi = np.diff(pi)
+    T = 250.0 + 50.0 * rng.random(nz)
+    lnr = np.log(pi[1:] / pi[:-1])
+    pibar = dpi / lnr
+    theta = T * (P0 / pibar) ** KAPPA
+    delz = -(RD * T / G) * lnr * (1.0 + perturb * rng.standard_normal(nz))
+    w = rng.standard_normal(nz)
+    return pi, dpi, theta, delz, w
+
+
+def _assemble(dt, pi, dpi, theta, delz, w):
+    """Dense matrix of the implicit system, assembled from the discrete
+    equations (interface pressure linearised in the new w)."""
+    nz = len(dpi)
+    m = dpi / G
+    h = -delz
+    pibar = dpi / (np.log(pi[1:]) - np.log(pi[:-1]))
+    p = P0 * (RD * theta * m / (h * P0)) ** GAM
+    pp = p - pibar
+    PPs = np.zeros(nz + 1)
+    for K in range(1, nz):
+        PPs[K] = (dpi[K] * pp[K - 1] + dpi[K - 1] * pp[K]) / (dpi[K - 1] + dpi[K])
+    PPs[nz] = pp[nz - 1]
+    d = np.zeros(nz + 1)
+    d[1:nz] = 0.5 * (h[:-1] + h[1:])
+    d[nz] = 0.5 * h[-1]
+    A = np.zeros(nz + 1)
+    A[1:] = GAM * (pi[1:] + PPs[1:]) * dt * dt / d[1:]
+    M = np.zeros((nz, nz))
+    rhs = m * w + dt * (PPs[1:] - PPs[:-1])
+    for k in range(nz):
+        M[k, k] = m[k] + A[k] + A[k + 1]
+        if k > 0:
+            M[k, k - 1] = -A[k]
+        if k < nz - 1:
+            M[k, k + 1] = -A[k + 1]
+    return M, rhs, PPs, A, m, pibar
+
+
+@pytest.mark.parametrize("nz", [1, 2, 3, 5, 8, 20])
+def test_thomas_matches_dense_lu(orc, nz):
+    rng = np.random.default_rng(100 + nz)
+    for _ in range(5):
+        pi, dpi, theta, delz, w = _column(nz, rng)
+        dt = 7.5
+        r = orc.sim1(dt, 100.0, 0.0, dpi, theta, delz, w)
+        M, rhs, *_ = _assemble(dt, pi, dpi, theta, delz, w)
+        wd = np.linalg.solve(M, rhs)
+        assert np.max(np.abs(r["w"] - wd)) <= 1e-13 * max(1.0, np.max(np.abs(wd)))
+        assert r["min_pivot"] > 0
+
+
+def test_single_layer_closed_form(orc):
+    rng = np.random.default_rng(9)
+    pi, dpi, theta, delz, w = _column(1, rng, perturb=0.05)
+    dt = 3.0
+    r = orc.sim1(dt, 100.0, 0.0, dpi, theta, delz, w)
+    m = dpi[0] / G
+    h = -delz[0]
+    pibar = dpi[0] / math.log(pi[1] / pi[0])
+    pp0 = P0 * (RD * theta[0] * m / (h * P0)) ** GAM - pibar
+    A1 = GAM * (pi[1] + pp0) * dt * dt / (0.5 * h)
+    want = (m * w[0] + dt * pp0) / (m + A1)
+    assert abs(r["w"][0] - want) <= 1e-14 * max(1.0, abs(want))
+
+
+def test_rest_column_stays_at_rest(orc):
+    nz = 12
+    pi = np.linspace(100.0, 1.0e5, nz + 1)
+    dpi = np.diff(pi)
+    lnr = np.log(pi[1:] / pi[:-1])
+    T = np.linspace(220.0, 300.0, nz)
+    theta = T * (P0 / (dpi / lnr)) ** KAPPA
+    delz = -(RD * T / G) * lnr
+    r = orc.sim1(15.0, 100.0, 0.0, dpi, theta, delz, np.zeros(nz))
+    assert np.max(np.abs(r["w"])) <= 1e-12
+    np.testing.assert_allclose(r["delz"], delz, rtol=1e-14)
+    # hydrostatic interfaces and heights
+    np.testing.assert_allclose(r["pfull"], pi, rtol=1e-13)
+    z = np.concatenate([np.cumsum(-delz[::-1])[::-1], [0.0]])
+    np.testing.assert_allclose(r["phi"], G * z, rtol=1e-13, atol=1e-9)
+
+
+def test_scanned_perturbation_is_linearised_interface_pressure(orc):
+    rng = np.random.default_rng(21)
+    for nz in (2, 5, 9):
+        pi, dpi, theta, delz, w = _column(nz, rng)
+        dt = 10.0
+        r = orc.sim1(dt, 100.0, 0.0, dpi, theta, delz, w)
+        M, rhs, PPs, A, m, pibar = _assemble(dt, pi, dpi, theta, delz, w)
+        wn = r["w"]
+        wext = np.concatenate([wn, [0.0]])                # surface w = 0
+        Plin = PPs.copy()
+        for K in range(1, nz + 1):
+            Plin[K] = PPs[K] - (A[K] / dt) * (wext[K - 1] - wext[K])
+        scanned = r["pfull"] - pi
+        assert np.max(np.abs(scanned - Plin)) <= 1e-12 * np.max(np.abs(pi))
+
+
+def test_thickness_inverts_equation_of_state(orc):
+    rng = np.random.default_rng(31)
+    nz = 6
+    pi, dpi, theta, delz, w = _column(nz, rng)
+    dt = 5.0
+    r = orc.sim1(dt, 100.0, 0.0, dpi, theta, delz, w)
+    pnew = 0.5 * (r["pfull"][:-1] + r["pfull"][1:]) - 0.5 * (pi[:-1] + pi[1:]) + dpi / np.log(pi[1:] / pi[:-1])
+    m = dpi / G
+    p_eos = P0 * (RD * theta * m / (-r["delz"] * P0)) ** GAM
+    np.testing.assert_allclose(p_eos, pnew, rtol=1e-13)
+
+
+def test_compressed_layer_pushes_outward(orc):
+    # a squeezed middle layer has excess pressure: the layer above accelerates up,
+    # the one below down
+    nz = 5
+    pi = np.linspace(100.0, 1.0e5, nz + 1)
+    dpi = np.diff(pi)
+    lnr = np.log(pi[1:] / pi[:-1])
+    T = np.full(nz, 280.0)
+    theta = T * (P0 / (dpi / lnr)) ** KAPPA
+    delz = -(RD * T / G) * lnr
+    delz[2] *= 0.99
+    r = orc.sim1(2.0, 100.0, 0.0, dpi, theta, delz, np.zeros(nz))
+    assert r["w"][1] > 0 and r["w"][3] < 0
+
+
+def test_pgf_closed_forms(orc):
+    dt, L = 20.0, 5.0e4
+    # identical columns: exactly zero
+    assert orc.pgf(dt, L, 900.0, 900.0, 5e4, 4e4, 5e4, 4e4, 3e4, 3.09e4, 3e4, 3.09e4) == 0.0
+    # uniform offset of the east column's pressure: -dt * dp / (rho L)
+    phi0, phi1, dpi, dp = 5.0e4, 4.9e4, 900.0, 37.0
+    got = orc.pgf(dt, L, dpi, dpi, phi0, phi1, phi0, phi1, 3.0e4, 3.0e4 + dpi, 3.0e4 + dp, 3.0e4 + dpi + dp)
+    rho = dpi / (phi0 - phi1)          # delta-pi / (g dz), with phi = g z
+    want = -dt * dp / (rho * L)
+    assert abs(got - want) <= 1e-13 * abs(want)
+    assert got < 0                      # force toward the low pressure (west)
+    # antisymmetric under exchange of the two columns
+    args = (870.0, 910.0, 5.1e4, 4.0e4, 5.0e4, 4.1e4, 3.0e4, 3.09e4, 3.01e4, 3.1e4)
+    a = orc.pgf(dt, L, *args)
+    b = orc.pgf(dt, L, args[1], args[0], args[4], args[5], args[2], args[3], args[8], args[9], args[6], args[7])
+    assert abs(a + b) <= 1e-15 * abs(a)
+
+
+def test_long_step_limit_is_hydrostatic(orc):
+    # backward Euler with a very long step relaxes the column to zero
+    # nonhydrostatic perturbation (P'_{k+1} - P'_k = m dw/dt -> 0, P'_top = 0)
+    rng = np.random.default_rng(41)
+    pi, dpi, theta, delz, w = _column(7, rng, perturb=0.03)
+    r = orc.sim1(1.0e7, 100.0, 0.0, dpi, theta, delz, np.zeros(7))
+    pert = r["pfull"] - pi
+    assert np.max(np.abs(pert)) <= 1e-6 * pi[-1]
+    # w decays like (displacement needed to rebalance) / dt
+    assert np.max(np.abs(r["w"])) * 1.0e7 <= 0.1 * np.max(np.abs(delz))

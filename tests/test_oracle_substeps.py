@@ -1,0 +1,126 @@
+"""Pins of the oracle's whole acoustic substep loop (the innermost loop of
+Sec. II) on the doubly periodic grid and the cubed sphere.
+
+Pins: delp mass and pt*delp conserved to 1e-14 (flux form on a periodic
+domain); a hydrostatic rest state and a uniform flow are steady states; the
+transposed initial state evolves into the transposed result (catches any
+index or sign slip that breaks the x/y mirror structure); a compressed column
+pushes air outward in both directions (signs of both pressure gradients); the
+cube run stays finite with small global mass drift."""
+import numpy as np
+import pytest
+
+import fv3_inputs as fi
+
+H = 3
+
+
+def _int(a, n, st="C", lev=None):
+    ni = n + 1 if st in ("X", "B") else n
+    nj = n + 1 if st in ("Y", "B") else n
+    return a[..., H:H + nj, H:H + ni]
+
+
+def test_cfg1_mass_conservation(orc):
+    g = orc.Grid(0, 48, 8)
+    s = orc.new_state(g, fi.periodic_state())
+    m0 = orc.mass_sums(g, s["delp"], s["pt"])
+    assert orc.acoustic_substeps(g, s, 2.0, 10) == 0
+    m1 = orc.mass_sums(g, s["delp"], s["pt"])
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * np.abs(m0))
+    # delp changed: the test is not vacuous
+    assert np.abs(_int(s["delp"], 48) - _int(fi.periodic_state()["delp"], 48)).max() > 1e-3
+
+
+def _rest(n=16, nz=6, f0=0.0):
+    init = fi.periodic_state(n=n, nz=nz, wind=0.0)
+    init["u"][:] = 0.0
+    init["v"][:] = 0.0
+    return init
+
+
+@pytest.mark.parametrize("f0", [0.0, 1e-4])
+def test_rest_state_is_steady(orc, f0):
+    n, nz = 16, 6
+    g = orc.Grid(0, n, nz, f0=f0)
+    init = _rest(n, nz)
+    s = orc.new_state(g, init)
+    assert orc.acoustic_substeps(g, s, 20.0, 10) == 0
+    for k in ("delp", "pt", "delz"):
+        np.testing.assert_allclose(_int(s[k], n), _int(init[k], n), rtol=1e-13, atol=0)
+    assert np.abs(_int(s["w"], n)).max() <= 1e-12
+    assert np.abs(_int(s["u"], n, "Y")).max() <= 1e-12
+    assert np.abs(_int(s["v"], n, "X")).max() <= 1e-12
+
+
+def test_uniform_flow_is_steady(orc):
+    n, nz = 16, 6
+    g = orc.Grid(0, n, nz)
+    init = _rest(n, nz)
+    init["u"][0, :, H:H + n + 1, H:H + n] = 10.0
+    init["v"][0, :, H:H + n, H:H + n + 1] = 10.0
+    s = orc.new_state(g, init)
+    assert orc.acoustic_substeps(g, s, 20.0, 10) == 0
+    for k, st in (("u", "Y"), ("v", "X"), ("delp", "C"), ("pt", "C"), ("delz", "C")):
+        np.testing.assert_allclose(_int(s[k], n, st), _int(init[k], n, st), rtol=1e-13, atol=1e-12)
+    assert np.abs(_int(s["w"], n)).max() <= 1e-12
+    # accumulated Courant number of 10 substeps of 2 s at 10 m/s over 1 km
+    np.testing.assert_allclose(_int(s["cx"], n, "X"), 10 * 2.0 * 10.0 / 1000.0, rtol=1e-13)
+
+
+def _transpose_state(init):
+    out = dict(init)
+    out["u"] = np.ascontiguousarray(init["v"].swapaxes(-1, -2))
+    out["v"] = np.ascontiguousarray(init["u"].swapaxes(-1, -2))
+    for k in ("w", "delp", "pt", "delz"):
+        out[k] = np.ascontiguousarray(init[k].swapaxes(-1, -2))
+    return out
+
+
+def test_transpose_symmetry(orc):
+    n, nz = 20, 5
+    g = orc.Grid(0, n, nz)
+    init = fi.periodic_state(n=n, nz=nz, seed=12, temp_noise=1.0)
+    a = orc.new_state(g, init)
+    b = orc.new_state(g, _transpose_state(init))
+    assert orc.acoustic_substeps(g, a, 4.0, 4) == 0
+    assert orc.acoustic_substeps(g, b, 4.0, 4) == 0
+    pairs = (("u", "v", "Y", "X"), ("v", "u", "X", "Y"), ("w", "w", "C", "C"),
+             ("delp", "delp", "C", "C"), ("pt", "pt", "C", "C"), ("delz", "delz", "C", "C"),
+             ("mfx", "mfy", "X", "Y"), ("cx", "cy", "X", "Y"))
+    for ka, kb, sa, sb in pairs:
+        A = _int(a[ka], n, sa)
+        Bt = _int(b[kb], n, sb).swapaxes(-1, -2)
+        scale = np.abs(A).max()
+        assert np.abs(A - Bt).max() <= 1e-12 * scale, ka
+
+
+def test_compressed_column_pushes_outward(orc):
+    n, nz = 16, 6
+    g = orc.Grid(0, n, nz)
+    init = _rest(n, nz)
+    c = n // 2
+    init["delz"][0, :, H + c, H + c] *= 0.995      # squeeze one column: high pressure
+    s = orc.new_state(g, init)
+    assert orc.acoustic_substeps(g, s, 1.0, 1) == 0
+    k = nz - 1
+    u = s["u"][0, k]          # D-grid u on the y-face from corner (i, j) to (i+1, j)
+    # C-grid winds on the faces of the squeezed cell
+    west, east = s["uc"][0, k, H + c, H + c], s["uc"][0, k, H + c, H + c + 1]
+    assert west < 0 < east
+    south, north = s["vc"][0, k, H + c, H + c], s["vc"][0, k, H + c + 1, H + c]
+    assert south < 0 < north
+    # D-grid u on the edges east and west of the cell's top corners
+    assert u[H + c + 1, H + c + 1] > 0 and u[H + c + 1, H + c - 1] < 0
+
+
+def test_cube_runs_finite(orc):
+    n, nz = 12, 4
+    g = orc.Grid(1, n, nz)
+    s = orc.new_state(g, fi.cube_state(n=n, nz=nz))
+    m0 = orc.mass_sums(g, s["delp"], s["pt"])
+    assert orc.acoustic_substeps(g, s, 10 * 300.0, 10) == 0
+    m1 = orc.mass_sums(g, s["delp"], s["pt"])
+    assert np.all(np.abs(m1 / m0 - 1) < 1e-5)
+    for k in ("u", "v", "w", "delp", "pt", "delz"):
+        assert np.all(np.isfinite(s[k][:, :, H:H + n, H:H + n]))
