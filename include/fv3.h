@@ -1,0 +1,195 @@
+/*
+ * fv3.h -- C ABI of an MI355X-native implementation of the acoustic substep
+ * loop of the FV3 finite-volume cubed-sphere dynamical core and of its tracer
+ * transport.
+ *
+ * The paper (Sec. II) describes FV3 as three nested loops: the physics step,
+ * the remapping step (which advects tracers and remaps the vertical), and the
+ * innermost acoustic substep that integrates the nonhydrostatic dynamics on
+ * Lagrangian surfaces, with halo exchanges at several points of each
+ * substep.  It drives the whole time-stepping program as one call into a
+ * compiled library (Fig. 2 caption, Sec. III-C).  This header exposes that
+ * innermost loop and the tracer advection of the middle loop as such calls.
+ *
+ * Conventions shared by every entry point:
+ *  - All pointers to field data are DEVICE pointers (HIP, one GPU) laid out
+ *    as described by fv3_layout.  The caller allocates and frees them; the
+ *    library never frees caller memory.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream).  Argument validation is synchronous:
+ *    an invalid call returns an error and enqueues nothing.
+ *  - Grids are created by fv3_init_grid, owned by the library, immutable after
+ *    creation, and may be shared by concurrent calls on distinct states.
+ *  - Errors found on the device (|Courant| > 1, non-finite prognostics) are
+ *    latched per grid and returned by fv3_check_status.
+ *  - fv3_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef FV3_H
+#define FV3_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FV3_OK = 0,
+    FV3_EINVAL = -1,        /* bad argument value (NULL pointer, dt <= 0, n_split < 1, ...) */
+    FV3_ESHAPE = -2,        /* sizes inconsistent with the grid or limits                   */
+    FV3_EDTYPE = -3,        /* precision mode mismatch                                      */
+    FV3_EDEVICE = -4,       /* HIP runtime error / no device                                */
+    FV3_ENOMEM = -5,        /* device allocation failed (grid creation only)                */
+    FV3_ECFL = -6,          /* a Courant number exceeded 1 in d_sw (latched on device)      */
+    FV3_ENONFINITE = -7,    /* a prognostic became non-finite (latched on device)           */
+    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8, d2_bg != 0, beta != 1)    */
+    FV3_EINTERNAL = -99
+} fv3_status;
+
+typedef enum { FV3_GRID_DOUBLY_PERIODIC = 0, FV3_GRID_CUBED_SPHERE = 1 } fv3_grid_kind;
+typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
+
+/* Grid description.  Cubed sphere: 6 equiangular gnomonic tiles of n x n
+ * cells (Sec. II), radius and rotation rate given.  Doubly periodic: one
+ * n x n tile of spacing dx with constant Coriolis parameter f0.  Vertical:
+ * nz Lagrangian layers below the model top pressure ptop.  Only the monotone
+ * PPM order hord = 8, no divergence damping (d2_bg = 0) and a fully implicit
+ * vertical solve (beta = 1) are implemented; other values give
+ * FV3_EUNSUPPORTED. */
+typedef struct {
+    int kind;            /* fv3_grid_kind                                  */
+    int n, nz;           /* cells per tile edge, layers                    */
+    double dx, f0;       /* periodic: spacing [m], Coriolis [1/s]          */
+    double radius, omega;/* cubed sphere: [m], [1/s]                       */
+    double ptop;         /* top pressure [Pa]                              */
+    int precision;       /* fv3_precision                                  */
+    int hord;            /* 8                                              */
+    double d2_bg;        /* 0                                              */
+    double beta;         /* 1                                              */
+    int device;          /* HIP device ordinal                             */
+} fv3_grid_params;
+
+typedef struct fv3_grid fv3_grid;
+
+/* Memory layout of every field.  Element (t, k, j, i) of a field with L
+ * levels (L = nz for layer fields, nz + 1 for interface fields, 1 for 2-D
+ * fields) sits at
+ *     offset0 + (t * L + k) * level_elems + j * pitch + i
+ * for i, j in [-halo, n + halo] (index n + halo is used by face and corner
+ * staggerings only).  Rows are padded to `pitch` elements and every level is
+ * pre-padded so that interior column i = 0 starts on a 128-byte boundary.
+ * Staggering (point in units of the grid spacing, tile SW vertex at 0):
+ *   cell (i + 1/2, j + 1/2): w, delp, pt, delz, dp0, q, pfull, phi, phis
+ *   x-face (i, j + 1/2):     v (D grid), uc (C grid), mfx, cx
+ *   y-face (i + 1/2, j):     u (D grid), vc (C grid), mfy, cy
+ * A field of L levels needs alloc_elems(L) = offset0 - halo*(pitch + 1)
+ * + tiles * L * level_elems + pitch elements. */
+typedef struct {
+    int tiles, n, nz, halo;
+    long pitch, rows, level_elems, offset0;
+    int bulk_elem_bytes;   /* 8 for FV3_FP64, 4 for FV3_MIXED */
+} fv3_layout;
+
+/* Caller-owned device arrays of one model state.  Bulk-precision fields
+ * (u, v, w, delp, pt, uc, vc, cx, cy) are double in FV3_FP64 and float in
+ * FV3_MIXED; delz, mfx, mfy, dp0, pfull, phi and phis are always double.
+ * `workspace` must hold fv3_workspace_bytes(grid) bytes. */
+typedef struct {
+    void *u, *v, *w, *delp, *pt;     /* prognostics, updated in place              */
+    double *delz;                    /* layer thickness (negative) [m], in place    */
+    void *uc, *vc;                   /* C-grid winds (out)                          */
+    double *mfx, *mfy;               /* accumulated mass fluxes (out, zeroed)       */
+    void *cx, *cy;                   /* accumulated Courant numbers (out, zeroed)   */
+    double *dp0;                     /* delp at entry (out)                         */
+    double *pfull, *phi;             /* interface pressure [Pa], geopotential (out) */
+    const double *phis;              /* surface geopotential (2-D) or NULL = flat   */
+    void *workspace;
+    size_t workspace_bytes;
+} fv3_state;
+
+/* Build a grid on `p->device`: geometry and metric terms (FP64 on the host),
+ * tile connectivity by matching shared edges, the halo plan, upload to the
+ * device.  Synchronous.  Sec. II (gnomonic cubed sphere); the halo plan
+ * carries the orientation transform between adjoining faces of Sec. V-C.
+ * Returns FV3_OK and *out, or an error (nothing allocated). */
+fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out);
+
+/* Release a grid (synchronises the device).  NULL is accepted. */
+fv3_status fv3_free_grid(fv3_grid *g);
+
+/* Fill *out with the grid's field layout. */
+fv3_status fv3_grid_layout(const fv3_grid *g, fv3_layout *out);
+
+/* Bytes of workspace fv3_acoustic_substeps and fv3_tracer_transport need. */
+size_t fv3_workspace_bytes(const fv3_grid *g);
+
+/* Copy one metric term of the grid to host memory, as doubles in the field
+ * layout with L = 1 (alloc_elems(1) values).  which: 0 dx 1 dy 2 dxc 3 dyc
+ * 4 dxa 5 dya 6 area 7 area_c 8 fC 9 fB 10 sin_u 11 cos_u 12 sin_v 13 cos_v
+ * 14 sin_a 15 cos_a.  Synchronous. */
+fv3_status fv3_grid_metric(const fv3_grid *g, int which, double *host_out);
+
+/* Host-only variant for inspection and tests: compute metric `which` (as
+ * in fv3_grid_metric) for the grid `p` on the host, without a device, into
+ * host_out as a compact array [tiles][n + 7][n + 7] (row j + 3, column
+ * i + 3).  max_elems is the capacity of host_out; FV3_ESHAPE if too small. */
+fv3_status fv3_host_grid_metric(const fv3_grid_params *p, int which, double *host_out,
+                                long max_elems);
+
+/* Run n_split acoustic substeps of length dt / n_split (the innermost loop
+ * of Sec. II): per substep the halo exchange of the D-grid winds and cell
+ * fields, c_sw over half a substep, the C-grid vertical solve
+ * (riem_solver_c, Sec. IX-B) and pressure gradient, the C-grid wind halo,
+ * d_sw with fv_tp_2d transport (Sec. IX-C), riem_solver3, the halo of the
+ * interface pressure and geopotential, and the D-grid pressure gradient.
+ * On entry mfx, mfy, cx, cy are zeroed and dp0 = delp; they accumulate over
+ * the call for fv3_tracer_transport.  Asynchronous on `stream`.
+ * Errors: FV3_EINVAL (NULL field, dt not finite or <= 0, n_split < 1,
+ * workspace too small). */
+fv3_status fv3_acoustic_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split,
+                                 void *stream);
+
+/* Test entry point: as fv3_acoustic_substeps, but in the last substep stop
+ * after stage `stop_stage` (1 halo A, 2 c_sw, 3 dz_c + riem_solver_c,
+ * 4 p_grad_c, 5 halo B, 6 d_sw, 7 dz_d, 8 riem_solver3, 9 halo C,
+ * 10 nh_p_grad = complete).  Used to compare single stages with a
+ * reference implementation. */
+fv3_status fv3_acoustic_substeps_debug(fv3_state *s, const fv3_grid *g, double dt, int n_split,
+                                       int stop_stage, void *stream);
+
+/* Tracer advection of the remapping step (Sec. II) with the fluxes and
+ * Courant numbers accumulated by the last fv3_acoustic_substeps on `s`:
+ * nsplt sub-cycles (nsplt <= 0: the smallest count that keeps every
+ * sub-cycle Courant number <= 1, which costs one device-to-host read), each a
+ * halo fill of the tracers and a mass-weighted fv_tp_2d update.  q[m] are
+ * device pointers to nq bulk-precision cell fields, updated in place; s->cx
+ * and s->cy get their halos filled.  Errors: FV3_EINVAL (NULL pointers,
+ * nq < 1 or > 64). */
+fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_grid *g,
+                                int nsplt, void *stream);
+
+/* Compensated (Neumaier) FP64 global sums over the interior cells:
+ * out[0] = sum delp*area, out[1] = sum pt*delp*area, out[2+m] = sum
+ * q[m]*delp*area.  `delp` and `pt` are bulk-precision fields; out is a
+ * host array of 2 + nq doubles.  Synchronises `stream`. */
+fv3_status fv3_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                         int nq, double *host_out, void *stream);
+
+/* Fill the halos of n_fields cell-centred fields (L levels each, bulk
+ * precision unless fp64 != 0) from the neighbouring tiles.  Exposed for
+ * tests of the halo exchange. */
+fv3_status fv3_halo_fill(const fv3_grid *g, void *const *fields, int n_fields, int levels,
+                         int fp64, void *stream);
+
+/* Synchronise `stream`, then return and clear the first device-detected
+ * error latched on the grid (FV3_ECFL, FV3_ENONFINITE) or FV3_OK. */
+fv3_status fv3_check_status(const fv3_grid *g, void *stream);
+
+const char *fv3_status_string(fv3_status s);
+const char *fv3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,281 @@
+"""Python binding of the MI355X FV3 acoustic-substep library (libfv3.so).
+
+Argument marshalling only: every step of the acoustic substep loop and the
+tracer transport runs in the HIP kernels of libfv3.so.  PyTorch provides the
+device memory (tensors in the library's padded layout) and the stream.  If
+the shared library is missing the import of the entry points raises; there is
+no CPU fallback.
+
+    g = Grid(kind=1, n=96, nz=79)            # cubed sphere C96 x 79 levels
+    s = State.allocate(g)
+    s.load(init)                             # host arrays f[t][k][j+3][i+3]
+    acoustic_substeps(s, g, dt=1800.0, n_split=60)
+    tracer_transport([q...], s, g)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libfv3.so")
+H = 3
+RADIUS = 6.3712e6
+OMEGA = 7.2921e-5
+
+STATUS = {0: "ok", -1: "EINVAL", -2: "ESHAPE", -3: "EDTYPE", -4: "EDEVICE", -5: "ENOMEM",
+          -6: "ECFL", -7: "ENONFINITE", -8: "EUNSUPPORTED", -99: "EINTERNAL"}
+METRICS = ["dx", "dy", "dxc", "dyc", "dxa", "dya", "area", "area_c", "fC", "fB", "sin_u",
+           "cos_u", "sin_v", "cos_v", "sin_a", "cos_a"]
+EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_bytes",
+           "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
+           "fv3_tracer_transport", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
+           "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric"]
+
+
+class FV3Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridParams(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
+                ("f0", C.c_double), ("radius", C.c_double), ("omega", C.c_double),
+                ("ptop", C.c_double), ("precision", C.c_int), ("hord", C.c_int),
+                ("d2_bg", C.c_double), ("beta", C.c_double), ("device", C.c_int)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("tiles", C.c_int), ("n", C.c_int), ("nz", C.c_int), ("halo", C.c_int),
+                ("pitch", C.c_long), ("rows", C.c_long), ("level_elems", C.c_long),
+                ("offset0", C.c_long), ("bulk_elem_bytes", C.c_int)]
+
+
+class StateStruct(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx",
+                                          "mfy", "cx", "cy", "dp0", "pfull", "phi", "phis",
+                                          "workspace")] + [("workspace_bytes", C.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfv3.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            raise ImportError(f"{_LIBPATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(_LIBPATH)
+        vp = C.c_void_p
+        L.fv3_init_grid.argtypes = [C.POINTER(GridParams), C.POINTER(vp)]
+        L.fv3_free_grid.argtypes = [vp]
+        L.fv3_grid_layout.argtypes = [vp, C.POINTER(Layout)]
+        L.fv3_workspace_bytes.argtypes = [vp]
+        L.fv3_workspace_bytes.restype = C.c_size_t
+        L.fv3_grid_metric.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
+        L.fv3_host_grid_metric.argtypes = [C.POINTER(GridParams), C.c_int, C.POINTER(C.c_double),
+                                           C.c_long]
+        L.fv3_acoustic_substeps.argtypes = [C.POINTER(StateStruct), vp, C.c_double, C.c_int, vp]
+        L.fv3_acoustic_substeps_debug.argtypes = [C.POINTER(StateStruct), vp, C.c_double, C.c_int,
+                                                  C.c_int, vp]
+        L.fv3_tracer_transport.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(StateStruct), vp,
+                                           C.c_int, vp]
+        L.fv3_mass_sums.argtypes = [vp, vp, vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double), vp]
+        L.fv3_halo_fill.argtypes = [vp, C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp]
+        L.fv3_check_status.argtypes = [vp, vp]
+        L.fv3_status_string.argtypes = [C.c_int]
+        L.fv3_status_string.restype = C.c_char_p
+        L.fv3_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise FV3Error(st, lib().fv3_last_error().decode())
+
+
+def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device):
+    return GridParams(kind=kind, n=n, nz=nz, dx=dx, f0=f0, radius=radius, omega=omega, ptop=ptop,
+                      precision=0 if precision == "fp64" else 1, hord=8, d2_bg=0.0, beta=1.0,
+                      device=device)
+
+
+def host_metric(kind, n, nz, name, dx=1000.0, f0=0.0, radius=RADIUS, omega=OMEGA, ptop=100.0,
+                precision="fp64"):
+    """Metric term computed by the library's host grid builder (no device
+    needed), returned as [T][N][N] with N = n + 2*3 + 1."""
+    p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, 0)
+    T = 6 if kind == 1 else 1
+    N = n + 2 * H + 1
+    out = np.zeros(T * N * N)
+    _check(lib().fv3_host_grid_metric(C.byref(p), METRICS.index(name),
+                                      out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+    return out.reshape(T, N, N)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Grid:
+    """A library-owned grid on one HIP device (kind 0 doubly periodic, 1 cube)."""
+
+    def __init__(self, kind: int, n: int, nz: int, dx: float = 1000.0, f0: float = 0.0,
+                 radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
+                 precision: str = "fp64", device: int = 0):
+        torch = _torch()
+        torch.cuda.set_device(device)
+        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device)
+        h = C.c_void_p()
+        _check(lib().fv3_init_grid(C.byref(p), C.byref(h)))
+        self._h = h
+        lay = Layout()
+        _check(lib().fv3_grid_layout(h, C.byref(lay)))
+        self.layout = lay
+        self.kind, self.n, self.nz, self.T = kind, n, nz, lay.tiles
+        self.precision = precision
+        self.device = device
+        self.N = n + 2 * H + 1
+        self.pitch, self.rows, self.lev, self.off0 = lay.pitch, lay.rows, lay.level_elems, lay.offset0
+        self.pre = self.off0 - H * self.pitch - H
+        self.bulk_dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.ws_bytes = lib().fv3_workspace_bytes(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fv3_free_grid(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def alloc_elems(self, levels: int) -> int:
+        return self.pre + self.T * levels * self.lev + self.pitch
+
+    def new_field(self, levels: int, fp64: bool = False):
+        torch = _torch()
+        dt = torch.float64 if fp64 else self.bulk_dtype
+        return torch.zeros(self.alloc_elems(levels), dtype=dt, device=f"cuda:{self.device}")
+
+    def view(self, buf, levels: int):
+        """[T][L][N][N] view of a padded device buffer (i + 3, j + 3 indexing)."""
+        n = self.T * levels * self.lev
+        return buf[self.pre:self.pre + n].view(self.T, levels, self.rows, self.pitch)[..., :self.N]
+
+    def upload(self, host: np.ndarray, levels: int, fp64: bool = False):
+        torch = _torch()
+        buf = self.new_field(levels, fp64)
+        a = np.asarray(host).reshape(self.T, levels, self.N, self.N)
+        self.view(buf, levels).copy_(torch.from_numpy(np.ascontiguousarray(a)).to(buf.dtype))
+        return buf
+
+    def download(self, buf, levels: int) -> np.ndarray:
+        return self.view(buf, levels).double().cpu().numpy()
+
+    def metric(self, name: str) -> np.ndarray:
+        out = np.zeros(self.alloc_elems(1))
+        _check(lib().fv3_grid_metric(self._h, METRICS.index(name),
+                                     out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out[self.pre:self.pre + self.T * self.lev].reshape(
+            self.T, self.rows, self.pitch)[:, :, :self.N].copy()
+
+
+LAYER_BULK = ("u", "v", "w", "delp", "pt", "uc", "vc", "cx", "cy")
+LAYER_F64 = ("delz", "mfx", "mfy", "dp0")
+IFACE_F64 = ("pfull", "phi")
+
+
+class State:
+    """Device arrays of one model state (torch tensors in the padded layout)."""
+
+    def __init__(self, grid: Grid, fields: dict):
+        self.grid = grid
+        self.f = fields
+
+    @classmethod
+    def allocate(cls, grid: Grid) -> "State":
+        torch = _torch()
+        f = {}
+        for k in LAYER_BULK:
+            f[k] = grid.new_field(grid.nz)
+        for k in LAYER_F64:
+            f[k] = grid.new_field(grid.nz, fp64=True)
+        for k in IFACE_F64:
+            f[k] = grid.new_field(grid.nz + 1, fp64=True)
+        f["phis"] = grid.new_field(1, fp64=True)
+        f["workspace"] = torch.empty(grid.ws_bytes, dtype=torch.uint8, device=f"cuda:{grid.device}")
+        return cls(grid, f)
+
+    def load(self, init: dict) -> None:
+        g = self.grid
+        for k in ("u", "v", "w", "delp", "pt"):
+            g.view(self.f[k], g.nz).copy_(_torch().from_numpy(
+                np.ascontiguousarray(init[k])).to(self.f[k].dtype))
+        g.view(self.f["delz"], g.nz).copy_(_torch().from_numpy(np.ascontiguousarray(init["delz"])))
+        if "phis" in init:
+            g.view(self.f["phis"], 1).copy_(_torch().from_numpy(
+                np.ascontiguousarray(init["phis"]).reshape(g.T, 1, g.N, g.N)))
+
+    def get(self, name: str) -> np.ndarray:
+        L = self.grid.nz + 1 if name in IFACE_F64 else self.grid.nz
+        return self.grid.download(self.f[name], L)
+
+    def struct(self) -> StateStruct:
+        s = StateStruct()
+        for k in ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "cx", "cy",
+                  "dp0", "pfull", "phi", "phis", "workspace"):
+            setattr(s, k, self.f[k].data_ptr())
+        s.workspace_bytes = self.f["workspace"].numel()
+        return s
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def acoustic_substeps(state: State, grid: Grid, dt: float, n_split: int, stream=None,
+                      stop_stage: int = 0) -> None:
+    st = state.struct()
+    if stop_stage:
+        _check(lib().fv3_acoustic_substeps_debug(C.byref(st), grid.handle, float(dt), int(n_split),
+                                                 int(stop_stage), _stream(stream)))
+    else:
+        _check(lib().fv3_acoustic_substeps(C.byref(st), grid.handle, float(dt), int(n_split),
+                                           _stream(stream)))
+
+
+def tracer_transport(qs, state: State, grid: Grid, nsplt: int = 0, stream=None) -> None:
+    st = state.struct()
+    arr = (C.c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+    _check(lib().fv3_tracer_transport(arr, len(qs), C.byref(st), grid.handle, int(nsplt),
+                                      _stream(stream)))
+
+
+def mass_sums(grid: Grid, delp, pt, qs=(), stream=None) -> np.ndarray:
+    out = np.zeros(2 + len(qs))
+    arr = (C.c_void_p * max(1, len(qs)))(*[q.data_ptr() for q in qs])
+    _check(lib().fv3_mass_sums(grid.handle, C.c_void_p(delp.data_ptr()), C.c_void_p(pt.data_ptr()),
+                               arr, len(qs), out.ctypes.data_as(C.POINTER(C.c_double)),
+                               _stream(stream)))
+    return out
+
+
+def halo_fill(grid: Grid, fields, levels: int, fp64: bool = False, stream=None) -> None:
+    arr = (C.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+    _check(lib().fv3_halo_fill(grid.handle, arr, len(fields), int(levels), int(fp64),
+                               _stream(stream)))
+
+
+def check_status(grid: Grid, stream=None) -> int:
+    return lib().fv3_check_status(grid.handle, _stream(stream))

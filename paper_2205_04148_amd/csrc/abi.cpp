@@ -1,0 +1,231 @@
+// C ABI entry points: argument validation, grid lifetime, error reporting.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "fv3_internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+fv3_status fail(fv3_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+bool device_ok(const fv3_grid *g)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return false;
+    return cur == g->p.device;
+}
+
+fv3_status check_state(const fv3_state *s, const fv3_grid *g)
+{
+    if (!s || !g) return fail(FV3_EINVAL, "NULL state or grid");
+    const void *req[] = {s->u, s->v, s->w, s->delp, s->pt, s->delz, s->uc, s->vc, s->mfx, s->mfy,
+                         s->cx, s->cy, s->dp0, s->pfull, s->phi, s->workspace};
+    for (const void *p : req)
+        if (!p) return fail(FV3_EINVAL, "NULL field in fv3_state");
+    if (s->workspace_bytes < g->ws_bytes)
+        return fail(FV3_EINVAL, "workspace too small: need " + std::to_string(g->ws_bytes) + " bytes");
+    if (!device_ok(g)) return fail(FV3_EDEVICE, "current HIP device differs from the grid's device");
+    return FV3_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char *fv3_last_error(void) { return g_last_error.c_str(); }
+
+const char *fv3_status_string(fv3_status s)
+{
+    switch (s) {
+    case FV3_OK: return "ok";
+    case FV3_EINVAL: return "invalid argument";
+    case FV3_ESHAPE: return "inconsistent sizes";
+    case FV3_EDTYPE: return "precision mismatch";
+    case FV3_EDEVICE: return "HIP device error";
+    case FV3_ENOMEM: return "out of device memory";
+    case FV3_ECFL: return "Courant number above 1";
+    case FV3_ENONFINITE: return "non-finite prognostic";
+    case FV3_EUNSUPPORTED: return "unsupported option";
+    case FV3_EINTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
+{
+    if (!p || !out) return fail(FV3_EINVAL, "NULL params or output");
+    *out = nullptr;
+    if (p->kind != FV3_GRID_DOUBLY_PERIODIC && p->kind != FV3_GRID_CUBED_SPHERE)
+        return fail(FV3_EINVAL, "unknown grid kind");
+    if (p->n < 8 || p->n > 4096 || p->nz < 1 || p->nz > 512)
+        return fail(FV3_ESHAPE, "n must be in [8, 4096] and nz in [1, 512]");
+    if (p->precision != FV3_FP64 && p->precision != FV3_MIXED) return fail(FV3_EDTYPE, "unknown precision");
+    if (p->hord != 8) return fail(FV3_EUNSUPPORTED, "only the monotone PPM (hord = 8) is implemented");
+    if (p->d2_bg != 0.0) return fail(FV3_EUNSUPPORTED, "divergence damping is not implemented");
+    if (p->beta != 1.0) return fail(FV3_EUNSUPPORTED, "only the fully implicit vertical solve (beta = 1)");
+    if (!(p->ptop > 0.0) || !std::isfinite(p->ptop)) return fail(FV3_EINVAL, "ptop must be positive");
+    if (p->kind == FV3_GRID_DOUBLY_PERIODIC && !(p->dx > 0.0)) return fail(FV3_EINVAL, "dx must be positive");
+    if (p->kind == FV3_GRID_CUBED_SPHERE && !(p->radius > 0.0)) return fail(FV3_EINVAL, "radius must be positive");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || p->device < 0 || p->device >= ndev)
+        return fail(FV3_EDEVICE, "no such HIP device");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(FV3_EDEVICE, "hipSetDevice failed");
+    fv3_grid *g = new (std::nothrow) fv3_grid();
+    if (!g) return fail(FV3_ENOMEM, "host allocation failed");
+    std::string err;
+    fv3_status s = fv3::build_grid(p, g, err);
+    if (s != FV3_OK) {
+        fv3_free_grid(g);
+        return fail(s, "grid construction: " + err);
+    }
+    g->ws_bytes = fv3::workspace_bytes(g);
+    g->red_elems = fv3::reduction_elems(g);
+    if (hipMalloc((void **)&g->red, g->red_elems * sizeof(double)) != hipSuccess) {
+        fv3_free_grid(g);
+        return fail(FV3_ENOMEM, "reduction scratch allocation failed");
+    }
+    *out = g;
+    return FV3_OK;
+}
+
+fv3_status fv3_free_grid(fv3_grid *g)
+{
+    if (!g) return FV3_OK;
+    (void)hipDeviceSynchronize();
+    for (int m = 0; m < fv3::M_COUNT; m++) {
+        if (g->met[m]) (void)hipFree(g->met[m]);
+        if (g->metf[m]) (void)hipFree(g->metf[m]);
+    }
+    if (g->planC.d) (void)hipFree(g->planC.d);
+    if (g->planD.d) (void)hipFree(g->planD.d);
+    if (g->planCv.d) (void)hipFree(g->planCv.d);
+    if (g->flags) (void)hipFree(g->flags);
+    if (g->red) (void)hipFree(g->red);
+    delete g;
+    return FV3_OK;
+}
+
+fv3_status fv3_grid_layout(const fv3_grid *g, fv3_layout *out)
+{
+    if (!g || !out) return fail(FV3_EINVAL, "NULL grid or output");
+    out->tiles = g->T;
+    out->n = g->n;
+    out->nz = g->nz;
+    out->halo = fv3::HALO;
+    out->pitch = g->pitch;
+    out->rows = g->rows;
+    out->level_elems = g->lev;
+    out->offset0 = g->off0;
+    out->bulk_elem_bytes = g->bulk_bytes;
+    return FV3_OK;
+}
+
+size_t fv3_workspace_bytes(const fv3_grid *g) { return g ? g->ws_bytes : 0; }
+
+fv3_status fv3_grid_metric(const fv3_grid *g, int which, double *host_out)
+{
+    if (!g || !host_out) return fail(FV3_EINVAL, "NULL grid or output");
+    if (which < 0 || which >= fv3::M_COUNT) return fail(FV3_EINVAL, "metric index out of range");
+    std::memcpy(host_out, g->hmet[which].data(), g->hmet[which].size() * sizeof(double));
+    return FV3_OK;
+}
+
+fv3_status fv3_host_grid_metric(const fv3_grid_params *p, int which, double *host_out, long max_elems)
+{
+    if (!p || !host_out) return fail(FV3_EINVAL, "NULL params or output");
+    if (which < 0 || which >= fv3::M_COUNT) return fail(FV3_EINVAL, "metric index out of range");
+    if (p->kind != FV3_GRID_DOUBLY_PERIODIC && p->kind != FV3_GRID_CUBED_SPHERE)
+        return fail(FV3_EINVAL, "unknown grid kind");
+    if (p->n < 8 || p->n > 4096 || p->nz < 1) return fail(FV3_ESHAPE, "bad sizes");
+    std::string err;
+    fv3_status s = fv3::host_metric(p, which, host_out, max_elems, err);
+    if (s != FV3_OK) return fail(s, err);
+    return FV3_OK;
+}
+
+static fv3_status substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop,
+                           void *stream)
+{
+    fv3_status st = check_state(s, g);
+    if (st != FV3_OK) return st;
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV3_EINVAL, "dt must be finite and positive");
+    if (n_split < 1) return fail(FV3_EINVAL, "n_split must be >= 1");
+    st = fv3::run_substeps(s, g, dt, n_split, stop, (hipStream_t)stream);
+    if (st != FV3_OK) return fail(st, "substep launch failed");
+    return FV3_OK;
+}
+
+fv3_status fv3_acoustic_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, void *stream)
+{
+    return substeps(s, g, dt, n_split, 0, stream);
+}
+
+fv3_status fv3_acoustic_substeps_debug(fv3_state *s, const fv3_grid *g, double dt, int n_split,
+                                       int stop_stage, void *stream)
+{
+    if (stop_stage < 0 || stop_stage > 10) return fail(FV3_EINVAL, "stop_stage out of range");
+    return substeps(s, g, dt, n_split, stop_stage, stream);
+}
+
+fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_grid *g, int nsplt,
+                                void *stream)
+{
+    if (!q || nq < 1 || nq > 64) return fail(FV3_EINVAL, "need 1..64 tracers");
+    for (int m = 0; m < nq; m++)
+        if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
+    fv3_status st = check_state(s, g);
+    if (st != FV3_OK) return st;
+    st = fv3::run_tracer(q, nq, s, g, nsplt, (hipStream_t)stream);
+    if (st != FV3_OK) return fail(st, "tracer transport failed");
+    return FV3_OK;
+}
+
+fv3_status fv3_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q, int nq,
+                         double *host_out, void *stream)
+{
+    if (!g || !delp || !pt || !host_out || nq < 0 || (nq > 0 && !q))
+        return fail(FV3_EINVAL, "NULL argument");
+    for (int m = 0; m < nq; m++)
+        if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
+    if (!device_ok(g)) return fail(FV3_EDEVICE, "current HIP device differs from the grid's device");
+    static std::mutex mu;   // the grid's reduction scratch is shared
+    std::lock_guard<std::mutex> lock(mu);
+    fv3_status st = fv3::run_mass_sums(g, delp, pt, q, nq, host_out, (hipStream_t)stream);
+    if (st != FV3_OK) return fail(st, "mass sums failed");
+    return FV3_OK;
+}
+
+fv3_status fv3_halo_fill(const fv3_grid *g, void *const *fields, int n_fields, int levels, int fp64,
+                         void *stream)
+{
+    if (!g || !fields || n_fields < 1) return fail(FV3_EINVAL, "NULL argument");
+    if (levels < 1 || levels > g->nz + 1) return fail(FV3_ESHAPE, "levels must be in [1, nz + 1]");
+    for (int m = 0; m < n_fields; m++)
+        if (!fields[m]) return fail(FV3_EINVAL, "NULL field pointer");
+    return fv3::run_halo_cells(g, fields, n_fields, levels, fp64, (hipStream_t)stream);
+}
+
+fv3_status fv3_check_status(const fv3_grid *g, void *stream)
+{
+    if (!g) return fail(FV3_EINVAL, "NULL grid");
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(FV3_EDEVICE, "stream sync failed");
+    int h[2] = {0, 0};
+    if (hipMemcpy(h, g->flags, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(FV3_EDEVICE, "flag read failed");
+    int zero[2] = {0, 0};
+    if (hipMemcpy(g->flags, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FV3_EDEVICE, "flag reset failed");
+    if (h[0]) return fail(FV3_ECFL, "a Courant number exceeded 1");
+    if (h[1]) return fail(FV3_ENONFINITE, "a prognostic field became non-finite");
+    return FV3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same
+seeded inputs, element by element over the interior.
+
+Error measure: max |gpu - oracle| / max |oracle| per field over interior
+points.  Bar: 1e-11 after 10 substeps in FP64 (per stage: 1e-13)."""
+import numpy as np
+import pytest
+
+import fv3_inputs as fi
+
+pytestmark = pytest.mark.gpu
+H = 3
+STAG = {"u": "Y", "v": "X", "w": "C", "delp": "C", "pt": "C", "delz": "C", "uc": "X", "vc": "Y",
+        "mfx": "X", "mfy": "Y", "cx": "X", "cy": "Y", "dp0": "C", "pfull": "C", "phi": "C"}
+
+
+def _int(a, n, st):
+    ni = n + 1 if st in ("X", "B") else n
+    nj = n + 1 if st in ("Y", "B") else n
+    return a[..., H:H + nj, H:H + ni]
+
+
+def _relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fv3():
+    import torch
+
+    import paper_2205_04148_amd as m
+
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _pair(fv3, orc, kind, n, nz, init, dx=1000.0, f0=0.0):
+    g = fv3.Grid(kind, n, nz, dx=dx, f0=f0)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(kind, n, nz, delta=dx, f0=f0)
+    os_ = orc.new_state(og, init)
+    return g, s, og, os_
+
+
+def _compare(s, os_, n, fields, tol, label=""):
+    import torch
+
+    torch.cuda.synchronize()
+    errs = {}
+    for k in fields:
+        errs[k] = _relerr(_int(s.get(k), n, STAG[k]), _int(os_[k], n, STAG[k]))
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+    return errs
+
+
+def test_grid_metrics_on_device(fv3, orc):
+    g = fv3.Grid(1, 16, 2)
+    og = orc.Grid(1, 16, 2)
+    for name in ("area", "dxa", "cos_u", "sin_v", "dxc"):
+        a = g.metric(name)[:, H:H + 16, H:H + 16]
+        b = og.metric(name)[:, H:H + 16, H:H + 16]
+        assert _relerr(a, b) <= 1e-13
+
+
+@pytest.mark.parametrize("kind,n", [(0, 16), (1, 12)])
+def test_halo_fill_matches_oracle(fv3, orc, kind, n):
+    import torch
+
+    nz = 3
+    g = fv3.Grid(kind, n, nz)
+    og = orc.Grid(kind, n, nz)
+    rng = np.random.default_rng(4)
+    host = np.zeros((g.T, nz, g.N, g.N))
+    host[:, :, H:H + n, H:H + n] = rng.random((g.T, nz, n, n))
+    buf = g.upload(host, nz)
+    fv3.halo_fill(g, [buf], nz)
+    torch.cuda.synchronize()
+    got = g.download(buf, nz)
+    orc.halo_fill(og, host, "C")
+    mask = np.ones((g.N, g.N), dtype=bool)
+    if kind == 1:   # corner blocks are not stored on the cube
+        for a in (slice(0, H), slice(H + n, None)):
+            for b in (slice(0, H), slice(H + n, None)):
+                mask[a, b] = False
+    np.testing.assert_array_equal(got[:, :, mask], host[:, :, mask])
+
+
+STAGES = [(2, ("uc", "vc")), (4, ("uc", "vc")), (6, ("u", "v", "delp", "pt", "w", "mfx", "cx")),
+          (7, ("delz",)), (8, ("w", "delz", "pfull", "phi")), (10, ("u", "v"))]
+
+
+@pytest.mark.parametrize("kind,n,nz", [(0, 24, 6), (1, 12, 5)])
+@pytest.mark.parametrize("stop,fields", STAGES)
+def test_single_stage(fv3, orc, kind, n, nz, stop, fields):
+    init = fi.periodic_state(n=n, nz=nz) if kind == 0 else fi.cube_state(n=n, nz=nz)
+    g, s, og, os_ = _pair(fv3, orc, kind, n, nz, init)
+    dt = 0.4 if kind == 0 else 300.0
+    fv3.acoustic_substeps(s, g, dt, 1, stop_stage=stop)
+    orc.acoustic_substeps(og, os_, dt, 1, stop_stage=stop)
+    _compare(s, os_, n, fields, 1e-13, f"kind{kind} stage{stop}")
+
+
+def test_cfg1_ten_substeps(fv3, orc):
+    """48x48x8 doubly periodic, dt = 2 s, 10 substeps."""
+    n, nz = 48, 8
+    init = fi.periodic_state()
+    g, s, og, os_ = _pair(fv3, orc, 0, n, nz, init)
+    fv3.acoustic_substeps(s, g, 2.0, 10)
+    assert fv3.check_status(g) == 0
+    assert orc.acoustic_substeps(og, os_, 2.0, 10) == 0
+    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "cx",
+                         "cy", "dp0", "pfull", "phi"), 1e-11, "cfg1")
+
+
+def test_cube_c24_ten_substeps(fv3, orc):
+    n, nz = 24, 10
+    init = fi.cube_state(n=n, nz=nz)
+    g, s, og, os_ = _pair(fv3, orc, 1, n, nz, init)
+    fv3.acoustic_substeps(s, g, 10 * 200.0, 10)
+    assert fv3.check_status(g) == 0
+    assert orc.acoustic_substeps(og, os_, 10 * 200.0, 10) == 0
+    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "cx",
+                         "cy", "pfull", "phi"), 1e-11, "C24")
+
+
+def test_gpu_mass_conservation_and_sums(fv3, orc):
+    n, nz = 48, 8
+    init = fi.periodic_state(nq=1)
+    g, s, og, os_ = _pair(fv3, orc, 0, n, nz, init)
+    m0 = fv3.mass_sums(g, s.f["delp"], s.f["pt"])
+    ref0 = orc.mass_sums(og, os_["delp"], os_["pt"])
+    assert np.all(np.abs(m0 - ref0) <= 1e-14 * np.abs(ref0))
+    fv3.acoustic_substeps(s, g, 2.0, 10)
+    m1 = fv3.mass_sums(g, s.f["delp"], s.f["pt"])
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * np.abs(m0))
+
+
+def test_tracer_parity_periodic(fv3, orc):
+    n, nz = 48, 8
+    init = fi.periodic_state(nq=2)
+    g, s, og, os_ = _pair(fv3, orc, 0, n, nz, init)
+    fv3.acoustic_substeps(s, g, 2.0, 10)
+    orc.acoustic_substeps(og, os_, 2.0, 10)
+    qd = [g.upload(q, nz) for q in init["q"]]
+    qh = [q.copy() for q in init["q"]]
+    fv3.tracer_transport(qd, s, g)
+    used = orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+    import torch
+
+    torch.cuda.synchronize()
+    for a, b in zip(qd, qh):
+        assert _relerr(_int(g.download(a, nz), n, "C"), _int(b, n, "C")) <= 1e-11
+    # tracer mass conserved on the GPU
+    m0 = orc.mass_sums(og, os_["dp0"], os_["pt"], init["q"])[2:]
+    m1 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)[2:]
+    assert np.all(np.abs(m1 - m0) <= 1e-13 * np.abs(m0))
+    assert used >= 1
+
+
+def test_abi_errors(fv3):
+    import ctypes as C
+
+    g = fv3.Grid(0, 16, 2)
+    s = fv3.State.allocate(g)
+    st = s.struct()
+    L = fv3.lib()
+    assert L.fv3_acoustic_substeps(C.byref(st), g.handle, 1.0, 0, None) == -1
+    assert L.fv3_acoustic_substeps(C.byref(st), g.handle, -1.0, 2, None) == -1
+    assert L.fv3_acoustic_substeps(C.byref(st), g.handle, float("nan"), 2, None) == -1
+    st.u = None
+    assert L.fv3_acoustic_substeps(C.byref(st), g.handle, 1.0, 2, None) == -1
+    st = s.struct()
+    st.workspace_bytes = 16
+    assert L.fv3_acoustic_substeps(C.byref(st), g.handle, 1.0, 2, None) == -1
+    p = fv3.GridParams(kind=0, n=16, nz=2, dx=1000.0, f0=0.0, radius=1.0, omega=0.0, ptop=100.0,
+                       precision=0, hord=5, d2_bg=0.0, beta=1.0, device=0)
+    h = C.c_void_p()
+    assert L.fv3_init_grid(C.byref(p), C.byref(h)) == -8
+    p.hord = 8
+    p.n = 2
+    assert L.fv3_init_grid(C.byref(p), C.byref(h)) == -2
+
+
+def test_cfl_flag_latched(fv3):
+    """A wind giving Courant number 1.5 sets the device flag (no clamping)."""
+    n, nz = 16, 2
+    init = fi.periodic_state(n=n, nz=nz, wind=0.0)
+    init["u"][0, :, H:H + n + 1, H:H + n] = 1500.0
+    init["v"][0, :, H:H + n, H:H + n + 1] = 0.0
+    g = fv3.Grid(0, n, nz)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    fv3.acoustic_substeps(s, g, 1.0, 1)
+    assert fv3.check_status(g) == -6
+    assert fv3.check_status(g) == 0   # cleared
