@@ -185,6 +185,16 @@ fv3_status fv3_halo_fill(const fv3_grid *g, void *const *fields, int n_fields, i
  * error latched on the grid (FV3_ECFL, FV3_ENONFINITE) or FV3_OK. */
 fv3_status fv3_check_status(const fv3_grid *g, void *stream);
 
+/* Measurement support.  fv3_timing_start(filter) makes every later kernel
+ * launch of the library whose kernel name contains `filter` ("" = all) record
+ * a pair of HIP events on its stream; fv3_timing_stop() stops recording,
+ * synchronises the device and reports, per distinct kernel name (up to cap),
+ * the total elapsed milliseconds and the number of launches.  Kernel names
+ * are written NUL-separated into `names` (names_cap bytes).  Returns the
+ * number of kernels reported, or a negative fv3_status.  Not thread-safe. */
+fv3_status fv3_timing_start(const char *filter);
+int fv3_timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap);
+
 const char *fv3_status_string(fv3_status s);
 const char *fv3_last_error(void);
 

@@ -32,7 +32,8 @@ METRICS = ["dx", "dy", "dxc", "dyc", "dxa", "dya", "area", "area_c", "fC", "fB",
 EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_bytes",
            "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
            "fv3_tracer_transport", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
-           "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric"]
+           "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start",
+           "fv3_timing_stop"]
 
 
 class FV3Error(RuntimeError):
@@ -87,6 +88,9 @@ def lib():
         L.fv3_mass_sums.argtypes = [vp, vp, vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double), vp]
         L.fv3_halo_fill.argtypes = [vp, C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp]
         L.fv3_check_status.argtypes = [vp, vp]
+        L.fv3_timing_start.argtypes = [C.c_char_p]
+        L.fv3_timing_stop.argtypes = [C.c_char_p, C.c_int, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_long), C.c_int]
         L.fv3_status_string.argtypes = [C.c_int]
         L.fv3_status_string.restype = C.c_char_p
         L.fv3_last_error.restype = C.c_char_p
@@ -279,3 +283,21 @@ def halo_fill(grid: Grid, fields, levels: int, fp64: bool = False, stream=None) 
 
 def check_status(grid: Grid, stream=None) -> int:
     return lib().fv3_check_status(grid.handle, _stream(stream))
+
+
+def timing_start(filter_: str | None = "") -> None:
+    """Record HIP events around library kernel launches whose name contains filter_."""
+    lib().fv3_timing_start(None if filter_ is None else filter_.encode())
+
+
+def timing_stop() -> dict:
+    """Stop recording; {kernel name: (total ms, launches)} (synchronises the device)."""
+    cap = 256
+    names = C.create_string_buffer(cap * 64)
+    tot = (C.c_double * cap)()
+    cnt = (C.c_long * cap)()
+    nk = lib().fv3_timing_stop(names, cap * 64, tot, cnt, cap)
+    if nk < 0:
+        raise FV3Error(nk, "timing_stop failed")
+    keys = names.raw.split(b"\0")
+    return {keys[q].decode(): (tot[q], cnt[q]) for q in range(nk)}

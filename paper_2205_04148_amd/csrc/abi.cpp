@@ -213,6 +213,18 @@ fv3_status fv3_halo_fill(const fv3_grid *g, void *const *fields, int n_fields, i
     return fv3::run_halo_cells(g, fields, n_fields, levels, fp64, (hipStream_t)stream);
 }
 
+fv3_status fv3_timing_start(const char *filter)
+{
+    fv3::timing_start(filter);
+    return FV3_OK;
+}
+
+int fv3_timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap)
+{
+    if (!names || !total_ms || !counts || cap < 1) return (int)fail(FV3_EINVAL, "NULL output");
+    return fv3::timing_stop(names, names_cap, total_ms, counts, cap);
+}
+
 fv3_status fv3_check_status(const fv3_grid *g, void *stream)
 {
     if (!g) return fail(FV3_EINVAL, "NULL grid");

@@ -78,6 +78,8 @@ fv3_status host_metric(const fv3_grid_params *p, int m, double *out, long cap, s
 struct Work;   // workspace carve-up, defined in kernels.hip
 size_t workspace_bytes(const fv3_grid *g);
 long reduction_elems(const fv3_grid *g);
+void timing_start(const char *filter);
+int timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap);
 fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
                         hipStream_t st);
 fv3_status run_tracer(void *const *q, int nq, fv3_state *s, const fv3_grid *g, int nsplt,

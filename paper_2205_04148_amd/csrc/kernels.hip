@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "fv3_internal.hpp"
@@ -117,14 +118,47 @@ struct Met {
 // plane pointer of a 2-D metric for tile t
 #define MP(name) (M.m[name] + G.off0 + (long)t * G.lev)
 
+// ---------------------------------------------------------- launch timing
+struct TimingRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+static struct {
+    bool on = false;
+    std::string filter;
+    std::vector<TimingRec> recs;
+} g_timing;
+
+static bool timing_wanted(const char *name)
+{
+    return g_timing.on && std::strstr(name, g_timing.filter.c_str()) != nullptr;
+}
+static void timing_begin(const char *name, hipStream_t st, TimingRec &r)
+{
+    r.name = name;
+    (void)hipEventCreate(&r.a);
+    (void)hipEventCreate(&r.b);
+    (void)hipEventRecord(r.a, st);
+}
+static void timing_end(hipStream_t st, TimingRec &r)
+{
+    (void)hipEventRecord(r.b, st);
+    g_timing.recs.push_back(r);
+}
+
 template <class Kern, class... Args>
-static void launch2d(Kern kern, int ilo, int ihi, int jlo, int jhi, int planes, hipStream_t st,
-                     Args... args)
+static void launch2d_named(const char *name, Kern kern, int ilo, int ihi, int jlo, int jhi, int planes,
+                           hipStream_t st, Args... args)
 {
     dim3 blk(64, 4, 1);
     dim3 grd((unsigned)((ihi - ilo + 64) / 64), (unsigned)((jhi - jlo + 4) / 4), (unsigned)planes);
+    bool tm = timing_wanted(name);
+    TimingRec r;
+    if (tm) timing_begin(name, st, r);
     hipLaunchKernelGGL(kern, grd, blk, 0, st, ilo, ihi, jlo, jhi, args...);
+    if (tm) timing_end(st, r);
 }
+#define launch2d(kern, ...) launch2d_named(#kern, kern, __VA_ARGS__)
 
 // ====================================================================
 // 1-D PPM face value (monotone): face between cells m-1 and m along a
@@ -201,14 +235,22 @@ static void halo_scalar(const fv3_grid *g, T *f, int L, hipStream_t st)
 {
     if (g->planC.count == 0) return;
     dim3 grd((g->planC.count + 255) / 256, L);
+    bool tm = timing_wanted("k_halo_scalar");
+    TimingRec r;
+    if (tm) timing_begin("k_halo_scalar", st, r);
     hipLaunchKernelGGL(k_halo_scalar<T>, grd, dim3(256), 0, st, g->geo, g->planC.d, g->planC.count, f, L);
+    if (tm) timing_end(st, r);
 }
 template <class T>
 static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hipStream_t st)
 {
     if (p.count == 0) return;
     dim3 grd((p.count + 255) / 256, L);
+    bool tm = timing_wanted("k_halo_pair");
+    TimingRec r;
+    if (tm) timing_begin("k_halo_pair", st, r);
     hipLaunchKernelGGL(k_halo_pair<T>, grd, dim3(256), 0, st, g->geo, p.d, p.count, fx, fy, L);
+    if (tm) timing_end(st, r);
 }
 
 // ====================================================================
@@ -1024,6 +1066,49 @@ static size_t carve(const fv3_grid *g, char *base, Work *w)
 }
 
 long reduction_elems(const fv3_grid *g) { return 2 * part_count(g); }
+
+void timing_start(const char *filter)
+{
+    g_timing.on = filter != nullptr;
+    g_timing.filter = filter ? filter : "";
+    g_timing.recs.clear();
+}
+
+int timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap)
+{
+    g_timing.on = false;
+    if (hipDeviceSynchronize() != hipSuccess) return (int)FV3_EDEVICE;
+    std::vector<std::string> keys;
+    std::vector<double> tot;
+    std::vector<long> cnt;
+    for (TimingRec &r : g_timing.recs) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        size_t q = 0;
+        while (q < keys.size() && keys[q] != r.name) q++;
+        if (q == keys.size()) {
+            keys.push_back(r.name);
+            tot.push_back(0.0);
+            cnt.push_back(0);
+        }
+        tot[q] += ms;
+        cnt[q] += 1;
+    }
+    g_timing.recs.clear();
+    int nk = 0, pos = 0;
+    for (size_t q = 0; q < keys.size() && nk < cap; q++) {
+        int len = (int)keys[q].size() + 1;
+        if (pos + len > names_cap) break;
+        std::memcpy(names + pos, keys[q].c_str(), len);
+        pos += len;
+        total_ms[nk] = tot[q];
+        counts[nk] = cnt[q];
+        nk++;
+    }
+    return nk;
+}
 
 size_t workspace_bytes(const fv3_grid *g)
 {
