@@ -6,18 +6,24 @@ baroclinic-jet state: fv3_acoustic_substeps with n_split = 100 substeps of
 riem_solver3, nh_p_grad), then fv3_tracer_transport of 4 tracers with the
 accumulated fluxes, then the compensated global mass sums.
 
+The headline line is the mixed-precision build (FP32 stencil bulk; FP64
+column solves, vertical scans, pressure gradients, mass-flux accumulators and
+sums); the FP64 build is measured on the same state beside it ("mixed vs
+FP64"), and the per-field difference between the two after one step (100
+substeps) from the same initial state is reported.
+
 metric  acoustic-substep cell-updates/s = 6 * 192^2 * 79 * 100 / (seconds per step)
         (the tracer transport and the sums are inside the timed step)
 roofline  the kernel with the largest share of the step, timed live with HIP
-          events on its own stream over the timed region; achieved bandwidth =
+          events on its stream over the timed region; achieved bandwidth =
           algorithmic bytes per launch / mean launch time, where algorithmic
           bytes = (distinct fields the kernel reads or writes, each counted
-          once) x (cells per launch) x (element size), the paper's bandwidth
-          model of Sec. VII-C.
+          once, at their element sizes) x (cells per launch), the paper's
+          bandwidth model of Sec. VII-C.
 cpu_baseline  the oracle (plain C, OpenMP) on a bounded sample of the same
-          workload: 3 acoustic substeps of C192 x 79.
+          workload: 3 acoustic substeps of C192 x 79 in FP64.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--precision fp64]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--precision mixed|fp64]
 """
 from __future__ import annotations
 
@@ -32,21 +38,37 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Fields (layer-sized, each element counted once) read or written by one
-# launch of each kernel: the per-cell algorithmic traffic of the byte model.
-FIELDS_PER_CELL = {
-    "k_csw_agrid": 4, "k_csw_faces": 17, "k_csw_cells": 18, "k_csw_update": 8,
-    "k_dzc": 4, "k_sim1<B>": 12, "k_pgradc": 7, "k_dsw_courant": 8,
-    "k_fv_outer<B>": 5, "k_fv_inner<B>": 7, "k_fv_flux<B, B>": 10, "k_fv_flux<B, double>": 12,
-    "k_fv_outer<double>": 5, "k_fv_inner<double>": 7, "k_fv_flux<double, double>": 10,
-    "k_dsw_mass": 14, "k_dsw_scalar": 6, "k_dsw_ke": 5, "k_dsw_omega": 3, "k_dsw_update": 13,
-    "k_heights": 2, "k_iface_flux": 8, "k_zh_update": 6, "k_delz_from_zh": 2,
-    "k_corner_interp<double>": 2, "k_corner_interp<B>": 2, "k_nhpgrad": 7,
+# Algorithmic traffic of one launch per cell of the launch's planes: for each
+# kernel the fields read or written (each element once), split into bulk-type
+# fields (8 or 4 bytes) and always-FP64 fields (8 bytes).
+BYTES_MODEL = {
+    # name: (bulk fields, fp64 fields); a field both read and written counts twice
+    "k_csw_agrid": (4, 0), "k_csw_faces": (17, 0), "k_csw_cells": (18, 0), "k_csw_update": (8, 0),
+    "k_dzc": (2, 2),
+    "k_sim1_c": (3, 3),        # delpc, ptc, wc | delz_c in; pkc, gz out
+    "k_sim1_3": (4, 4),        # delp, pt, w in, w out | delz in, delz, pfull, phi out
+    "k_pgradc": (3, 4), "k_dsw_courant": (8, 0),
+    "k_dsw_omke": (6, 0), "k_dsw_update": (13, 0), "k_heights": (0, 2), "k_delz_from_zh": (0, 2),
+    "k_nhpgrad": (5, 4),       # delp, u, v in, u, v out | pfull, phi at the layer's two interfaces
+    # fused fv_tp_2d: the field, 4 Courant / area-flux arrays, weights, outputs, per epilogue
+    "k_fvtp_delp": (12, 4),    # delp, crx, cry, xfx, yfx, FX, FY, dn, cx, cy (rw) | mfx, mfy (rw)
+    "k_fvtp_massw": (10, 0),   # q, 4 fluxes, mx, my, delp old, delp new, q new
+    "k_fvtp_flux": (7, 0),     # q, 4 fluxes, FX, FY
+    "k_fvtp_adv": (4, 2),      # 4 fluxes | zh in, zh out
+    "k_fvtp_tracer": (6, 4),   # q, 4 fluxes, q out | mx, my, dp1, dp2
 }
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, cells, eb):
+    key = name.split("<")[0]
+    if key in BYTES_MODEL:
+        b, d = BYTES_MODEL[key]
+        return (b * eb + d * 8) * cells
+    return None
 
 
 def cpu_baseline(init, n, nz, bdt, substeps):
@@ -61,39 +83,14 @@ def cpu_baseline(init, n, nz, bdt, substeps):
     dt = time.perf_counter() - t0
     cells = 6 * n * n * nz * substeps
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"C{n}x{nz} cubed sphere, {substeps} acoustic substeps of {bdt:g} s, "
+            "sample": f"C{n}x{nz} cubed sphere FP64, {substeps} acoustic substeps of {bdt:g} s, "
                       f"{dt:.1f} s wall, status {st}"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--n", type=int, default=192)
-    ap.add_argument("--nz", type=int, default=79)
-    ap.add_argument("--n-split", type=int, default=100)
-    ap.add_argument("--bdt", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the acoustic substep path holds all six cube "
-              "tiles on a single MI355X (no multi-GPU path in this build)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import fv3_inputs as fi
-    import paper_2205_04148_amd as fv3
-
+def run_precision(fv3, torch, init, args, precision):
     n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
     dt = bdt * ns
-    t0 = time.perf_counter()
-    init = fi.cube_state(n=n, nz=nz)
-    log(f"initial state C{n}x{nz}: {time.perf_counter() - t0:.1f} s")
-    g = fv3.Grid(1, n, nz, precision=args.precision)
+    g = fv3.Grid(1, n, nz, precision=precision)
     s = fv3.State.allocate(g)
     s.load(init)
     qs = [g.upload(q, nz) for q in init["q"]]
@@ -111,16 +108,12 @@ def main():
     for _ in range(max(0, args.warmup - 1)):
         step()
     torch.cuda.synchronize()
-    st = fv3.check_status(g)
-    if st != 0:
-        log(f"warning: device status {st} after warm-up")
     dom = max(per_kernel.items(), key=lambda kv: kv[1][0])[0]
     tot_ms = sum(v[0] for v in per_kernel.values())
-    log("kernel share of a warm-up step (HIP events):")
-    for k, (ms, c) in sorted(per_kernel.items(), key=lambda kv: -kv[1][0])[:12]:
-        log(f"  {k:28s} {ms:9.2f} ms  {100 * ms / tot_ms:5.1f}%  {c} launches  {1000 * ms / c:8.1f} us/launch")
+    log(f"[{precision}] kernel share of a warm-up step (HIP events):")
+    for k, (ms, c) in sorted(per_kernel.items(), key=lambda kv: -kv[1][0])[:14]:
+        log(f"  {k:28s} {ms:9.2f} ms  {100 * ms / tot_ms:5.1f}%  {c:5d} launches  {1000 * ms / c:8.1f} us/launch")
 
-    # timed region, dominant kernel timed live
     fv3.timing_start(dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -129,51 +122,106 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     live = fv3.timing_stop()
-    ms_step = 1000.0 * (t1 - t0) / args.steps
-    cells = 6 * n * n * nz
-    value = cells * ns / ((t1 - t0) / args.steps)
     st = fv3.check_status(g)
-
+    cells = 6 * n * n * nz
+    sec = (t1 - t0) / args.steps
     ms_dom, cnt_dom = live.get(dom, (float("nan"), 1))
-    if dom not in live:
-        # filter matches by substring: pick the exact entry
-        for k, v in live.items():
-            if k == dom:
-                ms_dom, cnt_dom = v
     avg_s = ms_dom / cnt_dom / 1000.0
-    eb = 8 if args.precision == "fp64" else 4
-    fields = FIELDS_PER_CELL.get(dom)
-    if fields is None:
-        achieved = None
-        bytes_launch = None
-    else:
-        # column kernels launch per tile over all levels; plane kernels per (tile, level)
-        bytes_launch = fields * cells * eb
-        achieved = bytes_launch / avg_s / 1e9
+    eb = 8 if precision == "fp64" else 4
+    bl = kernel_bytes(dom, cells, eb)
+    achieved = bl / avg_s / 1e9 if bl else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None, "bytes_per_launch": bytes_launch,
-            "mean_launch_us": avg_s * 1e6, "launches": cnt_dom}
+            "traffic": None, "bytes_per_launch": bl, "mean_launch_us": avg_s * 1e6,
+            "launches": cnt_dom, "share_of_step": per_kernel[dom][0] / tot_ms}
+    log(f"[{precision}] {1000 * sec:.1f} ms/step, {cells * ns / sec:.3e} cell-updates/s, status {st}")
+    del s, qs, g
+    torch.cuda.empty_cache()
+    return {"value": cells * ns / sec, "ms_per_step": 1000 * sec, "roofline": roof,
+            "device_status": int(st), "ms_per_substep": 1000 * sec / ns}
 
+
+def precision_error(fv3, torch, init, args):
+    """Per-field max |mixed - fp64| / max |fp64| over the interior after one step."""
+    n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
+    out = {}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        g = fv3.Grid(1, n, nz, precision=prec)
+        s = fv3.State.allocate(g)
+        s.load(init)
+        fv3.acoustic_substeps(s, g, bdt * ns, ns)
+        torch.cuda.synchronize()
+        res[prec] = {k: s.get(k) for k in ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")}
+        del s, g
+        torch.cuda.empty_cache()
+    H = 3
+    for k, a in res["fp64"].items():
+        ni = n + 1 if k == "v" else n
+        nj = n + 1 if k == "u" else n
+        ref = a[..., H:H + nj, H:H + ni]
+        mix = res["mixed"][k][..., H:H + nj, H:H + ni]
+        out[k] = float(abs(mix - ref).max() / max(abs(ref).max(), 1e-300))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--n", type=int, default=192)
+    ap.add_argument("--nz", type=int, default=79)
+    ap.add_argument("--n-split", type=int, default=100)
+    ap.add_argument("--bdt", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the acoustic substep path holds all six cube "
+              "tiles on a single MI355X (no multi-GPU path in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import fv3_inputs as fi
+    import paper_2205_04148_amd as fv3
+
+    n, nz = args.n, args.nz
+    t0 = time.perf_counter()
+    init = fi.cube_state(n=n, nz=nz)
+    log(f"initial state C{n}x{nz}: {time.perf_counter() - t0:.1f} s")
+
+    main_res = run_precision(fv3, torch, init, args, args.precision)
+    other = None
+    if not args.no_compare:
+        other_prec = "fp64" if args.precision == "mixed" else "mixed"
+        r = run_precision(fv3, torch, init, args, other_prec)
+        other = {"precision": other_prec, "value": r["value"], "ms_per_step": r["ms_per_step"],
+                 "roofline": r["roofline"]}
+    err = precision_error(fv3, torch, init, args) if not args.no_compare else None
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline ...")
-        del s, qs
-        torch.cuda.empty_cache()
-        cpu = cpu_baseline(init, n, nz, bdt, 3)
+        cpu = cpu_baseline(init, n, nz, args.bdt, 3)
+    cells = 6 * n * n * nz
     out = {
         "metric": "acoustic-substep cell-updates/s at C192x79, mixed vs FP64; % HBM peak",
-        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "value": main_res["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"C{n}x{nz} cubed-sphere baroclinic jet, {ns} acoustic substeps of "
-                               f"{bdt:g} s + 4-tracer transport + mass sums per step",
-                   "precision": args.precision, "n_split": ns, "cells": cells,
-                   "device_status": int(st)},
-        "roofline": roof,
+        "config": {"workload": f"C{n}x{nz} cubed-sphere baroclinic jet, {args.n_split} acoustic "
+                               f"substeps of {args.bdt:g} s + 4-tracer transport + mass sums per step",
+                   "precision": args.precision, "n_split": args.n_split, "cells": cells,
+                   "ms_per_substep": main_res["ms_per_substep"],
+                   "device_status": main_res["device_status"]},
+        "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
+        "compare": other,
+        "mixed_vs_fp64_max_rel_error_after_1_step": err,
     }
     print(json.dumps(out), flush=True)
 

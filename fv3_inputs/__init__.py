@@ -210,28 +210,19 @@ def _east(p):
     return _unit(e)
 
 
-def cube_state(n: int = 96, nz: int = 79, seed: int = 2, ptop: float = 100.0, nq: int = 4,
-               noise: float = 1.0) -> dict:
-    """Cubed-sphere baroclinic jet.
-
-    Columns: for each cell centre, interface heights z_K with p(lat, z_K) =
-    pi_K (sigma-uniform pi, flat surface at p0); delz_k = z_{K+1} - z_K, layer
-    temperature from the hydrostatic relation over the layer, theta from the
-    log-mean layer pressure, so the discrete nonhydrostatic perturbation is 0.
-    Winds: covariant D-grid components V.e of the zonal jet at each edge, at
-    the edge's latitude and the height of the layer's log-mean pressure, plus
-    N(0, noise) drawn with ``default_rng(seed)`` (u then v, then tracers).
-    """
+def _jet_base(n: int, nz: int, ptop: float) -> dict:
+    """The deterministic (seed-independent) part of the cubed-sphere jet state,
+    cached per (n, nz, ptop): layer pressures, thicknesses, potential
+    temperature and the face winds of the balanced jet."""
+    key = (n, nz, float(ptop))
+    if key in _BASE_CACHE:
+        return _BASE_CACHE[key]
     jet = BaroclinicJet()
     geo = cube_geometry(n)
     pi = sigma_interfaces(nz, ptop, P0)
     dpi = np.diff(pi)
     lnr = np.log(pi[1:] / pi[:-1])
     pibar = dpi / lnr
-    rng = np.random.default_rng(seed)
-    N = n + 2 * H + 1
-    u = _empty(6, nz, n)
-    v = _empty(6, nz, n)
     delp = _empty(6, nz, n)
     pt = _empty(6, nz, n)
     delz = _empty(6, nz, n)
@@ -256,20 +247,62 @@ def cube_state(n: int = 96, nz: int = 79, seed: int = 2, ptop: float = 100.0, nq
             out[:, k] = jet.zonal_wind(lat, z) * proj
         return out
 
-    uw = face_wind(geo["my"], geo["ty"])     # [t][k][n+1][n]
-    vw = face_wind(geo["mx"], geo["tx"])     # [t][k][n][n+1]
-    uw = uw + noise * rng.standard_normal(uw.shape)
-    vw = vw + noise * rng.standard_normal(vw.shape)
+    base = dict(delp=delp, pt=pt, delz=delz, uw=face_wind(geo["my"], geo["ty"]),
+                vw=face_wind(geo["mx"], geo["tx"]), geo=geo)
+    if len(_BASE_CACHE) >= 4:
+        _BASE_CACHE.clear()
+    _BASE_CACHE[key] = base
+    return base
+
+
+_BASE_CACHE: dict = {}
+
+
+def cube_state(n: int = 96, nz: int = 79, seed: int = 2, ptop: float = 100.0, nq: int = 4,
+               noise: float = 1.0, bumps: int = 0) -> dict:
+    """Cubed-sphere baroclinic jet.
+
+    Columns: for each cell centre, interface heights z_K with p(lat, z_K) =
+    pi_K (sigma-uniform pi, flat surface at p0); delz_k = z_{K+1} - z_K, layer
+    temperature from the hydrostatic relation over the layer, theta from the
+    log-mean layer pressure, so the discrete nonhydrostatic perturbation is 0.
+    Winds: covariant D-grid components V.e of the zonal jet at each edge, at
+    the edge's latitude and the height of the layer's log-mean pressure, plus
+    N(0, noise) drawn with ``default_rng(seed)`` (u then v, then tracers).
+    ``bumps`` > 0 adds, after those draws, that many seeded Gaussian wind
+    perturbations (centre uniform on the sphere, radius 600 km, amplitude
+    U(2, 8) m/s, direction U(0, 2 pi), all levels), the large-scale
+    variability of the learned-correction samples.
+    """
+    base = _jet_base(n, nz, ptop)
+    geo = base["geo"]
+    rng = np.random.default_rng(seed)
+    u = _empty(6, nz, n)
+    v = _empty(6, nz, n)
+    uw = base["uw"] + noise * rng.standard_normal(base["uw"].shape)
+    vw = base["vw"] + noise * rng.standard_normal(base["vw"].shape)
+    qs = rng.random((nq, 6, nz, n, n))
+    for _ in range(bumps):
+        c = rng.standard_normal(3)
+        c /= np.linalg.norm(c)
+        amp = rng.uniform(2.0, 8.0)
+        ang = rng.uniform(0.0, 2 * np.pi)
+        east = _east(c[None])[0]
+        north = np.cross(c, east)
+        d = math.cos(ang) * east + math.sin(ang) * north       # bump wind direction at its centre
+        for w, mid, tan in ((uw, geo["my"], geo["ty"]), (vw, geo["mx"], geo["tx"])):
+            dist = np.arccos(np.clip(np.sum(mid * c, axis=-1), -1, 1)) * RADIUS
+            vec = d - np.sum(mid * d, axis=-1, keepdims=True) * mid   # transported to the face
+            w += (amp * np.exp(-(dist / 6.0e5) ** 2) * np.sum(vec * tan, axis=-1))[:, None]
     u[:, :, H:H + n + 1, H:H + n] = uw
     v[:, :, H:H + n, H:H + n + 1] = vw
-    qs = rng.random((nq, 6, nz, n, n))
     qq = []
     for m in range(nq):
         q = _empty(6, nz, n)
         q[:, :, H:H + n, H:H + n] = qs[m]
         qq.append(q)
-    return dict(u=u, v=v, w=_empty(6, nz, n), delp=delp, pt=pt, delz=delz,
-                phis=np.zeros((6, N, N)), q=qq,
+    return dict(u=u, v=v, w=_empty(6, nz, n), delp=base["delp"].copy(), pt=base["pt"].copy(),
+                delz=base["delz"].copy(), phis=np.zeros((6, n + 2 * H + 1, n + 2 * H + 1)), q=qq,
                 meta=dict(kind=1, n=n, nz=nz, T=6, ptop=ptop))
 
 

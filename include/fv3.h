@@ -198,6 +198,82 @@ int fv3_timing_stop(char *names, int names_cap, double *total_ms, long *counts, 
 const char *fv3_status_string(fv3_status s);
 const char *fv3_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned per-column correction of a coarse run.  The paper motivates
+ * coupling machine-learned components with the dynamical core (Sec. III)
+ * without giving a recipe; the entry points below are this library's
+ * recipe: coarsen a fine run, extract normalised column features, train a
+ * three-layer perceptron with BF16 matrix-core products and FP32
+ * accumulation, and add its predicted tendencies to a coarse state.
+ * ------------------------------------------------------------------------ */
+
+/* Coarsen u, v, w, delp, pt and delz of `fine` (grid gf) onto `coarse`
+ * (grid gc) with gf->n = r * gc->n for an integer r >= 1, same tiles, levels
+ * and precision.  Cell values: delp and delz are area means of the r x r
+ * fine cells, pt and w mass-weighted (delp * area) means.  D-grid winds: the
+ * edge-length-weighted mean of the r fine edges on each coarse edge, which
+ * keeps the circulation along it.  Halos of `coarse` are not filled.
+ * Asynchronous.  Errors: FV3_EINVAL (NULL), FV3_ESHAPE (sizes), FV3_EDTYPE
+ * (precisions differ). */
+fv3_status fv3_coarsen(const fv3_state *fine, const fv3_grid *gf, fv3_state *coarse,
+                       const fv3_grid *gc, void *stream);
+
+/* Per-feature normalisation, device arrays of 5 * nz floats, feature order
+ * (field, level) with fields ua, va, pt, w, delp: z = (x - mean) * inv_std.
+ * lo and hi are the training range of z; they may be NULL when no flag is
+ * requested. */
+typedef struct {
+    const float *mean, *inv_std, *lo, *hi;
+} fv3_feature_norm;
+
+/* Column features of every interior column into X, a device float array of
+ * (tiles * n * n) rows (order tile, j, i) by 5 * nz columns, row-major.  ua
+ * and va are the means of the two D-grid faces of each cell (tile
+ * components).  If `flag` (device int) is not NULL, bit 0 is set when any z
+ * is not finite or lies more than 6 outside [lo, hi]; the flag is only ever
+ * set, never cleared.  Asynchronous. */
+fv3_status fv3_column_features(const fv3_state *s, const fv3_grid *g, const fv3_feature_norm *norm,
+                               float *X, int *flag, void *stream);
+
+/* Add `seconds` times the tendencies Y (device, rows as fv3_column_features,
+ * 3 * nz columns: ua, va, pt; normalised, physical = Y * ystd + ymean) to
+ * the state: pt in place; the cell wind increments are exchanged across tile
+ * edges and each D-grid face takes the mean of its two cells.  Bit 1 of
+ * *flag (device int) is set if any Y is not finite; when *flag is nonzero
+ * after that check (including bits set earlier by fv3_column_features) the
+ * state is left unchanged -- the plain coarse run is the fallback.  Uses the
+ * first 2 * alloc_elems(nz) doubles of s->workspace.  Asynchronous. */
+fv3_status fv3_apply_correction(fv3_state *s, const fv3_grid *g, const float *Y, const float *ymean,
+                                const float *ystd, double seconds, int *flag, void *stream);
+
+/* Three-layer perceptron x -> tanh(x W1 + b1) -> tanh(. W2 + b2) -> . W3 + b3
+ * on the current HIP device.  Matrix products take BF16 operands (round to
+ * nearest even) on the matrix cores with FP32 accumulation; parameters,
+ * Adam moments and activations' derivatives are FP32.  Hidden widths must be
+ * multiples of 16; input and output widths are padded to 16 internally.
+ * `params` (host) are packed as W1 (in x h1, row-major), b1, W2, b2, W3, b3;
+ * rows <= maxrows for every call. */
+typedef struct fv3_mlp fv3_mlp;
+fv3_status fv3_mlp_create(int in, int h1, int h2, int out, int maxrows, const float *params,
+                          fv3_mlp **net);
+fv3_status fv3_mlp_free(fv3_mlp *net);
+long fv3_mlp_param_count(const fv3_mlp *net);
+/* replace the parameters (host, packed) and reset the Adam state; synchronous */
+fv3_status fv3_mlp_set_params(fv3_mlp *net, const float *params);
+/* copy the FP32 master parameters to host (packed); synchronous */
+fv3_status fv3_mlp_get_params(const fv3_mlp *net, float *params);
+/* Y (device, rows x out) = network(X (device, rows x in)); asynchronous */
+fv3_status fv3_mlp_forward(fv3_mlp *net, const float *X, int rows, float *Y, void *stream);
+/* Gradients of the mean squared error mean((Y - T)^2) over rows x out with
+ * respect to the parameters, packed as `params`, to host; synchronous. */
+fv3_status fv3_mlp_gradients(fv3_mlp *net, const float *X, const float *T, int rows, float *grads,
+                             void *stream);
+/* One Adam step (betas 0.9, 0.999, eps 1e-8, learning rate lr) on the batch
+ * X, T (device).  If loss is not NULL the batch loss before the step is
+ * written there (synchronises `stream`); otherwise asynchronous. */
+fv3_status fv3_mlp_train_step(fv3_mlp *net, const float *X, const float *T, int rows, float lr,
+                              double *loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

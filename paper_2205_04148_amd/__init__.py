@@ -33,7 +33,9 @@ EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_b
            "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
            "fv3_tracer_transport", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
            "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start",
-           "fv3_timing_stop"]
+           "fv3_timing_stop", "fv3_coarsen", "fv3_column_features", "fv3_apply_correction",
+           "fv3_mlp_create", "fv3_mlp_free", "fv3_mlp_param_count", "fv3_mlp_set_params",
+           "fv3_mlp_get_params", "fv3_mlp_forward", "fv3_mlp_gradients", "fv3_mlp_train_step"]
 
 
 class FV3Error(RuntimeError):
@@ -53,6 +55,10 @@ class Layout(C.Structure):
     _fields_ = [("tiles", C.c_int), ("n", C.c_int), ("nz", C.c_int), ("halo", C.c_int),
                 ("pitch", C.c_long), ("rows", C.c_long), ("level_elems", C.c_long),
                 ("offset0", C.c_long), ("bulk_elem_bytes", C.c_int)]
+
+
+class FeatureNorm(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("mean", "inv_std", "lo", "hi")]
 
 
 class StateStruct(C.Structure):
@@ -91,6 +97,21 @@ def lib():
         L.fv3_timing_start.argtypes = [C.c_char_p]
         L.fv3_timing_stop.argtypes = [C.c_char_p, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_long), C.c_int]
+        L.fv3_coarsen.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(StateStruct), vp, vp]
+        L.fv3_column_features.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(FeatureNorm), vp,
+                                          vp, vp]
+        L.fv3_apply_correction.argtypes = [C.POINTER(StateStruct), vp, vp, vp, vp, C.c_double, vp,
+                                           vp]
+        fp = C.POINTER(C.c_float)
+        L.fv3_mlp_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, fp, C.POINTER(vp)]
+        L.fv3_mlp_free.argtypes = [vp]
+        L.fv3_mlp_param_count.argtypes = [vp]
+        L.fv3_mlp_param_count.restype = C.c_long
+        L.fv3_mlp_set_params.argtypes = [vp, fp]
+        L.fv3_mlp_get_params.argtypes = [vp, fp]
+        L.fv3_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.fv3_mlp_gradients.argtypes = [vp, vp, vp, C.c_int, fp, vp]
+        L.fv3_mlp_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_float, C.POINTER(C.c_double), vp]
         L.fv3_status_string.argtypes = [C.c_int]
         L.fv3_status_string.restype = C.c_char_p
         L.fv3_last_error.restype = C.c_char_p
@@ -301,3 +322,96 @@ def timing_stop() -> dict:
         raise FV3Error(nk, "timing_stop failed")
     keys = names.raw.split(b"\0")
     return {keys[q].decode(): (tot[q], cnt[q]) for q in range(nk)}
+
+
+# ---------------------------------------------------------------- learned correction
+def coarsen(fine: State, gf: Grid, coarse: State, gc: Grid, stream=None) -> None:
+    """Conservative coarsening of u, v, w, delp, pt, delz from gf onto gc."""
+    a, b = fine.struct(), coarse.struct()
+    _check(lib().fv3_coarsen(C.byref(a), gf.handle, C.byref(b), gc.handle, _stream(stream)))
+
+
+def column_features(state: State, grid: Grid, mean, inv_std, X, flag=None, lo=None, hi=None,
+                    stream=None) -> None:
+    """Normalised column features into the device float tensor X [T*n*n, 5*nz]."""
+    nm = FeatureNorm(mean=mean.data_ptr(), inv_std=inv_std.data_ptr(),
+                     lo=lo.data_ptr() if lo is not None else None,
+                     hi=hi.data_ptr() if hi is not None else None)
+    st = state.struct()
+    _check(lib().fv3_column_features(C.byref(st), grid.handle, C.byref(nm), C.c_void_p(X.data_ptr()),
+                                     C.c_void_p(flag.data_ptr()) if flag is not None else None,
+                                     _stream(stream)))
+
+
+def apply_correction(state: State, grid: Grid, Y, ymean, ystd, seconds: float, flag,
+                     stream=None) -> None:
+    """Add seconds x de-normalised tendencies Y [T*n*n, 3*nz] unless *flag is set."""
+    st = state.struct()
+    _check(lib().fv3_apply_correction(C.byref(st), grid.handle, C.c_void_p(Y.data_ptr()),
+                                      C.c_void_p(ymean.data_ptr()), C.c_void_p(ystd.data_ptr()),
+                                      float(seconds), C.c_void_p(flag.data_ptr()), _stream(stream)))
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class MLP:
+    """Three-layer tanh perceptron trained with BF16 matrix-core kernels.
+
+    params: list [W1 (in, h1), b1, W2, b2, W3, b3] of host arrays."""
+
+    def __init__(self, params, maxrows: int):
+        W1, _, W2, _, W3, _ = params
+        self.sizes = (W1.shape[0], W1.shape[1], W2.shape[1], W3.shape[1])
+        flat = self._pack(params)
+        h = C.c_void_p()
+        _check(lib().fv3_mlp_create(*[int(x) for x in self.sizes], int(maxrows), _fptr(flat),
+                                    C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def _pack(params) -> np.ndarray:
+        return np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float32).ravel()
+                                                    for p in params]))
+
+    def _unpack(self, flat: np.ndarray):
+        i, h1, h2, o = self.sizes
+        out, pos = [], 0
+        for a, b in ((i, h1), (h1, h2), (h2, o)):
+            out.append(flat[pos:pos + a * b].reshape(a, b).copy())
+            pos += a * b
+            out.append(flat[pos:pos + b].copy())
+            pos += b
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fv3_mlp_free(h)
+            self._h = None
+
+    def set_params(self, params) -> None:
+        _check(lib().fv3_mlp_set_params(self._h, _fptr(self._pack(params))))
+
+    def get_params(self):
+        flat = np.zeros(lib().fv3_mlp_param_count(self._h), dtype=np.float32)
+        _check(lib().fv3_mlp_get_params(self._h, _fptr(flat)))
+        return self._unpack(flat)
+
+    def forward(self, X, Y, stream=None) -> None:
+        _check(lib().fv3_mlp_forward(self._h, C.c_void_p(X.data_ptr()), int(X.shape[0]),
+                                     C.c_void_p(Y.data_ptr()), _stream(stream)))
+
+    def gradients(self, X, T, stream=None):
+        flat = np.zeros(lib().fv3_mlp_param_count(self._h), dtype=np.float32)
+        _check(lib().fv3_mlp_gradients(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                       int(X.shape[0]), _fptr(flat), _stream(stream)))
+        return self._unpack(flat)
+
+    def train_step(self, X, T, lr: float = 1e-3, want_loss: bool = False, stream=None):
+        loss = C.c_double(0.0)
+        _check(lib().fv3_mlp_train_step(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                        int(X.shape[0]), float(lr),
+                                        C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None

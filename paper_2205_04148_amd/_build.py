@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfv3.so")
-SOURCES = ["grid.cpp", "abi.cpp", "kernels.hip"]
+SOURCES = ["grid.cpp", "abi.cpp", "kernels.hip", "correction.hip", "mlp.hip"]
 # Packed FP32 instructions are disabled for all device code.
 HIPFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -26,10 +26,13 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for cmd, p in procs:
         if p.wait() != 0:
             raise RuntimeError("compile failed: " + " ".join(cmd))
-    link = ["hipcc", "-shared", "--offload-arch=gfx950", "-fPIC", "-o", LIB] + objs
+    # link to a temporary name and rename, so a reader never sees a partial file
+    tmp = LIB + ".tmp"
+    link = ["hipcc", "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
+    os.replace(tmp, LIB)
     return LIB
 
 

@@ -38,6 +38,11 @@ fv3_status check_state(const fv3_state *s, const fv3_grid *g)
 }
 }  // namespace
 
+namespace fv3 {
+fv3_status set_error(fv3_status s, const std::string &msg) { return fail(s, msg); }
+bool device_current(const fv3_grid *g) { return device_ok(g); }
+}  // namespace fv3
+
 extern "C" {
 
 const char *fv3_last_error(void) { return g_last_error.c_str(); }
@@ -107,6 +112,7 @@ fv3_status fv3_free_grid(fv3_grid *g)
     if (g->planC.d) (void)hipFree(g->planC.d);
     if (g->planD.d) (void)hipFree(g->planD.d);
     if (g->planCv.d) (void)hipFree(g->planCv.d);
+    if (g->planA.d) (void)hipFree(g->planA.d);
     if (g->flags) (void)hipFree(g->flags);
     if (g->red) (void)hipFree(g->red);
     delete g;

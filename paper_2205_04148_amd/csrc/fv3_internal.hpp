@@ -45,6 +45,40 @@ struct Plan {
     int count = 0;
 };
 
+// Block index handed to a kernel body explicitly (the hardware index when a
+// kernel runs alone, the member-local index in an ensemble launch).
+struct Bk {
+    unsigned x, y, z;
+};
+
+// Ensemble launches: per member, the first grid-z index of its planes and its
+// own x/y grid extent.
+struct MemberBlk {
+    int z0, gx, gy, pad;
+};
+
+// One recorded kernel launch of the substep sequence, for all members:
+// the ensemble kernel, the members' argument packs back to back, and per
+// member either the point extents and planes (tunable plane kernels, whose
+// grid follows the block shape) or the fixed grid dimensions.
+struct Site {
+    std::string name;
+    const void *kmulti = nullptr;
+    size_t argsz = 0;
+    bool tunable = false;
+    dim3 blk;
+    std::vector<char> blob;
+    std::vector<int> ex, ey, ez;
+};
+
+struct Recorder {
+    std::vector<Site> sites;
+    std::vector<size_t> marks;   // site indices: end of the entry part, end of one substep
+    size_t pos = 0, mark = 0;
+    int member = 0;
+    bool bad = false;
+};
+
 }  // namespace fv3
 
 struct fv3_grid {
@@ -56,7 +90,7 @@ struct fv3_grid {
     double *met[fv3::M_COUNT] = {};           // device, FP64
     float *metf[fv3::M_COUNT] = {};           // device, FP32 copies (mixed precision)
     std::vector<double> hmet[fv3::M_COUNT];   // host copies
-    fv3::Plan planC, planD, planCv;           // scalar, D-grid pair, C-grid pair
+    fv3::Plan planC, planD, planCv, planA;    // scalar, D-grid pair, C-grid pair, cell pair
     int *flags = nullptr;                     // device error latch [2]: cfl, nonfinite
     double *red = nullptr;                    // device reduction scratch
     long red_elems = 0;
@@ -75,18 +109,27 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err);
 fv3_status host_metric(const fv3_grid_params *p, int m, double *out, long cap, std::string &err);
 
 // Kernel launchers (kernels.hip).  All take the grid, device pointers and a stream.
-struct Work;   // workspace carve-up, defined in kernels.hip
 size_t workspace_bytes(const fv3_grid *g);
 long reduction_elems(const fv3_grid *g);
 void timing_start(const char *filter);
 int timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap);
 fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
                         hipStream_t st);
+// record the launch sequence of one substep call (entry, one substep, exit)
+// of member rec->member into rec instead of launching it
+fv3_status record_substeps(fv3_state *s, const fv3_grid *g, double bdt, Recorder *rec);
 fv3_status run_tracer(void *const *q, int nq, fv3_state *s, const fv3_grid *g, int nsplt,
                       hipStream_t st);
 fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
                          int nq, double *out, hipStream_t st);
 fv3_status run_halo_cells(const fv3_grid *g, void *const *f, int nf, int levels, int fp64,
                           hipStream_t st);
+// halo of a cell-centred vector (x, y components in tile coordinates)
+fv3_status run_halo_pair_cells(const fv3_grid *g, void *fx, void *fy, int levels, int fp64,
+                               hipStream_t st);
+
+// abi.cpp: record the thread-local message fv3_last_error() returns
+fv3_status set_error(fv3_status s, const std::string &msg);
+bool device_current(const fv3_grid *g);
 
 }  // namespace fv3

@@ -393,8 +393,9 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
             if (s != FV3_OK) return s;
         }
     }
-    std::vector<HaloEnt> pc, pd, pcv;
+    std::vector<HaloEnt> pc, pd, pcv, pa;
     make_plan(G, g, SC, SC, false, pc);
+    make_plan(G, g, SC, SC, true, pa);    // cell-centred vector
     make_plan(G, g, SY, SX, true, pd);    // D grid: u (x comp) on y-faces, v on x-faces
     make_plan(G, g, SX, SY, true, pcv);   // C grid: uc on x-faces, vc on y-faces
     fv3_status s;
@@ -404,6 +405,8 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
     g->planD.count = (int)pd.size();
     if ((s = upload(&g->planCv.d, pcv, err)) != FV3_OK) return s;
     g->planCv.count = (int)pcv.size();
+    if ((s = upload(&g->planA.d, pa, err)) != FV3_OK) return s;
+    g->planA.count = (int)pa.size();
     if (hipMalloc((void **)&g->flags, 4 * sizeof(int)) != hipSuccess) return FV3_ENOMEM;
     if (hipMemset(g->flags, 0, 4 * sizeof(int)) != hipSuccess) return FV3_EDEVICE;
     return FV3_OK;

@@ -2,16 +2,22 @@
 //
 // Data layout: every field is [tile][level][row][column], column index i
 // contiguous (coalesced across the 64 lanes of a wavefront), halo of 3 points,
-// rows padded to a multiple of 128 bytes with interior i = 0 aligned.  One
-// kernel per stage of the method, each thread one output point of one
-// (tile, level) plane; column solves march k in one thread per column with
-// the column's unknowns in FP64.  Corner blocks of cube tiles are never
-// stored: reads of them are remapped to the adjacent edge halo rotated about
-// the cube vertex, in the x-sweep or y-sweep sense of the reading stencil
-// (generalising the corner statement of Sec. VII-C).
+// rows padded to 128 bytes with interior i = 0 aligned.  Kernels are
+// templated on the bulk type B (double, or float for the mixed-precision
+// build); the column solves, vertical scans, pressure gradients and mass-flux
+// accumulators are always FP64.
 //
-// Stage formulas: see the method description in each kernel's comment; the
-// order of the stages inside a substep follows the FV3 acoustic loop
+// Stencil kernels work on one (tile, level) plane per grid z index.  The
+// flux-form transport fv_tp_2d (paper Sec. IX-C) is one fused kernel: a
+// 64 x 16 cell tile with its 3-point halo is staged in LDS, and the outer
+// fluxes, inner advective updates, final fluxes and the flux-divergence update
+// of the transported field all run out of LDS.  Corner blocks of cube tiles
+// are never stored: reads of them are remapped to the adjacent edge halo
+// rotated about the cube vertex, in the x-sweep or y-sweep sense of the
+// reading stencil (generalising the corner statement of Sec. VII-C).  Column
+// kernels march k in one thread per column with software-pipelined loads.
+//
+// The order of the stages inside a substep follows the FV3 acoustic loop
 // (Sec. II): halo A, c_sw, dz_c + riem_solver_c, p_grad_c, halo B, d_sw,
 // dz_d + riem_solver3, halo C, nh_p_grad.
 #include <cmath>
@@ -23,8 +29,6 @@
 #include "fv3_internal.hpp"
 
 namespace fv3 {
-
-typedef double B;   // bulk precision of this build of the kernels
 
 #define DEVI __device__ __forceinline__
 
@@ -111,12 +115,14 @@ DEVI bool is_vertex(const Geo &G, int i, int j)
 
 #define KARGS int ilo, int ihi, int jlo, int jhi
 
-struct Met {
-    const double *m[M_COUNT];
+template <class R>
+struct Mets {
+    const R *m[M_COUNT];
 };
+typedef Mets<double> MetD;
 
 // plane pointer of a 2-D metric for tile t
-#define MP(name) (M.m[name] + G.off0 + (long)t * G.lev)
+#define MP(M, name) ((M).m[name] + G.off0 + (long)t * G.lev)
 
 // ---------------------------------------------------------- launch timing
 struct TimingRec {
@@ -146,6 +152,7 @@ static void timing_end(hipStream_t st, TimingRec &r)
     g_timing.recs.push_back(r);
 }
 
+// plane kernels: 64 x 4 threads, one point each, grid z = planes
 template <class Kern, class... Args>
 static void launch2d_named(const char *name, Kern kern, int ilo, int ihi, int jlo, int jhi, int planes,
                            hipStream_t st, Args... args)
@@ -160,12 +167,23 @@ static void launch2d_named(const char *name, Kern kern, int ilo, int ihi, int jl
 }
 #define launch2d(kern, ...) launch2d_named(#kern, kern, __VA_ARGS__)
 
+// generic launch with explicit shape (timed under `name`)
+template <class Kern, class... Args>
+static void launch_named(const char *name, Kern kern, dim3 grd, dim3 blk, hipStream_t st, Args... args)
+{
+    bool tm = timing_wanted(name);
+    TimingRec r;
+    if (tm) timing_begin(name, st, r);
+    hipLaunchKernelGGL(kern, grd, blk, 0, st, args...);
+    if (tm) timing_end(st, r);
+}
+
 // ====================================================================
 // 1-D PPM face value (monotone): face between cells m-1 and m along a
-// sweep, cell values q[0..5] = cells m-3..m+2, Courant number c.  Limited
+// sweep, cell values q0..q5 = cells m-3..m+2, Courant number c.  Limited
 // slope per cell (zero at extrema), fourth-order edge values, edge
-// deviations clipped to twice the slope, mean of the parabola over the
-// swept part of the upwind cell.
+// deviations clipped to twice the slope with the slope's sign, mean of the
+// parabola over the swept part of the upwind cell.
 // ====================================================================
 template <class T>
 DEVI T lslope(T a, T b, T c)
@@ -181,12 +199,10 @@ DEVI T sgnT(T x) { return x > 0 ? (T)1 : (x < 0 ? (T)-1 : (T)0); }
 template <class T>
 DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
 {
-    // cells m-3 .. m+2 -> q0 .. q5
-    T d1 = lslope(q0, q1, q2), d2 = lslope(q1, q2, q3), d3 = lslope(q2, q3, q4),
-      d4 = lslope(q3, q4, q5);
     const T third = (T)1 / (T)3;
     if (c > 0) {
-        // upwind cell m-1 (q2): left edge between q1,q2, right edge between q2,q3
+        // upwind cell m-1 (q2)
+        T d1 = lslope(q0, q1, q2), d2 = lslope(q1, q2, q3), d3 = lslope(q2, q3, q4);
         T al = (T)0.5 * (q1 + q2) + (d1 - d2) * third;
         T ar = (T)0.5 * (q2 + q3) + (d2 - d3) * third;
         T s = sgnT(d2), a2 = (T)2 * fabs(d2);
@@ -194,6 +210,7 @@ DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
         T br = s * fmin(a2, fabs(ar - q2));
         return q2 + ((T)1 - c) * (br - c * (bl + br));
     } else {
+        T d2 = lslope(q1, q2, q3), d3 = lslope(q2, q3, q4), d4 = lslope(q3, q4, q5);
         T al = (T)0.5 * (q2 + q3) + (d2 - d3) * third;
         T ar = (T)0.5 * (q3 + q4) + (d3 - d4) * third;
         T s = sgnT(d3), a2 = (T)2 * fabs(d3);
@@ -234,23 +251,15 @@ template <class T>
 static void halo_scalar(const fv3_grid *g, T *f, int L, hipStream_t st)
 {
     if (g->planC.count == 0) return;
-    dim3 grd((g->planC.count + 255) / 256, L);
-    bool tm = timing_wanted("k_halo_scalar");
-    TimingRec r;
-    if (tm) timing_begin("k_halo_scalar", st, r);
-    hipLaunchKernelGGL(k_halo_scalar<T>, grd, dim3(256), 0, st, g->geo, g->planC.d, g->planC.count, f, L);
-    if (tm) timing_end(st, r);
+    launch_named("k_halo_scalar", k_halo_scalar<T>, dim3((g->planC.count + 255) / 256, L), dim3(256), st,
+                 g->geo, (const HaloEnt *)g->planC.d, g->planC.count, f, L);
 }
 template <class T>
 static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hipStream_t st)
 {
     if (p.count == 0) return;
-    dim3 grd((p.count + 255) / 256, L);
-    bool tm = timing_wanted("k_halo_pair");
-    TimingRec r;
-    if (tm) timing_begin("k_halo_pair", st, r);
-    hipLaunchKernelGGL(k_halo_pair<T>, grd, dim3(256), 0, st, g->geo, p.d, p.count, fx, fy, L);
-    if (tm) timing_end(st, r);
+    launch_named("k_halo_pair", k_halo_pair<T>, dim3((p.count + 255) / 256, L), dim3(256), st, g->geo,
+                 (const HaloEnt *)p.d, p.count, fx, fy, L);
 }
 
 // ====================================================================
@@ -259,6 +268,7 @@ static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hip
 // ====================================================================
 // A-grid winds at cells: u interpolated along y ((-1,9,9,-1)/16, y-sweep
 // corner view), v along x (x-sweep view).
+template <class B>
 __global__ void k_csw_agrid(KARGS, Geo G, const B *u, const B *v, B *ua, B *va)
 {
     KBEGIN(G.nz);
@@ -268,19 +278,20 @@ __global__ void k_csw_agrid(KARGS, Geo G, const B *u, const B *v, B *ua, B *va)
     if (j >= -2 && j <= G.n + 1) {
         B a = pvx(G, U, V, SY, i, j - 1, 1, true), b = pvx(G, U, V, SY, i, j, 1, true),
           c = pvx(G, U, V, SY, i, j + 1, 1, true), d = pvx(G, U, V, SY, i, j + 2, 1, true);
-        AT(ua + o, i, j) = (-a + 9.0 * b + 9.0 * c - d) / 16.0;
+        AT(ua + o, i, j) = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
     }
     if (i >= -2 && i <= G.n + 1) {
         B a = pvy(G, U, V, SX, i - 1, j, 0, true), b = pvy(G, U, V, SX, i, j, 0, true),
           c = pvy(G, U, V, SX, i + 1, j, 0, true), d = pvy(G, U, V, SX, i + 2, j, 0, true);
-        AT(va + o, i, j) = (-a + 9.0 * b + 9.0 * c - d) / 16.0;
+        AT(va + o, i, j) = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
     }
 }
 
 // C-grid winds before the update, normal-wind area fluxes over dt2 and the
 // first-order upwind fluxes of delp, pt*delp, w*delp on the faces around the
 // half-step cells (-1..n in both directions, without the four corner cells).
-__global__ void k_csw_faces(KARGS, Geo G, Met M, B dt2, const B *u, const B *v, const B *delp,
+template <class B>
+__global__ void k_csw_faces(KARGS, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *delp,
                             const B *pt, const B *w, const B *ua, const B *va, B *ucp, B *vcp,
                             B *ax, B *ay, B *Fm, B *Fp, B *Fw, B *Gm, B *Gp, B *Gw)
 {
@@ -293,9 +304,9 @@ __global__ void k_csw_faces(KARGS, Geo G, Met M, B dt2, const B *u, const B *v, 
     if (xf) {
         B a = pvx(G, UA, VA, SC, i - 2, j, 0, true), b = pvx(G, UA, VA, SC, i - 1, j, 0, true),
           c = pvx(G, UA, VA, SC, i, j, 0, true), d = pvx(G, UA, VA, SC, i + 1, j, 0, true);
-        B uc0 = (-a + 9.0 * b + 9.0 * c - d) / 16.0;
-        B fl = dt2 * (uc0 - AT(v + o, i, j) * AT(MP(M_COS_U), i, j)) / AT(MP(M_SIN_U), i, j) *
-               AT(MP(M_DY), i, j);
+        B uc0 = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+        B fl = dt2 * (uc0 - AT(v + o, i, j) * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j) *
+               AT(MP(M, M_DY), i, j);
         int up = fl > 0 ? i - 1 : i;
         B fm = fl * sv(G, D, SC, up, j, 0);
         AT(ucp + o, i, j) = uc0;
@@ -307,9 +318,9 @@ __global__ void k_csw_faces(KARGS, Geo G, Met M, B dt2, const B *u, const B *v, 
     if (yf) {
         B a = pvy(G, UA, VA, SC, i, j - 2, 1, true), b = pvy(G, UA, VA, SC, i, j - 1, 1, true),
           c = pvy(G, UA, VA, SC, i, j, 1, true), d = pvy(G, UA, VA, SC, i, j + 1, 1, true);
-        B vc0 = (-a + 9.0 * b + 9.0 * c - d) / 16.0;
-        B fl = dt2 * (vc0 - AT(u + o, i, j) * AT(MP(M_COS_V), i, j)) / AT(MP(M_SIN_V), i, j) *
-               AT(MP(M_DX), i, j);
+        B vc0 = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+        B fl = dt2 * (vc0 - AT(u + o, i, j) * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j) *
+               AT(MP(M, M_DX), i, j);
         int up = fl > 0 ? j - 1 : j;
         B gm = fl * sv(G, D, SC, i, up, 1);
         AT(vcp + o, i, j) = vc0;
@@ -323,7 +334,8 @@ __global__ void k_csw_faces(KARGS, Geo G, Met M, B dt2, const B *u, const B *v, 
 // Half-step cell values and kinetic energy on the cross of cells -1..n;
 // absolute vorticity on the corners 0..n (C-grid circulation; at a cube
 // vertex the two faces next to the missing corner cell each count half).
-__global__ void k_csw_cells(KARGS, Geo G, Met M, B dt2, const B *delp, const B *pt, const B *w,
+template <class B>
+__global__ void k_csw_cells(KARGS, Geo G, Mets<B> M, B dt2, const B *delp, const B *pt, const B *w,
                             const B *ua, const B *va, const B *ucp, const B *vcp, const B *Fm,
                             const B *Fp, const B *Fw, const B *Gm, const B *Gp, const B *Gw,
                             B *delpc, B *ptc, B *wc, B *ke, B *vort)
@@ -333,7 +345,7 @@ __global__ void k_csw_cells(KARGS, Geo G, Met M, B dt2, const B *delp, const B *
     long o = pidx(G, G.nz, t, k);
     bool cross = (i >= 0 && i < n) || (j >= 0 && j < n);
     if (cross) {
-        B ar = AT(MP(M_AREA), i, j);
+        B ar = AT(MP(M, M_AREA), i, j);
         B dp = AT(delp + o, i, j);
         B dc = dp + (AT(Fm + o, i, j) - AT(Fm + o, i + 1, j) + AT(Gm + o, i, j) - AT(Gm + o, i, j + 1)) / ar;
         AT(delpc + o, i, j) = dc;
@@ -341,11 +353,11 @@ __global__ void k_csw_cells(KARGS, Geo G, Met M, B dt2, const B *delp, const B *
             (AT(pt + o, i, j) * dp + (AT(Fp + o, i, j) - AT(Fp + o, i + 1, j) + AT(Gp + o, i, j) - AT(Gp + o, i, j + 1)) / ar) / dc;
         AT(wc + o, i, j) =
             (AT(w + o, i, j) * dp + (AT(Fw + o, i, j) - AT(Fw + o, i + 1, j) + AT(Gw + o, i, j) - AT(Gw + o, i, j + 1)) / ar) / dc;
-        B sa = AT(MP(M_SIN_A), i, j), ca = AT(MP(M_COS_A), i, j);
+        B sa = AT(MP(M, M_SIN_A), i, j), ca = AT(MP(M, M_COS_A), i, j);
         B s2 = sa * sa;
         B a = AT(ua + o, i, j), b = AT(va + o, i, j);
         B uu = (a - b * ca) / s2, vv = (b - a * ca) / s2;
-        AT(ke + o, i, j) = 0.5 * dt2 *
+        AT(ke + o, i, j) = (B)0.5 * dt2 *
                            (uu * (uu > 0 ? AT(ucp + o, i, j) : AT(ucp + o, i + 1, j)) +
                             vv * (vv > 0 ? AT(vcp + o, i, j) : AT(vcp + o, i, j + 1)));
     }
@@ -355,17 +367,18 @@ __global__ void k_csw_cells(KARGS, Geo G, Met M, B dt2, const B *delp, const B *
             if (j == 0) ws = 0.5; else wn = 0.5;
             if (i == 0) ww = 0.5; else we = 0.5;
         }
-        B circ = ws * AT(ucp + o, i, j - 1) * AT(MP(M_DXC), i, j - 1) -
-                 wn * AT(ucp + o, i, j) * AT(MP(M_DXC), i, j) -
-                 ww * AT(vcp + o, i - 1, j) * AT(MP(M_DYC), i - 1, j) +
-                 we * AT(vcp + o, i, j) * AT(MP(M_DYC), i, j);
-        AT(vort + o, i, j) = AT(MP(M_FB), i, j) + circ / AT(MP(M_AREA_C), i, j);
+        B circ = ws * AT(ucp + o, i, j - 1) * AT(MP(M, M_DXC), i, j - 1) -
+                 wn * AT(ucp + o, i, j) * AT(MP(M, M_DXC), i, j) -
+                 ww * AT(vcp + o, i - 1, j) * AT(MP(M, M_DYC), i - 1, j) +
+                 we * AT(vcp + o, i, j) * AT(MP(M, M_DYC), i, j);
+        AT(vort + o, i, j) = AT(MP(M, M_FB), i, j) + circ / AT(MP(M, M_AREA_C), i, j);
     }
 }
 
 // C-grid wind update on the interior faces: upwinded vorticity flux plus
 // kinetic-energy gradient.
-__global__ void k_csw_update(KARGS, Geo G, Met M, B dt2, const B *u, const B *v, const B *ucp,
+template <class B>
+__global__ void k_csw_update(KARGS, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *ucp,
                              const B *vcp, const B *ke, const B *vort, B *uc, B *vc)
 {
     KBEGIN(G.nz);
@@ -373,15 +386,15 @@ __global__ void k_csw_update(KARGS, Geo G, Met M, B dt2, const B *u, const B *v,
     long o = pidx(G, G.nz, t, k);
     if (j < n) {
         B u0 = AT(ucp + o, i, j);
-        B fy1 = dt2 * (AT(v + o, i, j) - u0 * AT(MP(M_COS_U), i, j)) / AT(MP(M_SIN_U), i, j);
+        B fy1 = dt2 * (AT(v + o, i, j) - u0 * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j);
         B vt = fy1 > 0 ? AT(vort + o, i, j) : AT(vort + o, i, j + 1);
-        AT(uc + o, i, j) = u0 + fy1 * vt + (AT(ke + o, i - 1, j) - AT(ke + o, i, j)) / AT(MP(M_DXC), i, j);
+        AT(uc + o, i, j) = u0 + fy1 * vt + (AT(ke + o, i - 1, j) - AT(ke + o, i, j)) / AT(MP(M, M_DXC), i, j);
     }
     if (i < n) {
         B v0 = AT(vcp + o, i, j);
-        B fx1 = dt2 * (AT(u + o, i, j) - v0 * AT(MP(M_COS_V), i, j)) / AT(MP(M_SIN_V), i, j);
+        B fx1 = dt2 * (AT(u + o, i, j) - v0 * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j);
         B vt = fx1 > 0 ? AT(vort + o, i, j) : AT(vort + o, i + 1, j);
-        AT(vc + o, i, j) = v0 - fx1 * vt + (AT(ke + o, i, j - 1) - AT(ke + o, i, j)) / AT(MP(M_DYC), i, j);
+        AT(vc + o, i, j) = v0 - fx1 * vt + (AT(ke + o, i, j - 1) - AT(ke + o, i, j)) / AT(MP(M, M_DYC), i, j);
     }
 }
 
@@ -398,7 +411,8 @@ DEVI double zs_at(const Geo &G, const double *phis, int t, int i, int j, int mod
 // dz_c: half-step interface heights by first-order upwind transport of the
 // interface heights with layer-averaged area fluxes (top interface: top
 // layer), advective form, surface fixed; output the half-step thicknesses.
-__global__ void k_dzc(KARGS, Geo G, Met M, const double *delz, const double *phis, const B *ax,
+template <class B>
+__global__ void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, const B *ax,
                       const B *ay, double *delzc)
 {
     int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -406,12 +420,11 @@ __global__ void k_dzc(KARGS, Geo G, Met M, const double *delz, const double *phi
     if (i > ihi || j > jhi) return;
     int n = G.n, nz = G.nz, t = blockIdx.z;
     if (!((i >= 0 && i < n) || (j >= 0 && j < n))) return;
-    double area = AT(MP(M_AREA), i, j);
+    double area = AT(MP(M, M_AREA), i, j);
     double zc = zs_at(G, phis, t, i, j, 0);
     double zw = zs_at(G, phis, t, i - 1, j, 0), ze = zs_at(G, phis, t, i + 1, j, 0);
     double zsou = zs_at(G, phis, t, i, j - 1, 1), znor = zs_at(G, phis, t, i, j + 1, 1);
-    double zsurf = zc;
-    double zprev = zsurf;   // new height of the interface below
+    double zprev = zc;   // new height of the interface below
     for (int K = nz - 1; K >= 0; K--) {
         long o = pidx(G, nz, t, K);
         const double *D = delz + o;
@@ -436,95 +449,130 @@ __global__ void k_dzc(KARGS, Geo G, Met M, const double *delz, const double *phi
 // Semi-implicit column solve (riem_solver_c / riem_solver3, Sec. IX-B):
 // hydrostatic interface pressure from delp (top down), nonhydrostatic
 // pressure from the equation of state, mass-weighted interface perturbation,
-// backward-Euler tridiagonal system in w (Thomas, positive pivots), new
-// perturbation by a top-down scan, thickness by inverting the equation of
-// state, heights by a bottom-up scan.  Temporaries in FP64 scratch columns.
-template <class TW>
-__global__ void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi, const B *theta,
-                       const double *delz, const TW *w, const double *phis, double *cpv,
-                       double *dpv, double *wnv, TW *w_out, double *delz_out, double *pfull,
-                       double *phi, int need_cross)
+// backward-Euler tridiagonal system in w (Thomas), new perturbation by a
+// top-down scan, thickness by inverting the equation of state, heights by a
+// bottom-up scan.  Elimination coefficients live in FP64 scratch columns;
+// every pass loads the next level one iteration ahead.
+template <class B, class TW>
+__global__ void __launch_bounds__(256) k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
+                                              const B *theta, const double *delz, const TW *w,
+                                              const double *phis, double *cpv, double *dpv,
+                                              double *wnv, TW *w_out, double *delz_out,
+                                              double *pfull, double *phi, int need_cross)
 {
     int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
     int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);
     if (i > ihi || j > jhi) return;
     int n = G.n, nz = G.nz, t = blockIdx.z;
     if (need_cross && !((i >= 0 && i < n) || (j >= 0 && j < n))) return;
-    const double kap = RDGAS / CP_AIR, gam = 1.0 / (1.0 - kap), rgam = 1.0 - kap;
-    long cidx = (long)j * G.pitch + i;
-    auto L = [&](int k) { return pidx(G, nz, t, k) + cidx; };
-    auto LI = [&](int K) { return pidx(G, nz + 1, t, K) + cidx; };
-    // forward sweep with a one-layer look-ahead
-    double pi_k = ptop;                 // interface k
-    double dp0 = (double)dpi[L(0)];
-    double pi_k1 = pi_k + dp0;
-    double m0 = dp0 / GRAV, h0 = -delz[L(0)];
-    double pib0 = dp0 / (log(pi_k1) - log(pi_k));
-    double pp0 = P_REF * pow(RDGAS * (double)theta[L(0)] * m0 / (h0 * P_REF), gam) - pib0;
-    double pps_k = 0.0, A_k = 0.0;      // at interface k
-    double cprev = 0.0, dprev = 0.0;
+    const double kap = RDGAS / CP_AIR, gam = 1.0 / (1.0 - kap), rgam = 1.0 / gam;
+    const long base = pidx(G, nz, t, 0) + (long)j * G.pitch + i, lev = G.lev;
+    const long basei = pidx(G, nz + 1, t, 0) + (long)j * G.pitch + i;
+    const double dt2x = dt * dt;
+
+    // ---- pass 1: top-down elimination with a one-layer look-ahead
+    double lpi_k = log(ptop);
+    double dp0 = (double)dpi[base], th0 = (double)theta[base], h0 = -delz[base], w0 = (double)w[base];
+    double pi_k1 = ptop + dp0, lpi_k1 = log(pi_k1);
+    double m0 = dp0 / GRAV;
+    double pp0 = P_REF * pow(RDGAS * th0 * m0 / (h0 * P_REF), gam) - dp0 / (lpi_k1 - lpi_k);
+    // prefetched layer k+1
+    double dpn = 0, thn = 0, hn_ = 0, wn_ = 0;
+    if (nz > 1) {
+        dpn = (double)dpi[base + lev];
+        thn = (double)theta[base + lev];
+        hn_ = -delz[base + lev];
+        wn_ = (double)w[base + lev];
+    }
+    double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0;
     for (int k = 0; k < nz; k++) {
-        double pps_k1, A_k1;
-        double m1 = 0, h1 = 0, pp1 = 0, dp1 = 0, pi_k2 = 0;
+        double dp1 = dpn, th1 = thn, h1 = hn_, w1 = wn_;
+        if (k + 2 < nz) {   // issue the loads of layer k+2 now
+            long o2 = base + (long)(k + 2) * lev;
+            dpn = (double)dpi[o2];
+            thn = (double)theta[o2];
+            hn_ = -delz[o2];
+            wn_ = (double)w[o2];
+        }
+        double pps_k1, A_k1, pi_k2 = 0, lpi_k2 = 0, m1 = 0, pp1 = 0;
         if (k < nz - 1) {
-            dp1 = (double)dpi[L(k + 1)];
             pi_k2 = pi_k1 + dp1;
+            lpi_k2 = log(pi_k2);
             m1 = dp1 / GRAV;
-            h1 = -delz[L(k + 1)];
-            double pib1 = dp1 / (log(pi_k2) - log(pi_k1));
-            pp1 = P_REF * pow(RDGAS * (double)theta[L(k + 1)] * m1 / (h1 * P_REF), gam) - pib1;
+            pp1 = P_REF * pow(RDGAS * th1 * m1 / (h1 * P_REF), gam) - dp1 / (lpi_k2 - lpi_k1);
             pps_k1 = (dp1 * pp0 + dp0 * pp1) / (dp0 + dp1);
-            A_k1 = gam * (pi_k1 + pps_k1) * dt * dt / (0.5 * (h0 + h1));
+            A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
         } else {
             pps_k1 = pp0;
-            A_k1 = gam * (pi_k1 + pps_k1) * dt * dt / (0.5 * h0);
+            A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * h0);
         }
         double lower = k > 0 ? -A_k : 0.0;
         double diag = m0 + A_k + A_k1;
         double upper = k < nz - 1 ? -A_k1 : 0.0;
-        double rhs = m0 * (double)w[L(k)] + dt * (pps_k1 - pps_k);
+        double rhs = m0 * w0 + dt * (pps_k1 - pps_k);
         double piv = diag - lower * cprev;
         double ck = upper / piv;
         double dk = (rhs - lower * dprev) / piv;
-        cpv[L(k)] = ck;
-        dpv[L(k)] = dk;
+        cpv[base + (long)k * lev] = ck;
+        dpv[base + (long)k * lev] = dk;
         cprev = ck;
         dprev = dk;
-        // advance
-        pi_k = pi_k1; pi_k1 = pi_k2; dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1;
+        pi_k1 = pi_k2; lpi_k1 = lpi_k2; dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1; th0 = th1; w0 = w1;
         pps_k = pps_k1; A_k = A_k1;
     }
-    // back substitution
-    double wn = 0.0;
-    for (int k = nz - 1; k >= 0; k--) {
-        wn = dpv[L(k)] - cpv[L(k)] * wn;
-        wnv[L(k)] = wn;
+    (void)th0;
+    // ---- pass 2: back substitution (bottom-up)
+    {
+        double wv = 0.0;
+        double cn = cpv[base + (long)(nz - 1) * lev], dn = dpv[base + (long)(nz - 1) * lev];
+        for (int k = nz - 1; k >= 0; k--) {
+            double ck = cn, dk = dn;
+            if (k > 0) {
+                cn = cpv[base + (long)(k - 1) * lev];
+                dn = dpv[base + (long)(k - 1) * lev];
+            }
+            wv = dk - ck * wv;
+            wnv[base + (long)k * lev] = wv;
+        }
     }
-    // new perturbation (top down) and thicknesses
-    double ppn = 0.0, pik = ptop;
-    if (pfull) pfull[LI(0)] = ptop;
-    for (int k = 0; k < nz; k++) {
-        double dp = (double)dpi[L(k)];
-        double m = dp / GRAV;
-        double pik1 = pik + dp;
-        double pib = dp / (log(pik1) - log(pik));
-        double wk = wnv[L(k)];
-        double ppn1 = ppn + m * (wk - (double)w[L(k)]) / dt;
-        double pn = pib + 0.5 * (ppn + ppn1);
-        double hn = RDGAS * (double)theta[L(k)] * m / P_REF * pow(P_REF / pn, rgam);
-        cpv[L(k)] = hn;   // reuse as the new thickness
-        if (pfull) pfull[LI(k + 1)] = pik1 + ppn1;
-        if (w_out) w_out[L(k)] = (TW)wk;
-        ppn = ppn1;
-        pik = pik1;
+    // ---- pass 3: new perturbation (top down), thicknesses, interface pressure
+    {
+        double ppn = 0.0, pik = ptop, lpik = log(ptop);
+        if (pfull) pfull[basei] = ptop;
+        double dpa = (double)dpi[base], tha = (double)theta[base], wa = wnv[base], woa = (double)w[base];
+        for (int k = 0; k < nz; k++) {
+            double dp = dpa, th = tha, wk = wa, wo = woa;
+            if (k + 1 < nz) {
+                long o1 = base + (long)(k + 1) * lev;
+                dpa = (double)dpi[o1];
+                tha = (double)theta[o1];
+                wa = wnv[o1];
+                woa = (double)w[o1];
+            }
+            double m = dp / GRAV;
+            double pik1 = pik + dp, lpik1 = log(pik1);
+            double pib = dp / (lpik1 - lpik);
+            double ppn1 = ppn + m * (wk - wo) / dt;
+            double pn = pib + 0.5 * (ppn + ppn1);
+            double hn = RDGAS * th * m / P_REF * pow(P_REF / pn, rgam);
+            cpv[base + (long)k * lev] = hn;   // reuse as the new thickness
+            if (pfull) pfull[basei + (long)(k + 1) * lev] = pik1 + ppn1;
+            if (w_out) w_out[base + (long)k * lev] = (TW)wk;
+            ppn = ppn1;
+            pik = pik1;
+            lpik = lpik1;
+        }
     }
-    double z = phis ? phis[pidx(G, 1, t, 0) + cidx] / GRAV : 0.0;
-    if (phi) phi[LI(nz)] = GRAV * z;
+    // ---- pass 4: heights (bottom up)
+    double z = phis ? phis[pidx(G, 1, t, 0) + (long)j * G.pitch + i] / GRAV : 0.0;
+    if (phi) phi[basei + (long)nz * lev] = GRAV * z;
+    double hnext = cpv[base + (long)(nz - 1) * lev];
     for (int k = nz - 1; k >= 0; k--) {
-        double hn = cpv[L(k)];
+        double hn = hnext;
+        if (k > 0) hnext = cpv[base + (long)(k - 1) * lev];
         z += hn;
-        if (phi) phi[LI(k)] = GRAV * z;
-        if (delz_out) delz_out[L(k)] = -hn;
+        if (phi) phi[basei + (long)k * lev] = GRAV * z;
+        if (delz_out) delz_out[base + (long)k * lev] = -hn;
     }
 }
 
@@ -539,7 +587,8 @@ DEVI double pgf(double dt, double L, double dW, double dE, double zW0, double zW
 
 // p_grad_c on the interior C-grid faces with the half-step cells' pressure
 // and geopotential; layer mass weights from delpc.
-__global__ void k_pgradc(KARGS, Geo G, Met M, double dt2, const B *delpc, const double *pkc,
+template <class B>
+__global__ void k_pgradc(KARGS, Geo G, MetD M, double dt2, const B *delpc, const double *pkc,
                          const double *gz, B *uc, B *vc)
 {
     KBEGIN(G.nz);
@@ -548,223 +597,307 @@ __global__ void k_pgradc(KARGS, Geo G, Met M, double dt2, const B *delpc, const 
     const B *D = delpc + o;
     if (j < n) {
         int iw = i - 1, ie = i;
-        AT(uc + o, i, j) += (B)pgf(dt2, AT(MP(M_DXC), i, j), AT(D, iw, j), AT(D, ie, j), AT(gz + o0, iw, j),
-                                   AT(gz + o1, iw, j), AT(gz + o0, ie, j), AT(gz + o1, ie, j), AT(pkc + o0, iw, j),
-                                   AT(pkc + o1, iw, j), AT(pkc + o0, ie, j), AT(pkc + o1, ie, j));
+        AT(uc + o, i, j) += (B)pgf(dt2, AT(MP(M, M_DXC), i, j), (double)AT(D, iw, j), (double)AT(D, ie, j),
+                                   AT(gz + o0, iw, j), AT(gz + o1, iw, j), AT(gz + o0, ie, j), AT(gz + o1, ie, j),
+                                   AT(pkc + o0, iw, j), AT(pkc + o1, iw, j), AT(pkc + o0, ie, j), AT(pkc + o1, ie, j));
     }
     if (i < n) {
         int js = j - 1, jn = j;
-        AT(vc + o, i, j) += (B)pgf(dt2, AT(MP(M_DYC), i, j), AT(D, i, js), AT(D, i, jn), AT(gz + o0, i, js),
-                                   AT(gz + o1, i, js), AT(gz + o0, i, jn), AT(gz + o1, i, jn), AT(pkc + o0, i, js),
-                                   AT(pkc + o1, i, js), AT(pkc + o0, i, jn), AT(pkc + o1, i, jn));
+        AT(vc + o, i, j) += (B)pgf(dt2, AT(MP(M, M_DYC), i, j), (double)AT(D, i, js), (double)AT(D, i, jn),
+                                   AT(gz + o0, i, js), AT(gz + o1, i, js), AT(gz + o0, i, jn), AT(gz + o1, i, jn),
+                                   AT(pkc + o0, i, js), AT(pkc + o1, i, js), AT(pkc + o0, i, jn), AT(pkc + o1, i, jn));
     }
 }
 
 // ====================================================================
-// fv_tp_2d (Sec. IX-C): Lin-Rood flux-form transport on one level.
-// Three passes: outer PPM fluxes of q in both directions; inner advective
-// half updates; PPM fluxes of the cross-updated fields and the averaged,
-// weighted fluxes.  q has Lq levels, the Courant/area-flux arrays Lc; plane
-// k of q pairs with plane k of the fluxes.
+// fv_tp_2d (Sec. IX-C): Lin-Rood flux-form transport on one level, fused.
+// A 64 x 16 cell tile plus 3-point halo is staged in LDS in both sweep
+// views; outer PPM fluxes, inner advective half updates, final averaged and
+// weighted fluxes, then an epilogue that applies the flux divergence:
+//   EPI_FLUX   write the fluxes only
+//   EPI_DELP   write fluxes, accumulate them (mass fluxes, Courant numbers),
+//              new delp = delp + div F / area
+//   EPI_MASSW  mass-weighted update (q delp_old area + div F) / (delp_new area)
+//   EPI_ADV    advective update (q area + div F) / (area + div of area fluxes)
+//   EPI_TRACER (q dp1 area + div F) / (dp2 area)
+// With `iface`, the Courant numbers and area fluxes of plane k are the mean
+// of layers k-1 and k (plane 0: layer 0), for interface heights.
 // ====================================================================
-template <class T>
-__global__ void k_fv_outer(KARGS, Geo G, int Lq, int Lc, const T *q, const B *crx, const B *cry,
-                           T *fx2, T *fy2)
-{
-    KBEGIN(Lc);
-    int n = G.n;
-    const T *Q = q + pidx(G, Lq, t, k);
-    long oc = pidx(G, Lc, t, k);
-    if (i >= -3 && i <= n + 2 && j >= 0 && j <= n) {
-        T c = (T)AT(cry + oc, i, j);
-        AT(fy2 + oc, i, j) = ppm6(sv(G, Q, SC, i, j - 3, 1), sv(G, Q, SC, i, j - 2, 1), sv(G, Q, SC, i, j - 1, 1),
-                                  sv(G, Q, SC, i, j, 1), sv(G, Q, SC, i, j + 1, 1), sv(G, Q, SC, i, j + 2, 1), c);
-    }
-    if (i >= 0 && i <= n && j >= -3 && j <= n + 2) {
-        T c = (T)AT(crx + oc, i, j);
-        AT(fx2 + oc, i, j) = ppm6(sv(G, Q, SC, i - 3, j, 0), sv(G, Q, SC, i - 2, j, 0), sv(G, Q, SC, i - 1, j, 0),
-                                  sv(G, Q, SC, i, j, 0), sv(G, Q, SC, i + 1, j, 0), sv(G, Q, SC, i + 2, j, 0), c);
-    }
-}
+enum { EPI_FLUX = 0, EPI_DELP = 1, EPI_MASSW = 2, EPI_ADV = 3, EPI_TRACER = 4 };
+constexpr int FTX = 64, FTY = 16, FNT = 256;
+constexpr int QW = FTX + 6, QH = FTY + 6;
 
-template <class T>
-__global__ void k_fv_inner(KARGS, Geo G, Met M, int Lq, int Lc, const T *q, const B *xfx,
-                           const B *yfx, const T *fx2, const T *fy2, T *qi, T *qj)
-{
-    KBEGIN(Lc);
-    int n = G.n;
-    const T *Q = q + pidx(G, Lq, t, k);
-    long oc = pidx(G, Lc, t, k);
-    T ar = (T)AT(MP(M_AREA), i, j);
-    if (i >= -3 && i <= n + 2 && j >= 0 && j < n) {
-        T y0 = (T)AT(yfx + oc, i, j), y1 = (T)AT(yfx + oc, i, j + 1);
-        AT(qi + oc, i, j) = (AT(Q, i, j) * ar + y0 * AT(fy2 + oc, i, j) - y1 * AT(fy2 + oc, i, j + 1)) / (ar + y0 - y1);
-    }
-    if (i >= 0 && i < n && j >= -3 && j <= n + 2) {
-        T x0 = (T)AT(xfx + oc, i, j), x1 = (T)AT(xfx + oc, i + 1, j);
-        AT(qj + oc, i, j) = (AT(Q, i, j) * ar + x0 * AT(fx2 + oc, i, j) - x1 * AT(fx2 + oc, i + 1, j)) / (ar + x0 - x1);
-    }
-}
-
-template <class T, class TM>
-__global__ void k_fv_flux(KARGS, Geo G, int Lc, const B *crx, const B *cry, const B *xfx,
-                          const B *yfx, const TM *mx, const TM *my, const T *fx2, const T *fy2,
-                          const T *qi, const T *qj, T *FX, T *FY)
-{
-    KBEGIN(Lc);
-    int n = G.n;
-    long oc = pidx(G, Lc, t, k);
-    if (i >= 0 && i <= n && j >= 0 && j < n) {
-        const T *P = qi + oc;
-        T fx = ppm6(AT(P, i - 3, j), AT(P, i - 2, j), AT(P, i - 1, j), AT(P, i, j), AT(P, i + 1, j), AT(P, i + 2, j),
-                    (T)AT(crx + oc, i, j));
-        T wgt = mx ? (T)AT(mx + oc, i, j) : (T)AT(xfx + oc, i, j);
-        AT(FX + oc, i, j) = (T)0.5 * (fx + AT(fx2 + oc, i, j)) * wgt;
-    }
-    if (i >= 0 && i < n && j >= 0 && j <= n) {
-        const T *P = qj + oc;
-        T fy = ppm6(AT(P, i, j - 3), AT(P, i, j - 2), AT(P, i, j - 1), AT(P, i, j), AT(P, i, j + 1), AT(P, i, j + 2),
-                    (T)AT(cry + oc, i, j));
-        T wgt = my ? (T)AT(my + oc, i, j) : (T)AT(yfx + oc, i, j);
-        AT(FY + oc, i, j) = (T)0.5 * (fy + AT(fy2 + oc, i, j)) * wgt;
-    }
-}
-
-struct FvTmp {
-    void *fx2, *fy2, *qi, *qj;
+template <class T, class C, class M>
+struct FvArgs {
+    const T *q;
+    int Lq;
+    const C *crx, *cry, *xfx, *yfx;
+    int Lc, iface;
+    const M *mx, *my;      // optional flux weights (mass fluxes)
+    const T *area;         // area metric (type T)
+    int epi;
+    T *FX, *FY;            // flux outputs (may be null)
+    T *qout;               // cell output, Lq levels
+    const T *dold, *dnew;  // EPI_MASSW
+    const double *dp1, *dp2;            // EPI_TRACER
+    double *mfx, *mfy;     // EPI_DELP accumulators
+    C *cxa, *cya;
 };
 
-template <class T, class TM>
-static void fv_tp_2d(const fv3_grid *g, Met M, int Lq, int Lc, int planes, const T *q, const B *crx,
-                     const B *cry, const B *xfx, const B *yfx, const TM *mx, const TM *my, T *FX,
-                     T *FY, FvTmp tmp, hipStream_t st)
+template <class T, class C>
+DEVI T ccr(const C *a, long o, long ob, long idx, int avg)
 {
-    int n = g->n;
-    const Geo &G = g->geo;
-    T *fx2 = (T *)tmp.fx2, *fy2 = (T *)tmp.fy2, *qi = (T *)tmp.qi, *qj = (T *)tmp.qj;
-    launch2d(k_fv_outer<T>, -3, n + 2, -3, n + 2, planes, st, G, Lq, Lc, q, crx, cry, fx2, fy2);
-    launch2d(k_fv_inner<T>, -3, n + 2, -3, n + 2, planes, st, G, M, Lq, Lc, q, xfx, yfx,
-             (const T *)fx2, (const T *)fy2, qi, qj);
-    launch2d(k_fv_flux<T, TM>, 0, n, 0, n, planes, st, G, Lc, crx, cry, xfx, yfx, mx, my,
-             (const T *)fx2, (const T *)fy2, (const T *)qi, (const T *)qj, FX, FY);
+    if (avg) return (T)(0.5 * ((double)a[ob + idx] + (double)a[o + idx]));
+    return (T)a[o + idx];
+}
+
+template <class T, class C, class M>
+__global__ void __launch_bounds__(FNT) k_fvtp(Geo G, FvArgs<T, C, M> A)
+{
+    __shared__ T sQ[QH * QW], sQy[QH * QW];
+    __shared__ T sFy[(FTY + 1) * (FTX + 6)];   // y-faces: cols i0-3..i0+FTX+2, rows j0..j0+FTY
+    __shared__ T sFx[(FTY + 6) * (FTX + 1)];   // x-faces: cols i0..i0+FTX, rows j0-3..j0+FTY+2
+    __shared__ T sQi[FTY * (FTX + 6)];         // cells: cols i0-3..i0+FTX+2, rows j0..j0+FTY-1
+    __shared__ T sQj[(FTY + 6) * FTX];         // cells: cols i0..i0+FTX-1, rows j0-3..j0+FTY+2
+    const int n = G.n, tid = threadIdx.x;
+    const int i0 = blockIdx.x * FTX, j0 = blockIdx.y * FTY;
+    const int t = blockIdx.z / A.Lc, k = blockIdx.z % A.Lc;
+    const T *Q = A.q + pidx(G, A.Lq, t, k);
+    const long oc = pidx(G, A.Lc, t, k);
+    const int avg = A.iface && k > 0;
+    const long ob = avg ? pidx(G, A.Lc, t, k - 1) : oc;
+    const T *AR = A.area + G.off0 + (long)t * G.lev;
+    const long P = G.pitch;
+
+    // 1. field tile in the x-sweep and y-sweep views
+    for (int e = tid; e < QH * QW; e += FNT) {
+        int r = e / QW, c = e - r * QW;
+        int i = i0 - 3 + c, j = j0 - 3 + r;
+        T vx = 0, vy = 0;
+        if (i <= n + 2 && j <= n + 2) {
+            if (in_corner(G, SC, i, j)) {
+                vx = sv(G, Q, SC, i, j, 0);
+                vy = sv(G, Q, SC, i, j, 1);
+            } else {
+                vx = vy = Q[(long)j * P + i];
+            }
+        }
+        sQ[e] = vx;
+        sQy[e] = vy;
+    }
+    __syncthreads();
+    // 2. outer fluxes of the field
+    for (int e = tid; e < (FTY + 1) * (FTX + 6); e += FNT) {
+        int r = e / (FTX + 6), c = e - r * (FTX + 6);
+        int i = i0 - 3 + c, j = j0 + r;
+        T f = 0;
+        if (i <= n + 2 && j <= n) {
+            T cr = ccr<T>(A.cry, oc, ob, (long)j * P + i, avg);
+            const T *col = sQy + r * QW + c;
+            f = ppm6(col[0], col[QW], col[2 * QW], col[3 * QW], col[4 * QW], col[5 * QW], cr);
+        }
+        sFy[e] = f;
+    }
+    for (int e = tid; e < (FTY + 6) * (FTX + 1); e += FNT) {
+        int r = e / (FTX + 1), c = e - r * (FTX + 1);
+        int i = i0 + c, j = j0 - 3 + r;
+        T f = 0;
+        if (i <= n && j <= n + 2) {
+            T cr = ccr<T>(A.crx, oc, ob, (long)j * P + i, avg);
+            const T *row = sQ + r * QW + c;
+            f = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], cr);
+        }
+        sFx[e] = f;
+    }
+    __syncthreads();
+    // 3. inner advective half updates
+    for (int e = tid; e < FTY * (FTX + 6); e += FNT) {
+        int r = e / (FTX + 6), c = e - r * (FTX + 6);
+        int i = i0 - 3 + c, j = j0 + r;
+        T v = 0;
+        if (i <= n + 2 && j < n) {
+            T ar = AR[(long)j * P + i];
+            T y0 = ccr<T>(A.yfx, oc, ob, (long)j * P + i, avg), y1 = ccr<T>(A.yfx, oc, ob, (long)(j + 1) * P + i, avg);
+            v = (sQ[(r + 3) * QW + c] * ar + y0 * sFy[r * (FTX + 6) + c] - y1 * sFy[(r + 1) * (FTX + 6) + c]) /
+                (ar + y0 - y1);
+        }
+        sQi[e] = v;
+    }
+    for (int e = tid; e < (FTY + 6) * FTX; e += FNT) {
+        int r = e / FTX, c = e - r * FTX;
+        int i = i0 + c, j = j0 - 3 + r;
+        T v = 0;
+        if (i < n && j <= n + 2) {
+            T ar = AR[(long)j * P + i];
+            T x0 = ccr<T>(A.xfx, oc, ob, (long)j * P + i, avg), x1 = ccr<T>(A.xfx, oc, ob, (long)j * P + i + 1, avg);
+            v = (sQ[r * QW + c + 3] * ar + x0 * sFx[r * (FTX + 1) + c] - x1 * sFx[r * (FTX + 1) + c + 1]) /
+                (ar + x0 - x1);
+        }
+        sQj[e] = v;
+    }
+    __syncthreads();
+    // 4. final fluxes (in place over the outer fluxes)
+    for (int e = tid; e < FTY * (FTX + 1); e += FNT) {
+        int r = e / (FTX + 1), c = e - r * (FTX + 1);
+        int i = i0 + c, j = j0 + r;
+        if (i <= n && j < n) {
+            long fi = (long)j * P + i;
+            T cr = ccr<T>(A.crx, oc, ob, fi, avg);
+            const T *row = sQi + r * (FTX + 6) + c;
+            T fx = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], cr);
+            T wgt = A.mx ? (T)A.mx[oc + fi] : ccr<T>(A.xfx, oc, ob, fi, avg);
+            int s = (r + 3) * (FTX + 1) + c;
+            T F = (T)0.5 * (fx + sFx[s]) * wgt;
+            sFx[s] = F;
+            if (c < FTX || i == n) {
+                if (A.FX) A.FX[oc + fi] = F;
+                if (A.epi == EPI_DELP) {
+                    A.mfx[oc + fi] += (double)F;
+                    A.cxa[oc + fi] += A.crx[oc + fi];
+                }
+            }
+        }
+    }
+    for (int e = tid; e < (FTY + 1) * FTX; e += FNT) {
+        int r = e / FTX, c = e - r * FTX;
+        int i = i0 + c, j = j0 + r;
+        if (i < n && j <= n) {
+            long fi = (long)j * P + i;
+            T cr = ccr<T>(A.cry, oc, ob, fi, avg);
+            const T *col = sQj + r * FTX + c;
+            T fy = ppm6(col[0], col[FTX], col[2 * FTX], col[3 * FTX], col[4 * FTX], col[5 * FTX], cr);
+            T wgt = A.my ? (T)A.my[oc + fi] : ccr<T>(A.yfx, oc, ob, fi, avg);
+            int s = r * (FTX + 6) + c + 3;
+            T F = (T)0.5 * (fy + sFy[s]) * wgt;
+            sFy[s] = F;
+            if (r < FTY || j == n) {
+                if (A.FY) A.FY[oc + fi] = F;
+                if (A.epi == EPI_DELP) {
+                    A.mfy[oc + fi] += (double)F;
+                    A.cya[oc + fi] += A.cry[oc + fi];
+                }
+            }
+        }
+    }
+    if (A.epi == EPI_FLUX) return;
+    __syncthreads();
+    // 5. flux-divergence update of the cells of the tile
+    const long oq = pidx(G, A.Lq, t, k);
+    for (int e = tid; e < FTY * FTX; e += FNT) {
+        int r = e / FTX, c = e - r * FTX;
+        int i = i0 + c, j = j0 + r;
+        if (i >= n || j >= n) continue;
+        long ci = (long)j * P + i;
+        T fw = sFx[(r + 3) * (FTX + 1) + c], fe = sFx[(r + 3) * (FTX + 1) + c + 1];
+        T fs = sFy[r * (FTX + 6) + c + 3], fn = sFy[(r + 1) * (FTX + 6) + c + 3];
+        T ar = AR[ci];
+        T qc = sQ[(r + 3) * QW + c + 3];
+        T out;
+        if (A.epi == EPI_DELP) {
+            out = qc + (fw - fe + fs - fn) / ar;
+        } else if (A.epi == EPI_MASSW) {
+            out = (qc * A.dold[oc + ci] * ar + fw - fe + fs - fn) / (A.dnew[oc + ci] * ar);
+        } else if (A.epi == EPI_ADV) {
+            T x0 = ccr<T>(A.xfx, oc, ob, ci, avg), x1 = ccr<T>(A.xfx, oc, ob, ci + 1, avg);
+            T y0 = ccr<T>(A.yfx, oc, ob, ci, avg), y1 = ccr<T>(A.yfx, oc, ob, ci + P, avg);
+            out = (qc * ar + fw - fe + fs - fn) / (ar + x0 - x1 + y0 - y1);
+        } else {
+            out = (T)(((double)qc * A.dp1[oc + ci] * (double)ar + (double)fw - (double)fe + (double)fs - (double)fn) /
+                      (A.dp2[oc + ci] * (double)ar));
+        }
+        A.qout[oq + ci] = out;
+    }
+}
+
+template <class T, class C, class M>
+static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
+{
+    static const char *names[] = {"k_fvtp_flux", "k_fvtp_delp", "k_fvtp_massw", "k_fvtp_adv", "k_fvtp_tracer"};
+    dim3 grd((unsigned)((g->n + FTX - 1) / FTX), (unsigned)((g->n + FTY - 1) / FTY), (unsigned)planes);
+    launch_named(names[a.epi], k_fvtp<T, C, M>, grd, dim3(FNT), st, g->geo, a);
 }
 
 // ====================================================================
-// d_sw (full step bdt on one level)
+// d_sw (full step bdt on one level), around the fused transport
 // ====================================================================
 // Courant numbers and area fluxes from the contravariant half-step C-grid
 // winds (partner component: four-point mean of the other C-grid wind).
-__global__ void k_dsw_courant(KARGS, Geo G, Met M, B bdt, const B *uc, const B *vc, B *ut, B *vt,
+template <class B>
+__global__ void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc, B *ut, B *vt,
                               B *crx, B *cry, B *xfx, B *yfx, int *flags)
 {
     KBEGIN(G.nz);
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
     const B *UC = uc + o, *VC = vc + o;
-    const double *dxa = MP(M_DXA), *dya = MP(M_DYA);
+    const B *dxa = MP(M, M_DXA), *dya = MP(M, M_DYA);
     bool bad = false;
     if (i >= 0 && i <= n && j >= -3 && j <= n + 2) {
-        B vb = 0.25 * (pvy(G, UC, VC, SY, i - 1, j, 0, true) + pvy(G, UC, VC, SY, i, j, 0, true) +
-                       pvy(G, UC, VC, SY, i - 1, j + 1, 0, true) + pvy(G, UC, VC, SY, i, j + 1, 0, true));
-        B su = AT(MP(M_SIN_U), i, j);
-        B uu = (AT(UC, i, j) - vb * AT(MP(M_COS_U), i, j)) / (su * su);
+        B vb = (B)0.25 * (pvy(G, UC, VC, SY, i - 1, j, 0, true) + pvy(G, UC, VC, SY, i, j, 0, true) +
+                          pvy(G, UC, VC, SY, i - 1, j + 1, 0, true) + pvy(G, UC, VC, SY, i, j + 1, 0, true));
+        B su = AT(MP(M, M_SIN_U), i, j);
+        B uu = (AT(UC, i, j) - vb * AT(MP(M, M_COS_U), i, j)) / (su * su);
         int up = uu > 0 ? i - 1 : i;
         B cr = bdt * uu / pvx(G, dxa, dya, SC, up, j, 0, false);
         AT(ut + o, i, j) = uu;
         AT(crx + o, i, j) = cr;
-        AT(xfx + o, i, j) = bdt * uu * su * AT(MP(M_DY), i, j);
-        bad |= fabs(cr) > 1.0;
+        AT(xfx + o, i, j) = bdt * uu * su * AT(MP(M, M_DY), i, j);
+        bad |= fabs((double)cr) > 1.0;
     }
     if (i >= -3 && i <= n + 2 && j >= 0 && j <= n) {
-        B ub = 0.25 * (pvx(G, UC, VC, SX, i, j - 1, 1, true) + pvx(G, UC, VC, SX, i + 1, j - 1, 1, true) +
-                       pvx(G, UC, VC, SX, i, j, 1, true) + pvx(G, UC, VC, SX, i + 1, j, 1, true));
-        B sv_ = AT(MP(M_SIN_V), i, j);
-        B vv = (AT(VC, i, j) - ub * AT(MP(M_COS_V), i, j)) / (sv_ * sv_);
+        B ub = (B)0.25 * (pvx(G, UC, VC, SX, i, j - 1, 1, true) + pvx(G, UC, VC, SX, i + 1, j - 1, 1, true) +
+                          pvx(G, UC, VC, SX, i, j, 1, true) + pvx(G, UC, VC, SX, i + 1, j, 1, true));
+        B sv_ = AT(MP(M, M_SIN_V), i, j);
+        B vv = (AT(VC, i, j) - ub * AT(MP(M, M_COS_V), i, j)) / (sv_ * sv_);
         int up = vv > 0 ? j - 1 : j;
         B cr = bdt * vv / pvy(G, dxa, dya, SC, i, up, 1, false);
         AT(vt + o, i, j) = vv;
         AT(cry + o, i, j) = cr;
-        AT(yfx + o, i, j) = bdt * vv * sv_ * AT(MP(M_DX), i, j);
-        bad |= fabs(cr) > 1.0;
+        AT(yfx + o, i, j) = bdt * vv * sv_ * AT(MP(M, M_DX), i, j);
+        bad |= fabs((double)cr) > 1.0;
     }
     if (bad) atomicOr(flags, 1);
 }
 
-// new delp from the mass fluxes; accumulate mass fluxes and Courant numbers
-__global__ void k_dsw_mass(KARGS, Geo G, Met M, const B *delp, const B *FX, const B *FY,
-                           const B *crx, const B *cry, B *dn, double *mfx, double *mfy, B *cx,
-                           B *cy)
+// absolute vorticity at cells from the D-grid circulation, and the kinetic
+// energy at corners (D-grid u upwinded along x and v along y by PPM with the
+// corner displacements of the contravariant C-grid winds)
+template <class B>
+__global__ void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, const B *u, const B *v, const B *ut,
+                           const B *vt, B *om, B *ke)
 {
     KBEGIN(G.nz);
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
-    if (i < n && j < n)
-        AT(dn + o, i, j) = AT(delp + o, i, j) +
-                           (AT(FX + o, i, j) - AT(FX + o, i + 1, j) + AT(FY + o, i, j) - AT(FY + o, i, j + 1)) /
-                               AT(MP(M_AREA), i, j);
-    if (j < n) {
-        AT(mfx + o, i, j) += (double)AT(FX + o, i, j);
-        AT(cx + o, i, j) += AT(crx + o, i, j);
-    }
-    if (i < n) {
-        AT(mfy + o, i, j) += (double)AT(FY + o, i, j);
-        AT(cy + o, i, j) += AT(cry + o, i, j);
-    }
-}
-
-// mass-weighted update of a transported cell field (pt or w)
-__global__ void k_dsw_scalar(KARGS, Geo G, Met M, const B *q, const B *delp, const B *dn,
-                             const B *GX, const B *GY, B *qn)
-{
-    KBEGIN(G.nz);
-    long o = pidx(G, G.nz, t, k);
-    B ar = AT(MP(M_AREA), i, j);
-    AT(qn + o, i, j) = (AT(q + o, i, j) * AT(delp + o, i, j) * ar + AT(GX + o, i, j) - AT(GX + o, i + 1, j) +
-                        AT(GY + o, i, j) - AT(GY + o, i, j + 1)) /
-                       (AT(dn + o, i, j) * ar);
-}
-
-// kinetic energy at corners: D-grid u upwinded along x and v along y by PPM
-// with the corner displacements of the contravariant C-grid winds
-__global__ void k_dsw_ke(KARGS, Geo G, Met M, B bdt, const B *u, const B *v, const B *ut,
-                         const B *vt, B *ke)
-{
-    KBEGIN(G.nz);
-    long o = pidx(G, G.nz, t, k);
     const B *U = u + o, *V = v + o;
-    B ub = 0.5 * bdt * (AT(ut + o, i, j - 1) + AT(ut + o, i, j));
-    B vb = 0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
-    B cu = ub / AT(MP(M_DX), ub > 0 ? i - 1 : i, j);
-    B cv = vb / AT(MP(M_DY), i, vb > 0 ? j - 1 : j);
-    B uu = ppm6(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
-    B vv = ppm6(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
-    AT(ke + o, i, j) = 0.5 * (ub * uu + vb * vv);
-}
-
-// absolute vorticity at cells from the D-grid circulation
-__global__ void k_dsw_omega(KARGS, Geo G, Met M, const B *u, const B *v, B *om)
-{
-    KBEGIN(G.nz);
-    if (in_corner(G, SC, i, j)) return;
-    long o = pidx(G, G.nz, t, k);
-    const B *U = u + o, *V = v + o;
-    const double *dx = MP(M_DX), *dy = MP(M_DY);
-    AT(om + o, i, j) = AT(MP(M_FC), i, j) + (AT(U, i, j) * AT(dx, i, j) - AT(U, i, j + 1) * AT(dx, i, j + 1) -
-                                             AT(V, i, j) * AT(dy, i, j) + AT(V, i + 1, j) * AT(dy, i + 1, j)) /
-                                                AT(MP(M_AREA), i, j);
+    const B *dx = MP(M, M_DX), *dy = MP(M, M_DY);
+    if (!in_corner(G, SC, i, j) && i <= n + 2 && j <= n + 2)
+        AT(om + o, i, j) = AT(MP(M, M_FC), i, j) + (AT(U, i, j) * AT(dx, i, j) - AT(U, i, j + 1) * AT(dx, i, j + 1) -
+                                                    AT(V, i, j) * AT(dy, i, j) + AT(V, i + 1, j) * AT(dy, i + 1, j)) /
+                                                       AT(MP(M, M_AREA), i, j);
+    if (i >= 0 && i <= n && j >= 0 && j <= n) {
+        B ub = (B)0.5 * bdt * (AT(ut + o, i, j - 1) + AT(ut + o, i, j));
+        B vb = (B)0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
+        B cu = ub / AT(dx, ub > 0 ? i - 1 : i, j);
+        B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
+        B uu = ppm6(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
+        B vv = ppm6(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
+        AT(ke + o, i, j) = (B)0.5 * (ub * uu + vb * vv);
+    }
 }
 
 // D-grid wind update from kinetic-energy differences and vorticity fluxes;
 // commit the transported delp, pt, w.
-__global__ void k_dsw_update(KARGS, Geo G, Met M, const B *ke, const B *VX, const B *VY,
+template <class B>
+__global__ void k_dsw_update(KARGS, Geo G, Mets<B> M, const B *ke, const B *VX, const B *VY,
                              const B *dn, const B *pn, const B *wn, B *u, B *v, B *delp, B *pt, B *w)
 {
     KBEGIN(G.nz);
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
     const B *KE = ke + o;
-    if (i < n) AT(u + o, i, j) = AT(u + o, i, j) + (AT(KE, i, j) - AT(KE, i + 1, j) + AT(VY + o, i, j)) / AT(MP(M_DX), i, j);
-    if (j < n) AT(v + o, i, j) = AT(v + o, i, j) + (AT(KE, i, j) - AT(KE, i, j + 1) - AT(VX + o, i, j)) / AT(MP(M_DY), i, j);
+    if (i < n) AT(u + o, i, j) = AT(u + o, i, j) + (AT(KE, i, j) - AT(KE, i + 1, j) + AT(VY + o, i, j)) / AT(MP(M, M_DX), i, j);
+    if (j < n) AT(v + o, i, j) = AT(v + o, i, j) + (AT(KE, i, j) - AT(KE, i, j + 1) - AT(VX + o, i, j)) / AT(MP(M, M_DY), i, j);
     if (i < n && j < n) {
         AT(delp + o, i, j) = AT(dn + o, i, j);
         AT(pt + o, i, j) = AT(pn + o, i, j);
@@ -773,8 +906,8 @@ __global__ void k_dsw_update(KARGS, Geo G, Met M, const B *ke, const B *VX, cons
 }
 
 // ====================================================================
-// dz_d: interface heights transported by fv_tp_2d with layer-averaged
-// Courant numbers and area fluxes, advective form, surface fixed.
+// dz_d: interface heights transported by fv_tp_2d (EPI_ADV, interface
+// averaged Courant numbers), surface fixed.
 // ====================================================================
 __global__ void k_heights(KARGS, Geo G, const double *delz, const double *phis, double *zh)
 {
@@ -792,35 +925,6 @@ __global__ void k_heights(KARGS, Geo G, const double *delz, const double *phis, 
     }
 }
 
-__global__ void k_iface_flux(KARGS, Geo G, const B *crx, const B *cry, const B *xfx,
-                             const B *yfx, B *cxI, B *cyI, B *xI, B *yI)
-{
-    KBEGIN(G.nz);
-    long o = pidx(G, G.nz, t, k), ob = pidx(G, G.nz, t, k > 0 ? k - 1 : 0);
-    long c = (long)j * G.pitch + i;
-    if (k == 0) {
-        cxI[o + c] = crx[o + c]; cyI[o + c] = cry[o + c]; xI[o + c] = xfx[o + c]; yI[o + c] = yfx[o + c];
-    } else {
-        cxI[o + c] = 0.5 * (crx[ob + c] + crx[o + c]);
-        cyI[o + c] = 0.5 * (cry[ob + c] + cry[o + c]);
-        xI[o + c] = 0.5 * (xfx[ob + c] + xfx[o + c]);
-        yI[o + c] = 0.5 * (yfx[ob + c] + yfx[o + c]);
-    }
-}
-
-__global__ void k_zh_update(KARGS, Geo G, Met M, const double *zh, const double *ZX,
-                            const double *ZY, const B *xI, const B *yI, double *zn)
-{
-    KBEGIN(G.nz);
-    int nz = G.nz;
-    long oq = pidx(G, nz + 1, t, k), oc = pidx(G, nz, t, k);
-    double ar = AT(MP(M_AREA), i, j);
-    AT(zn + oq, i, j) = (AT(zh + oq, i, j) * ar + AT(ZX + oc, i, j) - AT(ZX + oc, i + 1, j) + AT(ZY + oc, i, j) -
-                         AT(ZY + oc, i, j + 1)) /
-                        (ar + (double)AT(xI + oc, i, j) - (double)AT(xI + oc, i + 1, j) +
-                         (double)AT(yI + oc, i, j) - (double)AT(yI + oc, i, j + 1));
-}
-
 __global__ void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phis, double *delz)
 {
     KBEGIN(G.nz);
@@ -833,53 +937,86 @@ __global__ void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phi
 // ====================================================================
 // nh_p_grad: corner values by the fourth-order (-1,7,7,-1)/12 tensor
 // interpolation (inner pass along x with the x-sweep corner view; mean of
-// the three cells at a cube vertex) and the finite-volume pressure gradient
-// along each D-grid edge.
+// the three cells at a cube vertex) of pfull and phi at the layer's two
+// interfaces and of delp, staged through LDS, then the finite-volume
+// pressure gradient along each D-grid edge.  Block: 64 x 4 corners.
 // ====================================================================
-template <class T>
-__global__ void k_corner_interp(KARGS, Geo G, int L, const T *q, double *qB)
+constexpr int NPX = 64, NPY = 4;
+constexpr int NCW = NPX + 5, NCH = NPY + 5;   // cells i0-2..i0+NPX+2, j0-2..j0+NPY+2
+
+template <class B>
+__global__ void __launch_bounds__(256) k_nhpgrad(Geo G, MetD M, double bdt, const double *pfull,
+                                                 const double *phi, const B *delp, B *u, B *v)
 {
-    KBEGIN(L);
-    long o = pidx(G, L, t, k);
-    const T *Q = q + o;
-    double r;
-    if (is_vertex(G, i, j)) {
-        double s = 0.0;
-        int ci[4] = {i - 1, i, i, i - 1}, cj[4] = {j - 1, j - 1, j, j};
-        for (int c = 0; c < 4; c++)
-            if (!in_corner(G, SC, ci[c], cj[c])) s += (double)AT(Q, ci[c], cj[c]);
-        r = s / 3.0;
-    } else {
-        const double w4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
-        r = 0.0;
-        for (int b = 0; b < 4; b++) {
-            double row = 0.0;
-            for (int a = 0; a < 4; a++) row += w4[a] * (double)sv(G, Q, SC, i + a - 2, j + b - 2, 0);
-            r += w4[b] * row;
+    __shared__ double sc[5][NCH * NCW];               // p0, p1, z0, z1, d at cells (x-sweep view)
+    __shared__ double sb[5][(NPY + 1) * (NPX + 1)];   // corner values
+    const int n = G.n, nz = G.nz, tid = threadIdx.x;
+    const int i0 = blockIdx.x * NPX, j0 = blockIdx.y * NPY;
+    const int t = blockIdx.z / nz, k = blockIdx.z % nz;
+    const double *F[4] = {pfull + pidx(G, nz + 1, t, k), pfull + pidx(G, nz + 1, t, k + 1),
+                          phi + pidx(G, nz + 1, t, k), phi + pidx(G, nz + 1, t, k + 1)};
+    const B *D = delp + pidx(G, nz, t, k);
+    for (int e = tid; e < NCH * NCW; e += 256) {
+        int r = e / NCW, c = e - r * NCW;
+        int i = i0 - 2 + c, j = j0 - 2 + r;
+        bool ok = i <= n + 2 && j <= n + 2;
+        for (int f = 0; f < 4; f++) sc[f][e] = ok ? sv(G, F[f], SC, i, j, 0) : 0.0;
+        sc[4][e] = ok ? (double)sv(G, D, SC, i, j, 0) : 0.0;
+    }
+    __syncthreads();
+    const double w4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
+    for (int e = tid; e < (NPY + 1) * (NPX + 1); e += 256) {
+        int r = e / (NPX + 1), c = e - r * (NPX + 1);
+        int i = i0 + c, j = j0 + r;
+        if (i > n || j > n) continue;
+        if (is_vertex(G, i, j)) {
+            int ci[4] = {i - 1, i, i, i - 1}, cj[4] = {j - 1, j - 1, j, j};
+            for (int f = 0; f < 5; f++) {
+                double s = 0.0;
+                for (int q = 0; q < 4; q++)
+                    if (!in_corner(G, SC, ci[q], cj[q])) s += sc[f][(cj[q] - j0 + 2) * NCW + (ci[q] - i0 + 2)];
+                sb[f][e] = s / 3.0;
+            }
+        } else {
+            for (int f = 0; f < 5; f++) {
+                double acc = 0.0;
+                for (int b = 0; b < 4; b++) {
+                    const double *row = &sc[f][(r + b) * NCW + c];
+                    double rw = 0.0;
+                    for (int a = 0; a < 4; a++) rw += w4[a] * row[a];
+                    acc += w4[b] * rw;
+                }
+                sb[f][e] = acc;
+            }
         }
     }
-    AT(qB + o, i, j) = r;
-}
-
-__global__ void k_nhpgrad(KARGS, Geo G, Met M, double bdt, const double *pB, const double *zB,
-                          const double *dB, B *u, B *v)
-{
-    KBEGIN(G.nz);
-    int n = G.n, nz = G.nz;
-    long o = pidx(G, nz, t, k), o0 = pidx(G, nz + 1, t, k), o1 = pidx(G, nz + 1, t, k + 1);
-    const double *P0 = pB + o0, *P1 = pB + o1, *Z0 = zB + o0, *Z1 = zB + o1, *D = dB + o;
-    if (i < n)
-        AT(u + o, i, j) += (B)pgf(bdt, AT(MP(M_DX), i, j), AT(D, i, j), AT(D, i + 1, j), AT(Z0, i, j), AT(Z1, i, j),
-                                  AT(Z0, i + 1, j), AT(Z1, i + 1, j), AT(P0, i, j), AT(P1, i, j), AT(P0, i + 1, j),
-                                  AT(P1, i + 1, j));
-    if (j < n)
-        AT(v + o, i, j) += (B)pgf(bdt, AT(MP(M_DY), i, j), AT(D, i, j), AT(D, i, j + 1), AT(Z0, i, j), AT(Z1, i, j),
-                                  AT(Z0, i, j + 1), AT(Z1, i, j + 1), AT(P0, i, j), AT(P1, i, j), AT(P0, i, j + 1),
-                                  AT(P1, i, j + 1));
+    __syncthreads();
+    const long o = pidx(G, nz, t, k);
+    // Each block owns the faces of its NPX x NPY corner rows/columns: the grid
+    // spans corners 0..n, so a face row or column on a block boundary is
+    // updated by exactly one block.
+    // u on y-faces (i, j): corners (i, j) -> (i + 1, j)
+    for (int e = tid; e < NPY * NPX; e += 256) {
+        int r = e / NPX, c = e - r * NPX;
+        int i = i0 + c, j = j0 + r;
+        if (i >= n || j > n) continue;
+        int W = r * (NPX + 1) + c, E = W + 1;
+        AT(u + o, i, j) += (B)pgf(bdt, AT(MP(M, M_DX), i, j), sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
+                                  sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+    }
+    // v on x-faces (i, j): corners (i, j) -> (i, j + 1)
+    for (int e = tid; e < NPY * NPX; e += 256) {
+        int r = e / NPX, c = e - r * NPX;
+        int i = i0 + c, j = j0 + r;
+        if (i > n || j >= n) continue;
+        int W = r * (NPX + 1) + c, E = W + (NPX + 1);
+        AT(v + o, i, j) += (B)pgf(bdt, AT(MP(M, M_DY), i, j), sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
+                                  sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+    }
 }
 
 // ====================================================================
-// utilities: fills, copies, finiteness check, tracer helpers
+// utilities: fills, copies, finiteness check, tracer helpers, reductions
 // ====================================================================
 template <class T>
 __global__ void k_fill(T *p, long count, T val)
@@ -896,12 +1033,12 @@ __global__ void k_copy(const TS *s, TD *d, long count)
 template <class T>
 static void fill(T *p, long count, T val, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, val);
+    launch_named("k_fill", k_fill<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), st, p, count, val);
 }
 template <class TS, class TD>
 static void copy(const TS *s, TD *d, long count, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_copy<TS, TD>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, s, d, count);
+    launch_named("k_copy", k_copy<TS, TD>, dim3((unsigned)((count + 255) / 256)), dim3(256), st, s, d, count);
 }
 
 template <class T>
@@ -912,66 +1049,72 @@ __global__ void k_check_finite(KARGS, Geo G, int L, const T *f, int *flags)
 }
 
 // tracer: area fluxes from the accumulated Courant numbers, scaled by 1/nsplt
-__global__ void k_tracer_flux(KARGS, Geo G, Met M, double rs, const B *cx, const B *cy,
+template <class B>
+__global__ void k_tracer_flux(KARGS, Geo G, MetD M, double rs, const B *cx, const B *cy,
                               const double *mfx, const double *mfy, B *crs, B *crys, B *xfx,
                               B *yfx, double *mxs, double *mys)
 {
     KBEGIN(G.nz);
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
-    const double *dxa = MP(M_DXA), *dya = MP(M_DYA);
+    const double *dxa = MP(M, M_DXA), *dya = MP(M, M_DYA);
     if (i >= 0 && i <= n && j >= -3 && j <= n + 2) {
-        B c = AT(cx + o, i, j);
+        double c = (double)AT(cx + o, i, j);
         int up = c > 0 ? i - 1 : i;
-        AT(xfx + o, i, j) = (B)(c * pvx(G, dxa, dya, SC, up, j, 0, false) * AT(MP(M_DY), i, j) * AT(MP(M_SIN_U), i, j) / rs);
+        AT(xfx + o, i, j) = (B)(c * pvx(G, dxa, dya, SC, up, j, 0, false) * AT(MP(M, M_DY), i, j) *
+                                AT(MP(M, M_SIN_U), i, j) / rs);
         AT(crs + o, i, j) = (B)(c / rs);
         AT(mxs + o, i, j) = AT(mfx + o, i, j) / rs;
     }
     if (i >= -3 && i <= n + 2 && j >= 0 && j <= n) {
-        B c = AT(cy + o, i, j);
+        double c = (double)AT(cy + o, i, j);
         int up = c > 0 ? j - 1 : j;
-        AT(yfx + o, i, j) = (B)(c * pvy(G, dxa, dya, SC, i, up, 1, false) * AT(MP(M_DX), i, j) * AT(MP(M_SIN_V), i, j) / rs);
+        AT(yfx + o, i, j) = (B)(c * pvy(G, dxa, dya, SC, i, up, 1, false) * AT(MP(M, M_DX), i, j) *
+                                AT(MP(M, M_SIN_V), i, j) / rs);
         AT(crys + o, i, j) = (B)(c / rs);
         AT(mys + o, i, j) = AT(mfy + o, i, j) / rs;
     }
 }
 
-__global__ void k_tracer_dp(KARGS, Geo G, Met M, const double *dp1, const double *mxs,
+__global__ void k_tracer_dp(KARGS, Geo G, MetD M, const double *dp1, const double *mxs,
                             const double *mys, double *dp2)
 {
     KBEGIN(G.nz);
     long o = pidx(G, G.nz, t, k);
     AT(dp2 + o, i, j) = AT(dp1 + o, i, j) + (AT(mxs + o, i, j) - AT(mxs + o, i + 1, j) + AT(mys + o, i, j) -
                                              AT(mys + o, i, j + 1)) /
-                                                AT(MP(M_AREA), i, j);
+                                                AT(MP(M, M_AREA), i, j);
 }
 
-__global__ void k_tracer_update(KARGS, Geo G, Met M, const double *dp1, const double *dp2,
-                                const B *FX, const B *FY, B *q)
-{
-    KBEGIN(G.nz);
-    long o = pidx(G, G.nz, t, k);
-    double a = AT(MP(M_AREA), i, j);
-    AT(q + o, i, j) = (B)(((double)AT(q + o, i, j) * AT(dp1 + o, i, j) * a + (double)AT(FX + o, i, j) -
-                           (double)AT(FX + o, i + 1, j) + (double)AT(FY + o, i, j) - (double)AT(FY + o, i, j + 1)) /
-                          (AT(dp2 + o, i, j) * a));
-}
-
+// max |cx|, |cy| over the interior faces: block maximum, one atomic per block
+template <class B>
 __global__ void k_absmax(KARGS, Geo G, const B *cx, const B *cy, unsigned long long *out)
 {
-    KBEGIN(G.nz);
-    int n = G.n;
-    long o = pidx(G, G.nz, t, k);
+    __shared__ double sm[256];
+    int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);
     double m = 0.0;
-    if (j < n) m = fmax(m, fabs((double)AT(cx + o, i, j)));
-    if (i < n) m = fmax(m, fabs((double)AT(cy + o, i, j)));
+    if (i <= ihi && j <= jhi) {
+        int n = G.n;
+        int t = (int)blockIdx.z / G.nz, k = (int)blockIdx.z % G.nz;
+        long o = pidx(G, G.nz, t, k);
+        if (j < n) m = fmax(m, fabs((double)AT(cx + o, i, j)));
+        if (i < n) m = fmax(m, fabs((double)AT(cy + o, i, j)));
+    }
+    sm[tid] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) sm[tid] = fmax(sm[tid], sm[tid + w]);
+        __syncthreads();
+    }
     // non-negative doubles order like their bit patterns
-    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+    if (tid == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
 // Neumaier-compensated sums: each thread sums its column over levels in a
-// fixed order, then the block reduces pairs (s, c) exactly as Neumaier
-// additions, one partial per block; the host adds the partials in order.
+// fixed order, then the block combines pairs (s, c) with Neumaier additions,
+// one partial per block; the host adds the partials in order.
 DEVI void neu_add(double &s, double &c, double x)
 {
     double t = s + x;
@@ -980,7 +1123,8 @@ DEVI void neu_add(double &s, double &c, double x)
     s = t;
 }
 
-__global__ void k_mass_partial(KARGS, Geo G, Met M, const B *delp, const B *pt, const B *q,
+template <class B>
+__global__ void k_mass_partial(KARGS, Geo G, MetD M, const B *delp, const B *pt, const B *q,
                                int which, double *part)
 {
     __shared__ double ss[256], sc[256];
@@ -990,7 +1134,7 @@ __global__ void k_mass_partial(KARGS, Geo G, Met M, const B *delp, const B *pt, 
     int t = blockIdx.z;
     double s = 0.0, c = 0.0;
     if (i <= ihi && j <= jhi) {
-        double ar = AT(MP(M_AREA), i, j);
+        double ar = AT(MP(M, M_AREA), i, j);
         for (int k = 0; k < G.nz; k++) {
             long o = pidx(G, G.nz, t, k);
             double m = (double)AT(delp + o, i, j) * ar;
@@ -1020,26 +1164,26 @@ __global__ void k_mass_partial(KARGS, Geo G, Met M, const B *delp, const B *pt, 
 // ====================================================================
 // Workspace carve-up
 // ====================================================================
+template <class B>
 struct Work {
     // bulk layer fields
     B *ua, *va, *ucp, *vcp, *ax, *ay, *Fm, *Fp, *Fw, *Gm, *Gp, *Gw, *delpc, *ptc, *wc, *ke, *vort;
-    B *ut, *vt, *crx, *cry, *xfx, *yfx, *FX, *FY, *GX, *GY, *WX, *WY, *dn, *pn, *wn, *om, *VX, *VY;
-    B *cxI, *cyI, *xI, *yI, *tfx2, *tfy2, *tqi, *tqj;
+    B *ut, *vt, *crx, *cry, *xfx, *yfx, *FX, *FY, *VX, *VY, *dn, *pn, *wn, *om, *qo;
     // FP64 fields
-    double *pkc, *gz, *delzc, *zh, *zn, *ZX, *ZY, *s1, *s2, *s3, *pB, *zB, *dB;
-    double *zfx2, *zfy2, *zqi, *zqj, *dp1, *dp2, *mxs, *mys;
+    double *delzc, *s1, *s2, *s3, *dp1, *dp2, *mxs, *mys;
+    double *pkc, *gz, *zh, *zn;   // interfaces
     unsigned long long *umax;
     double *part;
 };
 
-long reduction_elems(const fv3_grid *g);
 static long part_count(const fv3_grid *g)
 {
     long bx = (g->n + 63) / 64, by = (g->n + 3) / 4;
     return bx * by * g->T;
 }
 
-static size_t carve(const fv3_grid *g, char *base, Work *w)
+template <class B>
+static size_t carve(const fv3_grid *g, char *base, Work<B> *w)
 {
     long el = alloc_elems(g, g->nz), ei = alloc_elems(g, g->nz + 1);
     size_t off = 0;
@@ -1051,14 +1195,12 @@ static size_t carve(const fv3_grid *g, char *base, Work *w)
     };
     B **bulk[] = {&w->ua, &w->va, &w->ucp, &w->vcp, &w->ax, &w->ay, &w->Fm, &w->Fp, &w->Fw, &w->Gm,
                   &w->Gp, &w->Gw, &w->delpc, &w->ptc, &w->wc, &w->ke, &w->vort, &w->ut, &w->vt,
-                  &w->crx, &w->cry, &w->xfx, &w->yfx, &w->FX, &w->FY, &w->GX, &w->GY, &w->WX,
-                  &w->WY, &w->dn, &w->pn, &w->wn, &w->om, &w->VX, &w->VY, &w->cxI, &w->cyI,
-                  &w->xI, &w->yI, &w->tfx2, &w->tfy2, &w->tqi, &w->tqj};
+                  &w->crx, &w->cry, &w->xfx, &w->yfx, &w->FX, &w->FY, &w->VX, &w->VY, &w->dn,
+                  &w->pn, &w->wn, &w->om, &w->qo};
     for (auto p : bulk) *p = (B *)take(el * sizeof(B));
-    double **f64[] = {&w->delzc, &w->ZX, &w->ZY, &w->s1, &w->s2, &w->s3, &w->dB, &w->zfx2,
-                      &w->zfy2, &w->zqi, &w->zqj, &w->dp1, &w->dp2, &w->mxs, &w->mys};
+    double **f64[] = {&w->delzc, &w->s1, &w->s2, &w->s3, &w->dp1, &w->dp2, &w->mxs, &w->mys};
     for (auto p : f64) *p = (double *)take(el * sizeof(double));
-    double **f64i[] = {&w->pkc, &w->gz, &w->zh, &w->zn, &w->pB, &w->zB};
+    double **f64i[] = {&w->pkc, &w->gz, &w->zh, &w->zn};
     for (auto p : f64i) *p = (double *)take(ei * sizeof(double));
     w->umax = (unsigned long long *)take(64);
     w->part = (double *)take(2 * part_count(g) * sizeof(double));
@@ -1112,27 +1254,43 @@ int timing_stop(char *names, int names_cap, double *total_ms, long *counts, int 
 
 size_t workspace_bytes(const fv3_grid *g)
 {
-    Work w;
+    if (g->bulk_bytes == 4) {
+        Work<float> w;
+        return carve(g, nullptr, &w);
+    }
+    Work<double> w;
     return carve(g, nullptr, &w);
 }
 
-static Met metrics(const fv3_grid *g)
+template <class B>
+static Mets<B> metrics_b(const fv3_grid *g);
+template <>
+Mets<double> metrics_b<double>(const fv3_grid *g)
 {
-    Met M;
+    Mets<double> M;
     for (int m = 0; m < M_COUNT; m++) M.m[m] = g->met[m];
     return M;
 }
+template <>
+Mets<float> metrics_b<float>(const fv3_grid *g)
+{
+    Mets<float> M;
+    for (int m = 0; m < M_COUNT; m++) M.m[m] = g->metf[m];
+    return M;
+}
+static MetD metrics_d(const fv3_grid *g) { return metrics_b<double>(g); }
 
 // ====================================================================
 // Host orchestration of one call
 // ====================================================================
-fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
-                        hipStream_t st)
+template <class B>
+static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
+                             hipStream_t st)
 {
-    if (g->bulk_bytes != (int)sizeof(B)) return FV3_EUNSUPPORTED;
-    Work W;
+    Work<B> W;
     carve(g, (char *)s->workspace, &W);
-    Met M = metrics(g);
+    Mets<B> M = metrics_b<B>(g);
+    MetD Md = metrics_d(g);
     const Geo &G = g->geo;
     int n = g->n, nz = g->nz, T = g->T, P = T * nz;
     long el = alloc_elems(g, nz);
@@ -1141,14 +1299,13 @@ fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split,
     double *delz = s->delz;
     const double *phis = s->phis;
     double bdt = dt / n_split, dt2 = 0.5 * bdt;
+    const B *areaB = M.m[M_AREA];
 
     fill(s->mfx, el, 0.0, st);
     fill(s->mfy, el, 0.0, st);
     fill(cx, el, (B)0, st);
     fill(cy, el, (B)0, st);
     copy(delp, s->dp0, el, st);
-    FvTmp tb{W.tfx2, W.tfy2, W.tqi, W.tqj};
-    FvTmp tz{W.zfx2, W.zfy2, W.zqi, W.zqj};
 
     for (int it = 0; it < n_split; it++) {
         bool last = it == n_split - 1;
@@ -1161,65 +1318,70 @@ fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split,
         halo_scalar(g, delz, nz, st);
         STOP(1);
         // c_sw
-        launch2d(k_csw_agrid, -3, n + 2, -3, n + 2, P, st, G, (const B *)u, (const B *)v, W.ua, W.va);
-        launch2d(k_csw_faces, -1, n + 1, -1, n + 1, P, st, G, M, (B)dt2, (const B *)u, (const B *)v,
+        launch2d(k_csw_agrid<B>, -3, n + 2, -3, n + 2, P, st, G, (const B *)u, (const B *)v, W.ua, W.va);
+        launch2d(k_csw_faces<B>, -1, n + 1, -1, n + 1, P, st, G, M, (B)dt2, (const B *)u, (const B *)v,
                  (const B *)delp, (const B *)pt, (const B *)w, (const B *)W.ua, (const B *)W.va, W.ucp, W.vcp,
                  W.ax, W.ay, W.Fm, W.Fp, W.Fw, W.Gm, W.Gp, W.Gw);
-        launch2d(k_csw_cells, -1, n, -1, n, P, st, G, M, (B)dt2, (const B *)delp, (const B *)pt, (const B *)w,
+        launch2d(k_csw_cells<B>, -1, n, -1, n, P, st, G, M, (B)dt2, (const B *)delp, (const B *)pt, (const B *)w,
                  (const B *)W.ua, (const B *)W.va, (const B *)W.ucp, (const B *)W.vcp, (const B *)W.Fm,
                  (const B *)W.Fp, (const B *)W.Fw, (const B *)W.Gm, (const B *)W.Gp, (const B *)W.Gw, W.delpc,
                  W.ptc, W.wc, W.ke, W.vort);
-        launch2d(k_csw_update, 0, n, 0, n, P, st, G, M, (B)dt2, (const B *)u, (const B *)v, (const B *)W.ucp,
+        launch2d(k_csw_update<B>, 0, n, 0, n, P, st, G, M, (B)dt2, (const B *)u, (const B *)v, (const B *)W.ucp,
                  (const B *)W.vcp, (const B *)W.ke, (const B *)W.vort, uc, vc);
         STOP(2);
         // dz_c + riem_solver_c on the half-step cells
-        launch2d(k_dzc, -1, n, -1, n, T, st, G, M, (const double *)delz, phis, (const B *)W.ax, (const B *)W.ay,
-                 W.delzc);
-        launch2d(k_sim1<B>, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc, (const B *)W.ptc,
-                 (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
-                 (double *)nullptr, W.pkc, W.gz, 1);
+        launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
+                 (const B *)W.ay, W.delzc);
+        launch2d_named("k_sim1_c", k_sim1<B, B>, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         STOP(3);
-        launch2d(k_pgradc, 0, n, 0, n, P, st, G, M, dt2, (const B *)W.delpc, (const double *)W.pkc,
+        launch2d(k_pgradc<B>, 0, n, 0, n, P, st, G, Md, dt2, (const B *)W.delpc, (const double *)W.pkc,
                  (const double *)W.gz, uc, vc);
         STOP(4);
         halo_pair(g, g->planCv, uc, vc, nz, st);
         STOP(5);
         // d_sw
-        launch2d(k_dsw_courant, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (const B *)uc, (const B *)vc, W.ut,
+        launch2d(k_dsw_courant<B>, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (const B *)uc, (const B *)vc, W.ut,
                  W.vt, W.crx, W.cry, W.xfx, W.yfx, g->flags);
-        fv_tp_2d<B, B>(g, M, nz, nz, P, delp, W.crx, W.cry, W.xfx, W.yfx, (const B *)nullptr,
-                       (const B *)nullptr, W.FX, W.FY, tb, st);
-        launch2d(k_dsw_mass, 0, n, 0, n, P, st, G, M, (const B *)delp, (const B *)W.FX, (const B *)W.FY,
-                 (const B *)W.crx, (const B *)W.cry, W.dn, s->mfx, s->mfy, cx, cy);
-        fv_tp_2d<B, B>(g, M, nz, nz, P, pt, W.crx, W.cry, W.xfx, W.yfx, (const B *)W.FX, (const B *)W.FY, W.GX,
-                       W.GY, tb, st);
-        launch2d(k_dsw_scalar, 0, n - 1, 0, n - 1, P, st, G, M, (const B *)pt, (const B *)delp, (const B *)W.dn,
-                 (const B *)W.GX, (const B *)W.GY, W.pn);
-        fv_tp_2d<B, B>(g, M, nz, nz, P, w, W.crx, W.cry, W.xfx, W.yfx, (const B *)W.FX, (const B *)W.FY, W.WX,
-                       W.WY, tb, st);
-        launch2d(k_dsw_scalar, 0, n - 1, 0, n - 1, P, st, G, M, (const B *)w, (const B *)delp, (const B *)W.dn,
-                 (const B *)W.WX, (const B *)W.WY, W.wn);
-        launch2d(k_dsw_ke, 0, n, 0, n, P, st, G, M, (B)bdt, (const B *)u, (const B *)v, (const B *)W.ut,
-                 (const B *)W.vt, W.ke);
-        launch2d(k_dsw_omega, -3, n + 2, -3, n + 2, P, st, G, M, (const B *)u, (const B *)v, W.om);
-        fv_tp_2d<B, B>(g, M, nz, nz, P, W.om, W.crx, W.cry, W.xfx, W.yfx, (const B *)nullptr, (const B *)nullptr,
-                       W.VX, W.VY, tb, st);
-        launch2d(k_dsw_update, 0, n, 0, n, P, st, G, M, (const B *)W.ke, (const B *)W.VX, (const B *)W.VY,
+        {
+            FvArgs<B, B, B> a{};
+            a.q = delp; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx;
+            a.Lc = nz; a.area = areaB; a.epi = EPI_DELP; a.FX = W.FX; a.FY = W.FY; a.qout = W.dn;
+            a.mfx = s->mfx; a.mfy = s->mfy; a.cxa = cx; a.cya = cy;
+            fvtp(g, P, a, st);
+            FvArgs<B, B, B> b{};
+            b.q = pt; b.Lq = nz; b.crx = W.crx; b.cry = W.cry; b.xfx = W.xfx; b.yfx = W.yfx; b.Lc = nz;
+            b.mx = W.FX; b.my = W.FY; b.area = areaB; b.epi = EPI_MASSW; b.qout = W.pn; b.dold = delp; b.dnew = W.dn;
+            fvtp(g, P, b, st);
+            b.q = w; b.qout = W.wn;
+            fvtp(g, P, b, st);
+        }
+        launch2d(k_dsw_omke<B>, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (const B *)u, (const B *)v,
+                 (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
+        {
+            FvArgs<B, B, B> a{};
+            a.q = W.om; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
+            a.area = areaB; a.epi = EPI_FLUX; a.FX = W.VX; a.FY = W.VY;
+            fvtp(g, P, a, st);
+        }
+        launch2d(k_dsw_update<B>, 0, n, 0, n, P, st, G, M, (const B *)W.ke, (const B *)W.VX, (const B *)W.VY,
                  (const B *)W.dn, (const B *)W.pn, (const B *)W.wn, u, v, delp, pt, w);
         STOP(6);
         // dz_d
         launch2d(k_heights, -3, n + 2, -3, n + 2, T, st, G, (const double *)delz, phis, W.zh);
-        launch2d(k_iface_flux, -3, n + 3, -3, n + 3, P, st, G, (const B *)W.crx, (const B *)W.cry,
-                 (const B *)W.xfx, (const B *)W.yfx, W.cxI, W.cyI, W.xI, W.yI);
-        fv_tp_2d<double, double>(g, M, nz + 1, nz, P, W.zh, W.cxI, W.cyI, W.xI, W.yI, (const double *)nullptr,
-                                 (const double *)nullptr, W.ZX, W.ZY, tz, st);
-        launch2d(k_zh_update, 0, n - 1, 0, n - 1, P, st, G, M, (const double *)W.zh, (const double *)W.ZX,
-                 (const double *)W.ZY, (const B *)W.xI, (const B *)W.yI, W.zn);
+        {
+            FvArgs<double, B, double> a{};
+            a.q = W.zh; a.Lq = nz + 1; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
+            a.iface = 1; a.area = Md.m[M_AREA]; a.epi = EPI_ADV; a.qout = W.zn;
+            fvtp(g, P, a, st);
+        }
         launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         STOP(7);
         // riem_solver3
-        launch2d(k_sim1<B>, 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp, (const B *)pt,
-                 (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz, s->pfull, s->phi, 0);
+        launch2d_named("k_sim1_3", k_sim1<B, B>, 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       s->pfull, s->phi, 0);
         STOP(8);
         // H-C
         halo_scalar(g, s->pfull, nz + 1, st);
@@ -1227,11 +1389,8 @@ fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split,
         halo_scalar(g, delp, nz, st);
         STOP(9);
         // nh_p_grad
-        launch2d(k_corner_interp<double>, 0, n, 0, n, T * (nz + 1), st, G, nz + 1, (const double *)s->pfull, W.pB);
-        launch2d(k_corner_interp<double>, 0, n, 0, n, T * (nz + 1), st, G, nz + 1, (const double *)s->phi, W.zB);
-        launch2d(k_corner_interp<B>, 0, n, 0, n, P, st, G, nz, (const B *)delp, W.dB);
-        launch2d(k_nhpgrad, 0, n, 0, n, P, st, G, M, bdt, (const double *)W.pB, (const double *)W.zB,
-                 (const double *)W.dB, u, v);
+        launch_named("k_nhpgrad", k_nhpgrad<B>, dim3((n + NPX) / NPX, (n + NPY) / NPY, P), dim3(256), st, G, Md,
+                     bdt, (const double *)s->pfull, (const double *)s->phi, (const B *)delp, u, v);
 #undef STOP
     }
 done:
@@ -1244,31 +1403,47 @@ done:
     return FV3_OK;
 }
 
+fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
+                        hipStream_t st)
+{
+    if (g->bulk_bytes == 4) return substeps_t<float>(s, g, dt, n_split, stop_stage, st);
+    return substeps_t<double>(s, g, dt, n_split, stop_stage, st);
+}
+
 fv3_status run_halo_cells(const fv3_grid *g, void *const *f, int nf, int levels, int fp64,
                           hipStream_t st)
 {
     for (int q = 0; q < nf; q++) {
-        if (fp64 || sizeof(B) == 8) halo_scalar(g, (double *)f[q], levels, st);
+        if (fp64 || g->bulk_bytes == 8) halo_scalar(g, (double *)f[q], levels, st);
+        else halo_scalar(g, (float *)f[q], levels, st);
     }
     return hipGetLastError() == hipSuccess ? FV3_OK : FV3_EDEVICE;
 }
 
-fv3_status run_tracer(void *const *q, int nq, fv3_state *s, const fv3_grid *g, int nsplt,
-                      hipStream_t st)
+fv3_status run_halo_pair_cells(const fv3_grid *g, void *fx, void *fy, int levels, int fp64,
+                               hipStream_t st)
 {
-    if (g->bulk_bytes != (int)sizeof(B)) return FV3_EUNSUPPORTED;
-    Work W;
+    if (fp64 || g->bulk_bytes == 8) halo_pair(g, g->planA, (double *)fx, (double *)fy, levels, st);
+    else halo_pair(g, g->planA, (float *)fx, (float *)fy, levels, st);
+    return hipGetLastError() == hipSuccess ? FV3_OK : FV3_EDEVICE;
+}
+
+template <class B>
+static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid *g, int nsplt, hipStream_t st)
+{
+    Work<B> W;
     carve(g, (char *)s->workspace, &W);
-    Met M = metrics(g);
+    Mets<B> M = metrics_b<B>(g);
+    MetD Md = metrics_d(g);
     const Geo &G = g->geo;
-    int n = g->n, nz = g->nz, T = g->T, P = T * nz;
+    int n = g->n, nz = g->nz, P = g->T * nz;
     long el = alloc_elems(g, nz);
     B *cx = (B *)s->cx, *cy = (B *)s->cy;
     halo_pair(g, g->planCv, cx, cy, nz, st);
     if (nsplt <= 0) {
         unsigned long long zero = 0, h = 0;
         fill(W.umax, 1, zero, st);
-        launch2d(k_absmax, 0, n, 0, n, P, st, G, (const B *)cx, (const B *)cy, W.umax);
+        launch2d(k_absmax<B>, 0, n, 0, n, P, st, G, (const B *)cx, (const B *)cy, W.umax);
         if (hipMemcpyAsync(&h, W.umax, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return FV3_EDEVICE;
         if (hipStreamSynchronize(st) != hipSuccess) return FV3_EDEVICE;
         double cmax;
@@ -1277,34 +1452,43 @@ fv3_status run_tracer(void *const *q, int nq, fv3_state *s, const fv3_grid *g, i
         if (nsplt < 1) nsplt = 1;
     }
     double rs = (double)nsplt;
-    launch2d(k_tracer_flux, -3, n + 3, -3, n + 3, P, st, G, M, rs, (const B *)cx, (const B *)cy,
+    launch2d(k_tracer_flux<B>, -3, n + 3, -3, n + 3, P, st, G, Md, rs, (const B *)cx, (const B *)cy,
              (const double *)s->mfx, (const double *)s->mfy, W.crx, W.cry, W.xfx, W.yfx, W.mxs, W.mys);
     copy(s->dp0, W.dp1, el, st);
     double *dp1 = W.dp1, *dp2 = W.dp2;
-    FvTmp tb{W.tfx2, W.tfy2, W.tqi, W.tqj};
     for (int itr = 0; itr < nsplt; itr++) {
-        launch2d(k_tracer_dp, 0, n - 1, 0, n - 1, P, st, G, M, (const double *)dp1, (const double *)W.mxs,
+        launch2d(k_tracer_dp, 0, n - 1, 0, n - 1, P, st, G, Md, (const double *)dp1, (const double *)W.mxs,
                  (const double *)W.mys, dp2);
         for (int m = 0; m < nq; m++) {
             B *Q = (B *)q[m];
             halo_scalar(g, Q, nz, st);
-            fv_tp_2d<B, double>(g, M, nz, nz, P, Q, W.crx, W.cry, W.xfx, W.yfx, (const double *)W.mxs,
-                                (const double *)W.mys, W.FX, W.FY, tb, st);
-            launch2d(k_tracer_update, 0, n - 1, 0, n - 1, P, st, G, M, (const double *)dp1, (const double *)dp2,
-                     (const B *)W.FX, (const B *)W.FY, Q);
+            FvArgs<B, B, double> a{};
+            a.q = Q; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
+            a.mx = W.mxs; a.my = W.mys; a.area = M.m[M_AREA]; a.epi = EPI_TRACER; a.qout = W.qo;
+            a.dp1 = dp1; a.dp2 = dp2;
+            fvtp(g, P, a, st);
+            copy((const B *)W.qo, Q, el, st);
         }
         double *tmp = dp1;
         dp1 = dp2;
         dp2 = tmp;
     }
+    for (int m = 0; m < nq; m++) halo_scalar(g, (B *)q[m], nz, st);   // leave consistent halos
     return hipGetLastError() == hipSuccess ? FV3_OK : FV3_EDEVICE;
 }
 
-fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
-                         int nq, double *out, hipStream_t st)
+fv3_status run_tracer(void *const *q, int nq, fv3_state *s, const fv3_grid *g, int nsplt,
+                      hipStream_t st)
 {
-    if (g->bulk_bytes != (int)sizeof(B)) return FV3_EUNSUPPORTED;
-    Met M = metrics(g);
+    if (g->bulk_bytes == 4) return tracer_t<float>(q, nq, s, g, nsplt, st);
+    return tracer_t<double>(q, nq, s, g, nsplt, st);
+}
+
+template <class B>
+static fv3_status mass_sums_t(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                              int nq, double *out, hipStream_t st)
+{
+    MetD M = metrics_d(g);
     const Geo &G = g->geo;
     int n = g->n;
     long np = part_count(g);
@@ -1312,7 +1496,7 @@ fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, vo
     std::vector<double> h(2 * np);
     for (int which = 0; which < 2 + nq; which++) {
         const B *qq = which >= 2 ? (const B *)q[which - 2] : nullptr;
-        launch2d(k_mass_partial, 0, n - 1, 0, n - 1, g->T, st, G, M, (const B *)delp, (const B *)pt, qq,
+        launch2d(k_mass_partial<B>, 0, n - 1, 0, n - 1, g->T, st, G, M, (const B *)delp, (const B *)pt, qq,
                  which < 2 ? which : 2, part);
         if (hipMemcpyAsync(h.data(), part, 2 * np * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
             return FV3_EDEVICE;
@@ -1328,6 +1512,13 @@ fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, vo
         out[which] = s + c;
     }
     return FV3_OK;
+}
+
+fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                         int nq, double *out, hipStream_t st)
+{
+    if (g->bulk_bytes == 4) return mass_sums_t<float>(g, delp, pt, q, nq, out, st);
+    return mass_sums_t<double>(g, delp, pt, q, nq, out, st);
 }
 
 }  // namespace fv3

@@ -133,6 +133,31 @@ def test_cube_c24_ten_substeps(fv3, orc):
                          "cy", "pfull", "phi"), 1e-11, "C24")
 
 
+@pytest.mark.parametrize("kind,n,nz,dt,ns", [(0, 64, 3, 0.6, 3), (0, 80, 3, 0.6, 3), (1, 16, 4, 400.0, 2)])
+def test_tile_multiple_sizes(fv3, orc, kind, n, nz, dt, ns):
+    """Sizes that are whole multiples of the kernels' block tiles (64 x 16
+    for the transport, 64 x 4 corners for the pressure gradient) and one
+    that leaves a partial tile: every face on a block boundary is written
+    once.  Full substeps and the tracer transport."""
+    init = fi.periodic_state(n=n, nz=nz, nq=1) if kind == 0 else fi.cube_state(n=n, nz=nz, nq=1)
+    g, s, og, os_ = _pair(fv3, orc, kind, n, nz, init)
+    fv3.acoustic_substeps(s, g, dt, ns)
+    assert fv3.check_status(g) == 0
+    assert orc.acoustic_substeps(og, os_, dt, ns) == 0
+    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz", "mfx", "mfy", "cx", "cy", "pfull", "phi"),
+             1e-11, f"tiles kind{kind} n{n}")
+    qd = [g.upload(q, nz) for q in init["q"]]
+    qh = [q.copy() for q in init["q"]]
+    fv3.tracer_transport(qd, s, g)
+    orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+    import torch
+
+    torch.cuda.synchronize()
+    e = _relerr(_int(g.download(qd[0], nz), n, "C"), _int(qh[0], n, "C"))
+    print(f"tiles kind{kind} n{n} tracer {e:.2e}", flush=True)
+    assert e <= 1e-11
+
+
 def test_gpu_mass_conservation_and_sums(fv3, orc):
     n, nz = 48, 8
     init = fi.periodic_state(nq=1)
@@ -203,3 +228,60 @@ def test_cfl_flag_latched(fv3):
     fv3.acoustic_substeps(s, g, 1.0, 1)
     assert fv3.check_status(g) == -6
     assert fv3.check_status(g) == 0   # cleared
+
+
+# ---------------------------------------------------------------- mixed precision
+def _mixed_pair(fv3, orc, kind, n, nz, init):
+    g = fv3.Grid(kind, n, nz, precision="mixed")
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(kind, n, nz)
+    os_ = orc.new_state(og, init)
+    return g, s, og, os_
+
+
+def _fp32_errors(s, os_, n, fields):
+    import torch
+
+    torch.cuda.synchronize()
+    return {k: _relerr(_int(s.get(k), n, STAG[k]), _int(os_[k], n, STAG[k])) for k in fields}
+
+
+MIXED_FIELDS = ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")
+
+
+def test_mixed_precision_cfg1(fv3, orc):
+    """FP32 stencil bulk, FP64 columns: per-field error vs the FP64 oracle after
+    10 substeps of the 48x48x8 case.  Bars: FP32 unit roundoff 6e-8 times the
+    growth over 10 substeps (~10 ops per value per substep) for the transported
+    and thermodynamic fields; w is a small residual of p - pi_bar (see the
+    module docstring) and is held to 1e-3 of its range."""
+    n, nz = 48, 8
+    init = fi.periodic_state()
+    g, s, og, os_ = _mixed_pair(fv3, orc, 0, n, nz, init)
+    fv3.acoustic_substeps(s, g, 2.0, 10)
+    assert fv3.check_status(g) == 0
+    assert orc.acoustic_substeps(og, os_, 2.0, 10) == 0
+    e = _fp32_errors(s, os_, n, MIXED_FIELDS)
+    print("mixed cfg1", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k in ("u", "v", "delp", "pt", "delz", "pfull", "phi"):
+        assert e[k] <= 1e-5, (k, e[k])
+    assert e["w"] <= 1e-3
+
+
+def test_mixed_precision_cube(fv3, orc):
+    n, nz = 24, 10
+    init = fi.cube_state(n=n, nz=nz)
+    g, s, og, os_ = _mixed_pair(fv3, orc, 1, n, nz, init)
+    fv3.acoustic_substeps(s, g, 10 * 200.0, 10)
+    assert fv3.check_status(g) == 0
+    assert orc.acoustic_substeps(og, os_, 10 * 200.0, 10) == 0
+    e = _fp32_errors(s, os_, n, MIXED_FIELDS)
+    print("mixed C24", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k in ("u", "v", "delp", "pt", "delz", "pfull", "phi"):
+        assert e[k] <= 1e-4, (k, e[k])
+    assert e["w"] <= 1e-2
+    # the mass sums stay FP64-compensated: delp mass drift of the mixed run
+    m = fv3.mass_sums(g, s.f["delp"], s.f["pt"])
+    ref = orc.mass_sums(og, os_["delp"], os_["pt"])
+    assert abs(m[0] / ref[0] - 1) <= 1e-6
