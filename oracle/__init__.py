@@ -53,6 +53,7 @@ def lib():
         L.orc_grid_new.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, C.c_char_p, C.c_int]
         L.orc_grid_free.argtypes = [C.c_void_p]
+        L.orc_set_damping.argtypes = [C.c_void_p, C.c_double]
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_grid_conn.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_halo_fill.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, C.c_int]
@@ -91,12 +92,15 @@ class Grid:
     """Oracle grid: kind 0 = doubly periodic (one tile), 1 = cubed sphere (6 tiles)."""
 
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
-                 radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0):
+                 radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
+                 d2_bg: float = 0.0):
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
             raise RuntimeError("oracle grid: " + err.value.decode())
         self._h = h
+        self.d2_bg = d2_bg
+        lib().orc_set_damping(h, float(d2_bg))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1

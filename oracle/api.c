@@ -24,6 +24,21 @@ void *orc_grid_new(int kind, int n, int nz, double delta, double f0, double radi
 
 void orc_grid_free(void *g) { og_free((OGrid *)g); }
 
+/* del-2 divergence damping of d_sw (0 = off) */
+void orc_set_damping(void *gp, double d2_bg)
+{
+    OGrid *g = (OGrid *)gp;
+    g->d2_bg = d2_bg;
+    double m = 1e300;
+    for (int t = 0; t < g->T; t++)
+        for (int j = 0; j <= g->n; j++)
+            for (int i = 0; i <= g->n; i++) {
+                double a = g->area_c[(size_t)t * o_plane(g) + IX(g, i, j)];
+                if (a < m) m = a;
+            }
+    g->da_min = m;
+}
+
 /* which: 0 dx 1 dy 2 dxc 3 dyc 4 dxa 5 dya 6 area 7 area_c 8 fC 9 fB 10 sin_u 11 cos_u
  *        12 sin_v 13 cos_v 14 sin_a 15 cos_a 16..18 centre xyz 19..21 corner xyz */
 int orc_grid_metric(void *gp, int which, double *out)

@@ -407,6 +407,28 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             double vbv = o_ppm_face(a6, cyv);
             ke[b] = 0.5 * (ub * ubv + vb * vbv);
         }
+    /* (v') optional del-2 divergence damping: nu times the divergence of the
+     * D-grid winds over the dual cell of each corner (normal components
+     * through the four dual edges; at a cube vertex the two edges next to the
+     * missing cell count half) is subtracted from the kinetic energy, so that
+     * the wind update below adds nu times its gradient: a diffusion of the
+     * divergence with coefficient nu = d2_bg times the smallest dual-cell area */
+    if (g->d2_bg > 0.0) {
+        const double *dxc = g->dxc + o, *dyc = g->dyc + o, *area_c = g->area_c + o;
+        double nu = g->d2_bg * g->da_min;
+        for (int j = 0; j <= n; j++)
+            for (int i = 0; i <= n; i++) {
+                size_t b = IX(g, i, j);
+                double ws = 1.0, wn = 1.0, ww = 1.0, we = 1.0;
+                if (og_is_vertex(g, i, j)) {
+                    if (j == 0) ws = 0.5; else wn = 0.5;
+                    if (i == 0) ww = 0.5; else we = 0.5;
+                }
+                double flux = we * u[b] * dyc[b] - ww * u[IX(g, i - 1, j)] * dyc[IX(g, i - 1, j)] +
+                              wn * v[b] * dxc[b] - ws * v[IX(g, i, j - 1)] * dxc[IX(g, i, j - 1)];
+                ke[b] -= nu * flux / area_c[b];
+            }
+    }
     /* (vi) absolute vorticity at cells and its transport */
     for (int j = -3; j <= n + 2; j++)
         for (int i = -3; i <= n + 2; i++) {

@@ -42,6 +42,9 @@ typedef struct {
     int kind;              /* 0 doubly periodic, 1 cubed sphere */
     int n, nz, T, N;
     double delta, f0, radius, omega, ptop;
+    /* optional del-2 divergence damping of d_sw: coefficient and the smallest
+     * corner (dual-cell) area of the grid */
+    double d2_bg, da_min;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */

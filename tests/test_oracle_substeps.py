@@ -124,3 +124,59 @@ def test_cube_runs_finite(orc):
     assert np.all(np.abs(m1 / m0 - 1) < 1e-5)
     for k in ("u", "v", "w", "delp", "pt", "delz"):
         assert np.all(np.isfinite(s[k][:, :, H:H + n, H:H + n]))
+
+
+def _pure_wind_state(n, nz, u_cells, v_cells):
+    """Isothermal periodic columns at rest except the given D-grid winds
+    u (y-faces, [nz][n][n] for rows 0..n-1) and v (x-faces, columns 0..n-1);
+    the duplicate periodic faces n copy faces 0."""
+    st = fi.periodic_state(n=n, nz=nz, seed=3, wind=0.0)
+    st["u"][:] = 0.0
+    st["v"][:] = 0.0
+    st["u"][0, :, H:H + n, H:H + n] = u_cells
+    st["u"][0, :, H + n, H:H + n] = u_cells[:, 0, :]
+    st["v"][0, :, H:H + n, H:H + n] = v_cells
+    st["v"][0, :, H:H + n, H + n] = v_cells[:, :, 0]
+    return st
+
+
+def _one_substep(orc, st, n, nz, d2_bg, dt=0.2):
+    g = orc.Grid(0, n, nz, d2_bg=d2_bg)
+    s = orc.new_state(g, st)
+    assert orc.acoustic_substeps(g, s, dt, 1) == 0
+    return s
+
+
+def test_divergence_damping_closed_form(orc):
+    """A purely divergent mode u = a cos(2 pi (i + 1/2) / n), v = 0: the damping
+    changes u by nu times the discrete second difference of u over dx^2,
+    i.e. by -(4 nu / dx^2) sin^2(pi / n) u (del-2 diffusion of the
+    divergence; nu = d2_bg times the smallest dual-cell area = d2_bg dx^2)."""
+    n, nz, d2 = 16, 2, 0.1
+    i = np.arange(n)
+    ucol = np.cos(2 * np.pi * (i + 0.5) / n)
+    u = np.broadcast_to(ucol, (nz, n, n)).copy()
+    st = _pure_wind_state(n, nz, u, np.zeros((nz, n, n)))
+    a = _one_substep(orc, st, n, nz, 0.0)
+    b = _one_substep(orc, st, n, nz, d2)
+    du = (b["u"] - a["u"])[0, :, H:H + n, H:H + n]
+    want = -(4 * d2) * np.sin(np.pi / n) ** 2 * u
+    np.testing.assert_allclose(du, want, rtol=0, atol=1e-12)
+    np.testing.assert_allclose((b["v"] - a["v"])[0, :, H:H + n, H:H + n], 0.0, atol=1e-13)
+
+
+def test_divergence_damping_leaves_rotational_flow(orc):
+    """D-grid winds from a streamfunction at cell centres have zero discrete
+    divergence at every corner: the damping changes nothing beyond rounding."""
+    n, nz = 16, 2
+    rng = np.random.default_rng(9)
+    psi = rng.standard_normal((nz, n, n)) * 1000.0          # psi [m^2/s] at cells
+    dx = 1000.0
+    u = -(psi - np.roll(psi, 1, axis=1)) / dx               # y-face (i, j): cells (i, j-1), (i, j)
+    v = (psi - np.roll(psi, 1, axis=2)) / dx                # x-face (i, j): cells (i-1, j), (i, j)
+    st = _pure_wind_state(n, nz, u, v)
+    a = _one_substep(orc, st, n, nz, 0.0)
+    b = _one_substep(orc, st, n, nz, 0.2)
+    scale = np.abs(a["u"]).max()
+    assert np.abs(b["u"] - a["u"]).max() <= 1e-12 * scale
+    assert np.abs(b["v"] - a["v"]).max() <= 1e-12 * scale
