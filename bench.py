@@ -21,9 +21,17 @@ roofline  the kernel with the largest share of the step, timed live with HIP
           once, at their element sizes) x (cells per launch), the paper's
           bandwidth model of Sec. VII-C.
 cpu_baseline  the oracle (plain C, OpenMP) on a bounded sample of the same
-          workload: 3 acoustic substeps of C192 x 79 in FP64.
+          workload: 10 acoustic substeps of C192 x 79 in FP64.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--precision mixed|fp64]
+       python bench.py --ensemble     (batched uneven ensemble instead: one JSON line)
+
+--ensemble: 32 doubly periodic members with (n, nz) drawn uniformly from
+n in 64..256 (step 16) and nz in 32..79, each an isothermal flow with noise;
+one step = one call of 20 substeps of 0.2 s on every member.  Reported:
+members run one by one, one batched launch per kernel, the batched call
+replayed from a HIP graph, and the same after the block-shape autotuner
+(its search cost and reuse count), all in cell-updates/s.
 """
 from __future__ import annotations
 
@@ -43,10 +51,18 @@ HBM_PEAK_GBS = 8000.0
 # fields (8 or 4 bytes) and always-FP64 fields (8 bytes).
 BYTES_MODEL = {
     # name: (bulk fields, fp64 fields); a field both read and written counts twice
-    "k_csw_agrid": (4, 0), "k_csw_faces": (17, 0), "k_csw_cells": (18, 0), "k_csw_update": (8, 0),
+    "k_csw": (12, 0),          # fused c_sw: u, v, delp, pt, w in | uc, vc, delpc, ptc, wc, ax, ay out
     "k_dzc": (2, 2),
-    "k_sim1_c": (3, 3),        # delpc, ptc, wc | delz_c in; pkc, gz out
-    "k_sim1_3": (4, 4),        # delp, pt, w in, w out | delz in, delz, pfull, phi out
+    # column solve in four passes; FP64 scratch columns (elimination coefficients,
+    # new w, new thickness) are fields of the passes that write and read them
+    "k_sim1_c.p1": (3, 3),     # delpc, ptc, wc | delz_c; c', d' out
+    "k_sim1_c.p2": (0, 3),     # c', d' | w new out
+    "k_sim1_c.p3": (3, 3),     # delpc, ptc, wc | w new; thickness, pkc out
+    "k_sim1_c.p4": (0, 2),     # thickness | gz out
+    "k_sim1_3.p1": (3, 3),     # delp, pt, w | delz; c', d' out
+    "k_sim1_3.p2": (0, 3),
+    "k_sim1_3.p3": (4, 3),     # delp, pt, w in, w out | w new; thickness, pfull out
+    "k_sim1_3.p4": (0, 3),     # thickness | phi, delz out
     "k_pgradc": (3, 4), "k_dsw_courant": (8, 0),
     "k_dsw_omke": (6, 0), "k_dsw_update": (13, 0), "k_heights": (0, 2), "k_delz_from_zh": (0, 2),
     "k_nhpgrad": (5, 4),       # delp, u, v in, u, v out | pfull, phi at the layer's two interfaces
@@ -54,7 +70,7 @@ BYTES_MODEL = {
     "k_fvtp_delp": (12, 4),    # delp, crx, cry, xfx, yfx, FX, FY, dn, cx, cy (rw) | mfx, mfy (rw)
     "k_fvtp_massw": (10, 0),   # q, 4 fluxes, mx, my, delp old, delp new, q new
     "k_fvtp_flux": (7, 0),     # q, 4 fluxes, FX, FY
-    "k_fvtp_adv": (4, 2),      # 4 fluxes | zh in, zh out
+    "k_fvtp_adv": (8, 2),      # 4 Courant / area-flux arrays of the two layers around the interface | zh in, zh out
     "k_fvtp_tracer": (6, 4),   # q, 4 fluxes, q out | mx, my, dp1, dp2
 }
 
@@ -69,6 +85,24 @@ def kernel_bytes(name, cells, eb):
         b, d = BYTES_MODEL[key]
         return (b * eb + d * 8) * cells
     return None
+
+
+def committed_traffic(precision, n, nz, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, or None when absent or taken with a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_C{n}x{nz}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    import paper_2205_04148_amd.pmc as pmc
+
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("kernel_source_sha256") != pmc.source_sha256():
+        return None
+    k = doc["kernels"].get(kernel)
+    if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def cpu_baseline(init, n, nz, bdt, substeps):
@@ -130,9 +164,11 @@ def run_precision(fv3, torch, init, args, precision):
     eb = 8 if precision == "fp64" else 4
     bl = kernel_bytes(dom, cells, eb)
     achieved = bl / avg_s / 1e9 if bl else None
+    traffic = committed_traffic(precision, n, nz, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None, "bytes_per_launch": bl, "mean_launch_us": avg_s * 1e6,
+            "traffic": traffic, "bytes_per_launch": bl, "mean_launch_us": avg_s * 1e6,
+            "traffic_GBs": traffic / avg_s / 1e9 if traffic else None,
             "launches": cnt_dom, "share_of_step": per_kernel[dom][0] / tot_ms}
     log(f"[{precision}] {1000 * sec:.1f} ms/step, {cells * ns / sec:.3e} cell-updates/s, status {st}")
     del s, qs, g
@@ -165,6 +201,77 @@ def precision_error(fv3, torch, init, args):
     return out
 
 
+def ensemble_bench(fv3, torch, args):
+    import fv3_inputs as fi
+
+    sizes = fi.ensemble_sizes(32, seed=4)
+    ns, bdt = 20, 0.2
+    dt = ns * bdt
+    grids, states, inits = [], [], []
+    t0 = time.perf_counter()
+    for q, (n, nz) in enumerate(sizes):
+        g = fv3.Grid(0, n, nz, precision=args.precision)
+        s = fv3.State.allocate(g)
+        init = fi.periodic_state(n=n, nz=nz, seed=100 + q, nq=0)
+        s.load(init)
+        grids.append(g)
+        states.append(s)
+        inits.append(init)
+    cells = sum(n * n * nz for n, nz in sizes)
+    log(f"ensemble: {len(sizes)} members, {cells:.3e} cells, set up in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps
+
+    def reload():
+        for s, init in zip(states, inits):
+            s.load(init)
+        torch.cuda.synchronize()
+
+    def one_by_one():
+        for s, g in zip(states, grids):
+            fv3.acoustic_substeps(s, g, dt, ns, stream=stream)
+
+    res = {}
+    res["one_by_one_s"] = timed(one_by_one, args.steps)
+    reload()
+    e = fv3.Ensemble(states, grids, dt, ns, graph=False)
+    res["batched_s"] = timed(lambda: e.run(stream), args.steps)
+    reload()
+    eg = fv3.Ensemble(states, grids, dt, ns, graph=True)
+    res["batched_graph_s"] = timed(lambda: eg.run(stream), args.steps)
+    st_ok = all(fv3.check_status(g) == 0 for g in grids)
+    # autotune on the same states (left undefined by the search), then reload
+    tr = e.tune(reps=3, stream=stream)
+    reload()
+    et = fv3.Ensemble(states, grids, dt, ns, graph=True)
+    res["tuned_graph_s"] = timed(lambda: et.run(stream), args.steps)
+    st_ok = st_ok and all(fv3.check_status(g) == 0 for g in grids)
+    rate = {k.replace("_s", ""): cells * ns / v for k, v in res.items()}
+    for k, v in rate.items():
+        log(f"  {k:16s} {v:.3e} cell-updates/s  ({1000 * cells * ns / v / ns:.3f} ms/substep)")
+    best = max(rate.values())
+    return {
+        "metric": "ensemble acoustic-substep cell-updates/s, 32 uneven members, batched vs one by one",
+        "value": best, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1000 * cells * ns / best, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"32 doubly periodic members n in 64..256, nz in 32..79 "
+                               f"({cells} cells), {ns} substeps of {bdt} s per step",
+                   "precision": args.precision, "members": [list(x) for x in sizes]},
+        "rates": rate, "speedup_batched_graph_vs_one_by_one": rate["batched_graph"] / rate["one_by_one"],
+        "autotune": tr, "device_status_ok": st_ok,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +284,7 @@ def main():
     ap.add_argument("--bdt", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--ensemble", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the acoustic substep path holds all six cube "
@@ -187,6 +295,10 @@ def main():
 
     import fv3_inputs as fi
     import paper_2205_04148_amd as fv3
+
+    if args.ensemble:
+        print(json.dumps(ensemble_bench(fv3, torch, args)), flush=True)
+        return
 
     n, nz = args.n, args.nz
     t0 = time.perf_counter()
@@ -204,7 +316,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline ...")
-        cpu = cpu_baseline(init, n, nz, args.bdt, 3)
+        cpu = cpu_baseline(init, n, nz, args.bdt, 10)
     cells = 6 * n * n * nz
     out = {
         "metric": "acoustic-substep cell-updates/s at C192x79, mixed vs FP64; % HBM peak",

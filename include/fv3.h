@@ -42,7 +42,7 @@ typedef enum {
     FV3_ENOMEM = -5,        /* device allocation failed (grid creation only)                */
     FV3_ECFL = -6,          /* a Courant number exceeded 1 in d_sw (latched on device)      */
     FV3_ENONFINITE = -7,    /* a prognostic became non-finite (latched on device)           */
-    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8, d2_bg != 0, beta != 1)    */
+    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8, beta != 1)                */
     FV3_EINTERNAL = -99
 } fv3_status;
 
@@ -53,9 +53,12 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * cells (Sec. II), radius and rotation rate given.  Doubly periodic: one
  * n x n tile of spacing dx with constant Coriolis parameter f0.  Vertical:
  * nz Lagrangian layers below the model top pressure ptop.  Only the monotone
- * PPM order hord = 8, no divergence damping (d2_bg = 0) and a fully implicit
- * vertical solve (beta = 1) are implemented; other values give
- * FV3_EUNSUPPORTED. */
+ * PPM order hord = 8 and a fully implicit vertical solve (beta = 1) are
+ * implemented; other values give FV3_EUNSUPPORTED.  d2_bg in [0, 0.25] turns
+ * on del-2 divergence damping in d_sw: nu = d2_bg x (smallest dual-cell area
+ * of the grid) times the divergence of the D-grid winds at each corner is
+ * subtracted from the kinetic energy there, which diffuses the divergence
+ * (outside [0, 0.25]: FV3_EINVAL). */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -64,7 +67,7 @@ typedef struct {
     double ptop;         /* top pressure [Pa]                              */
     int precision;       /* fv3_precision                                  */
     int hord;            /* 8                                              */
-    double d2_bg;        /* 0                                              */
+    double d2_bg;        /* del-2 divergence damping, 0 (off) .. 0.25      */
     double beta;         /* 1                                              */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
@@ -197,6 +200,56 @@ int fv3_timing_stop(char *names, int names_cap, double *total_ms, long *counts, 
 
 const char *fv3_status_string(fv3_status s);
 const char *fv3_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched ensemble of independent grids.  The paper tunes one program
+ * across many stencil instances and reuses the tuning where the same
+ * pattern recurs (transfer tuning, Sec. VII-B); it runs one model per
+ * allocation.  Here many small, uneven members share one GPU: every kernel
+ * of the substep sequence runs once for all members (member-indexed blocks,
+ * per-member arguments in device memory), optionally replayed from a HIP
+ * graph, with block shapes chosen by timing and reused per kernel.
+ * ------------------------------------------------------------------------ */
+
+/* Run n_split acoustic substeps of dt / n_split on each of `members`
+ * (state, grid) pairs, exactly as fv3_acoustic_substeps would on each alone
+ * (same kernels, bit-identical results), with one launch per kernel for all
+ * members.  All grids must share one precision and be on the current device.
+ * Convenience form: builds an ensemble, runs it and synchronises `stream`. */
+fv3_status fv3_acoustic_substeps_batched(fv3_state *const *states, const fv3_grid *const *grids,
+                                         int members, double dt, int n_split, void *stream);
+
+typedef struct fv3_ensemble fv3_ensemble;
+enum { FV3_ENSEMBLE_GRAPH = 1 };   /* replay the whole call from a captured HIP graph */
+
+/* Record the substep launch sequence of every member (host only, nothing
+ * runs) and upload the per-member argument tables.  The states, grids and
+ * their device arrays must outlive the ensemble; each fv3_ensemble_run is
+ * one call of n_split substeps of dt / n_split on every member. */
+fv3_status fv3_ensemble_create(fv3_state *const *states, const fv3_grid *const *grids, int members,
+                               double dt, int n_split, int flags, fv3_ensemble **out);
+fv3_status fv3_ensemble_run(fv3_ensemble *e, void *stream);   /* asynchronous */
+fv3_status fv3_ensemble_free(fv3_ensemble *e);                /* synchronises the device */
+
+/* Autotuner report: plane kernels (tunable sites) whose block shape was
+ * searched by timing `reps` launches of each candidate shape, and those that
+ * reused a shape found earlier for the same kernel (at another stage of the
+ * sequence, or by an earlier ensemble in this process); search time; one
+ * substep's time before and after. */
+typedef struct {
+    int sites, tunable_sites, searched, reused;
+    double search_ms, substep_ms_before, substep_ms_after;
+} fv3_tune_report;
+
+/* Choose block shapes by timing.  Runs kernels of the sequence repeatedly on
+ * the ensemble's states, which are left in an undefined state: tune on
+ * scratch copies, then reload.  Synchronous. */
+fv3_status fv3_ensemble_tune(fv3_ensemble *e, int reps, fv3_tune_report *report, void *stream);
+
+/* Inspection: kernel names (NUL-separated) and block shapes of the recorded
+ * sequence; returns the number of sites written. */
+int fv3_ensemble_shapes(const fv3_ensemble *e, char *names, int names_cap, int *block_x,
+                        int *block_y, int cap);
 
 /* ------------------------------------------------------------------------
  * Learned per-column correction of a coarse run.  The paper motivates

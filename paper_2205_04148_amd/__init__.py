@@ -33,7 +33,9 @@ EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_b
            "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
            "fv3_tracer_transport", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
            "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start",
-           "fv3_timing_stop", "fv3_coarsen", "fv3_column_features", "fv3_apply_correction",
+           "fv3_timing_stop", "fv3_acoustic_substeps_batched", "fv3_ensemble_create",
+           "fv3_ensemble_run", "fv3_ensemble_free", "fv3_ensemble_tune", "fv3_ensemble_shapes",
+           "fv3_coarsen", "fv3_column_features", "fv3_apply_correction",
            "fv3_mlp_create", "fv3_mlp_free", "fv3_mlp_param_count", "fv3_mlp_set_params",
            "fv3_mlp_get_params", "fv3_mlp_forward", "fv3_mlp_gradients", "fv3_mlp_train_step"]
 
@@ -55,6 +57,12 @@ class Layout(C.Structure):
     _fields_ = [("tiles", C.c_int), ("n", C.c_int), ("nz", C.c_int), ("halo", C.c_int),
                 ("pitch", C.c_long), ("rows", C.c_long), ("level_elems", C.c_long),
                 ("offset0", C.c_long), ("bulk_elem_bytes", C.c_int)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("sites", C.c_int), ("tunable_sites", C.c_int), ("searched", C.c_int),
+                ("reused", C.c_int), ("search_ms", C.c_double), ("substep_ms_before", C.c_double),
+                ("substep_ms_after", C.c_double)]
 
 
 class FeatureNorm(C.Structure):
@@ -97,6 +105,15 @@ def lib():
         L.fv3_timing_start.argtypes = [C.c_char_p]
         L.fv3_timing_stop.argtypes = [C.c_char_p, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_long), C.c_int]
+        L.fv3_acoustic_substeps_batched.argtypes = [C.POINTER(C.POINTER(StateStruct)), C.POINTER(vp),
+                                                    C.c_int, C.c_double, C.c_int, vp]
+        L.fv3_ensemble_create.argtypes = [C.POINTER(C.POINTER(StateStruct)), C.POINTER(vp), C.c_int,
+                                          C.c_double, C.c_int, C.c_int, C.POINTER(vp)]
+        L.fv3_ensemble_run.argtypes = [vp, vp]
+        L.fv3_ensemble_free.argtypes = [vp]
+        L.fv3_ensemble_tune.argtypes = [vp, C.c_int, C.POINTER(TuneReport), vp]
+        L.fv3_ensemble_shapes.argtypes = [vp, C.c_char_p, C.c_int, C.POINTER(C.c_int),
+                                          C.POINTER(C.c_int), C.c_int]
         L.fv3_coarsen.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(StateStruct), vp, vp]
         L.fv3_column_features.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(FeatureNorm), vp,
                                           vp, vp]
@@ -124,9 +141,9 @@ def _check(st):
         raise FV3Error(st, lib().fv3_last_error().decode())
 
 
-def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device):
+def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg=0.0):
     return GridParams(kind=kind, n=n, nz=nz, dx=dx, f0=f0, radius=radius, omega=omega, ptop=ptop,
-                      precision=0 if precision == "fp64" else 1, hord=8, d2_bg=0.0, beta=1.0,
+                      precision=0 if precision == "fp64" else 1, hord=8, d2_bg=d2_bg, beta=1.0,
                       device=device)
 
 
@@ -153,10 +170,10 @@ class Grid:
 
     def __init__(self, kind: int, n: int, nz: int, dx: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
-                 precision: str = "fp64", device: int = 0):
+                 precision: str = "fp64", device: int = 0, d2_bg: float = 0.0):
         torch = _torch()
         torch.cuda.set_device(device)
-        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device)
+        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg)
         h = C.c_void_p()
         _check(lib().fv3_init_grid(C.byref(p), C.byref(h)))
         self._h = h
@@ -322,6 +339,62 @@ def timing_stop() -> dict:
         raise FV3Error(nk, "timing_stop failed")
     keys = names.raw.split(b"\0")
     return {keys[q].decode(): (tot[q], cnt[q]) for q in range(nk)}
+
+
+# ---------------------------------------------------------------- batched ensemble
+def _member_arrays(states, grids):
+    if len(states) != len(grids) or not states:
+        raise ValueError("need one grid per state and at least one member")
+    structs = [s.struct() for s in states]
+    sp = (C.POINTER(StateStruct) * len(structs))(*[C.pointer(x) for x in structs])
+    gp = (C.c_void_p * len(grids))(*[g.handle for g in grids])
+    return structs, sp, gp
+
+
+def acoustic_substeps_batched(states, grids, dt: float, n_split: int, stream=None) -> None:
+    """n_split substeps on every (state, grid) member with one launch per kernel
+    for all members (synchronises the stream)."""
+    keep, sp, gp = _member_arrays(states, grids)
+    _check(lib().fv3_acoustic_substeps_batched(sp, gp, len(keep), float(dt), int(n_split),
+                                               _stream(stream)))
+
+
+class Ensemble:
+    """Recorded batched substep call over many members (optionally a HIP graph)."""
+
+    def __init__(self, states, grids, dt: float, n_split: int, graph: bool = False):
+        self.states, self.grids = list(states), list(grids)
+        keep, sp, gp = _member_arrays(self.states, self.grids)
+        h = C.c_void_p()
+        _check(lib().fv3_ensemble_create(sp, gp, len(keep), float(dt), int(n_split),
+                                         1 if graph else 0, C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fv3_ensemble_free(h)
+            self._h = None
+
+    def run(self, stream=None) -> None:
+        _check(lib().fv3_ensemble_run(self._h, _stream(stream)))
+
+    def tune(self, reps: int = 3, stream=None) -> dict:
+        """Time candidate block shapes (leaves the member states undefined)."""
+        r = TuneReport()
+        _check(lib().fv3_ensemble_tune(self._h, int(reps), C.byref(r), _stream(stream)))
+        return {k: getattr(r, k) for k, _ in TuneReport._fields_}
+
+    def shapes(self):
+        cap = 512
+        names = C.create_string_buffer(cap * 48)
+        bx = (C.c_int * cap)()
+        by = (C.c_int * cap)()
+        k = lib().fv3_ensemble_shapes(self._h, names, cap * 48, bx, by, cap)
+        if k < 0:
+            raise FV3Error(k, lib().fv3_last_error().decode())
+        ks = names.raw.split(b"\0")
+        return [(ks[q].decode(), bx[q], by[q]) for q in range(k)]
 
 
 # ---------------------------------------------------------------- learned correction

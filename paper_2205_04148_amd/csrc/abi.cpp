@@ -74,7 +74,8 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
         return fail(FV3_ESHAPE, "n must be in [8, 4096] and nz in [1, 512]");
     if (p->precision != FV3_FP64 && p->precision != FV3_MIXED) return fail(FV3_EDTYPE, "unknown precision");
     if (p->hord != 8) return fail(FV3_EUNSUPPORTED, "only the monotone PPM (hord = 8) is implemented");
-    if (p->d2_bg != 0.0) return fail(FV3_EUNSUPPORTED, "divergence damping is not implemented");
+    if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))
+        return fail(FV3_EINVAL, "d2_bg must be in [0, 0.25] (explicit del-2 damping)");
     if (p->beta != 1.0) return fail(FV3_EUNSUPPORTED, "only the fully implicit vertical solve (beta = 1)");
     if (!(p->ptop > 0.0) || !std::isfinite(p->ptop)) return fail(FV3_EINVAL, "ptop must be positive");
     if (p->kind == FV3_GRID_DOUBLY_PERIODIC && !(p->dx > 0.0)) return fail(FV3_EINVAL, "dx must be positive");

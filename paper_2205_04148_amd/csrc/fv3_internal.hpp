@@ -95,6 +95,7 @@ struct fv3_grid {
     double *red = nullptr;                    // device reduction scratch
     long red_elems = 0;
     size_t ws_bytes = 0;
+    double da_min = 0.0;                      // smallest corner (dual-cell) area
 };
 
 namespace fv3 {

@@ -12,6 +12,7 @@
 // cells (so halo stencils see exactly the neighbour's geometry); tile-edge
 // faces carry cos = 0, sin = 1, which makes the normal wind there the stored
 // wind (the tile-edge rule of Sec. V-B).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -392,6 +393,15 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
             s = upload(&g->metf[m], f, err);
             if (s != FV3_OK) return s;
         }
+    }
+    {
+        const std::vector<double> &ac = g->hmet[M_AREA_C];
+        double m = 1e300;
+        for (int t = 0; t < g->T; t++)
+            for (int j = 0; j <= g->n; j++)
+                for (int i = 0; i <= g->n; i++)
+                    m = std::min(m, ac[g->off0 + (long)t * g->lev + (long)j * g->pitch + i]);
+        g->da_min = m;
     }
     std::vector<HaloEnt> pc, pd, pcv, pa;
     make_plan(G, g, SC, SC, false, pc);

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -107,13 +108,17 @@ DEVI bool is_vertex(const Geo &G, int i, int j)
 }
 
 #define KBEGIN(L)                                                    \
-    int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);      \
-    int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);      \
-    if (i > ihi || j > jhi) return;                                  \
-    int t = (int)blockIdx.z / (L), k = (int)blockIdx.z % (L);        \
+    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);       \
+    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);      \
+    if (i < ilo || i > ihi || j > jhi) return;                       \
+    int t = (int)bk.z / (L), k = (int)bk.z % (L);        \
     (void)t; (void)k;
 
-#define KARGS int ilo, int ihi, int jlo, int jhi
+// Plane kernels: point range [ilo, ihi] x [jlo, jhi]; thread columns start at
+// ib <= ilo, a multiple of 32 elements from the interior origin, so that every
+// wavefront's 64 columns begin on a 128-byte line (interior column 0 is
+// line-aligned in the layout).
+#define KARGS Bk bk, int ib, int ilo, int ihi, int jlo, int jhi
 
 template <class R>
 struct Mets {
@@ -152,29 +157,148 @@ static void timing_end(hipStream_t st, TimingRec &r)
     g_timing.recs.push_back(r);
 }
 
+// ---------------------------------------------------------- kernel launch
+// Every kernel of the substep path is a device function that takes its block
+// index explicitly.  It is launched either alone (k_one: the block index is
+// the hardware one), or for an ensemble of grids in one launch (k_multi: grid
+// z runs over the planes of all members, each block looks its member up in a
+// small table and reads that member's arguments from device memory; blocks
+// outside the member's own x/y extent exit at once).  Both paths run the same
+// device code, so an ensemble member computes exactly what it computes alone.
+template <class... A>
+struct Tup;
+template <>
+struct Tup<> {
+};
+template <class H, class... R>
+struct Tup<H, R...> {
+    H h;
+    Tup<R...> r;
+};
+static inline Tup<> tup() { return {}; }
+template <class H, class... R>
+static Tup<H, R...> tup(H h, R... r)
+{
+    return Tup<H, R...>{h, tup(r...)};
+}
+template <size_t I, class H, class... R>
+DEVI const auto &tget(const Tup<H, R...> &t)
+{
+    if constexpr (I == 0) return t.h;
+    else return tget<I - 1>(t.r);
+}
+template <auto F, class... A, size_t... I>
+DEVI void tcall(Bk bk, const Tup<A...> &t, std::index_sequence<I...>)
+{
+    F(bk, tget<I>(t)...);
+}
+
+template <auto F, class... A>
+__global__ void __launch_bounds__(256) k_one(A... a)
+{
+    F(Bk{blockIdx.x, blockIdx.y, blockIdx.z}, a...);
+}
+
+template <auto F, class... A>
+__global__ void __launch_bounds__(256) k_multi(const Tup<A...> *__restrict__ args, const MemberBlk *__restrict__ tab,
+                                               int members)
+{
+    const int z = (int)blockIdx.z;
+    int lo = 0, hi = members - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].z0 <= z) lo = mid;
+        else hi = mid - 1;
+    }
+    const MemberBlk mb = tab[lo];
+    if ((int)blockIdx.x >= mb.gx || (int)blockIdx.y >= mb.gy) return;
+    tcall<F>(Bk{blockIdx.x, blockIdx.y, (unsigned)(z - mb.z0)}, args[lo], std::index_sequence_for<A...>{});
+}
+
+// Recording of the launch sequence of one call per member (ensemble mode).
+static thread_local Recorder *g_rec = nullptr;
+
+template <class Tp>
+static void rec_site(const char *name, const void *km, bool tunable, dim3 blk, int ex, int ey, int ez, const Tp &t)
+{
+    Recorder &R = *g_rec;
+    if (R.member == 0) {
+        Site s;
+        s.name = name;
+        s.kmulti = km;
+        s.argsz = sizeof(Tp);
+        s.tunable = tunable;
+        s.blk = blk;
+        R.sites.push_back(std::move(s));
+    }
+    if (R.pos >= R.sites.size() || R.sites[R.pos].kmulti != km) {
+        R.bad = true;
+        return;
+    }
+    Site &s = R.sites[R.pos++];
+    const char *b = (const char *)&t;
+    s.blob.insert(s.blob.end(), b, b + sizeof(Tp));
+    s.ex.push_back(ex);
+    s.ey.push_back(ey);
+    s.ez.push_back(ez);
+}
+
+// marks the boundaries entry | substep | exit of the recorded sequence
+static void rec_mark()
+{
+    if (!g_rec) return;
+    Recorder &R = *g_rec;
+    if (R.member == 0) R.marks.push_back(R.pos);
+    else if (R.mark >= R.marks.size() || R.marks[R.mark] != R.pos) R.bad = true;
+    R.mark++;
+}
+
 // plane kernels: 64 x 4 threads, one point each, grid z = planes
-template <class Kern, class... Args>
-static void launch2d_named(const char *name, Kern kern, int ilo, int ihi, int jlo, int jhi, int planes,
-                           hipStream_t st, Args... args)
+template <auto F, class... A>
+static void launch2d_fn(const char *name, int ilo, int ihi, int jlo, int jhi, int planes, hipStream_t st, A... a)
+{
+    const int ib = ilo >= 0 ? ilo : -32;
+    if (g_rec) {
+        rec_site(name, (const void *)k_multi<F, int, int, int, int, int, A...>, true, dim3(64, 4, 1), ihi - ib + 1,
+                 jhi - jlo + 1, planes, tup(ib, ilo, ihi, jlo, jhi, a...));
+        return;
+    }
+    dim3 blk(64, 4, 1);
+    dim3 grd((unsigned)((ihi - ib + 64) / 64), (unsigned)((jhi - jlo + 4) / 4), (unsigned)planes);
+    bool tm = timing_wanted(name);
+    TimingRec r;
+    if (tm) timing_begin(name, st, r);
+    hipLaunchKernelGGL((k_one<F, int, int, int, int, int, A...>), grd, blk, 0, st, ib, ilo, ihi, jlo, jhi, a...);
+    if (tm) timing_end(st, r);
+}
+#define launch2d(kern, ...) launch2d_fn<kern>(#kern, __VA_ARGS__)
+
+// generic launch with explicit shape (timed under `name`)
+template <auto F, class... A>
+static void launch_fn(const char *name, dim3 grd, dim3 blk, hipStream_t st, A... a)
+{
+    if (g_rec) {
+        rec_site(name, (const void *)k_multi<F, A...>, false, blk, (int)grd.x, (int)grd.y, (int)grd.z, tup(a...));
+        return;
+    }
+    bool tm = timing_wanted(name);
+    TimingRec r;
+    if (tm) timing_begin(name, st, r);
+    hipLaunchKernelGGL((k_one<F, A...>), grd, blk, 0, st, a...);
+    if (tm) timing_end(st, r);
+}
+
+// plain __global__ kernels outside the substep path (reductions)
+template <class Kern, class... A>
+static void launch2d_native(const char *name, Kern kern, int ilo, int ihi, int jlo, int jhi, int planes,
+                            hipStream_t st, A... a)
 {
     dim3 blk(64, 4, 1);
     dim3 grd((unsigned)((ihi - ilo + 64) / 64), (unsigned)((jhi - jlo + 4) / 4), (unsigned)planes);
     bool tm = timing_wanted(name);
     TimingRec r;
     if (tm) timing_begin(name, st, r);
-    hipLaunchKernelGGL(kern, grd, blk, 0, st, ilo, ihi, jlo, jhi, args...);
-    if (tm) timing_end(st, r);
-}
-#define launch2d(kern, ...) launch2d_named(#kern, kern, __VA_ARGS__)
-
-// generic launch with explicit shape (timed under `name`)
-template <class Kern, class... Args>
-static void launch_named(const char *name, Kern kern, dim3 grd, dim3 blk, hipStream_t st, Args... args)
-{
-    bool tm = timing_wanted(name);
-    TimingRec r;
-    if (tm) timing_begin(name, st, r);
-    hipLaunchKernelGGL(kern, grd, blk, 0, st, args...);
+    hipLaunchKernelGGL(kern, grd, blk, 0, st, ilo, ihi, jlo, jhi, a...);
     if (tm) timing_end(st, r);
 }
 
@@ -225,21 +349,21 @@ DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
 // (orientation transform folded into the plan for vector pairs).
 // ====================================================================
 template <class T>
-__global__ void k_halo_scalar(Geo G, const HaloEnt *__restrict__ plan, int count, T *f, int L)
+DEVI void k_halo_scalar(Bk bk, Geo G, const HaloEnt *__restrict__ plan, int count, T *f, int L)
 {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    int e = bk.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
-    int k = blockIdx.y;
+    int k = bk.y;
     HaloEnt h = plan[e];
     f[pidx(G, L, h.dt, k) + h.di] = f[pidx(G, L, h.st, k) + h.si];
 }
 
 template <class T>
-__global__ void k_halo_pair(Geo G, const HaloEnt *__restrict__ plan, int count, T *fx, T *fy, int L)
+DEVI void k_halo_pair(Bk bk, Geo G, const HaloEnt *__restrict__ plan, int count, T *fx, T *fy, int L)
 {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    int e = bk.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
-    int k = blockIdx.y;
+    int k = bk.y;
     HaloEnt h = plan[e];
     const T *src = (h.sel & 1) ? fy : fx;
     T *dst = (h.sel & 4) ? fy : fx;
@@ -251,14 +375,14 @@ template <class T>
 static void halo_scalar(const fv3_grid *g, T *f, int L, hipStream_t st)
 {
     if (g->planC.count == 0) return;
-    launch_named("k_halo_scalar", k_halo_scalar<T>, dim3((g->planC.count + 255) / 256, L), dim3(256), st,
+    launch_fn<k_halo_scalar<T>>("k_halo_scalar", dim3((g->planC.count + 255) / 256, L), dim3(256), st,
                  g->geo, (const HaloEnt *)g->planC.d, g->planC.count, f, L);
 }
 template <class T>
 static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hipStream_t st)
 {
     if (p.count == 0) return;
-    launch_named("k_halo_pair", k_halo_pair<T>, dim3((p.count + 255) / 256, L), dim3(256), st, g->geo,
+    launch_fn<k_halo_pair<T>>("k_halo_pair", dim3((p.count + 255) / 256, L), dim3(256), st, g->geo,
                  (const HaloEnt *)p.d, p.count, fx, fy, L);
 }
 
@@ -266,136 +390,270 @@ static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hip
 // c_sw (half step dt2 on one level): D -> A -> C interpolation, upwind
 // half-step cell fluxes, kinetic energy, corner vorticity, C-grid winds.
 // ====================================================================
-// A-grid winds at cells: u interpolated along y ((-1,9,9,-1)/16, y-sweep
-// corner view), v along x (x-sweep view).
+// --------------------------------------------------------------------
+// c_sw fused: one launch per level for the whole half step.  A tile of
+// CTX x CTY points (point (i, j) = cell (i, j), its west x-face and south
+// y-face, its SW corner) over i, j in [-1, n + 1] stages in LDS the A-grid
+// winds (cells i0-3..i0+CTX+1), delp, pt, w (cells i0-2..i0+CTX), then the
+// C-grid face quantities, the half-step kinetic energy and the corner
+// vorticity, and writes only what later stages read: uc, vc, delpc, ptc,
+// wc and the area fluxes ax, ay.  Each block writes the outputs of its own
+// points.  Corner-block reads follow the same corner views as the
+// per-stage kernels; a view source outside the staged region is read (or,
+// for the A-grid winds, recomputed) from global memory.
+// --------------------------------------------------------------------
+constexpr int CTX = 32, CNT = 256;
+// tile rows per precision: the FP64 tile is shorter so that its LDS allows
+// five blocks per CU
 template <class B>
-__global__ void k_csw_agrid(KARGS, Geo G, const B *u, const B *v, B *ua, B *va)
+struct CswRows {
+    static constexpr int Y = 8;
+};
+template <>
+struct CswRows<double> {
+    static constexpr int Y = 4;
+};
+
+// A-grid winds at a cell from the D-grid winds; CORNER = false for blocks
+// whose reads cannot reach a cube corner block (no view checks)
+template <class B, bool CORNER>
+DEVI B ua_at(const Geo &G, const B *U, const B *V, int i, int j)
 {
-    KBEGIN(G.nz);
-    if (in_corner(G, SC, i, j)) return;
-    long o = pidx(G, G.nz, t, k);
-    const B *U = u + o, *V = v + o;
-    if (j >= -2 && j <= G.n + 1) {
-        B a = pvx(G, U, V, SY, i, j - 1, 1, true), b = pvx(G, U, V, SY, i, j, 1, true),
-          c = pvx(G, U, V, SY, i, j + 1, 1, true), d = pvx(G, U, V, SY, i, j + 2, 1, true);
-        AT(ua + o, i, j) = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+    B a, b, c, d;
+    if constexpr (CORNER) {
+        a = pvx(G, U, V, SY, i, j - 1, 1, true), b = pvx(G, U, V, SY, i, j, 1, true);
+        c = pvx(G, U, V, SY, i, j + 1, 1, true), d = pvx(G, U, V, SY, i, j + 2, 1, true);
+    } else {
+        a = AT(U, i, j - 1), b = AT(U, i, j), c = AT(U, i, j + 1), d = AT(U, i, j + 2);
     }
-    if (i >= -2 && i <= G.n + 1) {
-        B a = pvy(G, U, V, SX, i - 1, j, 0, true), b = pvy(G, U, V, SX, i, j, 0, true),
-          c = pvy(G, U, V, SX, i + 1, j, 0, true), d = pvy(G, U, V, SX, i + 2, j, 0, true);
-        AT(va + o, i, j) = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+    return (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+}
+template <class B, bool CORNER>
+DEVI B va_at(const Geo &G, const B *U, const B *V, int i, int j)
+{
+    B a, b, c, d;
+    if constexpr (CORNER) {
+        a = pvy(G, U, V, SX, i - 1, j, 0, true), b = pvy(G, U, V, SX, i, j, 0, true);
+        c = pvy(G, U, V, SX, i + 1, j, 0, true), d = pvy(G, U, V, SX, i + 2, j, 0, true);
+    } else {
+        a = AT(V, i - 1, j), b = AT(V, i, j), c = AT(V, i + 1, j), d = AT(V, i + 2, j);
     }
+    return (-a + (B)9 * b + (B)9 * c - d) / (B)16;
 }
 
-// C-grid winds before the update, normal-wind area fluxes over dt2 and the
-// first-order upwind fluxes of delp, pt*delp, w*delp on the faces around the
-// half-step cells (-1..n in both directions, without the four corner cells).
-template <class B>
-__global__ void k_csw_faces(KARGS, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *delp,
-                            const B *pt, const B *w, const B *ua, const B *va, B *ucp, B *vcp,
-                            B *ax, B *ay, B *Fm, B *Fp, B *Fw, B *Gm, B *Gp, B *Gw)
+// LDS elements of one c_sw block
+template <int CTY>
+constexpr int csw_lds()
 {
-    KBEGIN(G.nz);
-    int n = G.n;
-    long o = pidx(G, G.nz, t, k);
-    const B *UA = ua + o, *VA = va + o, *D = delp + o, *PT = pt + o, *W = w + o;
-    bool xf = (j >= -1 && j <= n) && ((j >= 0 && j < n) ? (i >= -1 && i <= n + 1) : (i >= 0 && i <= n));
-    bool yf = (i >= -1 && i <= n) && ((i >= 0 && i < n) ? (j >= -1 && j <= n + 1) : (j >= 0 && j <= n));
-    if (xf) {
-        B a = pvx(G, UA, VA, SC, i - 2, j, 0, true), b = pvx(G, UA, VA, SC, i - 1, j, 0, true),
-          c = pvx(G, UA, VA, SC, i, j, 0, true), d = pvx(G, UA, VA, SC, i + 1, j, 0, true);
-        B uc0 = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
-        B fl = dt2 * (uc0 - AT(v + o, i, j) * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j) *
-               AT(MP(M, M_DY), i, j);
-        int up = fl > 0 ? i - 1 : i;
-        B fm = fl * sv(G, D, SC, up, j, 0);
-        AT(ucp + o, i, j) = uc0;
-        AT(ax + o, i, j) = fl;
-        AT(Fm + o, i, j) = fm;
-        AT(Fp + o, i, j) = fm * sv(G, PT, SC, up, j, 0);
-        AT(Fw + o, i, j) = fm * sv(G, W, SC, up, j, 0);
-    }
-    if (yf) {
-        B a = pvy(G, UA, VA, SC, i, j - 2, 1, true), b = pvy(G, UA, VA, SC, i, j - 1, 1, true),
-          c = pvy(G, UA, VA, SC, i, j, 1, true), d = pvy(G, UA, VA, SC, i, j + 1, 1, true);
-        B vc0 = (-a + (B)9 * b + (B)9 * c - d) / (B)16;
-        B fl = dt2 * (vc0 - AT(u + o, i, j) * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j) *
-               AT(MP(M, M_DX), i, j);
-        int up = fl > 0 ? j - 1 : j;
-        B gm = fl * sv(G, D, SC, i, up, 1);
-        AT(vcp + o, i, j) = vc0;
-        AT(ay + o, i, j) = fl;
-        AT(Gm + o, i, j) = gm;
-        AT(Gp + o, i, j) = gm * sv(G, PT, SC, i, up, 1);
-        AT(Gw + o, i, j) = gm * sv(G, W, SC, i, up, 1);
-    }
+    return 2 * (CTY + 5) * (CTX + 5) + 3 * (CTY + 3) * (CTX + 3) + 8 * (CTY + 2) * (CTX + 2) + 2 * (CTY + 1) * (CTX + 1);
 }
 
-// Half-step cell values and kinetic energy on the cross of cells -1..n;
-// absolute vorticity on the corners 0..n (C-grid circulation; at a cube
-// vertex the two faces next to the missing corner cell each count half).
-template <class B>
-__global__ void k_csw_cells(KARGS, Geo G, Mets<B> M, B dt2, const B *delp, const B *pt, const B *w,
-                            const B *ua, const B *va, const B *ucp, const B *vcp, const B *Fm,
-                            const B *Fp, const B *Fw, const B *Gm, const B *Gp, const B *Gw,
-                            B *delpc, B *ptc, B *wc, B *ke, B *vort)
+template <class B, bool CORNER>
+DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *delp, const B *pt,
+                   const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc, B *ax, B *ay)
 {
-    KBEGIN(G.nz);
-    int n = G.n;
-    long o = pidx(G, G.nz, t, k);
-    bool cross = (i >= 0 && i < n) || (j >= 0 && j < n);
-    if (cross) {
-        B ar = AT(MP(M, M_AREA), i, j);
-        B dp = AT(delp + o, i, j);
-        B dc = dp + (AT(Fm + o, i, j) - AT(Fm + o, i + 1, j) + AT(Gm + o, i, j) - AT(Gm + o, i, j + 1)) / ar;
-        AT(delpc + o, i, j) = dc;
-        AT(ptc + o, i, j) =
-            (AT(pt + o, i, j) * dp + (AT(Fp + o, i, j) - AT(Fp + o, i + 1, j) + AT(Gp + o, i, j) - AT(Gp + o, i, j + 1)) / ar) / dc;
-        AT(wc + o, i, j) =
-            (AT(w + o, i, j) * dp + (AT(Fw + o, i, j) - AT(Fw + o, i + 1, j) + AT(Gw + o, i, j) - AT(Gw + o, i, j + 1)) / ar) / dc;
-        B sa = AT(MP(M, M_SIN_A), i, j), ca = AT(MP(M, M_COS_A), i, j);
-        B s2 = sa * sa;
-        B a = AT(ua + o, i, j), b = AT(va + o, i, j);
-        B uu = (a - b * ca) / s2, vv = (b - a * ca) / s2;
-        AT(ke + o, i, j) = (B)0.5 * dt2 *
-                           (uu * (uu > 0 ? AT(ucp + o, i, j) : AT(ucp + o, i + 1, j)) +
-                            vv * (vv > 0 ? AT(vcp + o, i, j) : AT(vcp + o, i, j + 1)));
-    }
-    if (i >= 0 && i <= n && j >= 0 && j <= n) {
-        B ws = 1, wn = 1, ww = 1, we = 1;
-        if (is_vertex(G, i, j)) {
-            if (j == 0) ws = 0.5; else wn = 0.5;
-            if (i == 0) ww = 0.5; else we = 0.5;
+    constexpr int CTY = CswRows<B>::Y;
+    constexpr int WA = CTX + 5, HA = CTY + 5;   // A-grid cells i0-3.., j0-3..
+    constexpr int WD = CTX + 3, HD = CTY + 3;   // delp/pt/w cells i0-2.., j0-2..
+    constexpr int WF = CTX + 2, HF = CTY + 2;   // faces i0-1.., j0-1..
+    constexpr int WK = CTX + 1, HK = CTY + 1;   // ke cells i0-1..; vorticity corners i0..
+    B *sUA = L, *sVA = sUA + HA * WA;
+    B *sD = sVA + HA * WA, *sPT = sD + HD * WD, *sW = sPT + HD * WD;
+    B *sUC = sW + HD * WD, *sFm = sUC + HF * WF, *sFp = sFm + HF * WF, *sFw = sFp + HF * WF;
+    B *sVC = sFw + HF * WF, *sGm = sVC + HF * WF, *sGp = sGm + HF * WF, *sGw = sGp + HF * WF;
+    B *sKE = sGw + HF * WF, *sVO = sKE + HK * WK;
+    const int n = G.n, tid = threadIdx.x;
+    const int i0 = -CTX + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;   // i0: 32-aligned, first tile holds i = -1
+    const int t = bk.z / G.nz, k = bk.z % G.nz;
+    const long o = pidx(G, G.nz, t, k);
+    const B *U = u + o, *V = v + o, *D = delp + o, *PT = pt + o, *Wf = w + o;
+
+    auto inA = [&](int i, int j) { return i >= i0 - 3 && i <= i0 + CTX + 1 && j >= j0 - 3 && j <= j0 + CTY + 1; };
+    auto aA = [&](int i, int j) { return (j - (j0 - 3)) * WA + (i - (i0 - 3)); };
+    auto inD = [&](int i, int j) { return i >= i0 - 2 && i <= i0 + CTX && j >= j0 - 2 && j <= j0 + CTY; };
+    auto aD = [&](int i, int j) { return (j - (j0 - 2)) * WD + (i - (i0 - 2)); };
+    auto aF = [&](int i, int j) { return (j - (j0 - 1)) * WF + (i - (i0 - 1)); };
+    auto aK = [&](int i, int j) { return (j - (j0 - 1)) * WK + (i - (i0 - 1)); };
+    auto aV = [&](int i, int j) { return (j - j0) * WK + (i - i0); };
+
+    // A-grid vector through the corner view (x / y component), from LDS
+    // when the source cell is staged, else recomputed from the D-grid winds
+    auto UAx = [&](int i, int j, int mode) -> B {
+        if (CORNER && in_corner(G, SC, i, j)) {
+            int qi, qj;
+            bool cw;
+            corner_src(G, SC, i, j, mode, qi, qj, cw);
+            B val = inA(qi, qj) ? sVA[aA(qi, qj)] : va_at<B, true>(G, U, V, qi, qj);
+            return cw ? -val : val;
         }
-        B circ = ws * AT(ucp + o, i, j - 1) * AT(MP(M, M_DXC), i, j - 1) -
-                 wn * AT(ucp + o, i, j) * AT(MP(M, M_DXC), i, j) -
-                 ww * AT(vcp + o, i - 1, j) * AT(MP(M, M_DYC), i - 1, j) +
-                 we * AT(vcp + o, i, j) * AT(MP(M, M_DYC), i, j);
-        AT(vort + o, i, j) = AT(MP(M, M_FB), i, j) + circ / AT(MP(M, M_AREA_C), i, j);
+        return sUA[aA(i, j)];
+    };
+    auto VAy = [&](int i, int j, int mode) -> B {
+        if (CORNER && in_corner(G, SC, i, j)) {
+            int qi, qj;
+            bool cw;
+            corner_src(G, SC, i, j, mode, qi, qj, cw);
+            B val = inA(qi, qj) ? sUA[aA(qi, qj)] : ua_at<B, true>(G, U, V, qi, qj);
+            return !cw ? -val : val;
+        }
+        return sVA[aA(i, j)];
+    };
+    // cell scalar through the corner view
+    auto cv = [&](const B *sArr, const B *gArr, int i, int j, int mode) -> B {
+        if (CORNER && in_corner(G, SC, i, j)) {
+            int qi, qj;
+            bool cw;
+            corner_src(G, SC, i, j, mode, qi, qj, cw);
+            return inD(qi, qj) ? sArr[aD(qi, qj)] : AT(gArr, qi, qj);
+        }
+        return sArr[aD(i, j)];
+    };
+
+    // 1. A-grid winds and cell scalars (corner cells are not stored)
+    for (int e = tid; e < HA * WA; e += CNT) {
+        int r = e / WA, c = e - r * WA;
+        int i = i0 - 3 + c, j = j0 - 3 + r;
+        B a = 0, b = 0;
+        if (i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2 && !(CORNER && in_corner(G, SC, i, j))) {
+            if (j >= -2 && j <= n + 1) a = ua_at<B, CORNER>(G, U, V, i, j);
+            if (i >= -2 && i <= n + 1) b = va_at<B, CORNER>(G, U, V, i, j);
+        }
+        sUA[e] = a;
+        sVA[e] = b;
+    }
+    for (int e = tid; e < HD * WD; e += CNT) {
+        int r = e / WD, c = e - r * WD;
+        int i = i0 - 2 + c, j = j0 - 2 + r;
+        B a = 0, b = 0, c2 = 0;
+        if (i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2 && !(CORNER && in_corner(G, SC, i, j))) {
+            a = AT(D, i, j);
+            b = AT(PT, i, j);
+            c2 = AT(Wf, i, j);
+        }
+        sD[e] = a;
+        sPT[e] = b;
+        sW[e] = c2;
+    }
+    __syncthreads();
+    // 2. C-grid faces: winds before the update, area fluxes, upwind fluxes
+    for (int e = tid; e < HF * WF; e += CNT) {
+        int r = e / WF, c = e - r * WF;
+        int i = i0 - 1 + c, j = j0 - 1 + r;
+        bool own = i >= i0 && i < i0 + CTX && j >= j0 && j < j0 + CTY;
+        bool xf = (j >= -1 && j <= n) && ((j >= 0 && j < n) ? (i >= -1 && i <= n + 1) : (i >= 0 && i <= n));
+        bool yf = (i >= -1 && i <= n) && ((i >= 0 && i < n) ? (j >= -1 && j <= n + 1) : (j >= 0 && j <= n));
+        B uc0 = 0, fm = 0, fp = 0, fw = 0;
+        if (xf) {
+            B a = UAx(i - 2, j, 0), b = UAx(i - 1, j, 0), c1 = UAx(i, j, 0), d = UAx(i + 1, j, 0);
+            uc0 = (-a + (B)9 * b + (B)9 * c1 - d) / (B)16;
+            B fl = dt2 * (uc0 - AT(V, i, j) * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j) *
+                   AT(MP(M, M_DY), i, j);
+            int up = fl > 0 ? i - 1 : i;
+            fm = fl * cv(sD, D, up, j, 0);
+            fp = fm * cv(sPT, PT, up, j, 0);
+            fw = fm * cv(sW, Wf, up, j, 0);
+            if (own) AT(ax + o, i, j) = fl;
+        }
+        sUC[e] = uc0;
+        sFm[e] = fm;
+        sFp[e] = fp;
+        sFw[e] = fw;
+        B vc0 = 0, gm = 0, gp = 0, gw = 0;
+        if (yf) {
+            B a = VAy(i, j - 2, 1), b = VAy(i, j - 1, 1), c1 = VAy(i, j, 1), d = VAy(i, j + 1, 1);
+            vc0 = (-a + (B)9 * b + (B)9 * c1 - d) / (B)16;
+            B fl = dt2 * (vc0 - AT(U, i, j) * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j) *
+                   AT(MP(M, M_DX), i, j);
+            int up = fl > 0 ? j - 1 : j;
+            gm = fl * cv(sD, D, i, up, 1);
+            gp = gm * cv(sPT, PT, i, up, 1);
+            gw = gm * cv(sW, Wf, i, up, 1);
+            if (own) AT(ay + o, i, j) = fl;
+        }
+        sVC[e] = vc0;
+        sGm[e] = gm;
+        sGp[e] = gp;
+        sGw[e] = gw;
+    }
+    __syncthreads();
+    // 3. half-step cells (own points) and kinetic energy (one ring wider);
+    //    absolute vorticity at the corners
+    for (int e = tid; e < HK * WK; e += CNT) {
+        int r = e / WK, c = e - r * WK;
+        int i = i0 - 1 + c, j = j0 - 1 + r;
+        bool cross = i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
+        B kev = 0;
+        if (cross) {
+            B sa = AT(MP(M, M_SIN_A), i, j), ca = AT(MP(M, M_COS_A), i, j);
+            B s2 = sa * sa;
+            B a = sUA[aA(i, j)], b = sVA[aA(i, j)];
+            B uu = (a - b * ca) / s2, vv = (b - a * ca) / s2;
+            kev = (B)0.5 * dt2 * (uu * (uu > 0 ? sUC[aF(i, j)] : sUC[aF(i + 1, j)]) +
+                                  vv * (vv > 0 ? sVC[aF(i, j)] : sVC[aF(i, j + 1)]));
+            if (i >= i0 && j >= j0) {
+                B ar = AT(MP(M, M_AREA), i, j);
+                B dp = sD[aD(i, j)];
+                B dc = dp + (sFm[aF(i, j)] - sFm[aF(i + 1, j)] + sGm[aF(i, j)] - sGm[aF(i, j + 1)]) / ar;
+                AT(delpc + o, i, j) = dc;
+                AT(ptc + o, i, j) =
+                    (sPT[aD(i, j)] * dp + (sFp[aF(i, j)] - sFp[aF(i + 1, j)] + sGp[aF(i, j)] - sGp[aF(i, j + 1)]) / ar) / dc;
+                AT(wc + o, i, j) =
+                    (sW[aD(i, j)] * dp + (sFw[aF(i, j)] - sFw[aF(i + 1, j)] + sGw[aF(i, j)] - sGw[aF(i, j + 1)]) / ar) / dc;
+            }
+        }
+        sKE[e] = kev;
+    }
+    for (int e = tid; e < HK * WK; e += CNT) {
+        int r = e / WK, c = e - r * WK;
+        int i = i0 + c, j = j0 + r;
+        B vo = 0;
+        if (i >= 0 && i <= n && j >= 0 && j <= n) {
+            B ws = 1, wn = 1, ww = 1, we = 1;
+            if (CORNER && is_vertex(G, i, j)) {
+                if (j == 0) ws = 0.5; else wn = 0.5;
+                if (i == 0) ww = 0.5; else we = 0.5;
+            }
+            B circ = ws * sUC[aF(i, j - 1)] * AT(MP(M, M_DXC), i, j - 1) - wn * sUC[aF(i, j)] * AT(MP(M, M_DXC), i, j) -
+                     ww * sVC[aF(i - 1, j)] * AT(MP(M, M_DYC), i - 1, j) + we * sVC[aF(i, j)] * AT(MP(M, M_DYC), i, j);
+            vo = AT(MP(M, M_FB), i, j) + circ / AT(MP(M, M_AREA_C), i, j);
+        }
+        sVO[e] = vo;
+    }
+    __syncthreads();
+    // 4. C-grid wind update on the interior faces of the own points
+    for (int e = tid; e < CTX * CTY; e += CNT) {
+        int r = e / CTX, c = e - r * CTX;
+        int i = i0 + c, j = j0 + r;
+        if (i >= 0 && i <= n && j >= 0 && j < n) {
+            B u0 = sUC[aF(i, j)];
+            B fy1 = dt2 * (AT(V, i, j) - u0 * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j);
+            B vt = fy1 > 0 ? sVO[aV(i, j)] : sVO[aV(i, j + 1)];
+            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) / AT(MP(M, M_DXC), i, j);
+        }
+        if (i >= 0 && i < n && j >= 0 && j <= n) {
+            B v0 = sVC[aF(i, j)];
+            B fx1 = dt2 * (AT(U, i, j) - v0 * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j);
+            B vt = fx1 > 0 ? sVO[aV(i, j)] : sVO[aV(i + 1, j)];
+            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) / AT(MP(M, M_DYC), i, j);
+        }
     }
 }
 
-// C-grid wind update on the interior faces: upwinded vorticity flux plus
-// kinetic-energy gradient.
 template <class B>
-__global__ void k_csw_update(KARGS, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *ucp,
-                             const B *vcp, const B *ke, const B *vort, B *uc, B *vc)
+DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *delp, const B *pt,
+                const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc, B *ax, B *ay)
 {
-    KBEGIN(G.nz);
-    int n = G.n;
-    long o = pidx(G, G.nz, t, k);
-    if (j < n) {
-        B u0 = AT(ucp + o, i, j);
-        B fy1 = dt2 * (AT(v + o, i, j) - u0 * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j);
-        B vt = fy1 > 0 ? AT(vort + o, i, j) : AT(vort + o, i, j + 1);
-        AT(uc + o, i, j) = u0 + fy1 * vt + (AT(ke + o, i - 1, j) - AT(ke + o, i, j)) / AT(MP(M, M_DXC), i, j);
-    }
-    if (i < n) {
-        B v0 = AT(vcp + o, i, j);
-        B fx1 = dt2 * (AT(u + o, i, j) - v0 * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j);
-        B vt = fx1 > 0 ? AT(vort + o, i, j) : AT(vort + o, i + 1, j);
-        AT(vc + o, i, j) = v0 - fx1 * vt + (AT(ke + o, i, j - 1) - AT(ke + o, i, j)) / AT(MP(M, M_DYC), i, j);
-    }
+    // a block needs the corner views only if its reads (tile, staging halo
+    // and the interpolation stencils around it) reach a cube corner block
+    constexpr int CTY = CswRows<B>::Y;
+    const int n = G.n;
+    const int i0 = -CTX + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
+    const bool nx = i0 - 6 < 0 || i0 + CTX + 5 > n, ny = j0 - 6 < 0 || j0 + CTY + 5 > n;
+    __shared__ B L[csw_lds<CTY>()];
+    if (G.cube && nx && ny)
+        csw_body<B, true>(bk, L, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+    else
+        csw_body<B, false>(bk, L, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
 }
 
 // ====================================================================
@@ -412,13 +670,13 @@ DEVI double zs_at(const Geo &G, const double *phis, int t, int i, int j, int mod
 // interface heights with layer-averaged area fluxes (top interface: top
 // layer), advective form, surface fixed; output the half-step thicknesses.
 template <class B>
-__global__ void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, const B *ax,
+DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, const B *ax,
                       const B *ay, double *delzc)
 {
-    int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    if (i > ihi || j > jhi) return;
-    int n = G.n, nz = G.nz, t = blockIdx.z;
+    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+    if (i < ilo || i > ihi || j > jhi) return;
+    int n = G.n, nz = G.nz, t = bk.z;
     if (!((i >= 0 && i < n) || (j >= 0 && j < n))) return;
     double area = AT(MP(M, M_AREA), i, j);
     double zc = zs_at(G, phis, t, i, j, 0);
@@ -451,128 +709,232 @@ __global__ void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *ph
 // pressure from the equation of state, mass-weighted interface perturbation,
 // backward-Euler tridiagonal system in w (Thomas), new perturbation by a
 // top-down scan, thickness by inverting the equation of state, heights by a
-// bottom-up scan.  Elimination coefficients live in FP64 scratch columns;
-// every pass loads the next level one iteration ahead.
-template <class B, class TW>
-__global__ void __launch_bounds__(256) k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
+// bottom-up scan.  Elimination coefficients live in FP64 scratch columns.
+// The four passes are four launches (PASS = 1..4): one thread per column
+// each, so that the light passes run at high occupancy and the two passes
+// with the equation of state are not limited by the registers of the others.
+// Every pass walks the column in groups of levels and issues the next
+// group's loads before computing the current one.
+#ifndef FV3_SIM1_SU
+#define FV3_SIM1_SU 1
+#endif
+constexpr int SU = FV3_SIM1_SU;   // levels per prefetch group, passes 1 and 3
+constexpr int SU2 = 8;            // levels per prefetch group, passes 2 and 4
+
+// SITE tells the two solves apart in profiles (0 riem_solver_c, 1 riem_solver3)
+template <class B, class TW, int PASS, int SITE>
+DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
                                               const B *theta, const double *delz, const TW *w,
                                               const double *phis, double *cpv, double *dpv,
                                               double *wnv, TW *w_out, double *delz_out,
                                               double *pfull, double *phi, int need_cross)
 {
-    int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    if (i > ihi || j > jhi) return;
-    int n = G.n, nz = G.nz, t = blockIdx.z;
+    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+    if (i < ilo || i > ihi || j > jhi) return;
+    int n = G.n, nz = G.nz, t = bk.z;
     if (need_cross && !((i >= 0 && i < n) || (j >= 0 && j < n))) return;
     const double kap = RDGAS / CP_AIR, gam = 1.0 / (1.0 - kap), rgam = 1.0 / gam;
     const long base = pidx(G, nz, t, 0) + (long)j * G.pitch + i, lev = G.lev;
     const long basei = pidx(G, nz + 1, t, 0) + (long)j * G.pitch + i;
     const double dt2x = dt * dt;
+    // Each pass walks the column in groups of SU levels and issues the loads
+    // of the next group before computing the current one, so that SU levels
+    // of every input are in flight per thread (the column recurrences are
+    // sequential; this is what hides HBM latency).
+    struct G4 {
+        double a[SU], b[SU], c[SU], d[SU];
+    };
+    struct G2 {
+        double a[SU2], b[SU2];
+    };
+    (void)dt2x;
+    (void)rgam;
 
-    // ---- pass 1: top-down elimination with a one-layer look-ahead
+    // ---- pass 1: top-down elimination; step k consumes layer k + 1
+    if constexpr (PASS == 1) {
     double lpi_k = log(ptop);
     double dp0 = (double)dpi[base], th0 = (double)theta[base], h0 = -delz[base], w0 = (double)w[base];
     double pi_k1 = ptop + dp0, lpi_k1 = log(pi_k1);
     double m0 = dp0 / GRAV;
-    double pp0 = P_REF * pow(RDGAS * th0 * m0 / (h0 * P_REF), gam) - dp0 / (lpi_k1 - lpi_k);
-    // prefetched layer k+1
-    double dpn = 0, thn = 0, hn_ = 0, wn_ = 0;
-    if (nz > 1) {
-        dpn = (double)dpi[base + lev];
-        thn = (double)theta[base + lev];
-        hn_ = -delz[base + lev];
-        wn_ = (double)w[base + lev];
-    }
+    double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi_k1 - lpi_k);
     double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0;
-    for (int k = 0; k < nz; k++) {
-        double dp1 = dpn, th1 = thn, h1 = hn_, w1 = wn_;
-        if (k + 2 < nz) {   // issue the loads of layer k+2 now
-            long o2 = base + (long)(k + 2) * lev;
-            dpn = (double)dpi[o2];
-            thn = (double)theta[o2];
-            hn_ = -delz[o2];
-            wn_ = (double)w[o2];
-        }
-        double pps_k1, A_k1, pi_k2 = 0, lpi_k2 = 0, m1 = 0, pp1 = 0;
-        if (k < nz - 1) {
-            pi_k2 = pi_k1 + dp1;
-            lpi_k2 = log(pi_k2);
-            m1 = dp1 / GRAV;
-            pp1 = P_REF * pow(RDGAS * th1 * m1 / (h1 * P_REF), gam) - dp1 / (lpi_k2 - lpi_k1);
-            pps_k1 = (dp1 * pp0 + dp0 * pp1) / (dp0 + dp1);
-            A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
-        } else {
-            pps_k1 = pp0;
-            A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * h0);
-        }
-        double lower = k > 0 ? -A_k : 0.0;
-        double diag = m0 + A_k + A_k1;
-        double upper = k < nz - 1 ? -A_k1 : 0.0;
-        double rhs = m0 * w0 + dt * (pps_k1 - pps_k);
-        double piv = diag - lower * cprev;
-        double ck = upper / piv;
-        double dk = (rhs - lower * dprev) / piv;
-        cpv[base + (long)k * lev] = ck;
-        dpv[base + (long)k * lev] = dk;
-        cprev = ck;
-        dprev = dk;
-        pi_k1 = pi_k2; lpi_k1 = lpi_k2; dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1; th0 = th1; w0 = w1;
-        pps_k = pps_k1; A_k = A_k1;
-    }
-    (void)th0;
-    // ---- pass 2: back substitution (bottom-up)
     {
-        double wv = 0.0;
-        double cn = cpv[base + (long)(nz - 1) * lev], dn = dpv[base + (long)(nz - 1) * lev];
-        for (int k = nz - 1; k >= 0; k--) {
-            double ck = cn, dk = dn;
-            if (k > 0) {
-                cn = cpv[base + (long)(k - 1) * lev];
-                dn = dpv[base + (long)(k - 1) * lev];
+        G4 cur, nxt;
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            int kk = 1 + u;
+            long o = base + (long)kk * lev;
+            bool in = kk < nz;
+            cur.a[u] = in ? (double)dpi[o] : 0.0;
+            cur.b[u] = in ? (double)theta[o] : 0.0;
+            cur.c[u] = in ? -delz[o] : 0.0;
+            cur.d[u] = in ? (double)w[o] : 0.0;
+        }
+        for (int k0 = 0; k0 < nz; k0 += SU) {
+            if (k0 + SU < nz) {
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    int kk = k0 + SU + 1 + u;
+                    long o = base + (long)kk * lev;
+                    bool in = kk < nz;
+                    nxt.a[u] = in ? (double)dpi[o] : 0.0;
+                    nxt.b[u] = in ? (double)theta[o] : 0.0;
+                    nxt.c[u] = in ? -delz[o] : 0.0;
+                    nxt.d[u] = in ? (double)w[o] : 0.0;
+                }
             }
-            wv = dk - ck * wv;
-            wnv[base + (long)k * lev] = wv;
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                int k = k0 + u;
+                if (k < nz) {
+                    double dp1 = cur.a[u], th1 = cur.b[u], h1 = cur.c[u], w1 = cur.d[u];
+                    double pps_k1, A_k1, pi_k2 = 0, lpi_k2 = 0, m1 = 0, pp1 = 0;
+                    if (k < nz - 1) {
+                        pi_k2 = pi_k1 + dp1;
+                        lpi_k2 = log(pi_k2);
+                        m1 = dp1 / GRAV;
+                        pp1 = P_REF * exp(gam * log(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi_k2 - lpi_k1);
+                        pps_k1 = (dp1 * pp0 + dp0 * pp1) / (dp0 + dp1);
+                        A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
+                    } else {
+                        pps_k1 = pp0;
+                        A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * h0);
+                    }
+                    double lower = k > 0 ? -A_k : 0.0;
+                    double diag = m0 + A_k + A_k1;
+                    double upper = k < nz - 1 ? -A_k1 : 0.0;
+                    double rhs = m0 * w0 + dt * (pps_k1 - pps_k);
+                    double piv = diag - lower * cprev;
+                    double rpiv = 1.0 / piv;
+                    double ck = upper * rpiv;
+                    double dk = (rhs - lower * dprev) * rpiv;
+                    cpv[base + (long)k * lev] = ck;
+                    dpv[base + (long)k * lev] = dk;
+                    cprev = ck;
+                    dprev = dk;
+                    pi_k1 = pi_k2; lpi_k1 = lpi_k2; dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1; w0 = w1;
+                    pps_k = pps_k1; A_k = A_k1;
+                }
+            }
+            cur = nxt;
+        }
+    }
+    }
+    // ---- pass 2: back substitution (bottom-up)
+    if constexpr (PASS == 2) {
+        double wv = 0.0;
+        G2 cur, nxt;
+#pragma unroll
+        for (int u = 0; u < SU2; u++) {
+            int kk = nz - 1 - u;
+            long o = base + (long)kk * lev;
+            cur.a[u] = kk >= 0 ? cpv[o] : 0.0;
+            cur.b[u] = kk >= 0 ? dpv[o] : 0.0;
+        }
+        for (int k0 = nz - 1; k0 >= 0; k0 -= SU2) {
+            if (k0 - SU2 >= 0) {
+#pragma unroll
+                for (int u = 0; u < SU2; u++) {
+                    int kk = k0 - SU2 - u;
+                    long o = base + (long)kk * lev;
+                    nxt.a[u] = kk >= 0 ? cpv[o] : 0.0;
+                    nxt.b[u] = kk >= 0 ? dpv[o] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU2; u++) {
+                int k = k0 - u;
+                if (k >= 0) {
+                    wv = cur.b[u] - cur.a[u] * wv;
+                    wnv[base + (long)k * lev] = wv;
+                }
+            }
+            cur = nxt;
         }
     }
     // ---- pass 3: new perturbation (top down), thicknesses, interface pressure
-    {
+    if constexpr (PASS == 3) {
+        const double lpref = log(P_REF);
         double ppn = 0.0, pik = ptop, lpik = log(ptop);
         if (pfull) pfull[basei] = ptop;
-        double dpa = (double)dpi[base], tha = (double)theta[base], wa = wnv[base], woa = (double)w[base];
-        for (int k = 0; k < nz; k++) {
-            double dp = dpa, th = tha, wk = wa, wo = woa;
-            if (k + 1 < nz) {
-                long o1 = base + (long)(k + 1) * lev;
-                dpa = (double)dpi[o1];
-                tha = (double)theta[o1];
-                wa = wnv[o1];
-                woa = (double)w[o1];
+        G4 cur, nxt;
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            int kk = u;
+            long o = base + (long)kk * lev;
+            bool in = kk < nz;
+            cur.a[u] = in ? (double)dpi[o] : 0.0;
+            cur.b[u] = in ? (double)theta[o] : 0.0;
+            cur.c[u] = in ? wnv[o] : 0.0;
+            cur.d[u] = in ? (double)w[o] : 0.0;
+        }
+        for (int k0 = 0; k0 < nz; k0 += SU) {
+            if (k0 + SU < nz) {
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    int kk = k0 + SU + u;
+                    long o = base + (long)kk * lev;
+                    bool in = kk < nz;
+                    nxt.a[u] = in ? (double)dpi[o] : 0.0;
+                    nxt.b[u] = in ? (double)theta[o] : 0.0;
+                    nxt.c[u] = in ? wnv[o] : 0.0;
+                    nxt.d[u] = in ? (double)w[o] : 0.0;
+                }
             }
-            double m = dp / GRAV;
-            double pik1 = pik + dp, lpik1 = log(pik1);
-            double pib = dp / (lpik1 - lpik);
-            double ppn1 = ppn + m * (wk - wo) / dt;
-            double pn = pib + 0.5 * (ppn + ppn1);
-            double hn = RDGAS * th * m / P_REF * pow(P_REF / pn, rgam);
-            cpv[base + (long)k * lev] = hn;   // reuse as the new thickness
-            if (pfull) pfull[basei + (long)(k + 1) * lev] = pik1 + ppn1;
-            if (w_out) w_out[base + (long)k * lev] = (TW)wk;
-            ppn = ppn1;
-            pik = pik1;
-            lpik = lpik1;
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                int k = k0 + u;
+                if (k < nz) {
+                    double dp = cur.a[u], th = cur.b[u], wk = cur.c[u], wo = cur.d[u];
+                    double m = dp / GRAV;
+                    double pik1 = pik + dp, lpik1 = log(pik1);
+                    double pib = dp / (lpik1 - lpik);
+                    double ppn1 = ppn + m * (wk - wo) / dt;
+                    double pn = pib + 0.5 * (ppn + ppn1);
+                    double hn = RDGAS * th * m / P_REF * exp(rgam * (lpref - log(pn)));
+                    cpv[base + (long)k * lev] = hn;   // reuse as the new thickness
+                    if (pfull) pfull[basei + (long)(k + 1) * lev] = pik1 + ppn1;
+                    if (w_out) w_out[base + (long)k * lev] = (TW)wk;
+                    ppn = ppn1;
+                    pik = pik1;
+                    lpik = lpik1;
+                }
+            }
+            cur = nxt;
         }
     }
     // ---- pass 4: heights (bottom up)
-    double z = phis ? phis[pidx(G, 1, t, 0) + (long)j * G.pitch + i] / GRAV : 0.0;
-    if (phi) phi[basei + (long)nz * lev] = GRAV * z;
-    double hnext = cpv[base + (long)(nz - 1) * lev];
-    for (int k = nz - 1; k >= 0; k--) {
-        double hn = hnext;
-        if (k > 0) hnext = cpv[base + (long)(k - 1) * lev];
-        z += hn;
-        if (phi) phi[basei + (long)k * lev] = GRAV * z;
-        if (delz_out) delz_out[base + (long)k * lev] = -hn;
+    if constexpr (PASS == 4) {
+        double z = phis ? phis[pidx(G, 1, t, 0) + (long)j * G.pitch + i] / GRAV : 0.0;
+        if (phi) phi[basei + (long)nz * lev] = GRAV * z;
+        double cur[SU2], nxt[SU2];
+#pragma unroll
+        for (int u = 0; u < SU2; u++) {
+            int kk = nz - 1 - u;
+            cur[u] = kk >= 0 ? cpv[base + (long)kk * lev] : 0.0;
+        }
+        for (int k0 = nz - 1; k0 >= 0; k0 -= SU2) {
+            if (k0 - SU2 >= 0) {
+#pragma unroll
+                for (int u = 0; u < SU2; u++) {
+                    int kk = k0 - SU2 - u;
+                    nxt[u] = kk >= 0 ? cpv[base + (long)kk * lev] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU2; u++) {
+                int k = k0 - u;
+                if (k >= 0) {
+                    double hn = cur[u];
+                    z += hn;
+                    if (phi) phi[basei + (long)k * lev] = GRAV * z;
+                    if (delz_out) delz_out[base + (long)k * lev] = -hn;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU2; u++) cur[u] = nxt[u];
+        }
     }
 }
 
@@ -588,7 +950,7 @@ DEVI double pgf(double dt, double L, double dW, double dE, double zW0, double zW
 // p_grad_c on the interior C-grid faces with the half-step cells' pressure
 // and geopotential; layer mass weights from delpc.
 template <class B>
-__global__ void k_pgradc(KARGS, Geo G, MetD M, double dt2, const B *delpc, const double *pkc,
+DEVI void k_pgradc(KARGS, Geo G, MetD M, double dt2, const B *delpc, const double *pkc,
                          const double *gz, B *uc, B *vc)
 {
     KBEGIN(G.nz);
@@ -624,8 +986,17 @@ __global__ void k_pgradc(KARGS, Geo G, MetD M, double dt2, const B *delpc, const
 // of layers k-1 and k (plane 0: layer 0), for interface heights.
 // ====================================================================
 enum { EPI_FLUX = 0, EPI_DELP = 1, EPI_MASSW = 2, EPI_ADV = 3, EPI_TRACER = 4 };
-constexpr int FTX = 64, FTY = 16, FNT = 256;
-constexpr int QW = FTX + 6, QH = FTY + 6;
+// Cell tile per field precision (measured on MI355X at C192 x 79: the FP64
+// tile is smaller so that four blocks fit a CU's LDS at 256 threads each).
+constexpr int FNT = 256;
+template <class T>
+struct FvTile {
+    static constexpr int X = 32, Y = 16;
+};
+template <>
+struct FvTile<double> {
+    static constexpr int X = 32, Y = 8;
+};
 
 template <class T, class C, class M>
 struct FvArgs {
@@ -651,17 +1022,23 @@ DEVI T ccr(const C *a, long o, long ob, long idx, int avg)
     return (T)a[o + idx];
 }
 
-template <class T, class C, class M>
-__global__ void __launch_bounds__(FNT) k_fvtp(Geo G, FvArgs<T, C, M> A)
+template <class T, class C, class M, int EPI>
+DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
 {
-    __shared__ T sQ[QH * QW], sQy[QH * QW];
-    __shared__ T sFy[(FTY + 1) * (FTX + 6)];   // y-faces: cols i0-3..i0+FTX+2, rows j0..j0+FTY
-    __shared__ T sFx[(FTY + 6) * (FTX + 1)];   // x-faces: cols i0..i0+FTX, rows j0-3..j0+FTY+2
-    __shared__ T sQi[FTY * (FTX + 6)];         // cells: cols i0-3..i0+FTX+2, rows j0..j0+FTY-1
-    __shared__ T sQj[(FTY + 6) * FTX];         // cells: cols i0..i0+FTX-1, rows j0-3..j0+FTY+2
+    constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
+    constexpr int QW = FTX + 6, QH = FTY + 6;
+    constexpr int YW = FTX + 6, YH = FTY + 1;   // y-faces: cols i0-3..i0+FTX+2, rows j0..j0+FTY
+    constexpr int XW = FTX + 1, XH = FTY + 6;   // x-faces: cols i0..i0+FTX, rows j0-3..j0+FTY+2
+    constexpr int N4X = (FTY * XW + FNT - 1) / FNT, N4Y = (YH * FTX + FNT - 1) / FNT;
+    constexpr int N5 = (FTY * FTX + FNT - 1) / FNT;
+    __shared__ T sQ[QH * QW], sQy[QH * QW], sAR[QH * QW];
+    __shared__ T sCY[YH * YW], sYF[YH * YW], sFy[YH * YW];
+    __shared__ T sCX[XH * XW], sXF[XH * XW], sFx[XH * XW];
+    __shared__ T sQi[FTY * QW];                // cells: cols i0-3..i0+FTX+2, rows j0..j0+FTY-1
+    __shared__ T sQj[QH * FTX];                // cells: cols i0..i0+FTX-1, rows j0-3..j0+FTY+2
     const int n = G.n, tid = threadIdx.x;
-    const int i0 = blockIdx.x * FTX, j0 = blockIdx.y * FTY;
-    const int t = blockIdx.z / A.Lc, k = blockIdx.z % A.Lc;
+    const int i0 = bk.x * FTX, j0 = bk.y * FTY;
+    const int t = bk.z / A.Lc, k = bk.z % A.Lc;
     const T *Q = A.q + pidx(G, A.Lq, t, k);
     const long oc = pidx(G, A.Lc, t, k);
     const int avg = A.iface && k > 0;
@@ -669,141 +1046,199 @@ __global__ void __launch_bounds__(FNT) k_fvtp(Geo G, FvArgs<T, C, M> A)
     const T *AR = A.area + G.off0 + (long)t * G.lev;
     const long P = G.pitch;
 
-    // 1. field tile in the x-sweep and y-sweep views
+    // 0. per-thread prefetch of the global operands of phases 4 and 5
+    double wx[N4X], wy[N4Y], pa[N5], pb[N5];
+#pragma unroll
+    for (int m = 0; m < N4X; m++) {
+        int e = tid + m * FNT, r = e / XW, c = e - r * XW;
+        int i = i0 + c, j = j0 + r;
+        wx[m] = (A.mx && e < FTY * XW && i <= n && j < n) ? (double)A.mx[oc + (long)j * P + i] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < N4Y; m++) {
+        int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
+        int i = i0 + c, j = j0 + r;
+        wy[m] = (A.my && e < YH * FTX && i < n && j <= n) ? (double)A.my[oc + (long)j * P + i] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < N5; m++) {
+        int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
+        int i = i0 + c, j = j0 + r;
+        bool in = e < FTY * FTX && i < n && j < n;
+        long ci = (long)j * P + i;
+        pa[m] = 0.0;
+        pb[m] = 0.0;
+        if (in && EPI == EPI_MASSW) {
+            pa[m] = (double)A.dold[oc + ci];
+            pb[m] = (double)A.dnew[oc + ci];
+        } else if (in && EPI == EPI_TRACER) {
+            pa[m] = A.dp1[oc + ci];
+            pb[m] = A.dp2[oc + ci];
+        }
+    }
+    // 1. stage the field (both sweep views), the area, the Courant numbers and
+    //    the area fluxes of the tile and its halo
     for (int e = tid; e < QH * QW; e += FNT) {
         int r = e / QW, c = e - r * QW;
         int i = i0 - 3 + c, j = j0 - 3 + r;
-        T vx = 0, vy = 0;
+        T vx = 0, vy = 0, ar = 0;
         if (i <= n + 2 && j <= n + 2) {
             if (in_corner(G, SC, i, j)) {
                 vx = sv(G, Q, SC, i, j, 0);
                 vy = sv(G, Q, SC, i, j, 1);
             } else {
                 vx = vy = Q[(long)j * P + i];
+                ar = AR[(long)j * P + i];
             }
         }
         sQ[e] = vx;
         sQy[e] = vy;
+        sAR[e] = ar;
+    }
+    for (int e = tid; e < YH * YW; e += FNT) {
+        int r = e / YW, c = e - r * YW;
+        int i = i0 - 3 + c, j = j0 + r;
+        T cr = 0, fl = 0;
+        if (i <= n + 2 && j <= n) {
+            cr = ccr<T>(A.cry, oc, ob, (long)j * P + i, avg);
+            fl = ccr<T>(A.yfx, oc, ob, (long)j * P + i, avg);
+        }
+        sCY[e] = cr;
+        sYF[e] = fl;
+    }
+    for (int e = tid; e < XH * XW; e += FNT) {
+        int r = e / XW, c = e - r * XW;
+        int i = i0 + c, j = j0 - 3 + r;
+        T cr = 0, fl = 0;
+        if (i <= n && j <= n + 2) {
+            cr = ccr<T>(A.crx, oc, ob, (long)j * P + i, avg);
+            fl = ccr<T>(A.xfx, oc, ob, (long)j * P + i, avg);
+        }
+        sCX[e] = cr;
+        sXF[e] = fl;
     }
     __syncthreads();
     // 2. outer fluxes of the field
-    for (int e = tid; e < (FTY + 1) * (FTX + 6); e += FNT) {
-        int r = e / (FTX + 6), c = e - r * (FTX + 6);
+    for (int e = tid; e < YH * YW; e += FNT) {
+        int r = e / YW, c = e - r * YW;
         int i = i0 - 3 + c, j = j0 + r;
         T f = 0;
         if (i <= n + 2 && j <= n) {
-            T cr = ccr<T>(A.cry, oc, ob, (long)j * P + i, avg);
             const T *col = sQy + r * QW + c;
-            f = ppm6(col[0], col[QW], col[2 * QW], col[3 * QW], col[4 * QW], col[5 * QW], cr);
+            f = ppm6(col[0], col[QW], col[2 * QW], col[3 * QW], col[4 * QW], col[5 * QW], sCY[e]);
         }
         sFy[e] = f;
     }
-    for (int e = tid; e < (FTY + 6) * (FTX + 1); e += FNT) {
-        int r = e / (FTX + 1), c = e - r * (FTX + 1);
+    for (int e = tid; e < XH * XW; e += FNT) {
+        int r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 - 3 + r;
         T f = 0;
         if (i <= n && j <= n + 2) {
-            T cr = ccr<T>(A.crx, oc, ob, (long)j * P + i, avg);
             const T *row = sQ + r * QW + c;
-            f = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], cr);
+            f = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], sCX[e]);
         }
         sFx[e] = f;
     }
     __syncthreads();
     // 3. inner advective half updates
-    for (int e = tid; e < FTY * (FTX + 6); e += FNT) {
-        int r = e / (FTX + 6), c = e - r * (FTX + 6);
+    for (int e = tid; e < FTY * QW; e += FNT) {
+        int r = e / QW, c = e - r * QW;
         int i = i0 - 3 + c, j = j0 + r;
         T v = 0;
         if (i <= n + 2 && j < n) {
-            T ar = AR[(long)j * P + i];
-            T y0 = ccr<T>(A.yfx, oc, ob, (long)j * P + i, avg), y1 = ccr<T>(A.yfx, oc, ob, (long)(j + 1) * P + i, avg);
-            v = (sQ[(r + 3) * QW + c] * ar + y0 * sFy[r * (FTX + 6) + c] - y1 * sFy[(r + 1) * (FTX + 6) + c]) /
-                (ar + y0 - y1);
+            T ar = sAR[(r + 3) * QW + c];
+            T y0 = sYF[r * YW + c], y1 = sYF[(r + 1) * YW + c];
+            v = (sQ[(r + 3) * QW + c] * ar + y0 * sFy[r * YW + c] - y1 * sFy[(r + 1) * YW + c]) / (ar + y0 - y1);
         }
         sQi[e] = v;
     }
-    for (int e = tid; e < (FTY + 6) * FTX; e += FNT) {
+    for (int e = tid; e < QH * FTX; e += FNT) {
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 - 3 + r;
         T v = 0;
         if (i < n && j <= n + 2) {
-            T ar = AR[(long)j * P + i];
-            T x0 = ccr<T>(A.xfx, oc, ob, (long)j * P + i, avg), x1 = ccr<T>(A.xfx, oc, ob, (long)j * P + i + 1, avg);
-            v = (sQ[r * QW + c + 3] * ar + x0 * sFx[r * (FTX + 1) + c] - x1 * sFx[r * (FTX + 1) + c + 1]) /
-                (ar + x0 - x1);
+            T ar = sAR[r * QW + c + 3];
+            T x0 = sXF[r * XW + c], x1 = sXF[r * XW + c + 1];
+            v = (sQ[r * QW + c + 3] * ar + x0 * sFx[r * XW + c] - x1 * sFx[r * XW + c + 1]) / (ar + x0 - x1);
         }
         sQj[e] = v;
     }
     __syncthreads();
     // 4. final fluxes (in place over the outer fluxes)
-    for (int e = tid; e < FTY * (FTX + 1); e += FNT) {
-        int r = e / (FTX + 1), c = e - r * (FTX + 1);
+#pragma unroll
+    for (int m = 0; m < N4X; m++) {
+        int e = tid + m * FNT;
+        if (e >= FTY * XW) break;
+        int r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 + r;
         if (i <= n && j < n) {
             long fi = (long)j * P + i;
-            T cr = ccr<T>(A.crx, oc, ob, fi, avg);
-            const T *row = sQi + r * (FTX + 6) + c;
-            T fx = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], cr);
-            T wgt = A.mx ? (T)A.mx[oc + fi] : ccr<T>(A.xfx, oc, ob, fi, avg);
-            int s = (r + 3) * (FTX + 1) + c;
+            int s = (r + 3) * XW + c;
+            const T *row = sQi + r * QW + c;
+            T fx = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], sCX[s]);
+            T wgt = A.mx ? (T)wx[m] : sXF[s];
             T F = (T)0.5 * (fx + sFx[s]) * wgt;
             sFx[s] = F;
             if (c < FTX || i == n) {
                 if (A.FX) A.FX[oc + fi] = F;
-                if (A.epi == EPI_DELP) {
+                if (EPI == EPI_DELP) {
                     A.mfx[oc + fi] += (double)F;
-                    A.cxa[oc + fi] += A.crx[oc + fi];
+                    A.cxa[oc + fi] += (C)sCX[s];
                 }
             }
         }
     }
-    for (int e = tid; e < (FTY + 1) * FTX; e += FNT) {
+#pragma unroll
+    for (int m = 0; m < N4Y; m++) {
+        int e = tid + m * FNT;
+        if (e >= YH * FTX) break;
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
         if (i < n && j <= n) {
             long fi = (long)j * P + i;
-            T cr = ccr<T>(A.cry, oc, ob, fi, avg);
+            int s = r * YW + c + 3;
             const T *col = sQj + r * FTX + c;
-            T fy = ppm6(col[0], col[FTX], col[2 * FTX], col[3 * FTX], col[4 * FTX], col[5 * FTX], cr);
-            T wgt = A.my ? (T)A.my[oc + fi] : ccr<T>(A.yfx, oc, ob, fi, avg);
-            int s = r * (FTX + 6) + c + 3;
+            T fy = ppm6(col[0], col[FTX], col[2 * FTX], col[3 * FTX], col[4 * FTX], col[5 * FTX], sCY[s]);
+            T wgt = A.my ? (T)wy[m] : sYF[s];
             T F = (T)0.5 * (fy + sFy[s]) * wgt;
             sFy[s] = F;
             if (r < FTY || j == n) {
                 if (A.FY) A.FY[oc + fi] = F;
-                if (A.epi == EPI_DELP) {
+                if (EPI == EPI_DELP) {
                     A.mfy[oc + fi] += (double)F;
-                    A.cya[oc + fi] += A.cry[oc + fi];
+                    A.cya[oc + fi] += (C)sCY[s];
                 }
             }
         }
     }
-    if (A.epi == EPI_FLUX) return;
+    if constexpr (EPI == EPI_FLUX) return;
     __syncthreads();
     // 5. flux-divergence update of the cells of the tile
     const long oq = pidx(G, A.Lq, t, k);
-    for (int e = tid; e < FTY * FTX; e += FNT) {
+#pragma unroll
+    for (int m = 0; m < N5; m++) {
+        int e = tid + m * FNT;
+        if (e >= FTY * FTX) break;
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
         if (i >= n || j >= n) continue;
         long ci = (long)j * P + i;
-        T fw = sFx[(r + 3) * (FTX + 1) + c], fe = sFx[(r + 3) * (FTX + 1) + c + 1];
-        T fs = sFy[r * (FTX + 6) + c + 3], fn = sFy[(r + 1) * (FTX + 6) + c + 3];
-        T ar = AR[ci];
+        T fw = sFx[(r + 3) * XW + c], fe = sFx[(r + 3) * XW + c + 1];
+        T fs = sFy[r * YW + c + 3], fn = sFy[(r + 1) * YW + c + 3];
+        T ar = sAR[(r + 3) * QW + c + 3];
         T qc = sQ[(r + 3) * QW + c + 3];
         T out;
-        if (A.epi == EPI_DELP) {
+        if constexpr (EPI == EPI_DELP) {
             out = qc + (fw - fe + fs - fn) / ar;
-        } else if (A.epi == EPI_MASSW) {
-            out = (qc * A.dold[oc + ci] * ar + fw - fe + fs - fn) / (A.dnew[oc + ci] * ar);
-        } else if (A.epi == EPI_ADV) {
-            T x0 = ccr<T>(A.xfx, oc, ob, ci, avg), x1 = ccr<T>(A.xfx, oc, ob, ci + 1, avg);
-            T y0 = ccr<T>(A.yfx, oc, ob, ci, avg), y1 = ccr<T>(A.yfx, oc, ob, ci + P, avg);
+        } else if constexpr (EPI == EPI_MASSW) {
+            out = (qc * (T)pa[m] * ar + fw - fe + fs - fn) / ((T)pb[m] * ar);
+        } else if constexpr (EPI == EPI_ADV) {
+            T x0 = sXF[(r + 3) * XW + c], x1 = sXF[(r + 3) * XW + c + 1];
+            T y0 = sYF[r * YW + c + 3], y1 = sYF[(r + 1) * YW + c + 3];
             out = (qc * ar + fw - fe + fs - fn) / (ar + x0 - x1 + y0 - y1);
         } else {
-            out = (T)(((double)qc * A.dp1[oc + ci] * (double)ar + (double)fw - (double)fe + (double)fs - (double)fn) /
-                      (A.dp2[oc + ci] * (double)ar));
+            out = (T)(((double)qc * pa[m] * (double)ar + (double)fw - (double)fe + (double)fs - (double)fn) /
+                      (pb[m] * (double)ar));
         }
         A.qout[oq + ci] = out;
     }
@@ -813,8 +1248,15 @@ template <class T, class C, class M>
 static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
 {
     static const char *names[] = {"k_fvtp_flux", "k_fvtp_delp", "k_fvtp_massw", "k_fvtp_adv", "k_fvtp_tracer"};
+    constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
     dim3 grd((unsigned)((g->n + FTX - 1) / FTX), (unsigned)((g->n + FTY - 1) / FTY), (unsigned)planes);
-    launch_named(names[a.epi], k_fvtp<T, C, M>, grd, dim3(FNT), st, g->geo, a);
+    switch (a.epi) {
+    case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    default: launch_fn<k_fvtp<T, C, M, EPI_TRACER>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    }
 }
 
 // ====================================================================
@@ -823,7 +1265,7 @@ static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStr
 // Courant numbers and area fluxes from the contravariant half-step C-grid
 // winds (partner component: four-point mean of the other C-grid wind).
 template <class B>
-__global__ void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc, B *ut, B *vt,
+DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc, B *ut, B *vt,
                               B *crx, B *cry, B *xfx, B *yfx, int *flags)
 {
     KBEGIN(G.nz);
@@ -863,7 +1305,7 @@ __global__ void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const
 // energy at corners (D-grid u upwinded along x and v along y by PPM with the
 // corner displacements of the contravariant C-grid winds)
 template <class B>
-__global__ void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, const B *u, const B *v, const B *ut,
+DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B nu, const B *u, const B *v, const B *ut,
                            const B *vt, B *om, B *ke)
 {
     KBEGIN(G.nz);
@@ -882,14 +1324,29 @@ __global__ void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, const B *u, const B *
         B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
         B uu = ppm6(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
         B vv = ppm6(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
-        AT(ke + o, i, j) = (B)0.5 * (ub * uu + vb * vv);
+        B kev = (B)0.5 * (ub * uu + vb * vv);
+        if (nu > (B)0) {
+            // del-2 divergence damping: minus nu times the divergence of the
+            // D-grid winds over the corner's dual cell (half weights next to
+            // the missing cell at a cube vertex)
+            B ws = 1, wn = 1, ww = 1, we = 1;
+            if (is_vertex(G, i, j)) {
+                if (j == 0) ws = 0.5; else wn = 0.5;
+                if (i == 0) ww = 0.5; else we = 0.5;
+            }
+            const B *dxc = MP(M, M_DXC), *dyc = MP(M, M_DYC);
+            B flux = we * AT(U, i, j) * AT(dyc, i, j) - ww * AT(U, i - 1, j) * AT(dyc, i - 1, j) +
+                     wn * AT(V, i, j) * AT(dxc, i, j) - ws * AT(V, i, j - 1) * AT(dxc, i, j - 1);
+            kev -= nu * flux / AT(MP(M, M_AREA_C), i, j);
+        }
+        AT(ke + o, i, j) = kev;
     }
 }
 
 // D-grid wind update from kinetic-energy differences and vorticity fluxes;
 // commit the transported delp, pt, w.
 template <class B>
-__global__ void k_dsw_update(KARGS, Geo G, Mets<B> M, const B *ke, const B *VX, const B *VY,
+DEVI void k_dsw_update(KARGS, Geo G, Mets<B> M, const B *ke, const B *VX, const B *VY,
                              const B *dn, const B *pn, const B *wn, B *u, B *v, B *delp, B *pt, B *w)
 {
     KBEGIN(G.nz);
@@ -909,12 +1366,12 @@ __global__ void k_dsw_update(KARGS, Geo G, Mets<B> M, const B *ke, const B *VX, 
 // dz_d: interface heights transported by fv_tp_2d (EPI_ADV, interface
 // averaged Courant numbers), surface fixed.
 // ====================================================================
-__global__ void k_heights(KARGS, Geo G, const double *delz, const double *phis, double *zh)
+DEVI void k_heights(KARGS, Geo G, const double *delz, const double *phis, double *zh)
 {
-    int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    if (i > ihi || j > jhi) return;
-    int nz = G.nz, t = blockIdx.z;
+    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+    if (i < ilo || i > ihi || j > jhi) return;
+    int nz = G.nz, t = bk.z;
     if (in_corner(G, SC, i, j)) return;
     long c = (long)j * G.pitch + i;
     double z = phis ? phis[pidx(G, 1, t, 0) + c] / GRAV : 0.0;
@@ -925,7 +1382,7 @@ __global__ void k_heights(KARGS, Geo G, const double *delz, const double *phis, 
     }
 }
 
-__global__ void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phis, double *delz)
+DEVI void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phis, double *delz)
 {
     KBEGIN(G.nz);
     int nz = G.nz;
@@ -939,23 +1396,44 @@ __global__ void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phi
 // interpolation (inner pass along x with the x-sweep corner view; mean of
 // the three cells at a cube vertex) of pfull and phi at the layer's two
 // interfaces and of delp, staged through LDS, then the finite-volume
-// pressure gradient along each D-grid edge.  Block: 64 x 4 corners.
+// pressure gradient along each D-grid edge.  Block: NPX x NPY corners.
 // ====================================================================
-constexpr int NPX = 64, NPY = 4;
+#ifndef FV3_NHP_TX
+#define FV3_NHP_TX 32
+#endif
+#ifndef FV3_NHP_TY
+#define FV3_NHP_TY 8
+#endif
+constexpr int NPX = FV3_NHP_TX, NPY = FV3_NHP_TY;   // nh_p_grad corner tile
 constexpr int NCW = NPX + 5, NCH = NPY + 5;   // cells i0-2..i0+NPX+2, j0-2..j0+NPY+2
 
 template <class B>
-__global__ void __launch_bounds__(256) k_nhpgrad(Geo G, MetD M, double bdt, const double *pfull,
+DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
                                                  const double *phi, const B *delp, B *u, B *v)
 {
     __shared__ double sc[5][NCH * NCW];               // p0, p1, z0, z1, d at cells (x-sweep view)
     __shared__ double sb[5][(NPY + 1) * (NPX + 1)];   // corner values
     const int n = G.n, nz = G.nz, tid = threadIdx.x;
-    const int i0 = blockIdx.x * NPX, j0 = blockIdx.y * NPY;
-    const int t = blockIdx.z / nz, k = blockIdx.z % nz;
+    const int i0 = bk.x * NPX, j0 = bk.y * NPY;
+    const int t = bk.z / nz, k = bk.z % nz;
     const double *F[4] = {pfull + pidx(G, nz + 1, t, k), pfull + pidx(G, nz + 1, t, k + 1),
                           phi + pidx(G, nz + 1, t, k), phi + pidx(G, nz + 1, t, k + 1)};
     const B *D = delp + pidx(G, nz, t, k);
+    const long o = pidx(G, nz, t, k);
+    // prefetch of the winds and edge lengths of the faces this thread updates
+    constexpr int NPP = (NPX * NPY + 255) / 256;
+    double pu[NPP], pdx[NPP], pv[NPP], pdy[NPP];
+#pragma unroll
+    for (int m = 0; m < NPP; m++) {
+        int e = tid + m * 256, r = e / NPX, c = e - r * NPX;
+        int i = i0 + c, j = j0 + r;
+        bool in = e < NPX * NPY;
+        bool fu = in && i < n && j <= n, fv = in && i <= n && j < n;
+        pu[m] = fu ? (double)AT(u + o, i, j) : 0.0;
+        pdx[m] = fu ? AT(MP(M, M_DX), i, j) : 1.0;
+        pv[m] = fv ? (double)AT(v + o, i, j) : 0.0;
+        pdy[m] = fv ? AT(MP(M, M_DY), i, j) : 1.0;
+    }
     for (int e = tid; e < NCH * NCW; e += 256) {
         int r = e / NCW, c = e - r * NCW;
         int i = i0 - 2 + c, j = j0 - 2 + r;
@@ -991,27 +1469,27 @@ __global__ void __launch_bounds__(256) k_nhpgrad(Geo G, MetD M, double bdt, cons
         }
     }
     __syncthreads();
-    const long o = pidx(G, nz, t, k);
     // Each block owns the faces of its NPX x NPY corner rows/columns: the grid
     // spans corners 0..n, so a face row or column on a block boundary is
-    // updated by exactly one block.
-    // u on y-faces (i, j): corners (i, j) -> (i + 1, j)
-    for (int e = tid; e < NPY * NPX; e += 256) {
+    // updated by exactly one block.  u on y-faces (i, j) uses corners (i, j)
+    // and (i + 1, j); v on x-faces (i, j) corners (i, j) and (i, j + 1).
+#pragma unroll
+    for (int m = 0; m < NPP; m++) {
+        int e = tid + m * 256;
+        if (e >= NPX * NPY) break;
         int r = e / NPX, c = e - r * NPX;
         int i = i0 + c, j = j0 + r;
-        if (i >= n || j > n) continue;
-        int W = r * (NPX + 1) + c, E = W + 1;
-        AT(u + o, i, j) += (B)pgf(bdt, AT(MP(M, M_DX), i, j), sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
-                                  sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
-    }
-    // v on x-faces (i, j): corners (i, j) -> (i, j + 1)
-    for (int e = tid; e < NPY * NPX; e += 256) {
-        int r = e / NPX, c = e - r * NPX;
-        int i = i0 + c, j = j0 + r;
-        if (i > n || j >= n) continue;
-        int W = r * (NPX + 1) + c, E = W + (NPX + 1);
-        AT(v + o, i, j) += (B)pgf(bdt, AT(MP(M, M_DY), i, j), sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
-                                  sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+        int W = r * (NPX + 1) + c;
+        if (i < n && j <= n) {
+            int E = W + 1;
+            AT(u + o, i, j) = (B)pu[m] + (B)pgf(bdt, pdx[m], sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
+                                                sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+        }
+        if (i <= n && j < n) {
+            int E = W + (NPX + 1);
+            AT(v + o, i, j) = (B)pv[m] + (B)pgf(bdt, pdy[m], sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
+                                                sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+        }
     }
 }
 
@@ -1019,30 +1497,30 @@ __global__ void __launch_bounds__(256) k_nhpgrad(Geo G, MetD M, double bdt, cons
 // utilities: fills, copies, finiteness check, tracer helpers, reductions
 // ====================================================================
 template <class T>
-__global__ void k_fill(T *p, long count, T val)
+DEVI void k_fill(Bk bk, T *p, long count, T val)
 {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long e = (long)bk.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = val;
 }
 template <class TS, class TD>
-__global__ void k_copy(const TS *s, TD *d, long count)
+DEVI void k_copy(Bk bk, const TS *s, TD *d, long count)
 {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long e = (long)bk.x * blockDim.x + threadIdx.x;
     if (e < count) d[e] = (TD)s[e];
 }
 template <class T>
 static void fill(T *p, long count, T val, hipStream_t st)
 {
-    launch_named("k_fill", k_fill<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), st, p, count, val);
+    launch_fn<k_fill<T>>("k_fill", dim3((unsigned)((count + 255) / 256)), dim3(256), st, p, count, val);
 }
 template <class TS, class TD>
 static void copy(const TS *s, TD *d, long count, hipStream_t st)
 {
-    launch_named("k_copy", k_copy<TS, TD>, dim3((unsigned)((count + 255) / 256)), dim3(256), st, s, d, count);
+    launch_fn<k_copy<TS, TD>>("k_copy", dim3((unsigned)((count + 255) / 256)), dim3(256), st, s, d, count);
 }
 
 template <class T>
-__global__ void k_check_finite(KARGS, Geo G, int L, const T *f, int *flags)
+DEVI void k_check_finite(KARGS, Geo G, int L, const T *f, int *flags)
 {
     KBEGIN(L);
     if (!isfinite((double)AT(f + pidx(G, L, t, k), i, j))) atomicOr(flags + 1, 1);
@@ -1050,7 +1528,7 @@ __global__ void k_check_finite(KARGS, Geo G, int L, const T *f, int *flags)
 
 // tracer: area fluxes from the accumulated Courant numbers, scaled by 1/nsplt
 template <class B>
-__global__ void k_tracer_flux(KARGS, Geo G, MetD M, double rs, const B *cx, const B *cy,
+DEVI void k_tracer_flux(KARGS, Geo G, MetD M, double rs, const B *cx, const B *cy,
                               const double *mfx, const double *mfy, B *crs, B *crys, B *xfx,
                               B *yfx, double *mxs, double *mys)
 {
@@ -1076,7 +1554,7 @@ __global__ void k_tracer_flux(KARGS, Geo G, MetD M, double rs, const B *cx, cons
     }
 }
 
-__global__ void k_tracer_dp(KARGS, Geo G, MetD M, const double *dp1, const double *mxs,
+DEVI void k_tracer_dp(KARGS, Geo G, MetD M, const double *dp1, const double *mxs,
                             const double *mys, double *dp2)
 {
     KBEGIN(G.nz);
@@ -1088,7 +1566,7 @@ __global__ void k_tracer_dp(KARGS, Geo G, MetD M, const double *dp1, const doubl
 
 // max |cx|, |cy| over the interior faces: block maximum, one atomic per block
 template <class B>
-__global__ void k_absmax(KARGS, Geo G, const B *cx, const B *cy, unsigned long long *out)
+__global__ void k_absmax(int ilo, int ihi, int jlo, int jhi, Geo G, const B *cx, const B *cy, unsigned long long *out)
 {
     __shared__ double sm[256];
     int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -1124,7 +1602,7 @@ DEVI void neu_add(double &s, double &c, double x)
 }
 
 template <class B>
-__global__ void k_mass_partial(KARGS, Geo G, MetD M, const B *delp, const B *pt, const B *q,
+__global__ void k_mass_partial(int ilo, int ihi, int jlo, int jhi, Geo G, MetD M, const B *delp, const B *pt, const B *q,
                                int which, double *part)
 {
     __shared__ double ss[256], sc[256];
@@ -1167,7 +1645,7 @@ __global__ void k_mass_partial(KARGS, Geo G, MetD M, const B *delp, const B *pt,
 template <class B>
 struct Work {
     // bulk layer fields
-    B *ua, *va, *ucp, *vcp, *ax, *ay, *Fm, *Fp, *Fw, *Gm, *Gp, *Gw, *delpc, *ptc, *wc, *ke, *vort;
+    B *ax, *ay, *delpc, *ptc, *wc, *ke;
     B *ut, *vt, *crx, *cry, *xfx, *yfx, *FX, *FY, *VX, *VY, *dn, *pn, *wn, *om, *qo;
     // FP64 fields
     double *delzc, *s1, *s2, *s3, *dp1, *dp2, *mxs, *mys;
@@ -1193,10 +1671,8 @@ static size_t carve(const fv3_grid *g, char *base, Work<B> *w)
         off += bytes;
         return p;
     };
-    B **bulk[] = {&w->ua, &w->va, &w->ucp, &w->vcp, &w->ax, &w->ay, &w->Fm, &w->Fp, &w->Fw, &w->Gm,
-                  &w->Gp, &w->Gw, &w->delpc, &w->ptc, &w->wc, &w->ke, &w->vort, &w->ut, &w->vt,
-                  &w->crx, &w->cry, &w->xfx, &w->yfx, &w->FX, &w->FY, &w->VX, &w->VY, &w->dn,
-                  &w->pn, &w->wn, &w->om, &w->qo};
+    B **bulk[] = {&w->ax, &w->ay, &w->delpc, &w->ptc, &w->wc, &w->ke, &w->ut, &w->vt, &w->crx, &w->cry,
+                  &w->xfx, &w->yfx, &w->FX, &w->FY, &w->VX, &w->VY, &w->dn, &w->pn, &w->wn, &w->om, &w->qo};
     for (auto p : bulk) *p = (B *)take(el * sizeof(B));
     double **f64[] = {&w->delzc, &w->s1, &w->s2, &w->s3, &w->dp1, &w->dp2, &w->mxs, &w->mys};
     for (auto p : f64) *p = (double *)take(el * sizeof(double));
@@ -1306,6 +1782,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
     fill(cx, el, (B)0, st);
     fill(cy, el, (B)0, st);
     copy(delp, s->dp0, el, st);
+    rec_mark();
 
     for (int it = 0; it < n_split; it++) {
         bool last = it == n_split - 1;
@@ -1318,21 +1795,24 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         halo_scalar(g, delz, nz, st);
         STOP(1);
         // c_sw
-        launch2d(k_csw_agrid<B>, -3, n + 2, -3, n + 2, P, st, G, (const B *)u, (const B *)v, W.ua, W.va);
-        launch2d(k_csw_faces<B>, -1, n + 1, -1, n + 1, P, st, G, M, (B)dt2, (const B *)u, (const B *)v,
-                 (const B *)delp, (const B *)pt, (const B *)w, (const B *)W.ua, (const B *)W.va, W.ucp, W.vcp,
-                 W.ax, W.ay, W.Fm, W.Fp, W.Fw, W.Gm, W.Gp, W.Gw);
-        launch2d(k_csw_cells<B>, -1, n, -1, n, P, st, G, M, (B)dt2, (const B *)delp, (const B *)pt, (const B *)w,
-                 (const B *)W.ua, (const B *)W.va, (const B *)W.ucp, (const B *)W.vcp, (const B *)W.Fm,
-                 (const B *)W.Fp, (const B *)W.Fw, (const B *)W.Gm, (const B *)W.Gp, (const B *)W.Gw, W.delpc,
-                 W.ptc, W.wc, W.ke, W.vort);
-        launch2d(k_csw_update<B>, 0, n, 0, n, P, st, G, M, (B)dt2, (const B *)u, (const B *)v, (const B *)W.ucp,
-                 (const B *)W.vcp, (const B *)W.ke, (const B *)W.vort, uc, vc);
+        launch_fn<k_csw<B>>("k_csw", dim3((unsigned)((n + 1 + CTX + CTX) / CTX),
+                                          (unsigned)((n + 3 + CswRows<B>::Y - 1) / CswRows<B>::Y), P),
+                            dim3(CNT), st, G, M, (B)dt2, (const B *)u, (const B *)v, (const B *)delp, (const B *)pt,
+                            (const B *)w, uc, vc, W.delpc, W.ptc, W.wc, W.ax, W.ay);
         STOP(2);
         // dz_c + riem_solver_c on the half-step cells
         launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
                  (const B *)W.ay, W.delzc);
-        launch2d_named("k_sim1_c", k_sim1<B, B>, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        launch2d_fn<k_sim1<B, B, 1, 0>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        launch2d_fn<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        launch2d_fn<k_sim1<B, B, 3, 0>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        launch2d_fn<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         STOP(3);
@@ -1357,7 +1837,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             b.q = w; b.qout = W.wn;
             fvtp(g, P, b, st);
         }
-        launch2d(k_dsw_omke<B>, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (const B *)u, (const B *)v,
+        launch2d(k_dsw_omke<B>, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)(g->p.d2_bg * g->da_min), (const B *)u, (const B *)v,
                  (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
         {
             FvArgs<B, B, B> a{};
@@ -1379,7 +1859,16 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         STOP(7);
         // riem_solver3
-        launch2d_named("k_sim1_3", k_sim1<B, B>, 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+        launch2d_fn<k_sim1<B, B, 1, 1>>("k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       s->pfull, s->phi, 0);
+        launch2d_fn<k_sim1<B, B, 2, 1>>("k_sim1_3.p2", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       s->pfull, s->phi, 0);
+        launch2d_fn<k_sim1<B, B, 3, 1>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       s->pfull, s->phi, 0);
+        launch2d_fn<k_sim1<B, B, 4, 1>>("k_sim1_3.p4", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
                        (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
         STOP(8);
@@ -1389,10 +1878,11 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         halo_scalar(g, delp, nz, st);
         STOP(9);
         // nh_p_grad
-        launch_named("k_nhpgrad", k_nhpgrad<B>, dim3((n + NPX) / NPX, (n + NPY) / NPY, P), dim3(256), st, G, Md,
+        launch_fn<k_nhpgrad<B>>("k_nhpgrad", dim3((n + NPX) / NPX, (n + NPY) / NPY, P), dim3(256), st, G, Md,
                      bdt, (const double *)s->pfull, (const double *)s->phi, (const B *)delp, u, v);
 #undef STOP
     }
+    rec_mark();
 done:
     {
         B *chk[] = {u, v, w, delp, pt};
@@ -1400,6 +1890,19 @@ done:
         launch2d(k_check_finite<double>, 0, n - 1, 0, n - 1, P, st, G, nz, (const double *)delz, g->flags);
     }
     if (hipGetLastError() != hipSuccess) return FV3_EDEVICE;
+    return FV3_OK;
+}
+
+fv3_status record_substeps(fv3_state *s, const fv3_grid *g, double bdt, Recorder *rec)
+{
+    rec->pos = 0;
+    rec->mark = 0;
+    g_rec = rec;
+    fv3_status r = g->bulk_bytes == 4 ? substeps_t<float>(s, g, bdt, 1, 0, nullptr)
+                                      : substeps_t<double>(s, g, bdt, 1, 0, nullptr);
+    g_rec = nullptr;
+    if (r != FV3_OK) return r;
+    if (rec->bad || rec->pos != rec->sites.size() || rec->mark != 2) return FV3_EINTERNAL;
     return FV3_OK;
 }
 
@@ -1443,7 +1946,7 @@ static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid 
     if (nsplt <= 0) {
         unsigned long long zero = 0, h = 0;
         fill(W.umax, 1, zero, st);
-        launch2d(k_absmax<B>, 0, n, 0, n, P, st, G, (const B *)cx, (const B *)cy, W.umax);
+        launch2d_native("k_absmax", k_absmax<B>, 0, n, 0, n, P, st, G, (const B *)cx, (const B *)cy, W.umax);
         if (hipMemcpyAsync(&h, W.umax, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return FV3_EDEVICE;
         if (hipStreamSynchronize(st) != hipSuccess) return FV3_EDEVICE;
         double cmax;
@@ -1496,7 +1999,7 @@ static fv3_status mass_sums_t(const fv3_grid *g, const void *delp, const void *p
     std::vector<double> h(2 * np);
     for (int which = 0; which < 2 + nq; which++) {
         const B *qq = which >= 2 ? (const B *)q[which - 2] : nullptr;
-        launch2d(k_mass_partial<B>, 0, n - 1, 0, n - 1, g->T, st, G, M, (const B *)delp, (const B *)pt, qq,
+        launch2d_native("k_mass_partial", k_mass_partial<B>, 0, n - 1, 0, n - 1, g->T, st, G, M, (const B *)delp, (const B *)pt, qq,
                  which < 2 ? which : 2, part);
         if (hipMemcpyAsync(h.data(), part, 2 * np * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
             return FV3_EDEVICE;

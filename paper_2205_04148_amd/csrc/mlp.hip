@@ -42,42 +42,108 @@ DEVI float from_bf16(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 // epilogue: tanh, and a BF16 copy of the result (ldcb).
 enum { GE_NONE = 0, GE_TANH = 1 };
 
-__global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const bf16_t *A, long sam, long sak,
-                                                  const bf16_t *Bm, long sbk, long sbn, const float *bias,
-                                                  int epi, float *C, long ldc, bf16_t *Cb, long ldcb)
+// Block tile 64 x 64 (four wavefronts, 32 x 32 each = 2 x 2 MFMA tiles), K
+// staged through LDS 32 at a time.  Operands are loaded with the thread
+// index running along whichever of their two dimensions is contiguous, and
+// stored in LDS k-contiguous (A as [m][k], B as [n][k]) so that each lane
+// reads its four k-consecutive values of an MFMA operand as one 8-byte word.
+// Accumulation runs over K in ascending chunks of 16 as one MFMA chain per
+// output tile.
+constexpr int GBM = 64, GBN = 64, GBK = 32, GKP = GBK + 8;
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const bf16_t *A, long sam, long sak,
+                                                   const bf16_t *Bm, long sbk, long sbn, const float *bias,
+                                                   int epi, float *C, long ldc, bf16_t *Cb, long ldcb)
 {
-    const int lane = threadIdx.x;
-    const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
-    const int r = lane & 15, g = lane >> 4;   // row/col within the tile, k group
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    const int am = m0 + r, bn = n0 + r;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        v4s a, b;
-        for (int q = 0; q < 4; q++) {
-            int k = k0 + 4 * g + q;
-            bf16_t av = (am < M && k < K) ? A[(long)am * sam + (long)k * sak] : (bf16_t)0;
-            bf16_t bv = (bn < N && k < K) ? Bm[(long)k * sbk + (long)bn * sbn] : (bf16_t)0;
-            a[q] = (short)av;
-            b[q] = (short)bv;
+    __shared__ __align__(16) bf16_t sA[GBM * GKP];
+    __shared__ __align__(16) bf16_t sB[GBN * GKP];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const int r = lane & 15, g = lane >> 4;
+    v4f acc[2][2];
+    for (int x = 0; x < 2; x++)
+        for (int y = 0; y < 2; y++) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    const bool a_kc = sak == 1, b_nc = sbn == 1;
+    for (int k0 = 0; k0 < K; k0 += GBK) {
+        // A tile: 64 x 32, eight values per thread
+        if (a_kc) {
+            int m = tid >> 2, kq = (tid & 3) * 8;
+            int gm = m0 + m;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int gk = k0 + kq + q;
+                sA[m * GKP + kq + q] = (gm < M && gk < K) ? A[(long)gm * sam + gk] : (bf16_t)0;
+            }
+        } else {
+            int kk = tid >> 3, mq = (tid & 7) * 8;
+            int gk = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int gm = m0 + mq + q;
+                sA[(mq + q) * GKP + kk] = (gm < M && gk < K) ? A[(long)gm * sam + (long)gk * sak] : (bf16_t)0;
+            }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        // B tile: 32 x 64, stored [n][k]
+        if (b_nc) {
+            int kk = tid >> 3, nq = (tid & 7) * 8;
+            int gk = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int gn = n0 + nq + q;
+                sB[(nq + q) * GKP + kk] = (gn < N && gk < K) ? Bm[(long)gk * sbk + gn] : (bf16_t)0;
+            }
+        } else {
+            int nn = tid >> 2, kq = (tid & 3) * 8;
+            int gn = n0 + nn;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int gk = k0 + kq + q;
+                sB[nn * GKP + kq + q] = (gn < N && gk < K) ? Bm[(long)gk * sbk + (long)gn * sbn] : (bf16_t)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 16) {
+            v4s a[2], b[2];
+#pragma unroll
+            for (int x = 0; x < 2; x++) {
+                const bf16_t *pa = sA + (wm + 16 * x + r) * GKP + kk + 4 * g;
+                const bf16_t *pb = sB + (wn + 16 * x + r) * GKP + kk + 4 * g;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    a[x][q] = (short)pa[q];
+                    b[x][q] = (short)pb[q];
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < 2; x++)
+#pragma unroll
+                for (int y = 0; y < 2; y++) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+        __syncthreads();
     }
-    // lane holds rows 4g..4g+3 of column r
-    for (int q = 0; q < 4; q++) {
-        int m = m0 + 4 * g + q, n = n0 + r;
-        if (m >= M || n >= N) continue;
-        float v = acc[q] + (bias ? bias[n] : 0.f);
-        if (epi == GE_TANH) v = tanhf(v);
-        if (C) C[(long)m * ldc + n] = v;
-        if (Cb) Cb[(long)m * ldcb + n] = to_bf16(v);
-    }
+    // lane holds rows 4g..4g+3 of column r of each 16 x 16 tile
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int m = m0 + wm + 16 * x + 4 * g + q, n = n0 + wn + 16 * y + r;
+                if (m >= M || n >= N) continue;
+                float v = acc[x][y][q] + (bias ? bias[n] : 0.f);
+                if (epi == GE_TANH) v = tanhf(v);
+                if (C) C[(long)m * ldc + n] = v;
+                if (Cb) Cb[(long)m * ldcb + n] = to_bf16(v);
+            }
 }
 
 static void gemm(int M, int N, int K, const bf16_t *A, long sam, long sak, const bf16_t *B, long sbk, long sbn,
                  const float *bias, int epi, float *C, long ldc, bf16_t *Cb, long ldcb, hipStream_t st)
 {
-    dim3 grd((unsigned)((N + 15) / 16), (unsigned)((M + 15) / 16));
-    hipLaunchKernelGGL(k_gemm_bf16, grd, dim3(64), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, bias, epi, C, ldc,
+    dim3 grd((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM));
+    hipLaunchKernelGGL(k_gemm_bf16, grd, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, bias, epi, C, ldc,
                        Cb, ldcb);
 }
 

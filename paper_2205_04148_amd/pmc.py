@@ -1,0 +1,106 @@
+"""HBM traffic per kernel launch from two rocprofv3 counter databases.
+
+    python -m paper_2205_04148_amd.pmc FETCH_DIR WRITE_DIR OUT.json WORKLOAD
+
+FETCH_DIR / WRITE_DIR hold the rocpd databases of one ``rocprofv3 --pmc
+FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of the same command.  Both
+counters are scaled by what they read for the plain copy kernel of the run
+(``k_copy``: each thread reads one element of its source type and writes one
+of its destination type, so its bytes are known exactly).  The output maps
+each launch name used by the library's timing hooks to its mean calibrated
+bytes read and written per launch, with the SHA-256 of the kernel source the
+counters were taken with (a reader treats the numbers as stale when the
+source has changed).
+"""
+from __future__ import annotations
+
+import collections
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+FVTP_EPI = {0: "k_fvtp_flux", 1: "k_fvtp_delp", 2: "k_fvtp_massw", 3: "k_fvtp_adv", 4: "k_fvtp_tracer"}
+TSIZE = {"f": 4, "d": 8}
+
+
+def source_sha256() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def launch_name(symbol: str):
+    """Launch name of a library kernel from its mangled k_one<...> symbol."""
+    m = re.search(r"k_oneITnDaXadL_ZNS_(\d+)(k_\w+)", symbol)
+    if not m:
+        return None
+    ln = int(m.group(1))
+    rest = m.group(2)
+    name, targs = rest[:ln], rest[ln:]
+    ints = [int(x) for x in re.findall(r"Li(\d+)E", targs.split("EEvNS_")[0])]
+    if name == "k_fvtp" and ints:
+        return FVTP_EPI.get(ints[-1], name)
+    if name == "k_sim1" and len(ints) >= 2:
+        return f"k_sim1_{'c' if ints[1] == 0 else '3'}.p{ints[0]}"
+    if name in ("k_csw", "k_nhpgrad", "k_halo_scalar", "k_halo_pair", "k_fill"):
+        return name
+    if name == "k_copy":
+        t = re.match(r"I([fd])([fd])E", targs)
+        return f"k_copy<{t.group(1)}{t.group(2)}>" if t else name
+    if name in ("k_heights", "k_delz_from_zh"):
+        return name
+    return name + "<B>"
+
+
+def load(dirname: str, counter: str):
+    db = glob.glob(os.path.join(dirname, "**", "*.db"), recursive=True)
+    if not db:
+        raise FileNotFoundError(f"no rocpd database under {dirname}")
+    con = sqlite3.connect(db[0])
+    out = collections.defaultdict(list)
+    for sym, val, grid in con.execute(
+            "select kernel_name, value, grid_size from counters_collection where counter_name = ?", (counter,)):
+        name = launch_name(sym)
+        if name:
+            out[name].append((float(val), int(grid)))
+    return out
+
+
+def calibrate(rows, counter: str) -> float:
+    """Bytes per counter KiB from the copy kernel of the run."""
+    for key in ("k_copy<fd>", "k_copy<dd>", "k_copy<ff>", "k_copy<df>"):
+        if key in rows:
+            src, dst = key[7], key[8]
+            kib, grid = rows[key][0]
+            elem = TSIZE[src] if counter == "FETCH_SIZE" else TSIZE[dst]
+            return elem * grid / kib
+    raise KeyError("no copy kernel in the counter run")
+
+
+def main(argv=None):
+    a = argv if argv is not None else sys.argv[1:]
+    fdir, wdir, out, workload = a[0], a[1], a[2], a[3]
+    f = load(fdir, "FETCH_SIZE")
+    w = load(wdir, "WRITE_SIZE")
+    ff, wf = calibrate(f, "FETCH_SIZE"), calibrate(w, "WRITE_SIZE")
+    kern = {}
+    for name in sorted(set(f) | set(w)):
+        fv = [v for v, _ in f.get(name, [])]
+        wv = [v for v, _ in w.get(name, [])]
+        kern[name] = {"dispatches": max(len(fv), len(wv)),
+                      "fetch_bytes": (sum(fv) / len(fv) * ff) if fv else None,
+                      "write_bytes": (sum(wv) / len(wv) * wf) if wv else None}
+    doc = {"workload": workload, "kernel_source_sha256": source_sha256(),
+           "fetch_bytes_per_kib": ff, "write_bytes_per_kib": wf, "kernels": kern}
+    with open(out, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(f"calibration: FETCH x{ff / 1024:.3f}, WRITE x{wf / 1024:.3f}; {len(kern)} kernels -> {out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,5 +1,4 @@
-"""Learned-correction pipeline at toy size (run by naming this file until it
-passes on the GPU)."""
+"""Learned-correction pipeline at toy size, end to end through the C ABI."""
 import numpy as np
 import pytest
 

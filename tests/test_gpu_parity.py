@@ -135,10 +135,10 @@ def test_cube_c24_ten_substeps(fv3, orc):
 
 @pytest.mark.parametrize("kind,n,nz,dt,ns", [(0, 64, 3, 0.6, 3), (0, 80, 3, 0.6, 3), (1, 16, 4, 400.0, 2)])
 def test_tile_multiple_sizes(fv3, orc, kind, n, nz, dt, ns):
-    """Sizes that are whole multiples of the kernels' block tiles (64 x 16
-    for the transport, 64 x 4 corners for the pressure gradient) and one
-    that leaves a partial tile: every face on a block boundary is written
-    once.  Full substeps and the tracer transport."""
+    """Sizes that are whole multiples of the kernels' block tiles (32 x 16 /
+    32 x 8 cells for the transport, 32 x 8 corners for the pressure
+    gradient) and one that leaves a partial tile: every face on a block
+    boundary is written once.  Full substeps and the tracer transport."""
     init = fi.periodic_state(n=n, nz=nz, nq=1) if kind == 0 else fi.cube_state(n=n, nz=nz, nq=1)
     g, s, og, os_ = _pair(fv3, orc, kind, n, nz, init)
     fv3.acoustic_substeps(s, g, dt, ns)
@@ -214,6 +214,34 @@ def test_abi_errors(fv3):
     p.hord = 8
     p.n = 2
     assert L.fv3_init_grid(C.byref(p), C.byref(h)) == -2
+    p.n = 16
+    p.d2_bg = 0.5
+    assert L.fv3_init_grid(C.byref(p), C.byref(h)) == -1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_divergence_damping_parity(fv3, orc, precision):
+    """del-2 divergence damping (d2_bg > 0) on the periodic 48x48x8 case and a
+    C24 cube against the oracle after 10 substeps (FP64: 1e-11; the mixed
+    build at the mixed-precision bars of the tests below)."""
+    import torch
+
+    for kind, n, nz, dt, d2 in ((0, 48, 8, 2.0, 0.12), (1, 24, 10, 2000.0, 0.06)):
+        init = fi.periodic_state() if kind == 0 else fi.cube_state(n=n, nz=nz)
+        g = fv3.Grid(kind, n, nz, precision=precision, d2_bg=d2)
+        s = fv3.State.allocate(g)
+        s.load(init)
+        og = orc.Grid(kind, n, nz, d2_bg=d2)
+        os_ = orc.new_state(og, init)
+        fv3.acoustic_substeps(s, g, dt, 10)
+        assert fv3.check_status(g) == 0
+        assert orc.acoustic_substeps(og, os_, dt, 10) == 0
+        torch.cuda.synchronize()
+        if precision == "fp64":
+            tol = 1e-11
+        else:
+            tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
+        _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz"), tol, f"damping kind{kind} {precision}")
 
 
 def test_cfl_flag_latched(fv3):
