@@ -105,6 +105,24 @@ def committed_traffic(precision, n, nz, kernel):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
+def copy_roof(torch, nbytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device-to-device copy (torch's
+    copy kernel, 2 GiB, read + write counted), the practical roof next to
+    the 8 TB/s peak."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
+
+
 def cpu_baseline(init, n, nz, bdt, substeps):
     import oracle
 
@@ -305,7 +323,11 @@ def main():
     init = fi.cube_state(n=n, nz=nz)
     log(f"initial state C{n}x{nz}: {time.perf_counter() - t0:.1f} s")
 
+    roof_copy = copy_roof(torch)
+    log(f"device copy roof: {roof_copy:.0f} GB/s")
     main_res = run_precision(fv3, torch, init, args, args.precision)
+    main_res["roofline"]["copy_roof_GBs"] = roof_copy
+    main_res["roofline"]["frac_of_copy_roof"] = (main_res["roofline"]["achieved"] or 0) / roof_copy
     other = None
     if not args.no_compare:
         other_prec = "fp64" if args.precision == "mixed" else "mixed"

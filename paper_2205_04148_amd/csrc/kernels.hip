@@ -35,7 +35,7 @@ namespace fv3 {
 
 // ------------------------------------------------------------ indexing
 DEVI long pidx(const Geo &G, int L, int t, int k) { return G.off0 + ((long)t * L + k) * G.lev; }
-#define AT(P, i, j) (P)[(long)(j) * G.pitch + (i)]
+#define AT(P, i, j) (P)[(int)(j) * (int)G.pitch + (int)(i)]
 
 DEVI int stx_(int st) { return (st == SC || st == SY) ? 1 : 0; }
 DEVI int sty_(int st) { return (st == SC || st == SX) ? 1 : 0; }
@@ -193,17 +193,34 @@ DEVI void tcall(Bk bk, const Tup<A...> &t, std::index_sequence<I...>)
     F(bk, tget<I>(t)...);
 }
 
+// MI355X hands consecutive workgroups of a launch to its eight XCDs in turn,
+// and each XCD has its own L2.  The block index a kernel body sees is
+// therefore permuted so that every XCD works on one contiguous range of the
+// grid (x fastest, then y, then z): neighbouring tiles, which share halo
+// lines, and the planes of one tile, which share the 2-D metric terms, then
+// meet in the same L2.  The permutation is a bijection of the grid.
+constexpr unsigned NXCD = 8;
+DEVI Bk xcd_block()
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+    const unsigned id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = total / NXCD, rem = total % NXCD, xcd = id % NXCD, local = id / NXCD;
+    const unsigned lid = xcd * q + (xcd < rem ? xcd : rem) + local;
+    return Bk{lid % gx, (lid / gx) % gy, lid / (gx * gy)};
+}
+
 template <auto F, class... A>
 __global__ void __launch_bounds__(256) k_one(A... a)
 {
-    F(Bk{blockIdx.x, blockIdx.y, blockIdx.z}, a...);
+    F(xcd_block(), a...);
 }
 
 template <auto F, class... A>
 __global__ void __launch_bounds__(256) k_multi(const Tup<A...> *__restrict__ args, const MemberBlk *__restrict__ tab,
                                                int members)
 {
-    const int z = (int)blockIdx.z;
+    const Bk b = xcd_block();
+    const int z = (int)b.z;
     int lo = 0, hi = members - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -211,8 +228,8 @@ __global__ void __launch_bounds__(256) k_multi(const Tup<A...> *__restrict__ arg
         else hi = mid - 1;
     }
     const MemberBlk mb = tab[lo];
-    if ((int)blockIdx.x >= mb.gx || (int)blockIdx.y >= mb.gy) return;
-    tcall<F>(Bk{blockIdx.x, blockIdx.y, (unsigned)(z - mb.z0)}, args[lo], std::index_sequence_for<A...>{});
+    if ((int)b.x >= mb.gx || (int)b.y >= mb.gy) return;
+    tcall<F>(Bk{b.x, b.y, (unsigned)(z - mb.z0)}, args[lo], std::index_sequence_for<A...>{});
 }
 
 // Recording of the launch sequence of one call per member (ensemble mode).
@@ -323,25 +340,22 @@ DEVI T sgnT(T x) { return x > 0 ? (T)1 : (x < 0 ? (T)-1 : (T)0); }
 template <class T>
 DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
 {
+    // Branch-free: select the upwind cell's five-point neighbourhood (cell
+    // m-1 for c > 0, else cell m), then one evaluation.  For the downwind
+    // orientation the parabola's edge deviations swap roles and the swept
+    // fraction is |c|: q + (1 - |c|) (e - |c| (bl + br)) with e = br for
+    // c > 0 and bl otherwise, the same arithmetic as the two one-sided forms.
     const T third = (T)1 / (T)3;
-    if (c > 0) {
-        // upwind cell m-1 (q2)
-        T d1 = lslope(q0, q1, q2), d2 = lslope(q1, q2, q3), d3 = lslope(q2, q3, q4);
-        T al = (T)0.5 * (q1 + q2) + (d1 - d2) * third;
-        T ar = (T)0.5 * (q2 + q3) + (d2 - d3) * third;
-        T s = sgnT(d2), a2 = (T)2 * fabs(d2);
-        T bl = -s * fmin(a2, fabs(al - q2));
-        T br = s * fmin(a2, fabs(ar - q2));
-        return q2 + ((T)1 - c) * (br - c * (bl + br));
-    } else {
-        T d2 = lslope(q1, q2, q3), d3 = lslope(q2, q3, q4), d4 = lslope(q3, q4, q5);
-        T al = (T)0.5 * (q2 + q3) + (d2 - d3) * third;
-        T ar = (T)0.5 * (q3 + q4) + (d3 - d4) * third;
-        T s = sgnT(d3), a2 = (T)2 * fabs(d3);
-        T bl = -s * fmin(a2, fabs(al - q3));
-        T br = s * fmin(a2, fabs(ar - q3));
-        return q3 + ((T)1 + c) * (bl + c * (bl + br));
-    }
+    const bool pos = c > 0;
+    const T a = pos ? q0 : q1, b = pos ? q1 : q2, q = pos ? q2 : q3, d = pos ? q3 : q4, e = pos ? q4 : q5;
+    const T dl = lslope(a, b, q), dm = lslope(b, q, d), dr = lslope(q, d, e);
+    const T al = (T)0.5 * (b + q) + (dl - dm) * third;
+    const T ar = (T)0.5 * (q + d) + (dm - dr) * third;
+    const T s = sgnT(dm), a2 = (T)2 * fabs(dm);
+    const T bl = -s * fmin(a2, fabs(al - q));
+    const T br = s * fmin(a2, fabs(ar - q));
+    const T cc = pos ? c : -c;
+    return q + ((T)1 - cc) * ((pos ? br : bl) - cc * (bl + br));
 }
 
 // ====================================================================
