@@ -21,6 +21,10 @@ of Sec. X, a uniform zonal jet with a perturbation; no dataset is involved):
   hydrostatic columns, N(0,1) m/s noise on the covariant D-grid winds, four
   tracers U[0,1].
 * ``ensemble_sizes`` -- the uneven member sizes of the batched ensemble.
+* ``sigma_coefficients`` / ``hybrid_coefficients`` -- reference vertical
+  coordinates pe_K = ak_K + bk_K ps for the remapping step, and
+  ``deform_layers`` -- seeded redistribution of the layer thicknesses of
+  every column (fixed column mass), standing in for Lagrangian deformation.
 """
 from __future__ import annotations
 
@@ -304,6 +308,45 @@ def cube_state(n: int = 96, nz: int = 79, seed: int = 2, ptop: float = 100.0, nq
     return dict(u=u, v=v, w=_empty(6, nz, n), delp=base["delp"].copy(), pt=base["pt"].copy(),
                 delz=base["delz"].copy(), phis=np.zeros((6, n + 2 * H + 1, n + 2 * H + 1)), q=qq,
                 meta=dict(kind=1, n=n, nz=nz, T=6, ptop=ptop))
+
+
+def sigma_coefficients(nz: int, ptop: float = 100.0):
+    """Evenly spaced sigma layers: ak_K = ptop (1 - K/nz), bk_K = K/nz, so that
+    ak + bk ps reproduces ``sigma_interfaces(nz, ptop, ps)``."""
+    eta = np.arange(nz + 1, dtype=np.float64) / nz
+    ak = ptop * (1.0 - eta)
+    bk = eta.copy()
+    ak[-1], bk[-1] = 0.0, 1.0
+    return ak, bk
+
+
+def hybrid_coefficients(nz: int, ptop: float = 100.0, ps0: float = 1.0e5, eta_c: float = 0.3):
+    """Hybrid pressure-sigma interfaces: pure pressure above eta_c, bk rising
+    quadratically to 1 below; at ps = ps0 the interfaces are evenly spaced.
+    Interfaces increase downwards for every ps above about ps0 - (ps0 - ptop)
+    (1 - eta_c) / 2."""
+    eta = np.arange(nz + 1, dtype=np.float64) / nz
+    bk = np.clip((eta - eta_c) / (1.0 - eta_c), 0.0, None) ** 2
+    ak = ptop + (ps0 - ptop) * eta - bk * ps0
+    ak[0], bk[0] = ptop, 0.0
+    ak[-1], bk[-1] = 0.0, 1.0
+    return ak, bk
+
+
+def deform_layers(delp: np.ndarray, seed: int = 9, amp: float = 0.25) -> np.ndarray:
+    """Redistribute each column's layer thicknesses by seeded factors in
+    [1 - amp, 1 + amp] (smooth in k, random per column), keeping the column
+    sum.  Works on any [T][K][N][N] array; returns a new array."""
+    rng = np.random.default_rng(seed)
+    T, K, N, _ = delp.shape
+    k = np.arange(K, dtype=np.float64)[None, :, None, None]
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=(T, 1, N, N))
+    wav = rng.uniform(1.0, 3.0, size=(T, 1, N, N))
+    f = 1.0 + amp * np.sin(wav * 2.0 * math.pi * k / K + ph)
+    out = delp * f
+    tot0 = delp.sum(axis=1, keepdims=True)
+    tot1 = out.sum(axis=1, keepdims=True)
+    return out * np.where(tot1 != 0.0, tot0 / np.where(tot1 != 0.0, tot1, 1.0), 1.0)
 
 
 def ensemble_sizes(members: int = 32, seed: int = 4):

@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["grid.c", "halo.c", "ppm.c", "column.c", "dyn.c", "api.c"]
+_SRCS = ["grid.c", "halo.c", "ppm.c", "column.c", "dyn.c", "remap.c", "api.c"]
 
 ST = {"C": 0, "X": 1, "Y": 2, "B": 3}
 MODE = {"x": 0, "y": 1}
@@ -73,6 +73,10 @@ def lib():
             C.c_int, C.POINTER(C.c_int)]
         L.orc_mass_sums.argtypes = [C.c_void_p, dp, dp, C.POINTER(dp), C.c_int, dp]
         L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_ppm_profile.argtypes = [C.c_int] + [dp] * 5
+        L.orc_ppm_edges.argtypes = [C.c_int] + [dp] * 3
+        L.orc_remap_column.argtypes = [C.c_int] + [dp] * 4
+        L.orc_remap.argtypes = [C.c_void_p] + [dp] * 6 + [C.POINTER(dp), C.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -220,6 +224,48 @@ def tracer_transport(g: Grid, qs, dp0, mfx, mfy, cx, cy, nsplt: int = 0) -> int:
     lib().orc_tracer_transport(g._h, arr, len(qs), _p(dp0), _p(mfx), _p(mfy), _p(cx), _p(cy),
                                int(nsplt), C.byref(used))
     return used.value
+
+
+def ppm_edges(d, a):
+    """Interface values of a column before the parabola limiter: e[K] for
+    K = 1..nz-1 (e[0] and e[nz] are unused and returned as 0)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    e = np.zeros(len(a) + 1)
+    lib().orc_ppm_edges(len(a), _p(d), _p(a), _p(e))
+    return e
+
+
+def ppm_profile(d, a):
+    """Limited parabola of every layer of a column (thicknesses d, means a):
+    top value aL, bottom value aR, curvature a6."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    aL, aR, a6 = np.zeros_like(a), np.zeros_like(a), np.zeros_like(a)
+    lib().orc_ppm_profile(len(a), _p(d), _p(a), _p(aL), _p(aR), _p(a6))
+    return aL, aR, a6
+
+
+def remap_column(pe1, pe2, q1) -> np.ndarray:
+    """Remap the layer means q1 on interfaces pe1 to interfaces pe2."""
+    pe1 = np.ascontiguousarray(pe1, dtype=np.float64)
+    pe2 = np.ascontiguousarray(pe2, dtype=np.float64)
+    q1 = np.ascontiguousarray(q1, dtype=np.float64)
+    assert pe1.shape == pe2.shape == (len(q1) + 1,)
+    q2 = np.zeros_like(q1)
+    lib().orc_remap_column(len(q1), _p(pe1), _p(pe2), _p(q1), _p(q2))
+    return q2
+
+
+def remap(g: Grid, s: dict, ak, bk, qs=()) -> int:
+    """Remap a state in place to the reference interfaces ak + bk * ps
+    (u, v, w, delp, pt, delz and the tracer fields qs)."""
+    ak = np.ascontiguousarray(ak, dtype=np.float64)
+    bk = np.ascontiguousarray(bk, dtype=np.float64)
+    assert ak.shape == bk.shape == (g.nz + 1,)
+    arr = (C.POINTER(C.c_double) * max(1, len(qs)))(*[_p(q) for q in qs])
+    return lib().orc_remap(g._h, *[_p(s[k]) for k in ("u", "v", "w", "delp", "pt", "delz")], arr,
+                           len(qs), _p(ak), _p(bk))
 
 
 def mass_sums(g: Grid, delp, pt, qs=()) -> np.ndarray:

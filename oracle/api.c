@@ -143,6 +143,24 @@ int orc_mass_sums(void *gp, const double *delp, const double *pt, const double *
     return 0;
 }
 
+void orc_ppm_edges(int nz, const double *d, const double *a, double *e) { o_ppm_edges(nz, d, a, e); }
+
+void orc_ppm_profile(int nz, const double *d, const double *a, double *aL, double *aR, double *a6)
+{
+    o_ppm_profile(nz, d, a, aL, aR, a6);
+}
+
+void orc_remap_column(int nz, const double *pe1, const double *pe2, const double *q1, double *q2)
+{
+    o_remap_column(nz, pe1, pe2, q1, q2);
+}
+
+int orc_remap(void *gp, double *u, double *v, double *w, double *delp, double *pt, double *delz,
+              double *const *q, int nq, const double *ak, const double *bk)
+{
+    return orc_remap_impl((OGrid *)gp, u, v, w, delp, pt, delz, q, nq, ak, bk);
+}
+
 int orc_set_threads(int n)
 {
 #ifdef _OPENMP

@@ -93,4 +93,11 @@ double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, cons
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
              double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
 
+/* remap.c */
+void o_ppm_edges(int nz, const double *d, const double *a, double *e);
+void o_ppm_profile(int nz, const double *d, const double *a, double *aL, double *aR, double *a6);
+void o_remap_column(int nz, const double *pe1, const double *pe2, const double *q1, double *q2);
+int orc_remap_impl(const OGrid *g, double *u, double *v, double *w, double *delp, double *pt,
+                   double *delz, double *const *q, int nq, const double *ak, const double *bk);
+
 #endif
