@@ -43,6 +43,7 @@ typedef enum {
     FV3_ECFL = -6,          /* a Courant number exceeded 1 in d_sw (latched on device)      */
     FV3_ENONFINITE = -7,    /* a prognostic became non-finite (latched on device)           */
     FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8, beta != 1)                */
+    FV3_EREMAP = -9,        /* reference interfaces not increasing in a column (latched)    */
     FV3_EINTERNAL = -99
 } fv3_status;
 
@@ -171,6 +172,31 @@ fv3_status fv3_acoustic_substeps_debug(fv3_state *s, const fv3_grid *g, double d
 fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_grid *g,
                                 int nsplt, void *stream);
 
+/* Most layers fv3_remap accepts. */
+#define FV3_REMAP_MAX_LEVELS 128
+
+/* Vertical remapping of the remapping step (Sec. II): the Lagrangian layers
+ * every column has after acoustic substeps are mapped back to the reference
+ * interfaces pe_K = ak[K] + bk[K] * ps (K = 0..nz), ps = ptop + the column's
+ * sum of delp, by a mass-conserving piecewise-parabolic remap in pressure
+ * (Colella-Woodward reconstruction on the non-uniform layers with its
+ * monotonicity limiters; constant top and bottom layers).  pt, w and the nq
+ * tracer fields q[m] (bulk precision, device) are remapped mass-weighted;
+ * delz as delz/delp, so each column keeps its depth; u and v at their faces,
+ * with the interface pressures the mean of those of the two cells sharing
+ * the face (the halo of delp is filled first); delp becomes the reference
+ * thickness.  The column integral of every field times delp is conserved to
+ * rounding.  Computes in FP64 in both precision modes.
+ * ak, bk: host arrays of nz + 1 doubles, copied into the launch (the call
+ * keeps no pointer); ak[0] must equal the grid's ptop, bk[0] = 0, ak[nz] = 0
+ * and bk[nz] = 1 exactly.  Uses the state's workspace.  Asynchronous on
+ * `stream`.  Errors: FV3_EINVAL (NULL pointers, non-finite or mismatched end
+ * coefficients, nq < 0 or > 64), FV3_ESHAPE (nz > FV3_REMAP_MAX_LEVELS);
+ * a column whose reference interfaces do not increase latches FV3_EREMAP,
+ * reported by fv3_check_status. */
+fv3_status fv3_remap(fv3_state *s, const fv3_grid *g, const double *ak, const double *bk,
+                     void *const *q, int nq, void *stream);
+
 /* Compensated (Neumaier) FP64 global sums over the interior cells:
  * out[0] = sum delp*area, out[1] = sum pt*delp*area, out[2+m] = sum
  * q[m]*delp*area.  `delp` and `pt` are bulk-precision fields; out is a
@@ -185,7 +211,8 @@ fv3_status fv3_halo_fill(const fv3_grid *g, void *const *fields, int n_fields, i
                          int fp64, void *stream);
 
 /* Synchronise `stream`, then return and clear the first device-detected
- * error latched on the grid (FV3_ECFL, FV3_ENONFINITE) or FV3_OK. */
+ * error latched on the grid (FV3_ECFL, FV3_ENONFINITE, FV3_EREMAP) or
+ * FV3_OK. */
 fv3_status fv3_check_status(const fv3_grid *g, void *stream);
 
 /* Measurement support.  fv3_timing_start(filter) makes every later kernel

@@ -26,12 +26,12 @@ RADIUS = 6.3712e6
 OMEGA = 7.2921e-5
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ESHAPE", -3: "EDTYPE", -4: "EDEVICE", -5: "ENOMEM",
-          -6: "ECFL", -7: "ENONFINITE", -8: "EUNSUPPORTED", -99: "EINTERNAL"}
+          -6: "ECFL", -7: "ENONFINITE", -8: "EUNSUPPORTED", -9: "EREMAP", -99: "EINTERNAL"}
 METRICS = ["dx", "dy", "dxc", "dyc", "dxa", "dya", "area", "area_c", "fC", "fB", "sin_u",
            "cos_u", "sin_v", "cos_v", "sin_a", "cos_a"]
 EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_bytes",
            "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
-           "fv3_tracer_transport", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
+           "fv3_tracer_transport", "fv3_remap", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
            "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start",
            "fv3_timing_stop", "fv3_acoustic_substeps_batched", "fv3_ensemble_create",
            "fv3_ensemble_run", "fv3_ensemble_free", "fv3_ensemble_tune", "fv3_ensemble_shapes",
@@ -99,6 +99,8 @@ def lib():
                                                   C.c_int, vp]
         L.fv3_tracer_transport.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(StateStruct), vp,
                                            C.c_int, vp]
+        L.fv3_remap.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(vp), C.c_int, vp]
         L.fv3_mass_sums.argtypes = [vp, vp, vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double), vp]
         L.fv3_halo_fill.argtypes = [vp, C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp]
         L.fv3_check_status.argtypes = [vp, vp]
@@ -181,6 +183,7 @@ class Grid:
         _check(lib().fv3_grid_layout(h, C.byref(lay)))
         self.layout = lay
         self.kind, self.n, self.nz, self.T = kind, n, nz, lay.tiles
+        self.ptop = ptop
         self.precision = precision
         self.device = device
         self.N = n + 2 * H + 1
@@ -302,6 +305,19 @@ def tracer_transport(qs, state: State, grid: Grid, nsplt: int = 0, stream=None) 
     arr = (C.c_void_p * len(qs))(*[q.data_ptr() for q in qs])
     _check(lib().fv3_tracer_transport(arr, len(qs), C.byref(st), grid.handle, int(nsplt),
                                       _stream(stream)))
+
+
+def remap(state: State, grid: Grid, ak, bk, qs=(), stream=None) -> None:
+    """Remap the state's layers (and the tracer fields qs) in place to the
+    reference interfaces ak + bk * ps; ak, bk hold nz + 1 values."""
+    ak = np.ascontiguousarray(ak, dtype=np.float64)
+    bk = np.ascontiguousarray(bk, dtype=np.float64)
+    if ak.shape != (grid.nz + 1,) or bk.shape != (grid.nz + 1,):
+        raise ValueError("ak and bk need nz + 1 values")
+    st = state.struct()
+    arr = (C.c_void_p * max(1, len(qs)))(*[q.data_ptr() for q in qs])
+    _check(lib().fv3_remap(C.byref(st), grid.handle, ak.ctypes.data_as(C.POINTER(C.c_double)),
+                           bk.ctypes.data_as(C.POINTER(C.c_double)), arr, len(qs), _stream(stream)))
 
 
 def mass_sums(grid: Grid, delp, pt, qs=(), stream=None) -> np.ndarray:

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfv3.so")
-SOURCES = ["grid.cpp", "abi.cpp", "kernels.hip", "ensemble.cpp", "correction.hip", "mlp.hip"]
+SOURCES = ["grid.cpp", "abi.cpp", "kernels.hip", "ensemble.cpp", "correction.hip", "mlp.hip", "remap.hip"]
 # Packed FP32 instructions are disabled for all device code.
 HIPFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

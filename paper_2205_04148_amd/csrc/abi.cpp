@@ -59,6 +59,7 @@ const char *fv3_status_string(fv3_status s)
     case FV3_ECFL: return "Courant number above 1";
     case FV3_ENONFINITE: return "non-finite prognostic";
     case FV3_EUNSUPPORTED: return "unsupported option";
+    case FV3_EREMAP: return "reference interfaces not increasing";
     case FV3_EINTERNAL: return "internal error";
     }
     return "unknown status";
@@ -195,6 +196,26 @@ fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_
     return FV3_OK;
 }
 
+fv3_status fv3_remap(fv3_state *s, const fv3_grid *g, const double *ak, const double *bk, void *const *q,
+                     int nq, void *stream)
+{
+    if (!ak || !bk) return fail(FV3_EINVAL, "NULL ak or bk");
+    if (nq < 0 || nq > 64 || (nq > 0 && !q)) return fail(FV3_EINVAL, "need 0..64 tracers");
+    for (int m = 0; m < nq; m++)
+        if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
+    fv3_status st = check_state(s, g);
+    if (st != FV3_OK) return st;
+    const int nz = g->nz;
+    if (nz > FV3_REMAP_MAX_LEVELS) return fail(FV3_ESHAPE, "nz exceeds FV3_REMAP_MAX_LEVELS");
+    for (int K = 0; K <= nz; K++)
+        if (!std::isfinite(ak[K]) || !std::isfinite(bk[K])) return fail(FV3_EINVAL, "non-finite ak or bk");
+    if (ak[0] != g->p.ptop || bk[0] != 0.0 || ak[nz] != 0.0 || bk[nz] != 1.0)
+        return fail(FV3_EINVAL, "need ak[0] = ptop, bk[0] = 0, ak[nz] = 0, bk[nz] = 1");
+    st = fv3::run_remap(s, g, ak, bk, q, nq, (hipStream_t)stream);
+    if (st != FV3_OK) return fail(st, "remap failed");
+    return FV3_OK;
+}
+
 fv3_status fv3_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q, int nq,
                          double *host_out, void *stream)
 {
@@ -236,14 +257,15 @@ fv3_status fv3_check_status(const fv3_grid *g, void *stream)
 {
     if (!g) return fail(FV3_EINVAL, "NULL grid");
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(FV3_EDEVICE, "stream sync failed");
-    int h[2] = {0, 0};
+    int h[3] = {0, 0, 0};
     if (hipMemcpy(h, g->flags, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(FV3_EDEVICE, "flag read failed");
-    int zero[2] = {0, 0};
+    int zero[3] = {0, 0, 0};
     if (hipMemcpy(g->flags, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FV3_EDEVICE, "flag reset failed");
     if (h[0]) return fail(FV3_ECFL, "a Courant number exceeded 1");
     if (h[1]) return fail(FV3_ENONFINITE, "a prognostic field became non-finite");
+    if (h[2]) return fail(FV3_EREMAP, "reference interfaces do not increase in some column");
     return FV3_OK;
 }
 

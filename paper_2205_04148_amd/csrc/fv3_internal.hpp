@@ -91,7 +91,7 @@ struct fv3_grid {
     float *metf[fv3::M_COUNT] = {};           // device, FP32 copies (mixed precision)
     std::vector<double> hmet[fv3::M_COUNT];   // host copies
     fv3::Plan planC, planD, planCv, planA;    // scalar, D-grid pair, C-grid pair, cell pair
-    int *flags = nullptr;                     // device error latch [2]: cfl, nonfinite
+    int *flags = nullptr;                     // device error latch [3]: cfl, nonfinite, remap
     double *red = nullptr;                    // device reduction scratch
     long red_elems = 0;
     size_t ws_bytes = 0;
@@ -114,6 +114,15 @@ size_t workspace_bytes(const fv3_grid *g);
 long reduction_elems(const fv3_grid *g);
 void timing_start(const char *filter);
 int timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap);
+// a launch bracketed by timing_begin / timing_end (when timing_wanted(name))
+// is reported by timing_stop under `name`
+struct TimingRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+bool timing_wanted(const char *name);
+void timing_begin(const char *name, hipStream_t st, TimingRec &r);
+void timing_end(hipStream_t st, TimingRec &r);
 fv3_status run_substeps(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
                         hipStream_t st);
 // record the launch sequence of one substep call (entry, one substep, exit)
@@ -128,6 +137,9 @@ fv3_status run_halo_cells(const fv3_grid *g, void *const *f, int nf, int levels,
 // halo of a cell-centred vector (x, y components in tile coordinates)
 fv3_status run_halo_pair_cells(const fv3_grid *g, void *fx, void *fy, int levels, int fp64,
                                hipStream_t st);
+// remap.hip: vertical remapping of a state to the coordinate ak + bk ps
+fv3_status run_remap(fv3_state *s, const fv3_grid *g, const double *ak, const double *bk,
+                     void *const *q, int nq, hipStream_t st);
 
 // abi.cpp: record the thread-local message fv3_last_error() returns
 fv3_status set_error(fv3_status s, const std::string &msg);

@@ -130,28 +130,24 @@ typedef Mets<double> MetD;
 #define MP(M, name) ((M).m[name] + G.off0 + (long)t * G.lev)
 
 // ---------------------------------------------------------- launch timing
-struct TimingRec {
-    const char *name;
-    hipEvent_t a, b;
-};
 static struct {
     bool on = false;
     std::string filter;
     std::vector<TimingRec> recs;
 } g_timing;
 
-static bool timing_wanted(const char *name)
+bool timing_wanted(const char *name)
 {
     return g_timing.on && std::strstr(name, g_timing.filter.c_str()) != nullptr;
 }
-static void timing_begin(const char *name, hipStream_t st, TimingRec &r)
+void timing_begin(const char *name, hipStream_t st, TimingRec &r)
 {
     r.name = name;
     (void)hipEventCreate(&r.a);
     (void)hipEventCreate(&r.b);
     (void)hipEventRecord(r.a, st);
 }
-static void timing_end(hipStream_t st, TimingRec &r)
+void timing_end(hipStream_t st, TimingRec &r)
 {
     (void)hipEventRecord(r.b, st);
     g_timing.recs.push_back(r);
