@@ -267,24 +267,41 @@ static void rec_mark()
 }
 
 // plane kernels: 64 x 4 threads, one point each, grid z = planes
+// Block shape of a plane kernel: 256 threads, bx consecutive points along i
+// (a multiple of 16, so that a wavefront's row segments are whole 64-byte
+// lines for FP32 and 128-byte lines for FP64).
+struct Shape {
+    int x, y;
+};
+constexpr Shape SH_DEFAULT{64, 4};
+
 template <auto F, class... A>
-static void launch2d_fn(const char *name, int ilo, int ihi, int jlo, int jhi, int planes, hipStream_t st, A... a)
+static void launch2d_sh(const char *name, Shape sh, int ilo, int ihi, int jlo, int jhi, int planes,
+                        hipStream_t st, A... a)
 {
-    const int ib = ilo >= 0 ? ilo : -32;
+    // columns start at an aligned point: ilo itself, or -min(bx, 32) for halo ranges
+    const int ib = ilo >= 0 ? ilo : -(sh.x < 32 ? sh.x : 32);
     if (g_rec) {
-        rec_site(name, (const void *)k_multi<F, int, int, int, int, int, A...>, true, dim3(64, 4, 1), ihi - ib + 1,
-                 jhi - jlo + 1, planes, tup(ib, ilo, ihi, jlo, jhi, a...));
+        rec_site(name, (const void *)k_multi<F, int, int, int, int, int, A...>, true, dim3(sh.x, sh.y, 1),
+                 ihi - ib + 1, jhi - jlo + 1, planes, tup(ib, ilo, ihi, jlo, jhi, a...));
         return;
     }
-    dim3 blk(64, 4, 1);
-    dim3 grd((unsigned)((ihi - ib + 64) / 64), (unsigned)((jhi - jlo + 4) / 4), (unsigned)planes);
+    dim3 blk((unsigned)sh.x, (unsigned)sh.y, 1);
+    dim3 grd((unsigned)((ihi - ib + sh.x) / sh.x), (unsigned)((jhi - jlo + sh.y) / sh.y), (unsigned)planes);
     bool tm = timing_wanted(name);
     TimingRec r;
     if (tm) timing_begin(name, st, r);
     hipLaunchKernelGGL((k_one<F, int, int, int, int, int, A...>), grd, blk, 0, st, ib, ilo, ihi, jlo, jhi, a...);
     if (tm) timing_end(st, r);
 }
+template <auto F, class... A>
+static void launch2d_fn(const char *name, int ilo, int ihi, int jlo, int jhi, int planes, hipStream_t st, A... a)
+{
+    launch2d_sh<F>(name, SH_DEFAULT, ilo, ihi, jlo, jhi, planes, st, a...);
+}
 #define launch2d(kern, ...) launch2d_fn<kern>(#kern, __VA_ARGS__)
+// with a block shape chosen per kernel (measured on MI355X at C192 x 79)
+#define launch2d_s(kern, shape, ...) launch2d_sh<kern>(#kern, shape, __VA_ARGS__)
 
 // generic launch with explicit shape (timed under `name`)
 template <auto F, class... A>
@@ -983,8 +1000,8 @@ DEVI void k_pgradc(KARGS, Geo G, MetD M, double dt2, const B *delpc, const doubl
 
 // ====================================================================
 // fv_tp_2d (Sec. IX-C): Lin-Rood flux-form transport on one level, fused.
-// A 64 x 16 cell tile plus 3-point halo is staged in LDS in both sweep
-// views; outer PPM fluxes, inner advective half updates, final averaged and
+// A cell tile (32 x 16 in FP32, 32 x 8 in FP64) plus 3-point halo is staged
+// in LDS in both sweep views; outer PPM fluxes, inner advective half updates, final averaged and
 // weighted fluxes, then an epilogue that applies the flux divergence:
 //   EPI_FLUX   write the fluxes only
 //   EPI_DELP   write fluxes, accumulate them (mass fluxes, Courant numbers),
@@ -1578,17 +1595,21 @@ DEVI void k_tracer_dp(KARGS, Geo G, MetD M, const double *dp1, const double *mxs
 template <class B>
 __global__ void k_absmax(int ilo, int ihi, int jlo, int jhi, Geo G, const B *cx, const B *cy, unsigned long long *out)
 {
+    // each block covers its (i, j) patch on every gridDim.z-th plane, so that
+    // only a few thousand blocks meet at the one atomic
     __shared__ double sm[256];
     int tid = threadIdx.y * blockDim.x + threadIdx.x;
     int i = ilo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
     int j = jlo + (int)(blockIdx.y * blockDim.y + threadIdx.y);
     double m = 0.0;
     if (i <= ihi && j <= jhi) {
-        int n = G.n;
-        int t = (int)blockIdx.z / G.nz, k = (int)blockIdx.z % G.nz;
-        long o = pidx(G, G.nz, t, k);
-        if (j < n) m = fmax(m, fabs((double)AT(cx + o, i, j)));
-        if (i < n) m = fmax(m, fabs((double)AT(cy + o, i, j)));
+        int n = G.n, planes = G.T * G.nz;
+        for (int z = (int)blockIdx.z; z < planes; z += (int)gridDim.z) {
+            int t = z / G.nz, k = z % G.nz;
+            long o = pidx(G, G.nz, t, k);
+            if (j < n) m = fmax(m, fabs((double)AT(cx + o, i, j)));
+            if (i < n) m = fmax(m, fabs((double)AT(cy + o, i, j)));
+        }
     }
     sm[tid] = m;
     __syncthreads();
@@ -1816,23 +1837,23 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d_fn<k_sim1<B, B, 1, 0>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        launch2d_fn<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        launch2d_sh<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         launch2d_fn<k_sim1<B, B, 3, 0>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        launch2d_fn<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        launch2d_sh<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         STOP(3);
-        launch2d(k_pgradc<B>, 0, n, 0, n, P, st, G, Md, dt2, (const B *)W.delpc, (const double *)W.pkc,
+        launch2d_s(k_pgradc<B>, (Shape{32, 8}), 0, n, 0, n, P, st, G, Md, dt2, (const B *)W.delpc, (const double *)W.pkc,
                  (const double *)W.gz, uc, vc);
         STOP(4);
         halo_pair(g, g->planCv, uc, vc, nz, st);
         STOP(5);
         // d_sw
-        launch2d(k_dsw_courant<B>, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (const B *)uc, (const B *)vc, W.ut,
+        launch2d_s(k_dsw_courant<B>, (Shape{16, 16}), -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (const B *)uc, (const B *)vc, W.ut,
                  W.vt, W.crx, W.cry, W.xfx, W.yfx, g->flags);
         {
             FvArgs<B, B, B> a{};
@@ -1847,7 +1868,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             b.q = w; b.qout = W.wn;
             fvtp(g, P, b, st);
         }
-        launch2d(k_dsw_omke<B>, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)(g->p.d2_bg * g->da_min), (const B *)u, (const B *)v,
+        launch2d_s(k_dsw_omke<B>, (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)(g->p.d2_bg * g->da_min), (const B *)u, (const B *)v,
                  (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
         {
             FvArgs<B, B, B> a{};
@@ -1855,7 +1876,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             a.area = areaB; a.epi = EPI_FLUX; a.FX = W.VX; a.FY = W.VY;
             fvtp(g, P, a, st);
         }
-        launch2d(k_dsw_update<B>, 0, n, 0, n, P, st, G, M, (const B *)W.ke, (const B *)W.VX, (const B *)W.VY,
+        launch2d_s(k_dsw_update<B>, (Shape{32, 8}), 0, n, 0, n, P, st, G, M, (const B *)W.ke, (const B *)W.VX, (const B *)W.VY,
                  (const B *)W.dn, (const B *)W.pn, (const B *)W.wn, u, v, delp, pt, w);
         STOP(6);
         // dz_d
@@ -1956,7 +1977,8 @@ static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid 
     if (nsplt <= 0) {
         unsigned long long zero = 0, h = 0;
         fill(W.umax, 1, zero, st);
-        launch2d_native("k_absmax", k_absmax<B>, 0, n, 0, n, P, st, G, (const B *)cx, (const B *)cy, W.umax);
+        launch2d_native("k_absmax", k_absmax<B>, 0, n, 0, n, P < 8 ? P : 8, st, G, (const B *)cx, (const B *)cy,
+                        W.umax);
         if (hipMemcpyAsync(&h, W.umax, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return FV3_EDEVICE;
         if (hipStreamSynchronize(st) != hipSuccess) return FV3_EDEVICE;
         double cmax;
@@ -1965,7 +1987,7 @@ static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid 
         if (nsplt < 1) nsplt = 1;
     }
     double rs = (double)nsplt;
-    launch2d(k_tracer_flux<B>, -3, n + 3, -3, n + 3, P, st, G, Md, rs, (const B *)cx, (const B *)cy,
+    launch2d_s(k_tracer_flux<B>, (Shape{128, 2}), -3, n + 3, -3, n + 3, P, st, G, Md, rs, (const B *)cx, (const B *)cy,
              (const double *)s->mfx, (const double *)s->mfy, W.crx, W.cry, W.xfx, W.yfx, W.mxs, W.mys);
     copy(s->dp0, W.dp1, el, st);
     double *dp1 = W.dp1, *dp2 = W.dp2;

@@ -31,6 +31,7 @@ namespace {
 
 constexpr int RMAX = FV3_REMAP_MAX_LEVELS;
 constexpr int RSLOTS = 8;   // fields per launch, at most
+constexpr int RNF = 4;      // cell fields per thread (one walk of the column serves them all)
 enum { RM_CELL = 0, RM_U = 1, RM_V = 2 };
 
 // reference coordinate, passed by value in the kernel arguments
@@ -58,28 +59,19 @@ __device__ __forceinline__ void st(void *p, long e, bool fp64, bool bulk64, doub
     else ((float *)p)[e] = (float)v;
 }
 
-// monotonised slope of the middle layer of three
-__device__ __forceinline__ double mslope(double dl, double dc, double dr, double al, double ac, double ar)
+// monotonised slope from the raw slope and the two one-sided differences
+__device__ __forceinline__ double mono(double raw, double lo, double hi)
 {
-    double lo = ac - al, hi = ar - ac;
     if (lo * hi <= 0.0) return 0.0;
-    double s = dc / (dl + dc + dr) * ((2.0 * dl + dc) / (dr + dc) * hi + (dc + 2.0 * dr) / (dl + dc) * lo);
-    double m = fmin(fabs(s), 2.0 * fmin(fabs(lo), fabs(hi)));
-    return copysign(m, s);
+    return copysign(fmin(fabs(raw), 2.0 * fmin(fabs(lo), fabs(hi))), raw);
 }
 
-// fourth-order interface value between layers 1 and 2 of four
-__device__ __forceinline__ double iface4(double d0, double d1, double d2, double d3, double a0, double a1,
-                                         double a2, double a3, double s1, double s2)
-{
-    double jump = a2 - a1;
-    double w = 2.0 * d2 * d1 / (d1 + d2) * ((d0 + d1) / (2.0 * d1 + d2) - (d3 + d2) / (2.0 * d2 + d1));
-    double c = w * jump - d1 * (d0 + d1) / (2.0 * d1 + d2) * s2 + d2 * (d2 + d3) / (d1 + 2.0 * d2) * s1;
-    return a1 + d1 / (d1 + d2) * jump + c / (d0 + d1 + d2 + d3);
-}
-
-// Remap one field of one column (cell or face, by MODE).
-template <int MODE>
+// Remap up to NF fields of one column (cell or face, by MODE) in one walk.
+// The layer geometry (reciprocals of the thickness sums of the interface
+// interpolation, the layer's own reciprocal thickness) is computed once per
+// source layer for all fields; the limited slope of layer s + 1, needed by the
+// interface below layer s, is kept for the interface below layer s + 1.
+template <int MODE, int NF>
 __global__ __launch_bounds__(256) void k_remap(Geo G, int bulk64, double ptop, RCoef C, RBatch F,
                                                const void *delp, int *flags)
 {
@@ -87,13 +79,13 @@ __global__ __launch_bounds__(256) void k_remap(Geo G, int bulk64, double ptop, R
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
     const int ni = MODE == RM_V ? n + 1 : n, nj = MODE == RM_U ? n + 1 : n;
     if (i >= ni || j >= nj) return;
-    const int t = (int)blockIdx.z / F.nf, f = (int)blockIdx.z % F.nf;
-    const bool b64 = bulk64 != 0, f64 = F.fp64[f] != 0, ratio = F.ratio[f] != 0;
+    const int groups = (F.nf + NF - 1) / NF;
+    const int t = (int)blockIdx.z / groups, f0 = ((int)blockIdx.z % groups) * NF;
+    const int nfg = min(NF, F.nf - f0);
+    const bool b64 = bulk64 != 0;
     const long lev = G.lev;
     const long c0 = G.off0 + (long)t * nz * lev + (long)j * G.pitch + i;
     const long c1 = MODE == RM_U ? c0 - G.pitch : MODE == RM_V ? c0 - 1 : c0;   // other cell of a face
-    const void *src = F.src[f];
-    void *dst = F.dst[f];
 
     auto thick = [&](int k) -> double {
         long o = (long)k * lev;
@@ -104,85 +96,148 @@ __global__ __launch_bounds__(256) void k_remap(Geo G, int bulk64, double ptop, R
     double ps = ptop;
     for (int k = 0; k < nz; k++) ps += thick(k);
 
-    // window: layers s-2 .. s+2 (a: means, d: thicknesses, b3/b4: bottom
-    // interfaces of layers s+1, s+2 as summed); pa = the bottom interface of
-    // the last layer read
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, d0 = 1, d1 = 1, d2 = 1, d3 = 1, d4 = 1;
-    double pa = ptop, b2 = ptop, b3 = ptop, b4 = ptop;
-    auto next = [&](int k, double &a, double &d, double &bot) {
+    // window over layers s-1 .. s+2 (positions 1..4): thicknesses d1..d4,
+    // means a2..a4 per field (layer s-1 enters only through its slope and
+    // thickness); b3, b4 = bottom interfaces of layers s+1, s+2 as summed
+    double d1 = 1, d2 = 1, d3 = 1, d4 = 1, pa = ptop, b2 = ptop, b3 = ptop, b4 = ptop;
+    double a2[NF], a3[NF], a4[NF];
+    auto next = [&](int k, double *a, double &d, double &bot) {
         if (k >= nz) return;
-        double h = thick(k), b = pa + h;
-        d = b - pa;
-        pa = b;
-        bot = b;
-        double v = ld(src, c0 + (long)k * lev, f64, b64);
-        a = ratio ? v / h : v;
+        double h = thick(k), bb = pa + h;
+        d = bb - pa;
+        pa = bb;
+        bot = bb;
+        double rh = 1.0 / h;
+#pragma unroll
+        for (int q = 0; q < NF; q++) {
+            if (q < nfg) {
+                double v = ld(F.src[f0 + q], c0 + (long)k * lev, F.fp64[f0 + q] != 0, b64);
+                a[q] = F.ratio[f0 + q] ? v * rh : v;
+            }
+        }
     };
+#pragma unroll
+    for (int q = 0; q < NF; q++) a2[q] = a3[q] = a4[q] = 0.0;
     next(0, a2, d2, b2);
     next(1, a3, d3, b3);
     next(2, a4, d4, b4);
-    // interface value below layer s before limiting (K = s + 1)
-    auto raw_below = [&](int s) -> double {
-        int K = s + 1;
-        if (K >= 2 && K <= nz - 2)
-            return iface4(d1, d2, d3, d4, a1, a2, a3, a4, mslope(d1, d2, d3, a1, a2, a3),
-                          mslope(d2, d3, d4, a2, a3, a4));
-        return (a2 * d3 + a3 * d2) / (d2 + d3);
+
+    // limited slope of the layer at position 3 (layers s, s+1, s+2 at
+    // positions 2, 3, 4) for every field
+    double sl3[NF];
+    auto slope3 = [&](bool have) {
+        double r = 1.0 / (d2 + d3 + d4), kh = d3 * r * (2.0 * d2 + d3) / (d4 + d3),
+               kl = d3 * r * (d3 + 2.0 * d4) / (d2 + d3);
+#pragma unroll
+        for (int q = 0; q < NF; q++) {
+            double lo = a3[q] - a2[q], hi = a4[q] - a3[q];
+            sl3[q] = have ? mono(kh * hi + kl * lo, lo, hi) : 0.0;
+        }
     };
+    slope3(nz >= 3);
+    // interface values below layer s (K = s + 1) before limiting; sl2 = the
+    // limited slope of layer s
+    double eR[NF], l[NF], r[NF], c6[NF], acc[NF];
+    auto below = [&](int s, const double *sl2) {
+        const int K = s + 1;
+        if (K >= 2 && K <= nz - 2) {
+            double s23 = d2 + d3, rs = 1.0 / s23, rsum = 1.0 / (d1 + d2 + d3 + d4);
+            double cj = d2 * rs;
+            double w = 2.0 * d3 * d2 * rs * ((d1 + d2) / (2.0 * d2 + d3) - (d4 + d3) / (2.0 * d3 + d2));
+            double g1 = d3 * (d3 + d4) / (d2 + 2.0 * d3), g2 = d2 * (d1 + d2) / (2.0 * d2 + d3);
+#pragma unroll
+            for (int q = 0; q < NF; q++) {
+                double jump = a3[q] - a2[q];
+                eR[q] = a2[q] + cj * jump + (w * jump - g2 * sl3[q] + g1 * sl2[q]) * rsum;
+            }
+        } else {
+            double rs = 1.0 / (d2 + d3);
+#pragma unroll
+            for (int q = 0; q < NF; q++) eR[q] = (a2[q] * d3 + a3[q] * d2) * rs;
+        }
+    };
+    {
+        double zero[NF];
+#pragma unroll
+        for (int q = 0; q < NF; q++) {
+            zero[q] = 0.0;
+            eR[q] = a2[q];
+        }
+        if (nz > 1) below(0, zero);
+    }
+#pragma unroll
+    for (int q = 0; q < NF; q++) {
+        l[q] = r[q] = a2[q];   // layer 0 is constant
+        c6[q] = 0.0;
+        acc[q] = 0.0;
+    }
     int s = 0;
-    double eR = nz > 1 ? raw_below(0) : a2, eL = a2;
-    double l = a2, r = a2, c6 = 0.0;   // layer 0 is constant
     // both walks end on ps exactly
-    double top1 = ptop, bot1 = nz > 1 ? b2 : ps;
+    double top1 = ptop, bot1 = nz > 1 ? b2 : ps, rds = 1.0 / (bot1 - top1);
     double top2 = ptop, bot2 = nz > 1 ? C.ak[1] + C.bk[1] * ps : ps;
-    double cur = ptop, acc = 0.0;
+    double cur = ptop;
     int m = 0;
     bool bad = false;
     for (int it = 0; it <= 2 * nz; it++) {
         double nxt = fmin(bot1, bot2);
-        double ds = bot1 - top1;
-        double x1 = (cur - top1) / ds, x2 = (nxt - top1) / ds;
-        // integral of l + x (r - l + c6 (1 - x)) over [x1, x2]
-        double q = l + 0.5 * (r - l + c6) * (x1 + x2) - c6 * (x1 * x1 + x1 * x2 + x2 * x2) / 3.0;
-        acc += ds * (x2 - x1) * q;
+        double x1 = (cur - top1) * rds, x2 = (nxt - top1) * rds;
+        // integral over [x1, x2] of l + x (r - l + c6 (1 - x)), times the thickness
+        double h = (nxt - cur), sx = 0.5 * (x1 + x2), qx = (x1 * x1 + x1 * x2 + x2 * x2) * (1.0 / 3.0);
+#pragma unroll
+        for (int q = 0; q < NF; q++) acc[q] += h * (l[q] + (r[q] - l[q] + c6[q]) * sx - c6[q] * qx);
         cur = nxt;
         if (nxt >= bot2) {   // target layer m complete
-            double dm = bot2 - top2;
+            double dm = bot2 - top2, rdm = 1.0 / dm;
             bad |= !(dm > 0.0);
-            st(dst, c0 + (long)m * lev, f64, b64, ratio ? acc : acc / dm);
-            acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < NF; q++) {
+                if (q < nfg)
+                    st(F.dst[f0 + q], c0 + (long)m * lev, F.fp64[f0 + q] != 0, b64,
+                       F.ratio[f0 + q] ? acc[q] : acc[q] * rdm);
+                acc[q] = 0.0;
+            }
             top2 = bot2;
             if (++m == nz) break;
             bot2 = m + 1 < nz ? C.ak[m + 1] + C.bk[m + 1] * ps : ps;
         }
         if (nxt >= bot1 && s < nz - 1) {   // into source layer s + 1
             s++;
-            a0 = a1; a1 = a2; a2 = a3; a3 = a4;
-            d0 = d1; d1 = d2; d2 = d3; d3 = d4;
+            double sl2[NF];
+#pragma unroll
+            for (int q = 0; q < NF; q++) {
+                a2[q] = a3[q];
+                a3[q] = a4[q];
+                sl2[q] = sl3[q];
+            }
+            d1 = d2; d2 = d3; d3 = d4;
             top1 = bot1;
             bot1 = s < nz - 1 ? b3 : ps;
+            rds = 1.0 / (bot1 - top1);
             b3 = b4;
             next(s + 2, a4, d4, b4);
-            eL = eR;
-            eR = s < nz - 1 ? raw_below(s) : a2;
-            if (s == nz - 1) {
-                l = r = a2;
-            } else {
-                l = eL;
-                r = eR;
-                if ((r - a2) * (a2 - l) <= 0.0) {
-                    l = r = a2;
+            slope3(s + 2 <= nz - 1);
+            double eL[NF];
+#pragma unroll
+            for (int q = 0; q < NF; q++) eL[q] = eR[q];
+            if (s < nz - 1) below(s, sl2);
+#pragma unroll
+            for (int q = 0; q < NF; q++) {
+                double lq = eL[q], rq = eR[q], aq = a2[q];
+                if (s == nz - 1) {
+                    lq = rq = aq;
+                } else if ((rq - aq) * (aq - lq) <= 0.0) {
+                    lq = rq = aq;
                 } else {
-                    double dq = r - l, cc = 6.0 * (a2 - 0.5 * (l + r));
-                    if (dq * cc > dq * dq) l = 3.0 * a2 - 2.0 * r;
-                    else if (-dq * dq > dq * cc) r = 3.0 * a2 - 2.0 * l;
+                    double dq = rq - lq, cc = 6.0 * (aq - 0.5 * (lq + rq));
+                    if (dq * cc > dq * dq) lq = 3.0 * aq - 2.0 * rq;
+                    else if (-dq * dq > dq * cc) rq = 3.0 * aq - 2.0 * lq;
                 }
+                l[q] = lq;
+                r[q] = rq;
+                c6[q] = 6.0 * (aq - 0.5 * (lq + rq));
             }
-            c6 = 6.0 * (a2 - 0.5 * (l + r));
         }
     }
-    (void)d0;
-    (void)a0;
     if (bad || m != nz) atomicOr(flags + 2, 1);
 }
 
@@ -261,8 +316,8 @@ fv3_status run_remap(fv3_state *s, const fv3_grid *g, const double *ak, const do
         V.nf = 1;
         dim3 gu((unsigned)((n + 63) / 64), (unsigned)((n + 1 + 3) / 4), (unsigned)g->T);
         dim3 gv((unsigned)((n + 1 + 63) / 64), (unsigned)((n + 3) / 4), (unsigned)g->T);
-        timed("k_remap_u", k_remap<RM_U>, gu, blk, st, G, b64, ptop, C, U, (const void *)s->delp, g->flags);
-        timed("k_remap_v", k_remap<RM_V>, gv, blk, st, G, b64, ptop, C, V, (const void *)s->delp, g->flags);
+        timed("k_remap_u", k_remap<RM_U, 1>, gu, blk, st, G, b64, ptop, C, U, (const void *)s->delp, g->flags);
+        timed("k_remap_v", k_remap<RM_V, 1>, gv, blk, st, G, b64, ptop, C, V, (const void *)s->delp, g->flags);
         gu.z = (unsigned)(g->T * nz);
         gv.z = (unsigned)(g->T * nz);
         timed("k_remap_back", k_remap_back<RM_U>, gu, blk, st, G, b64, U);
@@ -280,8 +335,9 @@ fv3_status run_remap(fv3_state *s, const fv3_grid *g, const double *ak, const do
             B.fp64[f] = fs[b + f] == (const void *)s->delz;
             B.ratio[f] = B.fp64[f];
         }
-        dim3 gc((unsigned)((n + 63) / 64), (unsigned)((n + 3) / 4), (unsigned)(g->T * B.nf));
-        timed("k_remap_cells", k_remap<RM_CELL>, gc, blk, st, G, b64, ptop, C, B, (const void *)s->delp,
+        const int groups = (B.nf + RNF - 1) / RNF;
+        dim3 gc((unsigned)((n + 63) / 64), (unsigned)((n + 3) / 4), (unsigned)(g->T * groups));
+        timed("k_remap_cells", k_remap<RM_CELL, RNF>, gc, blk, st, G, b64, ptop, C, B, (const void *)s->delp,
               g->flags);
         gc.z = (unsigned)(g->T * nz * B.nf);
         timed("k_remap_back", k_remap_back<RM_CELL>, gc, blk, st, G, b64, B);
