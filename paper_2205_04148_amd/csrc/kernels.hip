@@ -342,33 +342,47 @@ static void launch2d_native(const char *name, Kern kern, int ilo, int ihi, int j
 template <class T>
 DEVI T lslope(T a, T b, T c)
 {
+    // zero at an extremum of (a, b, c): then min(mx - b, b - mn) is zero
     T d = (c - a) * (T)0.25;
     T mx = fmax(a, fmax(b, c)), mn = fmin(a, fmin(b, c));
-    T lim = fmin(fabs(d), fmin(mx - b, b - mn));
-    return d > 0 ? lim : (d < 0 ? -lim : (T)0);
+    return copysign(fmin(fabs(d), fmin(mx - b, b - mn)), d);
 }
+
+// Face value from the upwind cell q's parabola (neighbours a, b | d, e), with
+// c the signed Courant number.  For the downwind orientation the parabola's
+// edge deviations swap roles and the swept fraction is |c|:
+// q + (1 - |c|) (e - |c| (bl + br)), e = br for c > 0 and bl otherwise.
 template <class T>
-DEVI T sgnT(T x) { return x > 0 ? (T)1 : (x < 0 ? (T)-1 : (T)0); }
+DEVI T ppm_up(T a, T b, T q, T d, T e, T c)
+{
+    const T third = (T)1 / (T)3;
+    const T dl = lslope(a, b, q), dm = lslope(b, q, d), dr = lslope(q, d, e);
+    const T al = (T)0.5 * (b + q) + (dl - dm) * third;
+    const T ar = (T)0.5 * (q + d) + (dm - dr) * third;
+    // deviations clipped to twice the slope, with the slope's sign (zero slope: zero)
+    const T a2 = (T)2 * fabs(dm);
+    const T bl = copysign(fmin(a2, fabs(al - q)), -dm);
+    const T br = copysign(fmin(a2, fabs(ar - q)), dm);
+    const T cc = fabs(c);
+    return q + ((T)1 - cc) * ((c > 0 ? br : bl) - cc * (bl + br));
+}
 
 template <class T>
 DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
 {
     // Branch-free: select the upwind cell's five-point neighbourhood (cell
-    // m-1 for c > 0, else cell m), then one evaluation.  For the downwind
-    // orientation the parabola's edge deviations swap roles and the swept
-    // fraction is |c|: q + (1 - |c|) (e - |c| (bl + br)) with e = br for
-    // c > 0 and bl otherwise, the same arithmetic as the two one-sided forms.
-    const T third = (T)1 / (T)3;
+    // m-1 for c > 0, else cell m), then one evaluation.
     const bool pos = c > 0;
-    const T a = pos ? q0 : q1, b = pos ? q1 : q2, q = pos ? q2 : q3, d = pos ? q3 : q4, e = pos ? q4 : q5;
-    const T dl = lslope(a, b, q), dm = lslope(b, q, d), dr = lslope(q, d, e);
-    const T al = (T)0.5 * (b + q) + (dl - dm) * third;
-    const T ar = (T)0.5 * (q + d) + (dm - dr) * third;
-    const T s = sgnT(dm), a2 = (T)2 * fabs(dm);
-    const T bl = -s * fmin(a2, fabs(al - q));
-    const T br = s * fmin(a2, fabs(ar - q));
-    const T cc = pos ? c : -c;
-    return q + ((T)1 - cc) * ((pos ? br : bl) - cc * (bl + br));
+    return ppm_up(pos ? q0 : q1, pos ? q1 : q2, pos ? q2 : q3, pos ? q3 : q4, pos ? q4 : q5, c);
+}
+
+// The same from six cells m-3..m+2 stored S apart from p (in LDS): the upwind
+// neighbourhood is selected by its address, five loads instead of six.
+template <int S, class T>
+DEVI T ppm_lds(const T *p, T c)
+{
+    const T *u = p + (c > 0 ? 0 : S);
+    return ppm_up(u[0], u[S], u[2 * S], u[3 * S], u[4 * S], c);
 }
 
 // ====================================================================
@@ -1043,10 +1057,10 @@ struct FvArgs {
 };
 
 template <class T, class C>
-DEVI T ccr(const C *a, long o, long ob, long idx, int avg)
+DEVI T ccr(const C *a, const C *a0, int idx, int avg)
 {
-    if (avg) return (T)(0.5 * ((double)a[ob + idx] + (double)a[o + idx]));
-    return (T)a[o + idx];
+    if (avg) return (T)(0.5 * ((double)a0[idx] + (double)a[idx]));
+    return (T)a[idx];
 }
 
 template <class T, class C, class M, int EPI>
@@ -1066,41 +1080,51 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     const int n = G.n, tid = threadIdx.x;
     const int i0 = bk.x * FTX, j0 = bk.y * FTY;
     const int t = bk.z / A.Lc, k = bk.z % A.Lc;
+    // plane pointers (block-uniform) and 32-bit in-plane offsets
     const T *Q = A.q + pidx(G, A.Lq, t, k);
     const long oc = pidx(G, A.Lc, t, k);
     const int avg = A.iface && k > 0;
     const long ob = avg ? pidx(G, A.Lc, t, k - 1) : oc;
     const T *AR = A.area + G.off0 + (long)t * G.lev;
-    const long P = G.pitch;
+    const int P = (int)G.pitch;
+    const C *cry = A.cry + oc, *yfx = A.yfx + oc, *crx = A.crx + oc, *xfx = A.xfx + oc;
+    const C *cry0 = A.cry + ob, *yfx0 = A.yfx + ob, *crx0 = A.crx + ob, *xfx0 = A.xfx + ob;
+    using PT = typename std::conditional<EPI == EPI_TRACER, double, T>::type;
 
-    // 0. per-thread prefetch of the global operands of phases 4 and 5
-    double wx[N4X], wy[N4Y], pa[N5], pb[N5];
+    // 0. per-thread prefetch of the global operands of phases 4 and 5, in
+    //    their storage types
+    M wx[N4X], wy[N4Y];
+    PT pa[N5], pb[N5];
 #pragma unroll
     for (int m = 0; m < N4X; m++) {
         int e = tid + m * FNT, r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 + r;
-        wx[m] = (A.mx && e < FTY * XW && i <= n && j < n) ? (double)A.mx[oc + (long)j * P + i] : 0.0;
+        wx[m] = (A.mx && e < FTY * XW && i <= n && j < n) ? A.mx[oc + j * P + i] : (M)0;
     }
 #pragma unroll
     for (int m = 0; m < N4Y; m++) {
         int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
-        wy[m] = (A.my && e < YH * FTX && i < n && j <= n) ? (double)A.my[oc + (long)j * P + i] : 0.0;
+        wy[m] = (A.my && e < YH * FTX && i < n && j <= n) ? A.my[oc + j * P + i] : (M)0;
     }
 #pragma unroll
     for (int m = 0; m < N5; m++) {
         int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
         bool in = e < FTY * FTX && i < n && j < n;
-        long ci = (long)j * P + i;
-        pa[m] = 0.0;
-        pb[m] = 0.0;
-        if (in && EPI == EPI_MASSW) {
-            pa[m] = (double)A.dold[oc + ci];
-            pb[m] = (double)A.dnew[oc + ci];
-        } else if (in && EPI == EPI_TRACER) {
-            pa[m] = A.dp1[oc + ci];
-            pb[m] = A.dp2[oc + ci];
+        int ci = j * P + i;
+        pa[m] = (PT)0;
+        pb[m] = (PT)0;
+        if constexpr (EPI == EPI_MASSW) {
+            if (in) {
+                pa[m] = A.dold[oc + ci];
+                pb[m] = A.dnew[oc + ci];
+            }
+        } else if constexpr (EPI == EPI_TRACER) {
+            if (in) {
+                pa[m] = A.dp1[oc + ci];
+                pb[m] = A.dp2[oc + ci];
+            }
         }
     }
     // 1. stage the field (both sweep views), the area, the Courant numbers and
@@ -1114,8 +1138,8 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
                 vx = sv(G, Q, SC, i, j, 0);
                 vy = sv(G, Q, SC, i, j, 1);
             } else {
-                vx = vy = Q[(long)j * P + i];
-                ar = AR[(long)j * P + i];
+                vx = vy = Q[j * P + i];
+                ar = AR[j * P + i];
             }
         }
         sQ[e] = vx;
@@ -1127,8 +1151,8 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int i = i0 - 3 + c, j = j0 + r;
         T cr = 0, fl = 0;
         if (i <= n + 2 && j <= n) {
-            cr = ccr<T>(A.cry, oc, ob, (long)j * P + i, avg);
-            fl = ccr<T>(A.yfx, oc, ob, (long)j * P + i, avg);
+            cr = ccr<T>(cry, cry0, j * P + i, avg);
+            fl = ccr<T>(yfx, yfx0, j * P + i, avg);
         }
         sCY[e] = cr;
         sYF[e] = fl;
@@ -1138,8 +1162,8 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int i = i0 + c, j = j0 - 3 + r;
         T cr = 0, fl = 0;
         if (i <= n && j <= n + 2) {
-            cr = ccr<T>(A.crx, oc, ob, (long)j * P + i, avg);
-            fl = ccr<T>(A.xfx, oc, ob, (long)j * P + i, avg);
+            cr = ccr<T>(crx, crx0, j * P + i, avg);
+            fl = ccr<T>(xfx, xfx0, j * P + i, avg);
         }
         sCX[e] = cr;
         sXF[e] = fl;
@@ -1152,7 +1176,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T f = 0;
         if (i <= n + 2 && j <= n) {
             const T *col = sQy + r * QW + c;
-            f = ppm6(col[0], col[QW], col[2 * QW], col[3 * QW], col[4 * QW], col[5 * QW], sCY[e]);
+            f = ppm_lds<QW>(col, sCY[e]);
         }
         sFy[e] = f;
     }
@@ -1162,7 +1186,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T f = 0;
         if (i <= n && j <= n + 2) {
             const T *row = sQ + r * QW + c;
-            f = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], sCX[e]);
+            f = ppm_lds<1>(row, sCX[e]);
         }
         sFx[e] = f;
     }
@@ -1199,10 +1223,10 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 + r;
         if (i <= n && j < n) {
-            long fi = (long)j * P + i;
+            int fi = j * P + i;
             int s = (r + 3) * XW + c;
             const T *row = sQi + r * QW + c;
-            T fx = ppm6(row[0], row[1], row[2], row[3], row[4], row[5], sCX[s]);
+            T fx = ppm_lds<1>(row, sCX[s]);
             T wgt = A.mx ? (T)wx[m] : sXF[s];
             T F = (T)0.5 * (fx + sFx[s]) * wgt;
             sFx[s] = F;
@@ -1222,10 +1246,10 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
         if (i < n && j <= n) {
-            long fi = (long)j * P + i;
+            int fi = j * P + i;
             int s = r * YW + c + 3;
             const T *col = sQj + r * FTX + c;
-            T fy = ppm6(col[0], col[FTX], col[2 * FTX], col[3 * FTX], col[4 * FTX], col[5 * FTX], sCY[s]);
+            T fy = ppm_lds<FTX>(col, sCY[s]);
             T wgt = A.my ? (T)wy[m] : sYF[s];
             T F = (T)0.5 * (fy + sFy[s]) * wgt;
             sFy[s] = F;
@@ -1249,7 +1273,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
         if (i >= n || j >= n) continue;
-        long ci = (long)j * P + i;
+        int ci = j * P + i;
         T fw = sFx[(r + 3) * XW + c], fe = sFx[(r + 3) * XW + c + 1];
         T fs = sFy[r * YW + c + 3], fn = sFy[(r + 1) * YW + c + 3];
         T ar = sAR[(r + 3) * QW + c + 3];
