@@ -107,7 +107,7 @@ fv3_status fv3_free_grid(fv3_grid *g)
 {
     if (!g) return FV3_OK;
     (void)hipDeviceSynchronize();
-    for (int m = 0; m < fv3::M_COUNT; m++) {
+    for (int m = 0; m < fv3::M_ALL; m++) {
         if (g->met[m]) (void)hipFree(g->met[m]);
         if (g->metf[m]) (void)hipFree(g->metf[m]);
     }

@@ -23,7 +23,10 @@ constexpr double P_REF = 1.0e5;
 enum Stag { SC = 0, SX = 1, SY = 2, SB = 3 };
 enum Metric {
     M_DX = 0, M_DY, M_DXC, M_DYC, M_DXA, M_DYA, M_AREA, M_AREA_C, M_FC, M_FB,
-    M_SIN_U, M_COS_U, M_SIN_V, M_COS_V, M_SIN_A, M_COS_A, M_COUNT
+    M_SIN_U, M_COS_U, M_SIN_V, M_COS_V, M_SIN_A, M_COS_A, M_COUNT,
+    // reciprocals (FP64 on the host, then rounded once), so that kernels
+    // multiply instead of dividing by a metric term; 0 where the term is 0
+    M_RDX = M_COUNT, M_RDY, M_RDXC, M_RDYC, M_RAREA, M_RAREA_C, M_RSIN_U, M_RSIN_V, M_RSIN2_A, M_ALL
 };
 
 // Field geometry handed to kernels by value.
@@ -87,9 +90,9 @@ struct fv3_grid {
     int T, n, nz;
     long pitch, rows, lev, off0, pre;
     int bulk_bytes;
-    double *met[fv3::M_COUNT] = {};           // device, FP64
-    float *metf[fv3::M_COUNT] = {};           // device, FP32 copies (mixed precision)
-    std::vector<double> hmet[fv3::M_COUNT];   // host copies
+    double *met[fv3::M_ALL] = {};             // device, FP64
+    float *metf[fv3::M_ALL] = {};             // device, FP32 copies (mixed precision)
+    std::vector<double> hmet[fv3::M_ALL];     // host copies
     fv3::Plan planC, planD, planCv, planA;    // scalar, D-grid pair, C-grid pair, cell pair
     int *flags = nullptr;                     // device error latch [3]: cfl, nonfinite, remap
     double *red = nullptr;                    // device reduction scratch

@@ -383,9 +383,24 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
     set_layout(p, g);
     Geometry G(g->p);
     if (!G.connect(err)) return FV3_EINTERNAL;
-    for (int m = 0; m < M_COUNT; m++) {
+    for (int m = 0; m < M_COUNT; m++) fill_metric(G, g, m, g->hmet[m]);
+    {
+        // derived reciprocals: base term and power
+        static const int base[M_ALL - M_COUNT] = {M_DX, M_DY, M_DXC, M_DYC, M_AREA, M_AREA_C,
+                                                  M_SIN_U, M_SIN_V, M_SIN_A};
+        static const int pw[M_ALL - M_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1, 2};
+        for (int m = M_COUNT; m < M_ALL; m++) {
+            const std::vector<double> &b = g->hmet[base[m - M_COUNT]];
+            std::vector<double> &h = g->hmet[m];
+            h.assign(b.size(), 0.0);
+            for (size_t e = 0; e < b.size(); e++) {
+                double x = pw[m - M_COUNT] == 2 ? b[e] * b[e] : b[e];
+                h[e] = x != 0.0 ? 1.0 / x : 0.0;
+            }
+        }
+    }
+    for (int m = 0; m < M_ALL; m++) {
         std::vector<double> &h = g->hmet[m];
-        fill_metric(G, g, m, h);
         fv3_status s = upload(&g->met[m], h, err);
         if (s != FV3_OK) return s;
         if (p->precision == FV3_MIXED) {

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <utility>
 #include <string>
 #include <vector>
@@ -122,7 +123,7 @@ DEVI bool is_vertex(const Geo &G, int i, int j)
 
 template <class R>
 struct Mets {
-    const R *m[M_COUNT];
+    const R *m[M_ALL];
 };
 typedef Mets<double> MetD;
 
@@ -412,6 +413,30 @@ DEVI void k_halo_pair(Bk bk, Geo G, const HaloEnt *__restrict__ plan, int count,
     dst[pidx(G, L, h.dt, k) + h.di] = (h.sel & 2) ? -v : v;
 }
 
+// up to four fields of one type and level count in one launch: grid y runs
+// over (field, level)
+template <class T>
+struct FieldSet {
+    T *p[4];
+};
+template <class T>
+DEVI void k_halo_set(Bk bk, Geo G, const HaloEnt *__restrict__ plan, int count, FieldSet<T> F, int L)
+{
+    int e = bk.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    int q = (int)bk.y / L, k = (int)bk.y % L;
+    T *f = q == 0 ? F.p[0] : q == 1 ? F.p[1] : q == 2 ? F.p[2] : F.p[3];
+    HaloEnt h = plan[e];
+    f[pidx(G, L, h.dt, k) + h.di] = f[pidx(G, L, h.st, k) + h.si];
+}
+template <class T>
+static void halo_set(const fv3_grid *g, FieldSet<T> F, int nf, int L, hipStream_t st)
+{
+    if (g->planC.count == 0) return;
+    launch_fn<k_halo_set<T>>("k_halo_scalar", dim3((g->planC.count + 255) / 256, L * nf), dim3(256), st,
+                 g->geo, (const HaloEnt *)g->planC.d, g->planC.count, F, L);
+}
+
 template <class T>
 static void halo_scalar(const fv3_grid *g, T *f, int L, hipStream_t st)
 {
@@ -587,7 +612,7 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
         if (xf) {
             B a = UAx(i - 2, j, 0), b = UAx(i - 1, j, 0), c1 = UAx(i, j, 0), d = UAx(i + 1, j, 0);
             uc0 = (-a + (B)9 * b + (B)9 * c1 - d) / (B)16;
-            B fl = dt2 * (uc0 - AT(V, i, j) * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j) *
+            B fl = dt2 * (uc0 - AT(V, i, j) * AT(MP(M, M_COS_U), i, j)) * AT(MP(M, M_RSIN_U), i, j) *
                    AT(MP(M, M_DY), i, j);
             int up = fl > 0 ? i - 1 : i;
             fm = fl * cv(sD, D, up, j, 0);
@@ -603,7 +628,7 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
         if (yf) {
             B a = VAy(i, j - 2, 1), b = VAy(i, j - 1, 1), c1 = VAy(i, j, 1), d = VAy(i, j + 1, 1);
             vc0 = (-a + (B)9 * b + (B)9 * c1 - d) / (B)16;
-            B fl = dt2 * (vc0 - AT(U, i, j) * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j) *
+            B fl = dt2 * (vc0 - AT(U, i, j) * AT(MP(M, M_COS_V), i, j)) * AT(MP(M, M_RSIN_V), i, j) *
                    AT(MP(M, M_DX), i, j);
             int up = fl > 0 ? j - 1 : j;
             gm = fl * cv(sD, D, i, up, 1);
@@ -625,21 +650,21 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
         bool cross = i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
         B kev = 0;
         if (cross) {
-            B sa = AT(MP(M, M_SIN_A), i, j), ca = AT(MP(M, M_COS_A), i, j);
-            B s2 = sa * sa;
+            B rs2 = AT(MP(M, M_RSIN2_A), i, j), ca = AT(MP(M, M_COS_A), i, j);
             B a = sUA[aA(i, j)], b = sVA[aA(i, j)];
-            B uu = (a - b * ca) / s2, vv = (b - a * ca) / s2;
+            B uu = (a - b * ca) * rs2, vv = (b - a * ca) * rs2;
             kev = (B)0.5 * dt2 * (uu * (uu > 0 ? sUC[aF(i, j)] : sUC[aF(i + 1, j)]) +
                                   vv * (vv > 0 ? sVC[aF(i, j)] : sVC[aF(i, j + 1)]));
             if (i >= i0 && j >= j0) {
-                B ar = AT(MP(M, M_AREA), i, j);
+                B rar = AT(MP(M, M_RAREA), i, j);
                 B dp = sD[aD(i, j)];
-                B dc = dp + (sFm[aF(i, j)] - sFm[aF(i + 1, j)] + sGm[aF(i, j)] - sGm[aF(i, j + 1)]) / ar;
+                B dc = dp + (sFm[aF(i, j)] - sFm[aF(i + 1, j)] + sGm[aF(i, j)] - sGm[aF(i, j + 1)]) * rar;
+                B rdc = (B)1 / dc;
                 AT(delpc + o, i, j) = dc;
                 AT(ptc + o, i, j) =
-                    (sPT[aD(i, j)] * dp + (sFp[aF(i, j)] - sFp[aF(i + 1, j)] + sGp[aF(i, j)] - sGp[aF(i, j + 1)]) / ar) / dc;
+                    (sPT[aD(i, j)] * dp + (sFp[aF(i, j)] - sFp[aF(i + 1, j)] + sGp[aF(i, j)] - sGp[aF(i, j + 1)]) * rar) * rdc;
                 AT(wc + o, i, j) =
-                    (sW[aD(i, j)] * dp + (sFw[aF(i, j)] - sFw[aF(i + 1, j)] + sGw[aF(i, j)] - sGw[aF(i, j + 1)]) / ar) / dc;
+                    (sW[aD(i, j)] * dp + (sFw[aF(i, j)] - sFw[aF(i + 1, j)] + sGw[aF(i, j)] - sGw[aF(i, j + 1)]) * rar) * rdc;
             }
         }
         sKE[e] = kev;
@@ -656,7 +681,7 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
             }
             B circ = ws * sUC[aF(i, j - 1)] * AT(MP(M, M_DXC), i, j - 1) - wn * sUC[aF(i, j)] * AT(MP(M, M_DXC), i, j) -
                      ww * sVC[aF(i - 1, j)] * AT(MP(M, M_DYC), i - 1, j) + we * sVC[aF(i, j)] * AT(MP(M, M_DYC), i, j);
-            vo = AT(MP(M, M_FB), i, j) + circ / AT(MP(M, M_AREA_C), i, j);
+            vo = AT(MP(M, M_FB), i, j) + circ * AT(MP(M, M_RAREA_C), i, j);
         }
         sVO[e] = vo;
     }
@@ -667,15 +692,15 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
         int i = i0 + c, j = j0 + r;
         if (i >= 0 && i <= n && j >= 0 && j < n) {
             B u0 = sUC[aF(i, j)];
-            B fy1 = dt2 * (AT(V, i, j) - u0 * AT(MP(M, M_COS_U), i, j)) / AT(MP(M, M_SIN_U), i, j);
+            B fy1 = dt2 * (AT(V, i, j) - u0 * AT(MP(M, M_COS_U), i, j)) * AT(MP(M, M_RSIN_U), i, j);
             B vt = fy1 > 0 ? sVO[aV(i, j)] : sVO[aV(i, j + 1)];
-            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) / AT(MP(M, M_DXC), i, j);
+            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * AT(MP(M, M_RDXC), i, j);
         }
         if (i >= 0 && i < n && j >= 0 && j <= n) {
             B v0 = sVC[aF(i, j)];
-            B fx1 = dt2 * (AT(U, i, j) - v0 * AT(MP(M, M_COS_V), i, j)) / AT(MP(M, M_SIN_V), i, j);
+            B fx1 = dt2 * (AT(U, i, j) - v0 * AT(MP(M, M_COS_V), i, j)) * AT(MP(M, M_RSIN_V), i, j);
             B vt = fx1 > 0 ? sVO[aV(i, j)] : sVO[aV(i + 1, j)];
-            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) / AT(MP(M, M_DYC), i, j);
+            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * AT(MP(M, M_RDYC), i, j);
         }
     }
 }
@@ -1388,7 +1413,7 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B nu, const B *u, const B *
             const B *dxc = MP(M, M_DXC), *dyc = MP(M, M_DYC);
             B flux = we * AT(U, i, j) * AT(dyc, i, j) - ww * AT(U, i - 1, j) * AT(dyc, i - 1, j) +
                      wn * AT(V, i, j) * AT(dxc, i, j) - ws * AT(V, i, j - 1) * AT(dxc, i, j - 1);
-            kev -= nu * flux / AT(MP(M, M_AREA_C), i, j);
+            kev -= nu * flux * AT(MP(M, M_RAREA_C), i, j);
         }
         AT(ke + o, i, j) = kev;
     }
@@ -1404,8 +1429,8 @@ DEVI void k_dsw_update(KARGS, Geo G, Mets<B> M, const B *ke, const B *VX, const 
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
     const B *KE = ke + o;
-    if (i < n) AT(u + o, i, j) = AT(u + o, i, j) + (AT(KE, i, j) - AT(KE, i + 1, j) + AT(VY + o, i, j)) / AT(MP(M, M_DX), i, j);
-    if (j < n) AT(v + o, i, j) = AT(v + o, i, j) + (AT(KE, i, j) - AT(KE, i, j + 1) - AT(VX + o, i, j)) / AT(MP(M, M_DY), i, j);
+    if (i < n) AT(u + o, i, j) = AT(u + o, i, j) + (AT(KE, i, j) - AT(KE, i + 1, j) + AT(VY + o, i, j)) * AT(MP(M, M_RDX), i, j);
+    if (j < n) AT(v + o, i, j) = AT(v + o, i, j) + (AT(KE, i, j) - AT(KE, i, j + 1) - AT(VX + o, i, j)) * AT(MP(M, M_RDY), i, j);
     if (i < n && j < n) {
         AT(delp + o, i, j) = AT(dn + o, i, j);
         AT(pt + o, i, j) = AT(pn + o, i, j);
@@ -1799,14 +1824,14 @@ template <>
 Mets<double> metrics_b<double>(const fv3_grid *g)
 {
     Mets<double> M;
-    for (int m = 0; m < M_COUNT; m++) M.m[m] = g->met[m];
+    for (int m = 0; m < M_ALL; m++) M.m[m] = g->met[m];
     return M;
 }
 template <>
 Mets<float> metrics_b<float>(const fv3_grid *g)
 {
     Mets<float> M;
-    for (int m = 0; m < M_COUNT; m++) M.m[m] = g->metf[m];
+    for (int m = 0; m < M_ALL; m++) M.m[m] = g->metf[m];
     return M;
 }
 static MetD metrics_d(const fv3_grid *g) { return metrics_b<double>(g); }
@@ -1844,10 +1869,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
 #define STOP(x) if (last && stop_stage == (x)) goto done
         // H-A
         halo_pair(g, g->planD, u, v, nz, st);
-        halo_scalar(g, delp, nz, st);
-        halo_scalar(g, pt, nz, st);
-        halo_scalar(g, w, nz, st);
-        halo_scalar(g, delz, nz, st);
+        if constexpr (std::is_same<B, double>::value) {
+            halo_set<double>(g, FieldSet<double>{{delp, pt, w, delz}}, 4, nz, st);
+        } else {
+            halo_set<B>(g, FieldSet<B>{{delp, pt, w, nullptr}}, 3, nz, st);
+            halo_scalar(g, delz, nz, st);
+        }
         STOP(1);
         // c_sw
         launch_fn<k_csw<B>>("k_csw", dim3((unsigned)((n + 1 + CTX + CTX) / CTX),
@@ -1928,8 +1955,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
                        s->pfull, s->phi, 0);
         STOP(8);
         // H-C
-        halo_scalar(g, s->pfull, nz + 1, st);
-        halo_scalar(g, s->phi, nz + 1, st);
+        halo_set<double>(g, FieldSet<double>{{s->pfull, s->phi, nullptr, nullptr}}, 2, nz + 1, st);
         halo_scalar(g, delp, nz, st);
         STOP(9);
         // nh_p_grad
