@@ -54,6 +54,9 @@ def lib():
                                    C.c_double, C.c_double, C.c_char_p, C.c_int]
         L.orc_grid_free.argtypes = [C.c_void_p]
         L.orc_set_damping.argtypes = [C.c_void_p, C.c_double]
+        L.orc_set_beta.argtypes = [C.c_void_p, C.c_double]
+        L.orc_sim1b.restype = C.c_double
+        L.orc_sim1b.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [dp] * 10
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_grid_conn.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_halo_fill.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, C.c_int]
@@ -97,7 +100,7 @@ class Grid:
 
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
-                 d2_bg: float = 0.0):
+                 d2_bg: float = 0.0, beta: float = 1.0):
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
@@ -105,6 +108,8 @@ class Grid:
         self._h = h
         self.d2_bg = d2_bg
         lib().orc_set_damping(h, float(d2_bg))
+        self.beta = beta
+        lib().orc_set_beta(h, float(beta))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -172,13 +177,17 @@ def fv_tp_2d(g: Grid, t: int, q, crx, cry, xfx, yfx, mx=None, my=None):
     return FX, FY
 
 
-def sim1(dt, ptop, zs, dpi, theta, delz, w):
+def sim1(dt, ptop, zs, dpi, theta, delz, w, beta: float = 1.0):
+    """One column solve; also returns the interface perturbation P* ("pstar")
+    and the unscaled coupling dt x linearised pressure response ("coupling")."""
     nz = len(dpi)
     ins = [np.ascontiguousarray(a, dtype=np.float64) for a in (dpi, theta, delz, w)]
     wo, dzo = np.zeros(nz), np.zeros(nz)
     pf, ph = np.zeros(nz + 1), np.zeros(nz + 1)
-    minpiv = lib().orc_sim1(nz, dt, ptop, zs, *[_p(a) for a in ins], _p(wo), _p(dzo), _p(pf), _p(ph))
-    return dict(w=wo, delz=dzo, pfull=pf, phi=ph, min_pivot=minpiv)
+    ps, cp = np.zeros(nz + 1), np.zeros(nz + 1)
+    minpiv = lib().orc_sim1b(nz, dt, float(beta), ptop, zs, *[_p(a) for a in ins], _p(wo), _p(dzo),
+                             _p(pf), _p(ph), _p(ps), _p(cp))
+    return dict(w=wo, delz=dzo, pfull=pf, phi=ph, min_pivot=minpiv, pstar=ps, coupling=cp)
 
 
 def pgf(dt, L, dpiW, dpiE, phW0, phW1, phE0, phE1, pW0, pW1, pE0, pE1) -> float:

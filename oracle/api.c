@@ -39,6 +39,9 @@ void orc_set_damping(void *gp, double d2_bg)
     g->da_min = m;
 }
 
+/* off-centring weight of the vertical solve */
+void orc_set_beta(void *gp, double beta) { ((OGrid *)gp)->beta = beta; }
+
 /* which: 0 dx 1 dy 2 dxc 3 dyc 4 dxa 5 dya 6 area 7 area_c 8 fC 9 fB 10 sin_u 11 cos_u
  *        12 sin_v 13 cos_v 14 sin_a 15 cos_a 16..18 centre xyz 19..21 corner xyz */
 int orc_grid_metric(void *gp, int which, double *out)
@@ -110,6 +113,13 @@ double orc_sim1(int nz, double dt, double ptop, double zs, const double *dpi, co
                 double *pfull, double *phi)
 {
     return o_sim1(nz, dt, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi);
+}
+
+double orc_sim1b(int nz, double dt, double beta, double ptop, double zs, const double *dpi,
+                 const double *theta, const double *delz, const double *w, double *w_out,
+                 double *delz_out, double *pfull, double *phi, double *pstar, double *coupling)
+{
+    return o_sim1b(nz, dt, beta, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi, pstar, coupling);
 }
 
 double orc_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,

@@ -22,6 +22,15 @@
  *   scan of m (w_new - w)/dt, the new thickness by inverting the equation of
  *   state, and heights by a bottom-up scan from the surface.
  *
+ * Off-centring (weight beta in [0.5, 1], 1 = backward Euler above): the
+ * momentum equation sees P^b = beta P^{n+1} + (1 - beta) P* and the pressure
+ * response is driven by w^b = beta w^{n+1} + (1 - beta) w^n.  Eliminating
+ * P^{n+1} leaves the same tridiagonal form with the coupling scaled by
+ * beta^2 and the explicit part (1 - beta)/beta times the coupling acting on
+ * w^n on the right-hand side; the top-down scan of m (w_new - w)/dt then
+ * gives P^b, and P^{n+1} = (P^b - (1 - beta) P*)/beta enters the equation of
+ * state.
+ *
  * The pressure-gradient force is the contour integral of p dPhi around the
  * quadrilateral spanned by two columns and two interfaces (Green's theorem),
  * divided by the mean layer mass and the distance between the columns.
@@ -31,9 +40,9 @@
 #include <stdlib.h>
 
 /* Returns the smallest Thomas pivot (positive for a well-posed column). */
-double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, const double *theta,
-              const double *delz, const double *w, double *w_out, double *delz_out,
-              double *pfull, double *phi)
+double o_sim1b(int nz, double dt, double beta, double ptop, double zs, const double *dpi,
+               const double *theta, const double *delz, const double *w, double *w_out,
+               double *delz_out, double *pfull, double *phi, double *pstar, double *coupling)
 {
     const double g = O_GRAV, rd = O_RDGAS, kappa = O_RDGAS / O_CP;
     const double gam = 1.0 / (1.0 - kappa), p0 = O_P0;
@@ -62,17 +71,28 @@ double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, cons
     for (int K = 1; K < nz; K++)
         pps[K] = (dpi[K] * pp[K - 1] + dpi[K - 1] * pp[K]) / (dpi[K - 1] + dpi[K]);
     pps[nz] = pp[nz - 1];
+    /* coupling of interface K: dt times the linearised pressure response to
+     * the convergence of w, times beta^2 (see the header) */
     A[0] = 0.0;
     for (int K = 1; K <= nz; K++) {
         double d = K < nz ? 0.5 * (h[K - 1] + h[K]) : 0.5 * h[nz - 1];
-        A[K] = gam * (pi[K] + pps[K]) * dt * dt / d;
+        A[K] = beta * beta * gam * (pi[K] + pps[K]) * dt * dt / d;
+        if (coupling) coupling[K] = gam * (pi[K] + pps[K]) * dt / d;
     }
+    if (coupling) coupling[0] = 0.0;
+    if (pstar)
+        for (int K = 0; K <= nz; K++) pstar[K] = pps[K];
+    const double ex = (1.0 - beta) / beta;
     /* Thomas elimination: lower -A[k], diagonal m + A[k] + A[k+1], upper -A[k+1] */
     for (int k = 0; k < nz; k++) {
         double lower = k > 0 ? -A[k] : 0.0;
         double diag = m[k] + A[k] + A[k + 1];
         double upper = k < nz - 1 ? -A[k + 1] : 0.0;
         double rhs = m[k] * w[k] + dt * (pps[k + 1] - pps[k]);   /* surface w = 0 */
+        if (beta != 1.0) {
+            double wa = k > 0 ? w[k - 1] : 0.0, wb = k < nz - 1 ? w[k + 1] : 0.0;
+            rhs -= ex * (A[k + 1] * (w[k] - wb) - A[k] * (wa - w[k]));
+        }
         double piv = k > 0 ? diag - lower * cp[k - 1] : diag;
         if (piv < minpiv) minpiv = piv;
         cp[k] = upper / piv;
@@ -81,8 +101,11 @@ double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, cons
     w_out[nz - 1] = dp[nz - 1];
     for (int k = nz - 2; k >= 0; k--) w_out[k] = dp[k] - cp[k] * w_out[k + 1];
 
+    /* the scan gives the off-centred perturbation; the new one follows */
     ppn[0] = 0.0;
     for (int k = 0; k < nz; k++) ppn[k + 1] = ppn[k] + m[k] * (w_out[k] - w[k]) / dt;
+    if (beta != 1.0)
+        for (int K = 0; K <= nz; K++) ppn[K] = (ppn[K] - (1.0 - beta) * pps[K]) / beta;
     double z = zs;
     if (phi) phi[nz] = g * z;
     double *hn = (double *)malloc(sizeof(double) * nz);
@@ -100,6 +123,13 @@ double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, cons
     free(pi); free(pibar); free(m); free(h); free(pp); free(pps); free(A);
     free(cp); free(dp); free(ppn); free(hn);
     return minpiv;
+}
+
+double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, const double *theta,
+              const double *delz, const double *w, double *w_out, double *delz_out,
+              double *pfull, double *phi)
+{
+    return o_sim1b(nz, dt, 1.0, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi, 0, 0);
 }
 
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,

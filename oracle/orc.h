@@ -45,6 +45,8 @@ typedef struct {
     /* optional del-2 divergence damping of d_sw: coefficient and the smallest
      * corner (dual-cell) area of the grid */
     double d2_bg, da_min;
+    /* off-centring weight of the vertical solve (1 = backward Euler) */
+    double beta;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -90,6 +92,12 @@ void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const 
 double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, const double *theta,
               const double *delz, const double *w, double *w_out, double *delz_out,
               double *pfull, double *phi);
+/* off-centred form (beta in [0.5, 1]); pstar / coupling (nz + 1, may be NULL)
+ * receive the interface perturbation P* and the unscaled coupling dt x the
+ * linearised pressure response */
+double o_sim1b(int nz, double dt, double beta, double ptop, double zs, const double *dpi,
+               const double *theta, const double *delz, const double *w, double *w_out,
+               double *delz_out, double *pfull, double *phi, double *pstar, double *coupling);
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
              double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
 

@@ -32,6 +32,23 @@ def test_cfg1_mass_conservation(orc):
     assert np.abs(_int(s["delp"], 48) - _int(fi.periodic_state()["delp"], 48)).max() > 1e-3
 
 
+def test_offcentred_substeps_conserve_mass_and_differ(orc):
+    """Ten substeps with an off-centred vertical solve (beta = 0.6): delp and
+    pt delp mass conserved to rounding, the run finite, and w different from
+    the backward-Euler run (the weight reaches the solve)."""
+    init = fi.periodic_state()
+    ga, gb = orc.Grid(0, 48, 8), orc.Grid(0, 48, 8, beta=0.6)
+    sa, sb = orc.new_state(ga, init), orc.new_state(gb, init)
+    m0 = orc.mass_sums(gb, sb["delp"], sb["pt"])
+    assert orc.acoustic_substeps(ga, sa, 2.0, 10) == 0
+    assert orc.acoustic_substeps(gb, sb, 2.0, 10) == 0
+    m1 = orc.mass_sums(gb, sb["delp"], sb["pt"])
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * np.abs(m0))
+    wa, wb = _int(sa["w"], 48), _int(sb["w"], 48)
+    assert np.isfinite(wb).all()
+    assert np.abs(wa - wb).max() > 1e-3 * np.abs(wa).max()
+
+
 def _rest(n=16, nz=6, f0=0.0):
     init = fi.periodic_state(n=n, nz=nz, wind=0.0)
     init["u"][:] = 0.0
