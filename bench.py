@@ -152,7 +152,7 @@ def cpu_baseline(init, n, nz, bdt, substeps):
 def run_precision(fv3, torch, init, args, precision):
     n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
     dt = bdt * ns
-    g = fv3.Grid(1, n, nz, precision=precision)
+    g = fv3.Grid(1, n, nz, precision=precision, beta=args.beta)
     s = fv3.State.allocate(g)
     s.load(init)
     qs = [g.upload(q, nz) for q in init["q"]]
@@ -377,6 +377,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--ensemble", action="store_true")
     ap.add_argument("--remap", action="store_true")
+    ap.add_argument("--beta", type=float, default=1.0, help="off-centring of the vertical solve (0.5 .. 1)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the acoustic substep path holds all six cube "
@@ -426,7 +427,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"C{n}x{nz} cubed-sphere baroclinic jet, {args.n_split} acoustic "
                                f"substeps of {args.bdt:g} s + 4-tracer transport + mass sums per step",
-                   "precision": args.precision, "n_split": args.n_split, "cells": cells,
+                   "precision": args.precision, "n_split": args.n_split, "cells": cells, "beta": args.beta,
                    "ms_per_substep": main_res["ms_per_substep"],
                    "device_status": main_res["device_status"]},
         "roofline": main_res["roofline"],

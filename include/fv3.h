@@ -42,7 +42,7 @@ typedef enum {
     FV3_ENOMEM = -5,        /* device allocation failed (grid creation only)                */
     FV3_ECFL = -6,          /* a Courant number exceeded 1 in d_sw (latched on device)      */
     FV3_ENONFINITE = -7,    /* a prognostic became non-finite (latched on device)           */
-    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8, beta != 1)                */
+    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8)                           */
     FV3_EREMAP = -9,        /* reference interfaces not increasing in a column (latched)    */
     FV3_EINTERNAL = -99
 } fv3_status;
@@ -54,8 +54,11 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * cells (Sec. II), radius and rotation rate given.  Doubly periodic: one
  * n x n tile of spacing dx with constant Coriolis parameter f0.  Vertical:
  * nz Lagrangian layers below the model top pressure ptop.  Only the monotone
- * PPM order hord = 8 and a fully implicit vertical solve (beta = 1) are
- * implemented; other values give FV3_EUNSUPPORTED.  d2_bg in [0, 0.25] turns
+ * PPM order hord = 8 is implemented (other values: FV3_EUNSUPPORTED).  beta
+ * in [0.5, 1] off-centres the semi-implicit vertical solve (Sec. IX-B): the
+ * momentum equation sees beta P^{n+1} + (1 - beta) P* and the pressure
+ * response is driven by beta w^{n+1} + (1 - beta) w^n; 1 is backward Euler
+ * (outside [0.5, 1]: FV3_EINVAL).  d2_bg in [0, 0.25] turns
  * on del-2 divergence damping in d_sw: nu = d2_bg x (smallest dual-cell area
  * of the grid) times the divergence of the D-grid winds at each corner is
  * subtracted from the kinetic energy there, which diffuses the divergence
@@ -69,7 +72,7 @@ typedef struct {
     int precision;       /* fv3_precision                                  */
     int hord;            /* 8                                              */
     double d2_bg;        /* del-2 divergence damping, 0 (off) .. 0.25      */
-    double beta;         /* 1                                              */
+    double beta;         /* vertical off-centring, 0.5 .. 1 (1: implicit)  */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

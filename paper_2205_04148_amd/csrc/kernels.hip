@@ -787,9 +787,11 @@ DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, co
 constexpr int SU = FV3_SIM1_SU;   // levels per prefetch group, passes 1 and 3
 constexpr int SU2 = 8;            // levels per prefetch group, passes 2 and 4
 
-// SITE tells the two solves apart in profiles (0 riem_solver_c, 1 riem_solver3)
-template <class B, class TW, int PASS, int SITE>
-DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
+// SITE tells the two solves apart in profiles (0 riem_solver_c, 1 riem_solver3);
+// OFFC: off-centred solve (beta < 1), a separate instantiation so that the
+// backward-Euler passes keep their registers
+template <class B, class TW, int PASS, int SITE, bool OFFC = false>
+DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi,
                                               const B *theta, const double *delz, const TW *w,
                                               const double *phis, double *cpv, double *dpv,
                                               double *wnv, TW *w_out, double *delz_out,
@@ -824,7 +826,11 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
     double pi_k1 = ptop + dp0, lpi_k1 = log(pi_k1);
     double m0 = dp0 / GRAV;
     double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi_k1 - lpi_k);
-    double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0;
+    double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0, wprev = 0.0;
+    // off-centring: coupling scaled by beta^2, the explicit part of the
+    // pressure response on the right-hand side; P* kept at the interfaces
+    // (in the interface-pressure output) for pass 3
+    const double bb = OFFC ? beta * beta : 1.0, ex = (1.0 - beta) / beta;
     {
         G4 cur, nxt;
 #pragma unroll
@@ -862,15 +868,20 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
                         m1 = dp1 / GRAV;
                         pp1 = P_REF * exp(gam * log(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi_k2 - lpi_k1);
                         pps_k1 = (dp1 * pp0 + dp0 * pp1) / (dp0 + dp1);
-                        A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
+                        A_k1 = bb * gam * (pi_k1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
                     } else {
                         pps_k1 = pp0;
-                        A_k1 = gam * (pi_k1 + pps_k1) * dt2x / (0.5 * h0);
+                        A_k1 = bb * gam * (pi_k1 + pps_k1) * dt2x / (0.5 * h0);
                     }
                     double lower = k > 0 ? -A_k : 0.0;
                     double diag = m0 + A_k + A_k1;
                     double upper = k < nz - 1 ? -A_k1 : 0.0;
                     double rhs = m0 * w0 + dt * (pps_k1 - pps_k);
+                    if constexpr (OFFC) {
+                        double wa = k > 0 ? wprev : 0.0, wb = k < nz - 1 ? w1 : 0.0;
+                        rhs -= ex * (A_k1 * (w0 - wb) - A_k * (wa - w0));
+                        pfull[basei + (long)(k + 1) * lev] = pps_k1;
+                    }
                     double piv = diag - lower * cprev;
                     double rpiv = 1.0 / piv;
                     double ck = upper * rpiv;
@@ -879,6 +890,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
                     dpv[base + (long)k * lev] = dk;
                     cprev = ck;
                     dprev = dk;
+                    wprev = w0;
                     pi_k1 = pi_k2; lpi_k1 = lpi_k2; dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1; w0 = w1;
                     pps_k = pps_k1; A_k = A_k1;
                 }
@@ -922,7 +934,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
     // ---- pass 3: new perturbation (top down), thicknesses, interface pressure
     if constexpr (PASS == 3) {
         const double lpref = log(P_REF);
-        double ppn = 0.0, pik = ptop, lpik = log(ptop);
+        double ppn = 0.0, pnk = 0.0, pik = ptop, lpik = log(ptop);
         if (pfull) pfull[basei] = ptop;
         G4 cur, nxt;
 #pragma unroll
@@ -956,13 +968,17 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double ptop, const B *dpi,
                     double m = dp / GRAV;
                     double pik1 = pik + dp, lpik1 = log(pik1);
                     double pib = dp / (lpik1 - lpik);
+                    // the scan gives the off-centred perturbation; the new one follows
                     double ppn1 = ppn + m * (wk - wo) / dt;
-                    double pn = pib + 0.5 * (ppn + ppn1);
+                    double pnk1 = ppn1;
+                    if constexpr (OFFC) pnk1 = (ppn1 - (1.0 - beta) * pfull[basei + (long)(k + 1) * lev]) / beta;
+                    double pn = pib + 0.5 * (pnk + pnk1);
                     double hn = RDGAS * th * m / P_REF * exp(rgam * (lpref - log(pn)));
                     cpv[base + (long)k * lev] = hn;   // reuse as the new thickness
-                    if (pfull) pfull[basei + (long)(k + 1) * lev] = pik1 + ppn1;
+                    if (pfull) pfull[basei + (long)(k + 1) * lev] = pik1 + pnk1;
                     if (w_out) w_out[base + (long)k * lev] = (TW)wk;
                     ppn = ppn1;
+                    pnk = pnk1;
                     pik = pik1;
                     lpik = lpik1;
                 }
@@ -1519,29 +1535,55 @@ DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
     }
     __syncthreads();
     const double w4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
+    // The tensor interpolation in two passes: along x for every staged row at
+    // every corner column (into registers), then along y at each corner.
+    constexpr int NRX = (NPY + 4) * (NPX + 1), NRP = (NRX + 255) / 256;
+    double xr[NRP][5];
+#pragma unroll
+    for (int m = 0; m < NRP; m++) {
+        int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+            double rw = 0.0;
+            if (e < NRX) {
+                const double *row = &sc[f][rr * NCW + c];
+                for (int a = 0; a < 4; a++) rw += w4[a] * row[a];
+            }
+            xr[m][f] = rw;
+        }
+    }
+    // corners at cube vertices: mean of the three cells, from the staged cells
     for (int e = tid; e < (NPY + 1) * (NPX + 1); e += 256) {
         int r = e / (NPX + 1), c = e - r * (NPX + 1);
         int i = i0 + c, j = j0 + r;
-        if (i > n || j > n) continue;
-        if (is_vertex(G, i, j)) {
-            int ci[4] = {i - 1, i, i, i - 1}, cj[4] = {j - 1, j - 1, j, j};
-            for (int f = 0; f < 5; f++) {
-                double s = 0.0;
-                for (int q = 0; q < 4; q++)
-                    if (!in_corner(G, SC, ci[q], cj[q])) s += sc[f][(cj[q] - j0 + 2) * NCW + (ci[q] - i0 + 2)];
-                sb[f][e] = s / 3.0;
-            }
-        } else {
-            for (int f = 0; f < 5; f++) {
-                double acc = 0.0;
-                for (int b = 0; b < 4; b++) {
-                    const double *row = &sc[f][(r + b) * NCW + c];
-                    double rw = 0.0;
-                    for (int a = 0; a < 4; a++) rw += w4[a] * row[a];
-                    acc += w4[b] * rw;
-                }
-                sb[f][e] = acc;
-            }
+        if (i > n || j > n || !is_vertex(G, i, j)) continue;
+        int ci[4] = {i - 1, i, i, i - 1}, cj[4] = {j - 1, j - 1, j, j};
+        for (int f = 0; f < 5; f++) {
+            double sum = 0.0;
+            for (int q = 0; q < 4; q++)
+                if (!in_corner(G, SC, ci[q], cj[q])) sum += sc[f][(cj[q] - j0 + 2) * NCW + (ci[q] - i0 + 2)];
+            sb[f][e] = sum / 3.0;
+        }
+    }
+    __syncthreads();
+    // the x pass in place of the staged cells (row rr, corner column c)
+#pragma unroll
+    for (int m = 0; m < NRP; m++) {
+        int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
+        if (e < NRX) {
+#pragma unroll
+            for (int f = 0; f < 5; f++) sc[f][rr * NCW + c] = xr[m][f];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < (NPY + 1) * (NPX + 1); e += 256) {
+        int r = e / (NPX + 1), c = e - r * (NPX + 1);
+        int i = i0 + c, j = j0 + r;
+        if (i > n || j > n || is_vertex(G, i, j)) continue;
+        for (int f = 0; f < 5; f++) {
+            double acc = 0.0;
+            for (int b = 0; b < 4; b++) acc += w4[b] * sc[f][(r + b) * NCW + c];
+            sb[f][e] = acc;
         }
     }
     __syncthreads();
@@ -1885,16 +1927,26 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         // dz_c + riem_solver_c on the half-step cells
         launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
                  (const B *)W.ay, W.delzc);
-        launch2d_fn<k_sim1<B, B, 1, 0>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        if (g->p.beta != 1.0)
+            launch2d_fn<k_sim1<B, B, 1, 0, true>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        launch2d_sh<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        else
+            launch2d_fn<k_sim1<B, B, 1, 0>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        launch2d_fn<k_sim1<B, B, 3, 0>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        launch2d_sh<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        launch2d_sh<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.ptop, (const B *)W.delpc,
+        if (g->p.beta != 1.0)
+            launch2d_fn<k_sim1<B, B, 3, 0, true>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
+                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        else
+            launch2d_fn<k_sim1<B, B, 3, 0>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
+                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        launch2d_sh<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         STOP(3);
@@ -1941,16 +1993,26 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         STOP(7);
         // riem_solver3
-        launch2d_fn<k_sim1<B, B, 1, 1>>("k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+        if (g->p.beta != 1.0)
+            launch2d_fn<k_sim1<B, B, 1, 1, true>>("k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
-        launch2d_fn<k_sim1<B, B, 2, 1>>("k_sim1_3.p2", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+        else
+            launch2d_fn<k_sim1<B, B, 1, 1>>("k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
-        launch2d_fn<k_sim1<B, B, 3, 1>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+        launch2d_fn<k_sim1<B, B, 2, 1>>("k_sim1_3.p2", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
-        launch2d_fn<k_sim1<B, B, 4, 1>>("k_sim1_3.p4", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.ptop, (const B *)delp,
+        if (g->p.beta != 1.0)
+            launch2d_fn<k_sim1<B, B, 3, 1, true>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
+                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       s->pfull, s->phi, 0);
+        else
+            launch2d_fn<k_sim1<B, B, 3, 1>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
+                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       s->pfull, s->phi, 0);
+        launch2d_fn<k_sim1<B, B, 4, 1>>("k_sim1_3.p4", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
         STOP(8);
