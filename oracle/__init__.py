@@ -55,6 +55,8 @@ def lib():
         L.orc_grid_free.argtypes = [C.c_void_p]
         L.orc_set_damping.argtypes = [C.c_void_p, C.c_double]
         L.orc_set_beta.argtypes = [C.c_void_p, C.c_double]
+        L.orc_set_smag.argtypes = [C.c_void_p, C.c_double]
+        L.orc_smag_corner.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_double, dp]
         L.orc_sim1b.restype = C.c_double
         L.orc_sim1b.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [dp] * 10
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
@@ -100,7 +102,7 @@ class Grid:
 
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
-                 d2_bg: float = 0.0, beta: float = 1.0):
+                 d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0):
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
@@ -110,6 +112,8 @@ class Grid:
         lib().orc_set_damping(h, float(d2_bg))
         self.beta = beta
         lib().orc_set_beta(h, float(beta))
+        self.dddmp = dddmp
+        lib().orc_set_smag(h, float(dddmp))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -233,6 +237,16 @@ def tracer_transport(g: Grid, qs, dp0, mfx, mfy, cx, cy, nsplt: int = 0) -> int:
     lib().orc_tracer_transport(g._h, arr, len(qs), _p(dp0), _p(mfx), _p(mfy), _p(cx), _p(cy),
                                int(nsplt), C.byref(used))
     return used.value
+
+
+def smag_corner(g: "Grid", t: int, u_plane, v_plane, dt: float) -> np.ndarray:
+    """Smagorinsky magnitude dt sqrt(DT^2 + DS^2) at the corners of one level
+    (u, v planes [N][N] with halos filled)."""
+    u = np.ascontiguousarray(u_plane, dtype=np.float64)
+    v = np.ascontiguousarray(v_plane, dtype=np.float64)
+    out = np.zeros((g.N, g.N))
+    lib().orc_smag_corner(g._h, int(t), _p(u), _p(v), float(dt), _p(out))
+    return out
 
 
 def ppm_edges(d, a):

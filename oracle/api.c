@@ -39,6 +39,15 @@ void orc_set_damping(void *gp, double d2_bg)
     g->da_min = m;
 }
 
+/* Smagorinsky coefficient of the divergence damping */
+void orc_set_smag(void *gp, double dddmp) { ((OGrid *)gp)->dddmp = dddmp; }
+
+/* Smagorinsky magnitude of one level (oracle plane layout, halos filled) */
+void orc_smag_corner(void *gp, int t, const double *u, const double *v, double dt, double *out)
+{
+    o_smag_corner((const OGrid *)gp, t, u, v, dt, out);
+}
+
 /* off-centring weight of the vertical solve */
 void orc_set_beta(void *gp, double beta) { ((OGrid *)gp)->beta = beta; }
 

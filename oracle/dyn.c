@@ -303,6 +303,56 @@ static void pgradc_plane(const OGrid *g, int t, int k, double dt2, const double 
  * transported by fv_tp_2d and its fluxes, with the kinetic-energy
  * differences, update the D-grid winds.
  */
+/*
+ * Smagorinsky magnitude at the corners of one level of tile t:
+ * dt sqrt(DT^2 + DS^2) (the expression the paper quotes for its Smagorinsky
+ * kernel, Sec. VII-C), with the deformation of the D-grid winds in finite
+ * volume form: tension DT = du/dx - dv/dy at the corner from the normal
+ * components through the four edges of its dual cell (the divergence's terms
+ * with the v part negated; at a cube vertex the two edges next to the missing
+ * cell count half), shear DS = dv/dx + du/dy at the cells from the tangential
+ * components around each cell (the vorticity's terms with the u part
+ * negated), averaged to the corner over its four cells (three at a cube
+ * vertex).  u, v need their halos.
+ */
+void o_smag_corner(const OGrid *g, int t, const double *u, const double *v, double dt, double *out)
+{
+    const int n = g->n;
+    const size_t o = (size_t)t * o_plane(g);
+    const double *dx = g->dx + o, *dy = g->dy + o, *dxc = g->dxc + o, *dyc = g->dyc + o;
+    const double *area = g->area + o, *area_c = g->area_c + o;
+    double *shear = (double *)calloc(o_plane(g), sizeof(double));
+    for (int j = -1; j <= n; j++)
+        for (int i = -1; i <= n; i++) {
+            if (skip_corner(g, ST_C, i, j)) continue;
+            size_t c = IX(g, i, j);
+            shear[c] = (v[IX(g, i + 1, j)] * dy[IX(g, i + 1, j)] - v[c] * dy[c] +
+                        u[IX(g, i, j + 1)] * dx[IX(g, i, j + 1)] - u[c] * dx[c]) / area[c];
+        }
+    for (int j = 0; j <= n; j++)
+        for (int i = 0; i <= n; i++) {
+            size_t b = IX(g, i, j);
+            double ws = 1.0, wn = 1.0, ww = 1.0, we = 1.0;
+            if (og_is_vertex(g, i, j)) {
+                if (j == 0) ws = 0.5; else wn = 0.5;
+                if (i == 0) ww = 0.5; else we = 0.5;
+            }
+            double tension = (we * u[b] * dyc[b] - ww * u[IX(g, i - 1, j)] * dyc[IX(g, i - 1, j)] -
+                              wn * v[b] * dxc[b] + ws * v[IX(g, i, j - 1)] * dxc[IX(g, i, j - 1)]) / area_c[b];
+            double s = 0.0;
+            int cnt = 0;
+            for (int dj = -1; dj <= 0; dj++)
+                for (int di = -1; di <= 0; di++) {
+                    if (skip_corner(g, ST_C, i + di, j + dj)) continue;
+                    s += shear[IX(g, i + di, j + dj)];
+                    cnt++;
+                }
+            double sh = s / cnt;
+            out[b] = dt * sqrt(tension * tension + sh * sh);
+        }
+    free(shear);
+}
+
 static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, double *v,
                        const double *uc, const double *vc, double *delp, double *pt, double *w,
                        double *mfx, double *mfy, double *cx, double *cy, double *crx,
@@ -413,12 +463,24 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
      * missing cell count half) is subtracted from the kinetic energy, so that
      * the wind update below adds nu times its gradient: a diffusion of the
      * divergence with coefficient nu = d2_bg times the smallest dual-cell area */
-    if (g->d2_bg > 0.0) {
+    if (g->d2_bg > 0.0 || g->dddmp > 0.0) {
         const double *dxc = g->dxc + o, *dyc = g->dyc + o, *area_c = g->area_c + o;
-        double nu = g->d2_bg * g->da_min;
+        double *smag = NULL;
+        if (g->dddmp > 0.0) {
+            smag = (double *)calloc(o_plane(g), sizeof(double));
+            o_smag_corner(g, t, u, v, bdt, smag);
+        }
         for (int j = 0; j <= n; j++)
             for (int i = 0; i <= n; i++) {
                 size_t b = IX(g, i, j);
+                /* coefficient: d2_bg, raised by the Smagorinsky magnitude up to 0.2 */
+                double c2 = g->d2_bg;
+                if (smag) {
+                    double cs = g->dddmp * smag[b];
+                    if (cs > 0.2) cs = 0.2;
+                    if (cs > c2) c2 = cs;
+                }
+                double nu = c2 * g->da_min;
                 double ws = 1.0, wn = 1.0, ww = 1.0, we = 1.0;
                 if (og_is_vertex(g, i, j)) {
                     if (j == 0) ws = 0.5; else wn = 0.5;
@@ -428,6 +490,7 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
                               wn * v[b] * dxc[b] - ws * v[IX(g, i, j - 1)] * dxc[IX(g, i, j - 1)];
                 ke[b] -= nu * flux / area_c[b];
             }
+        free(smag);
     }
     /* (vi) absolute vorticity at cells and its transport */
     for (int j = -3; j <= n + 2; j++)

@@ -47,6 +47,8 @@ typedef struct {
     double d2_bg, da_min;
     /* off-centring weight of the vertical solve (1 = backward Euler) */
     double beta;
+    /* Smagorinsky coefficient of the divergence damping (0 = off) */
+    double dddmp;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -100,6 +102,9 @@ double o_sim1b(int nz, double dt, double beta, double ptop, double zs, const dou
                double *delz_out, double *pfull, double *phi, double *pstar, double *coupling);
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
              double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
+
+/* dyn.c: Smagorinsky magnitude dt sqrt(DT^2 + DS^2) at the corners of one level */
+void o_smag_corner(const OGrid *g, int t, const double *u, const double *v, double dt, double *out);
 
 /* remap.c */
 void o_ppm_edges(int nz, const double *d, const double *a, double *e);
