@@ -62,7 +62,11 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * on del-2 divergence damping in d_sw: nu = d2_bg x (smallest dual-cell area
  * of the grid) times the divergence of the D-grid winds at each corner is
  * subtracted from the kinetic energy there, which diffuses the divergence
- * (outside [0, 0.25]: FV3_EINVAL). */
+ * (outside [0, 0.25]: FV3_EINVAL).  dddmp in [0, 1] raises that coefficient
+ * per corner to min(0.2, dddmp dt sqrt(DT^2 + DS^2)) where larger (the
+ * Smagorinsky magnitude of the paper's Sec. VII-C case study; DT the tension
+ * at the corner, DS the shear of its cells, dt the substep; it applies with
+ * d2_bg = 0 too). */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -73,6 +77,7 @@ typedef struct {
     int hord;            /* 8                                              */
     double d2_bg;        /* del-2 divergence damping, 0 (off) .. 0.25      */
     double beta;         /* vertical off-centring, 0.5 .. 1 (1: implicit)  */
+    double dddmp;        /* Smagorinsky divergence damping, 0 (off) .. 1   */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

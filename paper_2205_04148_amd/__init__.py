@@ -50,7 +50,7 @@ class GridParams(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
                 ("f0", C.c_double), ("radius", C.c_double), ("omega", C.c_double),
                 ("ptop", C.c_double), ("precision", C.c_int), ("hord", C.c_int),
-                ("d2_bg", C.c_double), ("beta", C.c_double), ("device", C.c_int)]
+                ("d2_bg", C.c_double), ("beta", C.c_double), ("dddmp", C.c_double), ("device", C.c_int)]
 
 
 class Layout(C.Structure):
@@ -143,10 +143,10 @@ def _check(st):
         raise FV3Error(st, lib().fv3_last_error().decode())
 
 
-def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg=0.0, beta=1.0):
+def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg=0.0, beta=1.0, dddmp=0.0):
     return GridParams(kind=kind, n=n, nz=nz, dx=dx, f0=f0, radius=radius, omega=omega, ptop=ptop,
                       precision=0 if precision == "fp64" else 1, hord=8, d2_bg=d2_bg, beta=beta,
-                      device=device)
+                      dddmp=dddmp, device=device)
 
 
 def host_metric(kind, n, nz, name, dx=1000.0, f0=0.0, radius=RADIUS, omega=OMEGA, ptop=100.0,
@@ -172,10 +172,11 @@ class Grid:
 
     def __init__(self, kind: int, n: int, nz: int, dx: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
-                 precision: str = "fp64", device: int = 0, d2_bg: float = 0.0, beta: float = 1.0):
+                 precision: str = "fp64", device: int = 0, d2_bg: float = 0.0, beta: float = 1.0,
+                 dddmp: float = 0.0):
         torch = _torch()
         torch.cuda.set_device(device)
-        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg, beta)
+        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg, beta, dddmp)
         h = C.c_void_p()
         _check(lib().fv3_init_grid(C.byref(p), C.byref(h)))
         self._h = h

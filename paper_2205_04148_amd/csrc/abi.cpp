@@ -77,6 +77,8 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
     if (p->hord != 8) return fail(FV3_EUNSUPPORTED, "only the monotone PPM (hord = 8) is implemented");
     if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))
         return fail(FV3_EINVAL, "d2_bg must be in [0, 0.25] (explicit del-2 damping)");
+    if (!(p->dddmp >= 0.0 && p->dddmp <= 1.0))
+        return fail(FV3_EINVAL, "dddmp (Smagorinsky divergence damping) must be in [0, 1]");
     if (!(p->beta >= 0.5 && p->beta <= 1.0))
         return fail(FV3_EINVAL, "beta (off-centring of the vertical solve) must be in [0.5, 1]");
     if (!(p->ptop > 0.0) || !std::isfinite(p->ptop)) return fail(FV3_EINVAL, "ptop must be positive");

@@ -1397,8 +1397,8 @@ DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc
 // energy at corners (D-grid u upwinded along x and v along y by PPM with the
 // corner displacements of the contravariant C-grid winds)
 template <class B>
-DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B nu, const B *u, const B *v, const B *ut,
-                           const B *vt, B *om, B *ke)
+DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const B *u, const B *v,
+                           const B *ut, const B *vt, B *om, B *ke)
 {
     KBEGIN(G.nz);
     int n = G.n;
@@ -1417,19 +1417,40 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B nu, const B *u, const B *
         B uu = ppm6(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
         B vv = ppm6(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
         B kev = (B)0.5 * (ub * uu + vb * vv);
-        if (nu > (B)0) {
+        if (d2 > (B)0 || dd > (B)0) {
             // del-2 divergence damping: minus nu times the divergence of the
             // D-grid winds over the corner's dual cell (half weights next to
-            // the missing cell at a cube vertex)
+            // the missing cell at a cube vertex), nu = damin times d2, raised
+            // by the Smagorinsky magnitude dd sqrt(DT^2 + DS^2) up to 0.2
             B ws = 1, wn = 1, ww = 1, we = 1;
             if (is_vertex(G, i, j)) {
                 if (j == 0) ws = 0.5; else wn = 0.5;
                 if (i == 0) ww = 0.5; else we = 0.5;
             }
             const B *dxc = MP(M, M_DXC), *dyc = MP(M, M_DYC);
-            B flux = we * AT(U, i, j) * AT(dyc, i, j) - ww * AT(U, i - 1, j) * AT(dyc, i - 1, j) +
-                     wn * AT(V, i, j) * AT(dxc, i, j) - ws * AT(V, i, j - 1) * AT(dxc, i, j - 1);
-            kev -= nu * flux * AT(MP(M, M_RAREA_C), i, j);
+            B rac = AT(MP(M, M_RAREA_C), i, j);
+            B fe = we * AT(U, i, j) * AT(dyc, i, j), fw = ww * AT(U, i - 1, j) * AT(dyc, i - 1, j);
+            B fn = wn * AT(V, i, j) * AT(dxc, i, j), fs = ws * AT(V, i, j - 1) * AT(dxc, i, j - 1);
+            B c2 = d2;
+            if (dd > (B)0) {
+                // tension at the corner; shear of the stored cells around it
+                B ten = (fe - fw - fn + fs) * rac, sh = 0;
+                int cnt = 0;
+                const B *ra = MP(M, M_RAREA);
+                for (int cj = j - 1; cj <= j; cj++)
+                    for (int ci = i - 1; ci <= i; ci++) {
+                        if (in_corner(G, SC, ci, cj)) continue;
+                        sh += (AT(V, ci + 1, cj) * AT(dy, ci + 1, cj) - AT(V, ci, cj) * AT(dy, ci, cj) +
+                               AT(U, ci, cj + 1) * AT(dx, ci, cj + 1) - AT(U, ci, cj) * AT(dx, ci, cj)) *
+                              AT(ra, ci, cj);
+                        cnt++;
+                    }
+                sh /= (B)cnt;
+                B cs = dd * sqrt(ten * ten + sh * sh);
+                cs = cs < (B)0.2 ? cs : (B)0.2;
+                c2 = cs > c2 ? cs : c2;
+            }
+            kev -= c2 * damin * (fe - fw + fn - fs) * rac;
         }
         AT(ke + o, i, j) = kev;
     }
@@ -1971,7 +1992,8 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             b.q = w; b.qout = W.wn;
             fvtp(g, P, b, st);
         }
-        launch2d_s(k_dsw_omke<B>, (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)(g->p.d2_bg * g->da_min), (const B *)u, (const B *)v,
+        launch2d_s(k_dsw_omke<B>, (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)g->p.d2_bg,
+                   (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v,
                  (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
         {
             FvArgs<B, B, B> a{};

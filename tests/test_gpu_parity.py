@@ -278,6 +278,52 @@ def test_divergence_damping_parity(fv3, orc, precision):
         _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz"), tol, f"damping kind{kind} {precision}")
 
 
+def _sheared_periodic(n=48, nz=8):
+    init = fi.periodic_state(n=n, nz=nz, seed=3)
+    N = n + 2 * H + 1
+    J = np.arange(N)[:, None] - H
+    init["u"] = init["u"] + 20.0 * np.sin(2 * np.pi * J / n)[None, None, :, :] * np.ones((1, nz, 1, N))
+    return init
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_smagorinsky_damping_parity(fv3, orc, precision):
+    """Smagorinsky-scaled divergence damping (dddmp > 0) against the oracle
+    after 10 substeps: a sheared periodic flow with the Smagorinsky part alone
+    (d2_bg = 0), and a C24 cube with both parts (cube-vertex corners take the
+    three-cell shear); FP64 1e-11, mixed at the mixed-precision bars."""
+    import torch
+
+    for kind, n, nz, dt, d2, dd in ((0, 48, 8, 2.0, 0.0, 0.2), (1, 24, 10, 2000.0, 0.02, 0.15)):
+        init = _sheared_periodic(n, nz) if kind == 0 else fi.cube_state(n=n, nz=nz)
+        g = fv3.Grid(kind, n, nz, precision=precision, d2_bg=d2, dddmp=dd)
+        s = fv3.State.allocate(g)
+        s.load(init)
+        og = orc.Grid(kind, n, nz, d2_bg=d2, dddmp=dd)
+        os_ = orc.new_state(og, init)
+        print(f"smagorinsky kind{kind} {precision}", flush=True)
+        fv3.acoustic_substeps(s, g, dt, 10)
+        assert fv3.check_status(g) == 0
+        assert orc.acoustic_substeps(og, os_, dt, 10) == 0
+        torch.cuda.synchronize()
+        if precision == "fp64":
+            tol = 1e-11
+        else:
+            tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
+        _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz"), tol, f"smag kind{kind} {precision}")
+
+
+def test_smagorinsky_abi_range(fv3):
+    import ctypes as C
+
+    p = fv3.GridParams(kind=0, n=16, nz=2, dx=1000.0, f0=0.0, radius=1.0, omega=0.0, ptop=100.0,
+                       precision=0, hord=8, d2_bg=0.0, beta=1.0, dddmp=1.5, device=0)
+    h = C.c_void_p()
+    assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == -1
+    p.dddmp = -0.1
+    assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == -1
+
+
 def test_cfl_flag_latched(fv3):
     """A wind giving Courant number 1.5 sets the device flag (no clamping)."""
     n, nz = 16, 2
