@@ -67,6 +67,9 @@ def lib():
         L.orc_corner_view_pair.argtypes = [C.c_void_p, dp, C.c_int, dp, C.c_int, C.c_int, dp, dp]
         L.orc_ppm_face.restype = C.c_double
         L.orc_ppm_face.argtypes = [dp, C.c_double]
+        L.orc_ppm_face_order.restype = C.c_double
+        L.orc_ppm_face_order.argtypes = [dp, C.c_double, C.c_int]
+        L.orc_set_hord.argtypes = [C.c_void_p, C.c_int]
         L.orc_fv_tp_2d.argtypes = [C.c_void_p, C.c_int] + [dp] * 9
         L.orc_sim1.restype = C.c_double
         L.orc_sim1.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double] + [dp] * 8
@@ -102,7 +105,7 @@ class Grid:
 
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
-                 d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0):
+                 d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8):
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
@@ -114,6 +117,8 @@ class Grid:
         lib().orc_set_beta(h, float(beta))
         self.dddmp = dddmp
         lib().orc_set_smag(h, float(dddmp))
+        self.hord = hord
+        lib().orc_set_hord(h, int(hord))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -166,10 +171,12 @@ def corner_view_pair(g: Grid, px, stx, py, sty, mode):
     return ox, oy
 
 
-def ppm_face(q6, c: float) -> float:
+def ppm_face(q6, c: float, hord: int = 8) -> float:
     q = np.ascontiguousarray(q6, dtype=np.float64)
     assert q.shape == (6,)
-    return lib().orc_ppm_face(_p(q), float(c))
+    if hord == 8:
+        return lib().orc_ppm_face(_p(q), float(c))
+    return lib().orc_ppm_face_order(_p(q), float(c), 0 if hord == 6 else 1)
 
 
 def fv_tp_2d(g: Grid, t: int, q, crx, cry, xfx, yfx, mx=None, my=None):

@@ -451,10 +451,10 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             double a6[6];
             double cxu = ub / dx[ub > 0.0 ? IX(g, i - 1, j) : b];
             for (int s = 0; s < 6; s++) a6[s] = u[IX(g, i - 3 + s, j)];
-            double ubv = o_ppm_face(a6, cxu);
+            double ubv = o_ppm_face_order(a6, cxu, g->hord != 6);
             double cyv = vb / dy[vb > 0.0 ? IX(g, i, j - 1) : b];
             for (int s = 0; s < 6; s++) a6[s] = v[IX(g, i, j - 3 + s)];
-            double vbv = o_ppm_face(a6, cyv);
+            double vbv = o_ppm_face_order(a6, cyv, g->hord != 6);
             ke[b] = 0.5 * (ub * ubv + vb * vbv);
         }
     /* (v') optional del-2 divergence damping: nu times the divergence of the

@@ -295,6 +295,7 @@ OGrid *og_new(int kind, int n, int nz, double delta, double f0, double radius, d
     g->kind = kind; g->n = n; g->nz = nz; g->T = kind == 1 ? 6 : 1; g->N = n + 2 * H + 1;
     g->delta = delta; g->f0 = f0; g->radius = radius; g->omega = omega; g->ptop = ptop;
     g->beta = 1.0;
+    g->hord = 8;
     size_t P = (size_t)g->T * o_plane(g);
     ALLOC_METRICS(g, P);
     if (kind == 0) {

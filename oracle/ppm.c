@@ -11,7 +11,9 @@
  * average of the two orderings.  The 1-D operator is a monotone PPM: a
  * limited slope per cell, fourth-order edge values, edge deviations clipped
  * to twice the slope, and the mean of the cell parabola over the swept
- * interval.
+ * interval.  The unlimited order (hord 6, a reading of the "un-limited" PPM
+ * option) keeps the fourth-order edges and the parabola but drops both
+ * constraints: slopes (q+ - q-)/4 as they are, edge deviations unclipped.
  */
 #include "orc.h"
 #include <math.h>
@@ -31,38 +33,41 @@ static double limited_slope(double qm, double q0, double qp)
 }
 
 /* Face value between cells m-1 and m for Courant number c; q[0..5] holds the
- * cells m-3 .. m+2 along the sweep. */
-double o_ppm_face(const double q[6], double c)
+ * cells m-3 .. m+2 along the sweep.  lim = 0: the unlimited order. */
+double o_ppm_face_order(const double q[6], double c, int lim)
 {
     double dm[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = 1; s <= 4; s++) dm[s] = limited_slope(q[s - 1], q[s], q[s + 1]);
+    for (int s = 1; s <= 4; s++)
+        dm[s] = lim ? limited_slope(q[s - 1], q[s], q[s + 1]) : (q[s + 1] - q[s - 1]) / 4.0;
     /* left-edge value of cell s (s = 2, 3, 4 are m-1, m, m+1) */
     double al[6] = {0, 0, 0, 0, 0, 0};
     for (int s = 2; s <= 4; s++) al[s] = 0.5 * (q[s - 1] + q[s]) + (dm[s - 1] - dm[s]) / 3.0;
-    if (c > 0.0) {
-        int s = 2;
-        double bl = -sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s] - q[s]));
-        double br = sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s + 1] - q[s]));
-        return q[s] + (1.0 - c) * (br - c * (bl + br));
+    int s = c > 0.0 ? 2 : 3;
+    double bl, br;
+    if (lim) {
+        bl = -sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s] - q[s]));
+        br = sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s + 1] - q[s]));
     } else {
-        int s = 3;
-        double bl = -sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s] - q[s]));
-        double br = sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s + 1] - q[s]));
-        return q[s] + (1.0 + c) * (bl + c * (bl + br));
+        bl = al[s] - q[s];
+        br = al[s + 1] - q[s];
     }
+    if (c > 0.0) return q[s] + (1.0 - c) * (br - c * (bl + br));
+    return q[s] + (1.0 + c) * (bl + c * (bl + br));
 }
+
+double o_ppm_face(const double q[6], double c) { return o_ppm_face_order(q, c, 1); }
 
 static double ppm_x(const OGrid *g, const double *q, int i, int j, double c)
 {
     double a[6];
     for (int s = 0; s < 6; s++) a[s] = q[IX(g, i - 3 + s, j)];
-    return o_ppm_face(a, c);
+    return o_ppm_face_order(a, c, g->hord != 6);
 }
 static double ppm_y(const OGrid *g, const double *q, int i, int j, double c)
 {
     double a[6];
     for (int s = 0; s < 6; s++) a[s] = q[IX(g, i, j - 3 + s)];
-    return o_ppm_face(a, c);
+    return o_ppm_face_order(a, c, g->hord != 6);
 }
 
 /*
