@@ -42,7 +42,7 @@ typedef enum {
     FV3_ENOMEM = -5,        /* device allocation failed (grid creation only)                */
     FV3_ECFL = -6,          /* a Courant number exceeded 1 in d_sw (latched on device)      */
     FV3_ENONFINITE = -7,    /* a prognostic became non-finite (latched on device)           */
-    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord != 8)                           */
+    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord other than 6 or 8)              */
     FV3_EREMAP = -9,        /* reference interfaces not increasing in a column (latched)    */
     FV3_EINTERNAL = -99
 } fv3_status;
@@ -53,8 +53,12 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
 /* Grid description.  Cubed sphere: 6 equiangular gnomonic tiles of n x n
  * cells (Sec. II), radius and rotation rate given.  Doubly periodic: one
  * n x n tile of spacing dx with constant Coriolis parameter f0.  Vertical:
- * nz Lagrangian layers below the model top pressure ptop.  Only the monotone
- * PPM order hord = 8 is implemented (other values: FV3_EUNSUPPORTED).  beta
+ * nz Lagrangian layers below the model top pressure ptop.  hord selects the
+ * PPM order of every horizontal transport of the call (Lin-Rood fluxes of
+ * delp, pt, w, vorticity and tracers, and the kinetic-energy faces): 8 the
+ * monotone order (limited slopes, edge deviations clipped to twice the
+ * slope), 6 the unlimited order (the same fourth-order edges and parabola
+ * without either constraint); other values: FV3_EUNSUPPORTED.  beta
  * in [0.5, 1] off-centres the semi-implicit vertical solve (Sec. IX-B): the
  * momentum equation sees beta P^{n+1} + (1 - beta) P* and the pressure
  * response is driven by beta w^{n+1} + (1 - beta) w^n; 1 is backward Euler
@@ -74,7 +78,7 @@ typedef struct {
     double radius, omega;/* cubed sphere: [m], [1/s]                       */
     double ptop;         /* top pressure [Pa]                              */
     int precision;       /* fv3_precision                                  */
-    int hord;            /* 8                                              */
+    int hord;            /* PPM order: 8 monotone, 6 unlimited             */
     double d2_bg;        /* del-2 divergence damping, 0 (off) .. 0.25      */
     double beta;         /* vertical off-centring, 0.5 .. 1 (1: implicit)  */
     double dddmp;        /* Smagorinsky divergence damping, 0 (off) .. 1   */

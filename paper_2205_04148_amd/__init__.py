@@ -143,9 +143,10 @@ def _check(st):
         raise FV3Error(st, lib().fv3_last_error().decode())
 
 
-def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg=0.0, beta=1.0, dddmp=0.0):
+def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg=0.0, beta=1.0, dddmp=0.0,
+            hord=8):
     return GridParams(kind=kind, n=n, nz=nz, dx=dx, f0=f0, radius=radius, omega=omega, ptop=ptop,
-                      precision=0 if precision == "fp64" else 1, hord=8, d2_bg=d2_bg, beta=beta,
+                      precision=0 if precision == "fp64" else 1, hord=hord, d2_bg=d2_bg, beta=beta,
                       dddmp=dddmp, device=device)
 
 
@@ -173,10 +174,10 @@ class Grid:
     def __init__(self, kind: int, n: int, nz: int, dx: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
                  precision: str = "fp64", device: int = 0, d2_bg: float = 0.0, beta: float = 1.0,
-                 dddmp: float = 0.0):
+                 dddmp: float = 0.0, hord: int = 8):
         torch = _torch()
         torch.cuda.set_device(device)
-        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg, beta, dddmp)
+        p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg, beta, dddmp, hord)
         h = C.c_void_p()
         _check(lib().fv3_init_grid(C.byref(p), C.byref(h)))
         self._h = h
@@ -185,6 +186,7 @@ class Grid:
         self.layout = lay
         self.kind, self.n, self.nz, self.T = kind, n, nz, lay.tiles
         self.ptop = ptop
+        self.hord = hord
         self.precision = precision
         self.device = device
         self.N = n + 2 * H + 1

@@ -74,7 +74,8 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
     if (p->n < 8 || p->n > 4096 || p->nz < 1 || p->nz > 512)
         return fail(FV3_ESHAPE, "n must be in [8, 4096] and nz in [1, 512]");
     if (p->precision != FV3_FP64 && p->precision != FV3_MIXED) return fail(FV3_EDTYPE, "unknown precision");
-    if (p->hord != 8) return fail(FV3_EUNSUPPORTED, "only the monotone PPM (hord = 8) is implemented");
+    if (p->hord != 8 && p->hord != 6)
+        return fail(FV3_EUNSUPPORTED, "PPM order must be 8 (monotone) or 6 (unlimited)");
     if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))
         return fail(FV3_EINVAL, "d2_bg must be in [0, 0.25] (explicit del-2 damping)");
     if (!(p->dddmp >= 0.0 && p->dddmp <= 1.0))

@@ -334,11 +334,12 @@ static void launch2d_native(const char *name, Kern kern, int ilo, int ihi, int j
 }
 
 // ====================================================================
-// 1-D PPM face value (monotone): face between cells m-1 and m along a
-// sweep, cell values q0..q5 = cells m-3..m+2, Courant number c.  Limited
-// slope per cell (zero at extrema), fourth-order edge values, edge
+// 1-D PPM face value: face between cells m-1 and m along a sweep, cell
+// values q0..q5 = cells m-3..m+2, Courant number c.  Monotone order (LIM):
+// limited slope per cell (zero at extrema), fourth-order edge values, edge
 // deviations clipped to twice the slope with the slope's sign, mean of the
-// parabola over the swept part of the upwind cell.
+// parabola over the swept part of the upwind cell.  Unlimited order
+// (!LIM): slopes (q+ - q-)/4 and the edge deviations as they come.
 // ====================================================================
 template <class T>
 DEVI T lslope(T a, T b, T c)
@@ -353,37 +354,45 @@ DEVI T lslope(T a, T b, T c)
 // c the signed Courant number.  For the downwind orientation the parabola's
 // edge deviations swap roles and the swept fraction is |c|:
 // q + (1 - |c|) (e - |c| (bl + br)), e = br for c > 0 and bl otherwise.
-template <class T>
+template <bool LIM, class T>
 DEVI T ppm_up(T a, T b, T q, T d, T e, T c)
 {
     const T third = (T)1 / (T)3;
-    const T dl = lslope(a, b, q), dm = lslope(b, q, d), dr = lslope(q, d, e);
-    const T al = (T)0.5 * (b + q) + (dl - dm) * third;
-    const T ar = (T)0.5 * (q + d) + (dm - dr) * third;
-    // deviations clipped to twice the slope, with the slope's sign (zero slope: zero)
-    const T a2 = (T)2 * fabs(dm);
-    const T bl = copysign(fmin(a2, fabs(al - q)), -dm);
-    const T br = copysign(fmin(a2, fabs(ar - q)), dm);
+    T bl, br;
+    if constexpr (LIM) {
+        const T dl = lslope(a, b, q), dm = lslope(b, q, d), dr = lslope(q, d, e);
+        const T al = (T)0.5 * (b + q) + (dl - dm) * third;
+        const T ar = (T)0.5 * (q + d) + (dm - dr) * third;
+        // deviations clipped to twice the slope, with the slope's sign (zero slope: zero)
+        const T a2 = (T)2 * fabs(dm);
+        bl = copysign(fmin(a2, fabs(al - q)), -dm);
+        br = copysign(fmin(a2, fabs(ar - q)), dm);
+    } else {
+        const T qt = (T)0.25;
+        const T dl = (q - a) * qt, dm = (d - b) * qt, dr = (e - q) * qt;
+        bl = (T)0.5 * (b + q) + (dl - dm) * third - q;
+        br = (T)0.5 * (q + d) + (dm - dr) * third - q;
+    }
     const T cc = fabs(c);
     return q + ((T)1 - cc) * ((c > 0 ? br : bl) - cc * (bl + br));
 }
 
-template <class T>
+template <bool LIM, class T>
 DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
 {
     // Branch-free: select the upwind cell's five-point neighbourhood (cell
     // m-1 for c > 0, else cell m), then one evaluation.
     const bool pos = c > 0;
-    return ppm_up(pos ? q0 : q1, pos ? q1 : q2, pos ? q2 : q3, pos ? q3 : q4, pos ? q4 : q5, c);
+    return ppm_up<LIM>(pos ? q0 : q1, pos ? q1 : q2, pos ? q2 : q3, pos ? q3 : q4, pos ? q4 : q5, c);
 }
 
 // The same from six cells m-3..m+2 stored S apart from p (in LDS): the upwind
 // neighbourhood is selected by its address, five loads instead of six.
-template <int S, class T>
+template <int S, bool LIM, class T>
 DEVI T ppm_lds(const T *p, T c)
 {
     const T *u = p + (c > 0 ? 0 : S);
-    return ppm_up(u[0], u[S], u[2 * S], u[3 * S], u[4 * S], c);
+    return ppm_up<LIM>(u[0], u[S], u[2 * S], u[3 * S], u[4 * S], c);
 }
 
 // ====================================================================
@@ -1104,7 +1113,7 @@ DEVI T ccr(const C *a, const C *a0, int idx, int avg)
     return (T)a[idx];
 }
 
-template <class T, class C, class M, int EPI>
+template <class T, class C, class M, int EPI, bool LIM>
 DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
 {
     constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
@@ -1217,7 +1226,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T f = 0;
         if (i <= n + 2 && j <= n) {
             const T *col = sQy + r * QW + c;
-            f = ppm_lds<QW>(col, sCY[e]);
+            f = ppm_lds<QW, LIM>(col, sCY[e]);
         }
         sFy[e] = f;
     }
@@ -1227,7 +1236,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T f = 0;
         if (i <= n && j <= n + 2) {
             const T *row = sQ + r * QW + c;
-            f = ppm_lds<1>(row, sCX[e]);
+            f = ppm_lds<1, LIM>(row, sCX[e]);
         }
         sFx[e] = f;
     }
@@ -1267,7 +1276,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             int fi = j * P + i;
             int s = (r + 3) * XW + c;
             const T *row = sQi + r * QW + c;
-            T fx = ppm_lds<1>(row, sCX[s]);
+            T fx = ppm_lds<1, LIM>(row, sCX[s]);
             T wgt = A.mx ? (T)wx[m] : sXF[s];
             T F = (T)0.5 * (fx + sFx[s]) * wgt;
             sFx[s] = F;
@@ -1290,7 +1299,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             int fi = j * P + i;
             int s = r * YW + c + 3;
             const T *col = sQj + r * FTX + c;
-            T fy = ppm_lds<FTX>(col, sCY[s]);
+            T fy = ppm_lds<FTX, LIM>(col, sCY[s]);
             T wgt = A.my ? (T)wy[m] : sYF[s];
             T F = (T)0.5 * (fy + sFy[s]) * wgt;
             sFy[s] = F;
@@ -1336,19 +1345,27 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     }
 }
 
-template <class T, class C, class M>
-static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
+template <class T, class C, class M, bool LIM>
+static void fvtp_order(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
 {
     static const char *names[] = {"k_fvtp_flux", "k_fvtp_delp", "k_fvtp_massw", "k_fvtp_adv", "k_fvtp_tracer"};
     constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
     dim3 grd((unsigned)((g->n + FTX - 1) / FTX), (unsigned)((g->n + FTY - 1) / FTY), (unsigned)planes);
     switch (a.epi) {
-    case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    default: launch_fn<k_fvtp<T, C, M, EPI_TRACER>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    default: launch_fn<k_fvtp<T, C, M, EPI_TRACER, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
     }
+}
+
+// the grid's PPM order applies to every transport of the call
+template <class T, class C, class M>
+static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
+{
+    if (g->p.hord == 6) fvtp_order<T, C, M, false>(g, planes, a, st);
+    else fvtp_order<T, C, M, true>(g, planes, a, st);
 }
 
 // ====================================================================
@@ -1396,7 +1413,7 @@ DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc
 // absolute vorticity at cells from the D-grid circulation, and the kinetic
 // energy at corners (D-grid u upwinded along x and v along y by PPM with the
 // corner displacements of the contravariant C-grid winds)
-template <class B>
+template <class B, bool LIM>
 DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const B *u, const B *v,
                            const B *ut, const B *vt, B *om, B *ke)
 {
@@ -1414,8 +1431,8 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const 
         B vb = (B)0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
         B cu = ub / AT(dx, ub > 0 ? i - 1 : i, j);
         B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
-        B uu = ppm6(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
-        B vv = ppm6(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
+        B uu = ppm6<LIM>(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
+        B vv = ppm6<LIM>(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
         B kev = (B)0.5 * (ub * uu + vb * vv);
         if (d2 > (B)0 || dd > (B)0) {
             // del-2 divergence damping: minus nu times the divergence of the
@@ -1992,9 +2009,14 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             b.q = w; b.qout = W.wn;
             fvtp(g, P, b, st);
         }
-        launch2d_s(k_dsw_omke<B>, (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)g->p.d2_bg,
-                   (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v,
-                 (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
+        auto omke = [&](auto lim) {
+            launch2d_sh<k_dsw_omke<B, decltype(lim)::value>>(
+                "k_dsw_omke<B>", (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M,
+                (B)bdt, (B)g->p.d2_bg, (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v,
+                (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
+        };
+        if (g->p.hord == 6) omke(std::false_type{});
+        else omke(std::true_type{});
         {
             FvArgs<B, B, B> a{};
             a.q = W.om; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;

@@ -324,6 +324,65 @@ def test_smagorinsky_abi_range(fv3):
     assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == -1
 
 
+@pytest.mark.parametrize("kind,n,nz,dt,ns,stop", [(0, 24, 6, 0.4, 1, 6), (1, 12, 5, 300.0, 1, 6),
+                                                 (0, 48, 8, 2.0, 10, 0), (1, 24, 10, 2000.0, 10, 0)])
+def test_unlimited_ppm_parity(fv3, orc, kind, n, nz, dt, ns, stop):
+    """The unlimited PPM order (hord 6) against the oracle built with the same
+    order: after one d_sw (stage 6: every fv_tp_2d and the kinetic energy,
+    bar 1e-13), and after 10 substeps plus the tracer transport (bar 1e-11).
+    The orders' own results differ far above either bar, so the parity
+    tells the two apart."""
+    import torch
+
+    init = fi.periodic_state(n=n, nz=nz, nq=1) if kind == 0 else fi.cube_state(n=n, nz=nz, nq=1)
+    g = fv3.Grid(kind, n, nz, hord=6)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(kind, n, nz, hord=6)
+    os_ = orc.new_state(og, init)
+    print(f"hord6 kind{kind} n{n} ns{ns} stop{stop}", flush=True)
+    fv3.acoustic_substeps(s, g, dt, ns, stop_stage=stop)
+    assert orc.acoustic_substeps(og, os_, dt, ns, stop_stage=stop) == 0
+    o8 = orc.new_state(orc.Grid(kind, n, nz), init)
+    assert orc.acoustic_substeps(orc.Grid(kind, n, nz), o8, dt, ns, stop_stage=stop) == 0
+    fields = ("u", "v", "delp", "pt", "w", "mfx", "cx") if stop == 6 else \
+        ("u", "v", "w", "delp", "pt", "delz", "mfx", "mfy", "cx", "cy", "pfull", "phi")
+    tol = 1e-13 if stop == 6 else 1e-11
+    for k in ("u", "v"):
+        assert _relerr(_int(o8[k], n, STAG[k]), _int(os_[k], n, STAG[k])) > 1e3 * tol, k
+    if stop == 0:
+        assert fv3.check_status(g) == 0
+    _compare(s, os_, n, fields, tol, f"hord6 kind{kind}")
+    if stop != 0:
+        return
+    qd = [g.upload(q, nz) for q in init["q"]]
+    qh = [q.copy() for q in init["q"]]
+    fv3.tracer_transport(qd, s, g)
+    orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+    torch.cuda.synchronize()
+    e = _relerr(_int(g.download(qd[0], nz), n, "C"), _int(qh[0], n, "C"))
+    print(f"hord6 kind{kind} tracer {e:.2e}", flush=True)
+    assert e <= 1e-11
+
+
+def test_unlimited_ppm_mixed_cube(fv3, orc):
+    """hord 6 in mixed precision on the C24 cube after 10 substeps, at the
+    mixed-precision bars of the other mixed tests."""
+    n, nz = 24, 10
+    init = fi.cube_state(n=n, nz=nz)
+    g = fv3.Grid(1, n, nz, precision="mixed", hord=6)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(1, n, nz, hord=6)
+    os_ = orc.new_state(og, init)
+    print("hord6 mixed C24", flush=True)
+    fv3.acoustic_substeps(s, g, 2000.0, 10)
+    assert fv3.check_status(g) == 0
+    assert orc.acoustic_substeps(og, os_, 2000.0, 10) == 0
+    tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
+    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz"), tol, "hord6 mixed C24")
+
+
 def test_cfl_flag_latched(fv3):
     """A wind giving Courant number 1.5 sets the device flag (no clamping)."""
     n, nz = 16, 2
