@@ -69,7 +69,7 @@ def lib():
         L.orc_ppm_face.argtypes = [dp, C.c_double]
         L.orc_ppm_face_order.restype = C.c_double
         L.orc_ppm_face_order.argtypes = [dp, C.c_double, C.c_int]
-        L.orc_set_hord.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_hord.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_fv_tp_2d.argtypes = [C.c_void_p, C.c_int] + [dp] * 9
         L.orc_sim1.restype = C.c_double
         L.orc_sim1.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double] + [dp] * 8
@@ -105,7 +105,10 @@ class Grid:
 
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
-                 d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8):
+                 d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
+                 hord_tr: int = 0):
+        if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
+            raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
@@ -117,8 +120,8 @@ class Grid:
         lib().orc_set_beta(h, float(beta))
         self.dddmp = dddmp
         lib().orc_set_smag(h, float(dddmp))
-        self.hord = hord
-        lib().orc_set_hord(h, int(hord))
+        self.hord, self.hord_tr = hord, hord_tr
+        lib().orc_set_hord(h, int(hord), int(hord_tr))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -176,7 +179,7 @@ def ppm_face(q6, c: float, hord: int = 8) -> float:
     assert q.shape == (6,)
     if hord == 8:
         return lib().orc_ppm_face(_p(q), float(c))
-    return lib().orc_ppm_face_order(_p(q), float(c), 0 if hord == 6 else 1)
+    return lib().orc_ppm_face_order(_p(q), float(c), int(hord))
 
 
 def fv_tp_2d(g: Grid, t: int, q, crx, cry, xfx, yfx, mx=None, my=None):

@@ -102,8 +102,12 @@ int orc_corner_view_pair(void *gp, const double *px, int stx, const double *py, 
 }
 
 double orc_ppm_face(const double *q6, double c) { return o_ppm_face(q6, c); }
-double orc_ppm_face_order(const double *q6, double c, int lim) { return o_ppm_face_order(q6, c, lim); }
-void orc_set_hord(void *gp, int hord) { ((OGrid *)gp)->hord = hord; }
+double orc_ppm_face_order(const double *q6, double c, int ord) { return o_ppm_face_order(q6, c, ord); }
+void orc_set_hord(void *gp, int hord, int hord_tr)
+{
+    ((OGrid *)gp)->hord = hord;
+    ((OGrid *)gp)->hord_tr = hord_tr;
+}
 
 int orc_fv_tp_2d(void *gp, int t, const double *q, const double *crx, const double *cry,
                  const double *xfx, const double *yfx, const double *mx, const double *my,

@@ -451,10 +451,10 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             double a6[6];
             double cxu = ub / dx[ub > 0.0 ? IX(g, i - 1, j) : b];
             for (int s = 0; s < 6; s++) a6[s] = u[IX(g, i - 3 + s, j)];
-            double ubv = o_ppm_face_order(a6, cxu, g->hord != 6);
+            double ubv = o_ppm_face_order(a6, cxu, g->hord);
             double cyv = vb / dy[vb > 0.0 ? IX(g, i, j - 1) : b];
             for (int s = 0; s < 6; s++) a6[s] = v[IX(g, i, j - 3 + s)];
-            double vbv = o_ppm_face_order(a6, cyv, g->hord != 6);
+            double vbv = o_ppm_face_order(a6, cyv, g->hord);
             ke[b] = 0.5 * (ub * ubv + vb * vbv);
         }
     /* (v') optional del-2 divergence damping: nu times the divergence of the
@@ -874,7 +874,7 @@ int orc_tracer_impl(const OGrid *g, double **q, int nq, const double *dp0, const
                     double *qx = dalloc(P), *qy = dalloc(P), *FX = dalloc(P), *FY = dalloc(P);
                     og_view_scalar(g, Q, ST_C, MODE_X, 0, qx);
                     og_view_scalar(g, Q, ST_C, MODE_Y, 0, qy);
-                    o_fv_tp_2d(g, t, Q, qx, qy, PL(crs, t, k, nz), PL(crys, t, k, nz),
+                    o_fv_tp_2d_ord(g, g->hord_tr ? g->hord_tr : g->hord, t, Q, qx, qy, PL(crs, t, k, nz), PL(crys, t, k, nz),
                                PL(xfx, t, k, nz), PL(yfx, t, k, nz), PL(mxs, t, k, nz),
                                PL(mys, t, k, nz), FX, FY);
                     const double *d1 = PL(dp1, t, k, nz), *d2 = PL(dp2, t, k, nz);

@@ -49,8 +49,10 @@ typedef struct {
     double beta;
     /* Smagorinsky coefficient of the divergence damping (0 = off) */
     double dddmp;
-    /* PPM order of every transport: 8 monotone (default), 6 unlimited */
-    int hord;
+    /* PPM order of every transport: 8 monotone (default), 6 unlimited,
+     * 5 2dx-filtered; hord_tr that of the tracer transport (0: hord; also
+     * 7, positive-definite) */
+    int hord, hord_tr;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -88,7 +90,10 @@ int og_is_vertex(const OGrid *g, int i, int j);
 
 /* ppm.c */
 double o_ppm_face(const double q[6], double c);
-double o_ppm_face_order(const double q[6], double c, int lim);
+double o_ppm_face_order(const double q[6], double c, int ord);
+void o_fv_tp_2d_ord(const OGrid *g, int ord, int t, const double *q, const double *qx, const double *qy,
+                    const double *crx, const double *cry, const double *xfx, const double *yfx,
+                    const double *mx, const double *my, double *FX, double *FY);
 void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const double *qy,
                 const double *crx, const double *cry, const double *xfx, const double *yfx,
                 const double *mx, const double *my, double *FX, double *FY);

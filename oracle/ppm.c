@@ -11,9 +11,18 @@
  * average of the two orderings.  The 1-D operator is a monotone PPM: a
  * limited slope per cell, fourth-order edge values, edge deviations clipped
  * to twice the slope, and the mean of the cell parabola over the swept
- * interval.  The unlimited order (hord 6, a reading of the "un-limited" PPM
- * option) keeps the fourth-order edges and the parabola but drops both
- * constraints: slopes (q+ - q-)/4 as they are, edge deviations unclipped.
+ * interval (hord 8).  Three other orders, readings of the un-limited,
+ * 2dx-filtered and positive-definite PPM options:
+ *  - hord 6, unlimited: the same fourth-order edges and parabola without
+ *    either constraint (slopes (q+ - q-)/4, edge deviations unclipped);
+ *  - hord 5, 2dx-filtered: the unlimited face, except where the upwind cell
+ *    and one of its neighbours are both local extrema (an oscillation over
+ *    two cells), where the face takes the upwind cell mean;
+ *  - hord 7, positive-definite (tracers): the unlimited parabola of a cell
+ *    with a non-negative mean, scaled about that mean by
+ *    theta = q / (q - m) when its minimum m over the cell is negative (the
+ *    scaling limiter of Zhang and Shu, 2010), so the parabola stays
+ *    non-negative and keeps its mean.
  */
 #include "orc.h"
 #include <math.h>
@@ -32,42 +41,58 @@ static double limited_slope(double qm, double q0, double qp)
     return sgn(d) * min2(fabs(d), min2(qmax - q0, q0 - qmin));
 }
 
+/* cell k of the window is a strict local extremum of its two neighbours */
+static int extremum(const double q[6], int k) { return (q[k] - q[k - 1]) * (q[k + 1] - q[k]) < 0.0; }
+
 /* Face value between cells m-1 and m for Courant number c; q[0..5] holds the
- * cells m-3 .. m+2 along the sweep.  lim = 0: the unlimited order. */
-double o_ppm_face_order(const double q[6], double c, int lim)
+ * cells m-3 .. m+2 along the sweep; ord is the PPM order (5, 6, 7 or 8). */
+double o_ppm_face_order(const double q[6], double c, int ord)
 {
+    int s = c > 0.0 ? 2 : 3;   /* the upwind cell (m-1 or m) */
+    if (ord == 5 && extremum(q, s) && (extremum(q, s - 1) || extremum(q, s + 1))) return q[s];
     double dm[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = 1; s <= 4; s++)
-        dm[s] = lim ? limited_slope(q[s - 1], q[s], q[s + 1]) : (q[s + 1] - q[s - 1]) / 4.0;
-    /* left-edge value of cell s (s = 2, 3, 4 are m-1, m, m+1) */
+    for (int k = 1; k <= 4; k++)
+        dm[k] = ord == 8 ? limited_slope(q[k - 1], q[k], q[k + 1]) : (q[k + 1] - q[k - 1]) / 4.0;
+    /* left-edge value of cell k (k = 2, 3, 4 are m-1, m, m+1) */
     double al[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = 2; s <= 4; s++) al[s] = 0.5 * (q[s - 1] + q[s]) + (dm[s - 1] - dm[s]) / 3.0;
-    int s = c > 0.0 ? 2 : 3;
+    for (int k = 2; k <= 4; k++) al[k] = 0.5 * (q[k - 1] + q[k]) + (dm[k - 1] - dm[k]) / 3.0;
     double bl, br;
-    if (lim) {
+    if (ord == 8) {
         bl = -sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s] - q[s]));
         br = sgn(dm[s]) * min2(2.0 * fabs(dm[s]), fabs(al[s + 1] - q[s]));
     } else {
         bl = al[s] - q[s];
         br = al[s + 1] - q[s];
     }
+    if (ord == 7 && q[s] >= 0.0) {
+        /* minimum of the parabola over the cell: an edge, or the vertex when
+         * it is a minimum (a6 < 0) inside the cell (|aR - aL| < -a6) */
+        double aL = q[s] + bl, aR = q[s] + br, a6 = -3.0 * (bl + br), da = aR - aL;
+        double mn = min2(aL, aR);
+        if (a6 < 0.0 && fabs(da) < -a6) mn = min2(mn, q[s] + da * da / (4.0 * a6) + a6 / 12.0);
+        if (mn < 0.0) {
+            double th = q[s] / (q[s] - mn);
+            bl *= th;
+            br *= th;
+        }
+    }
     if (c > 0.0) return q[s] + (1.0 - c) * (br - c * (bl + br));
     return q[s] + (1.0 + c) * (bl + c * (bl + br));
 }
 
-double o_ppm_face(const double q[6], double c) { return o_ppm_face_order(q, c, 1); }
+double o_ppm_face(const double q[6], double c) { return o_ppm_face_order(q, c, 8); }
 
-static double ppm_x(const OGrid *g, const double *q, int i, int j, double c)
+static double ppm_x(const OGrid *g, const double *q, int i, int j, double c, int ord)
 {
     double a[6];
     for (int s = 0; s < 6; s++) a[s] = q[IX(g, i - 3 + s, j)];
-    return o_ppm_face_order(a, c, g->hord != 6);
+    return o_ppm_face_order(a, c, ord);
 }
-static double ppm_y(const OGrid *g, const double *q, int i, int j, double c)
+static double ppm_y(const OGrid *g, const double *q, int i, int j, double c, int ord)
 {
     double a[6];
     for (int s = 0; s < 6; s++) a[s] = q[IX(g, i, j - 3 + s)];
-    return o_ppm_face_order(a, c, g->hord != 6);
+    return o_ppm_face_order(a, c, ord);
 }
 
 /*
@@ -81,6 +106,13 @@ void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const 
                 const double *crx, const double *cry, const double *xfx, const double *yfx,
                 const double *mx, const double *my, double *FX, double *FY)
 {
+    o_fv_tp_2d_ord(g, g->hord, t, q, qx, qy, crx, cry, xfx, yfx, mx, my, FX, FY);
+}
+
+void o_fv_tp_2d_ord(const OGrid *g, int ord, int t, const double *q, const double *qx, const double *qy,
+                    const double *crx, const double *cry, const double *xfx, const double *yfx,
+                    const double *mx, const double *my, double *FX, double *FY)
+{
     int n = g->n;
     size_t P = o_plane(g);
     const double *area = g->area + (size_t)t * P;
@@ -91,7 +123,7 @@ void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const 
 
     /* y-direction outer fluxes of q, and the inner advective y update */
     for (int j = 0; j <= n; j++)
-        for (int i = -3; i <= n + 2; i++) fy2[IX(g, i, j)] = ppm_y(g, qy, i, j, cry[IX(g, i, j)]);
+        for (int i = -3; i <= n + 2; i++) fy2[IX(g, i, j)] = ppm_y(g, qy, i, j, cry[IX(g, i, j)], ord);
     for (int j = 0; j < n; j++)
         for (int i = -3; i <= n + 2; i++) {
             size_t c = IX(g, i, j), jn = IX(g, i, j + 1);
@@ -100,7 +132,7 @@ void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const 
         }
     /* x-direction outer fluxes of q, and the inner advective x update */
     for (int j = -3; j <= n + 2; j++)
-        for (int i = 0; i <= n; i++) fx2[IX(g, i, j)] = ppm_x(g, qx, i, j, crx[IX(g, i, j)]);
+        for (int i = 0; i <= n; i++) fx2[IX(g, i, j)] = ppm_x(g, qx, i, j, crx[IX(g, i, j)], ord);
     for (int j = -3; j <= n + 2; j++)
         for (int i = 0; i < n; i++) {
             size_t c = IX(g, i, j), ie = IX(g, i + 1, j);
@@ -111,13 +143,13 @@ void o_fv_tp_2d(const OGrid *g, int t, const double *q, const double *qx, const 
     for (int j = 0; j < n; j++)
         for (int i = 0; i <= n; i++) {
             size_t f = IX(g, i, j);
-            double fx = ppm_x(g, qi, i, j, crx[f]);
+            double fx = ppm_x(g, qi, i, j, crx[f], ord);
             FX[f] = 0.5 * (fx + fx2[f]) * (mx ? mx[f] : xfx[f]);
         }
     for (int j = 0; j <= n; j++)
         for (int i = 0; i < n; i++) {
             size_t f = IX(g, i, j);
-            double fy = ppm_y(g, qj, i, j, cry[f]);
+            double fy = ppm_y(g, qj, i, j, cry[f], ord);
             FY[f] = 0.5 * (fy + fy2[f]) * (my ? my[f] : yfx[f]);
         }
     free(fy2); free(fx2); free(qi); free(qj);

@@ -3,7 +3,10 @@ Sec. IX-C, Lin-Rood transport): closed forms on constant and linear data,
 the exact upwind shift at Courant number +-1, the monotone bound of the
 1-D flux-form update, and for the unlimited order (hord 6) the exact swept
 mean of quadratics, agreement with the monotone order on linear data and the
-new extrema it is allowed to make."""
+new extrema it is allowed to make; the 2dx-filtered order (hord 5) and the
+positive-definite tracer order (hord 7) against first-order upwind on
+two-cell oscillations, the unlimited order on smooth data, and non-negative
+1-D and 2-D updates."""
 import numpy as np
 import pytest
 
@@ -248,3 +251,210 @@ def test_unlimited_order_in_kinetic_energy_alone(orc, axis):
     k = "u" if axis == "x" else "v"
     ref = np.abs(init[k]).max()
     assert np.abs(out[6][k] - out[8][k]).max() > 1e-6 * ref
+
+
+# ---- the 2dx-filtered order (hord 5) ------------------------------------
+
+@pytest.mark.parametrize("c", [0.3, 0.8, 1.0, -0.3, -0.8, -1.0])
+def test_2dx_oscillation_is_upwind(orc, c):
+    """On data alternating between two values every cell is a local extremum,
+    so the face takes the upwind cell mean and the 1-D update is first-order
+    upwind: q_m - c (q_m - q_{m-1}) for c > 0, q_m - |c| (q_m - q_{m+1})
+    for c < 0."""
+    q = np.where(np.arange(12) % 2 == 0, 0.2, 1.7)
+    got = _update_1d_order(orc, q, c, 5)
+    want = q - c * (q - np.roll(q, 1)) if c > 0 else q + c * (q - np.roll(q, -1))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+    assert np.abs(_update_1d_order(orc, q, c, 6) - want).max() > 1e-2 or abs(c) == 1.0
+
+
+def test_2dx_one_neighbour_suffices(orc):
+    # upwind cell 2 and cell 3 are extrema, cell 1 is not: filtered
+    q = np.array([0.0, 0.0, 1.0, -1.0, 0.0, 0.0])
+    assert orc.ppm_face(q, 0.4, hord=5) == 1.0
+    assert orc.ppm_face(q, -0.4, hord=5) == -1.0
+    # an isolated spike: its neighbours are not strict extrema, no filter
+    q = np.array([0.0, 0.0, 1.0, 0.0, 0.0, 0.0])
+    assert orc.ppm_face(q, 0.4, hord=5) == orc.ppm_face(q, 0.4, hord=6)
+    assert orc.ppm_face(q, 0.4, hord=5) != 1.0
+
+
+def test_2dx_smooth_equals_unlimited(orc):
+    """Twelve cells per wavelength: extrema are single cells, never adjacent,
+    so every face equals the unlimited one (the same arithmetic, bit for bit),
+    and quadratics keep their exact swept means."""
+    q = np.sin(np.arange(24) * 2 * np.pi / 12) + 0.3 * np.cos(np.arange(24) * 2 * np.pi / 8)
+    for c in (0.45, -0.7):
+        for m in range(24):
+            w = np.array([q[(m + s - 3) % 24] for s in range(6)])
+            assert orc.ppm_face(w, c, hord=5) == orc.ppm_face(w, c, hord=6)
+    a, b, c2 = 0.4, -0.3, 0.05
+    qq = np.array([_quad_cells(a, b, c2, s) for s in range(6)])
+    assert abs(orc.ppm_face(qq, 0.3, hord=5) - _quad_swept(a, b, c2, 2.2, 2.5)) <= 1e-14
+
+
+def test_2dx_conserves(orc):
+    rng = np.random.default_rng(31)
+    for _ in range(20):
+        q = rng.random(14)
+        c = rng.uniform(-1, 1)
+        assert abs(_update_1d_order(orc, q, c, 5).sum() - q.sum()) <= 1e-13
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_2dx_transport_faces(orc, axis):
+    """fv_tp_2d on a grid built with hord 5: a field alternating along the
+    flow axis has every face equal to its upwind cell (both sweeps filter)."""
+    n = 16
+    g = orc.Grid(0, n, 1, delta=1000.0, hord=5)
+    N = g.N
+    A = g.metric("area")[0, H, H]
+    prof = np.where(np.arange(n) % 2 == 0, 0.25, 1.5)
+    Q = g.field(1)
+    Q[0, 0, H:H + n, H:H + n] = prof[None, :] if axis == "x" else prof[:, None]
+    orc.halo_fill(g, Q)
+    zero = np.zeros((N, N))
+    for c in (0.6, -0.35):
+        cr = np.full((N, N), c)
+        if axis == "x":
+            FX, _ = orc.fv_tp_2d(g, 0, Q[0, 0], cr, zero, cr * A, zero)
+            face = FX[H + 5, H:H + n + 1] / (c * A)
+        else:
+            _, FY = orc.fv_tp_2d(g, 0, Q[0, 0], zero, cr, zero, cr * A)
+            face = FY[H:H + n + 1, H + 5] / (c * A)
+        up = np.array([prof[(m - 1) % n] if c > 0 else prof[m % n] for m in range(n + 1)])
+        np.testing.assert_allclose(face, up, rtol=1e-14, atol=0)
+
+
+def _winds_along_x(fi, n, u1):
+    """D-grid u varying along x only, v = 0: zero circulation around every cell."""
+    init = fi.periodic_state(n=n, nz=1, seed=4)
+    init["u"][0, 0, H:H + n + 1, H:H + n] = u1[None, :]
+    init["v"][0, 0, H:H + n, H:H + n + 1] = 0.0
+    return init
+
+
+def test_2dx_order_in_kinetic_energy(orc):
+    """Irrotational D-grid winds along x (no vorticity flux): a wind
+    alternating every cell about a mean changes the momentum update between
+    hord 5 and 6 (through the kinetic-energy faces alone); a smooth one leaves
+    it bit for bit equal."""
+    import fv3_inputs as fi
+    n = 16
+    x = np.arange(n)
+    for u1, differ in ((10.0 + 2.0 * (-1.0) ** x, True),
+                       (10.0 + 3.0 * np.sin(x * 2 * np.pi / n) + np.cos(x * 4 * np.pi / n), False)):
+        init = _winds_along_x(fi, n, u1)
+        out = {}
+        for hord in (5, 6):
+            g = orc.Grid(0, n, 1, delta=1000.0, hord=hord)
+            s = orc.new_state(g, init)
+            assert orc.acoustic_substeps(g, s, 2.0, 1, stop_stage=6) == 0
+            out[hord] = s["u"]
+        d = np.abs(out[5] - out[6]).max()
+        assert (d > 1e-6 * np.abs(u1).max()) if differ else (d == 0.0), (differ, d)
+
+
+# ---- the positive-definite tracer order (hord 7) ------------------------
+
+def _pd_data(rng, n):
+    q = np.where(rng.random(n) > 0.6, rng.random(n) * 5.0, 0.0)
+    q[rng.integers(n)] = 0.0
+    return q
+
+
+def test_pd_update_non_negative(orc):
+    """For non-negative data every scaled parabola is non-negative with the
+    cell's mean, so each swept part carries at most the cell's content and the
+    1-D update stays non-negative for |c| <= 1; the unlimited order on the same
+    data goes negative."""
+    rng = np.random.default_rng(41)
+    neg6 = 0
+    for _ in range(300):
+        q = _pd_data(rng, 12)
+        c = rng.uniform(-1, 1)
+        q7 = _update_1d_order(orc, q, c, 7)
+        assert q7.min() >= -1e-15, (q, c, q7.min())
+        assert abs(q7.sum() - q.sum()) <= 1e-13
+        neg6 += _update_1d_order(orc, q, c, 6).min() < -1e-3
+    assert neg6 > 50
+
+
+def test_pd_scaling_closed_form(orc):
+    """A small cell next to a large one: the unlimited parabola dips below
+    zero.  Its minimum from a dense sampling of that parabola (edges by
+    7/12, -1/12 interpolation), theta = q / (q - min), and the swept mean of
+    the scaled parabola integrated exactly."""
+    q = np.array([0.0, 5.0, 0.1, 0.0, 0.0, 0.0])
+    e = lambda k: 7 / 12 * (q[k - 1] + q[k]) - 1 / 12 * (q[k - 2] + q[k + 1])
+    aL, aR, m = e(2), e(3), q[2]
+    a6 = 6 * m - 3 * (aL + aR)
+    P = lambda x: aL + x * (aR - aL + a6 * (1 - x))
+    xs = np.linspace(0, 1, 200001)
+    mn = P(xs).min()
+    assert mn < 0
+    th = m / (m - mn)
+    c = 0.35
+    # mean of m + th (P - m) over x in [1 - c, 1]
+    Pint = lambda x: aL * x + (aR - aL + a6) * x * x / 2 - a6 * x ** 3 / 3
+    want = m + th * ((Pint(1.0) - Pint(1 - c)) / c - m)
+    assert abs(orc.ppm_face(q, c, hord=7) - want) <= 1e-9
+    assert orc.ppm_face(q, c, hord=6) < 0
+
+
+def test_pd_positive_parabola_unchanged(orc):
+    rng = np.random.default_rng(43)
+    for _ in range(100):
+        q = 1.0 + rng.random(6)
+        c = rng.uniform(-1, 1)
+        assert orc.ppm_face(q, c, hord=7) == orc.ppm_face(q, c, hord=6)
+
+
+def _uniform_tracer(orc, n, hord_tr, cx, cy):
+    g = orc.Grid(0, n, 1, hord_tr=hord_tr)
+    dp0 = g.field(1)
+    dp0[:] = 1000.0
+    A = 1000.0 * 1000.0
+    CX, CY = g.field(1), g.field(1)
+    CX[:] = cx
+    CY[:] = cy
+    return g, dp0, CX * dp0 * A, CY * dp0 * A, CX, CY
+
+
+def test_pd_tracer_transport_non_negative(orc):
+    """Tracer transport with hord_tr 7 under uniform flow (the 2-D result is
+    the mean of the two orderings of 1-D updates, each non-negative) keeps a
+    sparse non-negative field non-negative over 20 steps and conserves its
+    sum; with hord_tr 6 the same run goes negative."""
+    n = 16
+    rng = np.random.default_rng(44)
+    q0 = np.where(rng.random((n, n)) > 0.7, rng.random((n, n)) * 3.0, 0.0)
+    mins = {}
+    for hord_tr in (7, 6):
+        g, dp0, mfx, mfy, cx, cy = _uniform_tracer(orc, n, hord_tr, 0.55, -0.3)
+        q = g.field(1)
+        q[0, 0, H:H + n, H:H + n] = q0
+        lo = np.inf
+        for _ in range(20):
+            orc.tracer_transport(g, [q], dp0, mfx, mfy, cx, cy)
+            lo = min(lo, q[0, 0, H:H + n, H:H + n].min())
+        mins[hord_tr] = lo
+        assert abs(q[0, 0, H:H + n, H:H + n].sum() - q0.sum()) <= 1e-12 * q0.sum()
+    assert mins[7] >= -1e-15, mins
+    assert mins[6] < -1e-3, mins
+
+
+def test_pd_only_in_tracer_transport(orc):
+    """hord_tr changes the tracer transport only: the substep is bit-equal
+    under hord_tr 7 and 0, and hord 7 is rejected for the substep."""
+    import fv3_inputs as fi
+    init = fi.periodic_state(n=16, nz=2, seed=4)
+    out = []
+    for hord_tr in (0, 7):
+        g = orc.Grid(0, 16, 2, hord_tr=hord_tr)
+        s = orc.new_state(g, init)
+        assert orc.acoustic_substeps(g, s, 2.0, 2) == 0
+        out.append(s["u"].copy())
+    np.testing.assert_array_equal(out[0], out[1])
+    with pytest.raises(ValueError):
+        orc.Grid(0, 16, 2, hord=7)
