@@ -42,7 +42,7 @@ typedef enum {
     FV3_ENOMEM = -5,        /* device allocation failed (grid creation only)                */
     FV3_ECFL = -6,          /* a Courant number exceeded 1 in d_sw (latched on device)      */
     FV3_ENONFINITE = -7,    /* a prognostic became non-finite (latched on device)           */
-    FV3_EUNSUPPORTED = -8,  /* option not implemented (hord other than 6 or 8)              */
+    FV3_EUNSUPPORTED = -8,  /* option not implemented (a PPM order not listed below)        */
     FV3_EREMAP = -9,        /* reference interfaces not increasing in a column (latched)    */
     FV3_EINTERNAL = -99
 } fv3_status;
@@ -54,11 +54,16 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * cells (Sec. II), radius and rotation rate given.  Doubly periodic: one
  * n x n tile of spacing dx with constant Coriolis parameter f0.  Vertical:
  * nz Lagrangian layers below the model top pressure ptop.  hord selects the
- * PPM order of every horizontal transport of the call (Lin-Rood fluxes of
- * delp, pt, w, vorticity and tracers, and the kinetic-energy faces): 8 the
- * monotone order (limited slopes, edge deviations clipped to twice the
- * slope), 6 the unlimited order (the same fourth-order edges and parabola
- * without either constraint); other values: FV3_EUNSUPPORTED.  beta
+ * PPM order of every horizontal transport (Lin-Rood fluxes of delp, pt, w,
+ * vorticity and tracers, and the kinetic-energy faces): 8 the monotone order
+ * (limited slopes, edge deviations clipped to twice the slope), 6 the
+ * unlimited order (the same fourth-order edges and parabola without either
+ * constraint), 5 the 2dx-filtered order (order 6, but the upwind cell mean
+ * where that cell and a neighbour are both strict local extrema).  hord_tr,
+ * if not 0, replaces hord in fv3_tracer_transport and also admits 7, the
+ * positive-definite order (order 6 with each parabola of non-negative mean
+ * scaled about its mean until its minimum over the cell is 0; non-negative
+ * tracers stay non-negative).  Other values: FV3_EUNSUPPORTED.  beta
  * in [0.5, 1] off-centres the semi-implicit vertical solve (Sec. IX-B): the
  * momentum equation sees beta P^{n+1} + (1 - beta) P* and the pressure
  * response is driven by beta w^{n+1} + (1 - beta) w^n; 1 is backward Euler
@@ -78,10 +83,11 @@ typedef struct {
     double radius, omega;/* cubed sphere: [m], [1/s]                       */
     double ptop;         /* top pressure [Pa]                              */
     int precision;       /* fv3_precision                                  */
-    int hord;            /* PPM order: 8 monotone, 6 unlimited             */
+    int hord;            /* PPM order: 8 monotone, 6 unlimited, 5 2dx-filt.*/
     double d2_bg;        /* del-2 divergence damping, 0 (off) .. 0.25      */
     double beta;         /* vertical off-centring, 0.5 .. 1 (1: implicit)  */
     double dddmp;        /* Smagorinsky divergence damping, 0 (off) .. 1   */
+    int hord_tr;         /* tracer PPM order: 0 (= hord), 5, 6, 7, 8       */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

@@ -74,8 +74,10 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
     if (p->n < 8 || p->n > 4096 || p->nz < 1 || p->nz > 512)
         return fail(FV3_ESHAPE, "n must be in [8, 4096] and nz in [1, 512]");
     if (p->precision != FV3_FP64 && p->precision != FV3_MIXED) return fail(FV3_EDTYPE, "unknown precision");
-    if (p->hord != 8 && p->hord != 6)
-        return fail(FV3_EUNSUPPORTED, "PPM order must be 8 (monotone) or 6 (unlimited)");
+    if (p->hord != 8 && p->hord != 6 && p->hord != 5)
+        return fail(FV3_EUNSUPPORTED, "PPM order hord must be 8 (monotone), 6 (unlimited) or 5 (2dx-filtered)");
+    if (p->hord_tr != 0 && p->hord_tr != 5 && p->hord_tr != 6 && p->hord_tr != 7 && p->hord_tr != 8)
+        return fail(FV3_EUNSUPPORTED, "tracer PPM order hord_tr must be 0 (= hord), 5, 6, 7 or 8");
     if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))
         return fail(FV3_EINVAL, "d2_bg must be in [0, 0.25] (explicit del-2 damping)");
     if (!(p->dddmp >= 0.0 && p->dddmp <= 1.0))

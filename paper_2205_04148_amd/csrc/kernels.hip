@@ -335,11 +335,16 @@ static void launch2d_native(const char *name, Kern kern, int ilo, int ihi, int j
 
 // ====================================================================
 // 1-D PPM face value: face between cells m-1 and m along a sweep, cell
-// values q0..q5 = cells m-3..m+2, Courant number c.  Monotone order (LIM):
-// limited slope per cell (zero at extrema), fourth-order edge values, edge
-// deviations clipped to twice the slope with the slope's sign, mean of the
-// parabola over the swept part of the upwind cell.  Unlimited order
-// (!LIM): slopes (q+ - q-)/4 and the edge deviations as they come.
+// values q0..q5 = cells m-3..m+2, Courant number c, order ORD.
+//  8 monotone: limited slope per cell (zero at extrema), fourth-order edge
+//    values, edge deviations clipped to twice the slope with the slope's
+//    sign, mean of the parabola over the swept part of the upwind cell;
+//  6 unlimited: slopes (q+ - q-)/4 and the edge deviations as they come;
+//  5 2dx-filtered: order 6, but the upwind cell mean where that cell and a
+//    neighbour are both strict local extrema (an oscillation over 2 cells);
+//  7 positive-definite (tracers): order 6 with the parabola of a cell of
+//    non-negative mean q scaled about q by q / (q - min) where its minimum
+//    over the cell is negative (Zhang & Shu's scaling limiter).
 // ====================================================================
 template <class T>
 DEVI T lslope(T a, T b, T c)
@@ -354,12 +359,16 @@ DEVI T lslope(T a, T b, T c)
 // c the signed Courant number.  For the downwind orientation the parabola's
 // edge deviations swap roles and the swept fraction is |c|:
 // q + (1 - |c|) (e - |c| (bl + br)), e = br for c > 0 and bl otherwise.
-template <bool LIM, class T>
+template <int ORD, class T>
 DEVI T ppm_up(T a, T b, T q, T d, T e, T c)
 {
     const T third = (T)1 / (T)3;
+    if constexpr (ORD == 5) {
+        const bool xb = (b - a) * (q - b) < (T)0, xq = (q - b) * (d - q) < (T)0, xd = (d - q) * (e - d) < (T)0;
+        if (xq && (xb || xd)) return q;
+    }
     T bl, br;
-    if constexpr (LIM) {
+    if constexpr (ORD == 8) {
         const T dl = lslope(a, b, q), dm = lslope(b, q, d), dr = lslope(q, d, e);
         const T al = (T)0.5 * (b + q) + (dl - dm) * third;
         const T ar = (T)0.5 * (q + d) + (dm - dr) * third;
@@ -373,26 +382,40 @@ DEVI T ppm_up(T a, T b, T q, T d, T e, T c)
         bl = (T)0.5 * (b + q) + (dl - dm) * third - q;
         br = (T)0.5 * (q + d) + (dm - dr) * third - q;
     }
+    if constexpr (ORD == 7) {
+        if (q >= (T)0) {
+            // minimum over the cell: an edge, or the vertex when it is a
+            // minimum (a6 < 0) inside the cell (|aR - aL| < -a6)
+            const T aL = q + bl, aR = q + br, a6 = (T)-3 * (bl + br), da = aR - aL;
+            T mn = fmin(aL, aR);
+            if (a6 < (T)0 && fabs(da) < -a6) mn = fmin(mn, q + da * da / ((T)4 * a6) + a6 / (T)12);
+            if (mn < (T)0) {
+                const T th = q / (q - mn);
+                bl *= th;
+                br *= th;
+            }
+        }
+    }
     const T cc = fabs(c);
     return q + ((T)1 - cc) * ((c > 0 ? br : bl) - cc * (bl + br));
 }
 
-template <bool LIM, class T>
+template <int ORD, class T>
 DEVI T ppm6(T q0, T q1, T q2, T q3, T q4, T q5, T c)
 {
     // Branch-free: select the upwind cell's five-point neighbourhood (cell
     // m-1 for c > 0, else cell m), then one evaluation.
     const bool pos = c > 0;
-    return ppm_up<LIM>(pos ? q0 : q1, pos ? q1 : q2, pos ? q2 : q3, pos ? q3 : q4, pos ? q4 : q5, c);
+    return ppm_up<ORD>(pos ? q0 : q1, pos ? q1 : q2, pos ? q2 : q3, pos ? q3 : q4, pos ? q4 : q5, c);
 }
 
 // The same from six cells m-3..m+2 stored S apart from p (in LDS): the upwind
 // neighbourhood is selected by its address, five loads instead of six.
-template <int S, bool LIM, class T>
+template <int S, int ORD, class T>
 DEVI T ppm_lds(const T *p, T c)
 {
     const T *u = p + (c > 0 ? 0 : S);
-    return ppm_up<LIM>(u[0], u[S], u[2 * S], u[3 * S], u[4 * S], c);
+    return ppm_up<ORD>(u[0], u[S], u[2 * S], u[3 * S], u[4 * S], c);
 }
 
 // ====================================================================
@@ -1113,7 +1136,7 @@ DEVI T ccr(const C *a, const C *a0, int idx, int avg)
     return (T)a[idx];
 }
 
-template <class T, class C, class M, int EPI, bool LIM>
+template <class T, class C, class M, int EPI, int ORD>
 DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
 {
     constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
@@ -1226,7 +1249,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T f = 0;
         if (i <= n + 2 && j <= n) {
             const T *col = sQy + r * QW + c;
-            f = ppm_lds<QW, LIM>(col, sCY[e]);
+            f = ppm_lds<QW, ORD>(col, sCY[e]);
         }
         sFy[e] = f;
     }
@@ -1236,7 +1259,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T f = 0;
         if (i <= n && j <= n + 2) {
             const T *row = sQ + r * QW + c;
-            f = ppm_lds<1, LIM>(row, sCX[e]);
+            f = ppm_lds<1, ORD>(row, sCX[e]);
         }
         sFx[e] = f;
     }
@@ -1276,7 +1299,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             int fi = j * P + i;
             int s = (r + 3) * XW + c;
             const T *row = sQi + r * QW + c;
-            T fx = ppm_lds<1, LIM>(row, sCX[s]);
+            T fx = ppm_lds<1, ORD>(row, sCX[s]);
             T wgt = A.mx ? (T)wx[m] : sXF[s];
             T F = (T)0.5 * (fx + sFx[s]) * wgt;
             sFx[s] = F;
@@ -1299,7 +1322,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             int fi = j * P + i;
             int s = r * YW + c + 3;
             const T *col = sQj + r * FTX + c;
-            T fy = ppm_lds<FTX, LIM>(col, sCY[s]);
+            T fy = ppm_lds<FTX, ORD>(col, sCY[s]);
             T wgt = A.my ? (T)wy[m] : sYF[s];
             T F = (T)0.5 * (fy + sFy[s]) * wgt;
             sFy[s] = F;
@@ -1345,27 +1368,39 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     }
 }
 
-template <class T, class C, class M, bool LIM>
+template <class T, class C, class M, int ORD>
 static void fvtp_order(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
 {
     static const char *names[] = {"k_fvtp_flux", "k_fvtp_delp", "k_fvtp_massw", "k_fvtp_adv", "k_fvtp_tracer"};
     constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
     dim3 grd((unsigned)((g->n + FTX - 1) / FTX), (unsigned)((g->n + FTY - 1) / FTY), (unsigned)planes);
-    switch (a.epi) {
-    case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-    default: launch_fn<k_fvtp<T, C, M, EPI_TRACER, LIM>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+    if constexpr (ORD == 7) {
+        // the positive-definite order exists for the tracer transport only
+        launch_fn<k_fvtp<T, C, M, EPI_TRACER, ORD>>(names[EPI_TRACER], grd, dim3(FNT), st, g->geo, a);
+    } else {
+        switch (a.epi) {
+        case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        default: launch_fn<k_fvtp<T, C, M, EPI_TRACER, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        }
     }
 }
 
-// the grid's PPM order applies to every transport of the call
+// the grid's PPM order applies to every transport of the call; the tracer
+// transport takes hord_tr when that is set
 template <class T, class C, class M>
 static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
 {
-    if (g->p.hord == 6) fvtp_order<T, C, M, false>(g, planes, a, st);
-    else fvtp_order<T, C, M, true>(g, planes, a, st);
+    int ord = g->p.hord;
+    if (a.epi == EPI_TRACER && g->p.hord_tr != 0) ord = g->p.hord_tr;
+    switch (ord) {
+    case 5: fvtp_order<T, C, M, 5>(g, planes, a, st); break;
+    case 6: fvtp_order<T, C, M, 6>(g, planes, a, st); break;
+    case 7: fvtp_order<T, C, M, 7>(g, planes, a, st); break;
+    default: fvtp_order<T, C, M, 8>(g, planes, a, st); break;
+    }
 }
 
 // ====================================================================
@@ -1413,7 +1448,7 @@ DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc
 // absolute vorticity at cells from the D-grid circulation, and the kinetic
 // energy at corners (D-grid u upwinded along x and v along y by PPM with the
 // corner displacements of the contravariant C-grid winds)
-template <class B, bool LIM>
+template <class B, int ORD>
 DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const B *u, const B *v,
                            const B *ut, const B *vt, B *om, B *ke)
 {
@@ -1431,8 +1466,8 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const 
         B vb = (B)0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
         B cu = ub / AT(dx, ub > 0 ? i - 1 : i, j);
         B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
-        B uu = ppm6<LIM>(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
-        B vv = ppm6<LIM>(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
+        B uu = ppm6<ORD>(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
+        B vv = ppm6<ORD>(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
         B kev = (B)0.5 * (ub * uu + vb * vv);
         if (d2 > (B)0 || dd > (B)0) {
             // del-2 divergence damping: minus nu times the divergence of the
@@ -2015,8 +2050,9 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
                 (B)bdt, (B)g->p.d2_bg, (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v,
                 (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
         };
-        if (g->p.hord == 6) omke(std::false_type{});
-        else omke(std::true_type{});
+        if (g->p.hord == 6) omke(std::integral_constant<int, 6>{});
+        else if (g->p.hord == 5) omke(std::integral_constant<int, 5>{});
+        else omke(std::integral_constant<int, 8>{});
         {
             FvArgs<B, B, B> a{};
             a.q = W.om; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;

@@ -208,7 +208,7 @@ def test_abi_errors(fv3):
     st.workspace_bytes = 16
     assert L.fv3_acoustic_substeps(C.byref(st), g.handle, 1.0, 2, None) == -1
     p = fv3.GridParams(kind=0, n=16, nz=2, dx=1000.0, f0=0.0, radius=1.0, omega=0.0, ptop=100.0,
-                       precision=0, hord=5, d2_bg=0.0, beta=1.0, device=0)
+                       precision=0, hord=4, d2_bg=0.0, beta=1.0, device=0)
     h = C.c_void_p()
     assert L.fv3_init_grid(C.byref(p), C.byref(h)) == -8
     p.hord = 8
@@ -324,35 +324,50 @@ def test_smagorinsky_abi_range(fv3):
     assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == -1
 
 
-@pytest.mark.parametrize("kind,n,nz,dt,ns,stop", [(0, 24, 6, 0.4, 1, 6), (1, 12, 5, 300.0, 1, 6),
-                                                 (0, 48, 8, 2.0, 10, 0), (1, 24, 10, 2000.0, 10, 0)])
-def test_unlimited_ppm_parity(fv3, orc, kind, n, nz, dt, ns, stop):
-    """The unlimited PPM order (hord 6) against the oracle built with the same
-    order: after one d_sw (stage 6: every fv_tp_2d and the kinetic energy,
-    bar 1e-13), and after 10 substeps plus the tracer transport (bar 1e-11).
-    The orders' own results differ far above either bar, so the parity
-    tells the two apart."""
+ORDER_CASES = [(0, 24, 6, 0.4, 1, 6), (1, 12, 5, 300.0, 1, 6), (0, 48, 8, 2.0, 10, 0), (1, 24, 10, 2000.0, 10, 0)]
+
+
+@pytest.mark.parametrize("hord,hord_tr", [(6, 0), (5, 0), (8, 7)])
+@pytest.mark.parametrize("kind,n,nz,dt,ns,stop", ORDER_CASES)
+def test_ppm_order_parity(fv3, orc, hord, hord_tr, kind, n, nz, dt, ns, stop):
+    """The other PPM orders against the oracle built with the same orders:
+    unlimited (hord 6), 2dx-filtered (hord 5) and the positive-definite tracer
+    order (hord_tr 7).  After one d_sw (stage 6: every fv_tp_2d and the
+    kinetic energy, bar 1e-13), and after 10 substeps plus the tracer
+    transport (bar 1e-11).  The results of the order under test differ from
+    the monotone order's far above either bar (winds for hord, the tracer for
+    hord_tr), so the parity tells them apart."""
     import torch
 
+    if hord_tr and stop:
+        pytest.skip("the tracer order acts in the tracer transport only")
     init = fi.periodic_state(n=n, nz=nz, nq=1) if kind == 0 else fi.cube_state(n=n, nz=nz, nq=1)
-    g = fv3.Grid(kind, n, nz, hord=6)
+    g = fv3.Grid(kind, n, nz, hord=hord, hord_tr=hord_tr)
     s = fv3.State.allocate(g)
     s.load(init)
-    og = orc.Grid(kind, n, nz, hord=6)
+    og = orc.Grid(kind, n, nz, hord=hord, hord_tr=hord_tr)
     os_ = orc.new_state(og, init)
-    print(f"hord6 kind{kind} n{n} ns{ns} stop{stop}", flush=True)
+    label = f"hord{hord}/{hord_tr} kind{kind} n{n} ns{ns} stop{stop}"
+    print(label, flush=True)
     fv3.acoustic_substeps(s, g, dt, ns, stop_stage=stop)
     assert orc.acoustic_substeps(og, os_, dt, ns, stop_stage=stop) == 0
-    o8 = orc.new_state(orc.Grid(kind, n, nz), init)
-    assert orc.acoustic_substeps(orc.Grid(kind, n, nz), o8, dt, ns, stop_stage=stop) == 0
+    o8g = orc.Grid(kind, n, nz)
+    o8 = orc.new_state(o8g, init)
+    assert orc.acoustic_substeps(o8g, o8, dt, ns, stop_stage=stop) == 0
     fields = ("u", "v", "delp", "pt", "w", "mfx", "cx") if stop == 6 else \
         ("u", "v", "w", "delp", "pt", "delz", "mfx", "mfy", "cx", "cy", "pfull", "phi")
     tol = 1e-13 if stop == 6 else 1e-11
-    for k in ("u", "v"):
-        assert _relerr(_int(o8[k], n, STAG[k]), _int(os_[k], n, STAG[k])) > 1e3 * tol, k
+    if hord != 8:
+        for k in ("u", "v"):
+            assert _relerr(_int(o8[k], n, STAG[k]), _int(os_[k], n, STAG[k])) > 1e3 * tol, k
+    if hord == 5:
+        o6g = orc.Grid(kind, n, nz, hord=6)
+        o6 = orc.new_state(o6g, init)
+        assert orc.acoustic_substeps(o6g, o6, dt, ns, stop_stage=stop) == 0
+        assert _relerr(_int(o6["u"], n, "Y"), _int(os_["u"], n, "Y")) > 1e3 * tol
     if stop == 0:
         assert fv3.check_status(g) == 0
-    _compare(s, os_, n, fields, tol, f"hord6 kind{kind}")
+    _compare(s, os_, n, fields, tol, label)
     if stop != 0:
         return
     qd = [g.upload(q, nz) for q in init["q"]]
@@ -360,27 +375,47 @@ def test_unlimited_ppm_parity(fv3, orc, kind, n, nz, dt, ns, stop):
     fv3.tracer_transport(qd, s, g)
     orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
     torch.cuda.synchronize()
-    e = _relerr(_int(g.download(qd[0], nz), n, "C"), _int(qh[0], n, "C"))
-    print(f"hord6 kind{kind} tracer {e:.2e}", flush=True)
+    qg = _int(g.download(qd[0], nz), n, "C")
+    e = _relerr(qg, _int(qh[0], n, "C"))
+    print(f"{label} tracer {e:.2e} min {qg.min():.3e}", flush=True)
     assert e <= 1e-11
+    if hord_tr:
+        q8 = [q.copy() for q in init["q"]]
+        orc.tracer_transport(o8g, q8, o8["dp0"], o8["mfx"], o8["mfy"], o8["cx"], o8["cy"])
+        assert _relerr(_int(q8[0], n, "C"), _int(qh[0], n, "C")) > 1e3 * 1e-11
 
 
-def test_unlimited_ppm_mixed_cube(fv3, orc):
-    """hord 6 in mixed precision on the C24 cube after 10 substeps, at the
-    mixed-precision bars of the other mixed tests."""
+@pytest.mark.parametrize("hord", [6, 5])
+def test_ppm_order_mixed_cube(fv3, orc, hord):
+    """hord 6 and 5 in mixed precision on the C24 cube after 10 substeps, at
+    the mixed-precision bars of the other mixed tests."""
     n, nz = 24, 10
     init = fi.cube_state(n=n, nz=nz)
-    g = fv3.Grid(1, n, nz, precision="mixed", hord=6)
+    g = fv3.Grid(1, n, nz, precision="mixed", hord=hord)
     s = fv3.State.allocate(g)
     s.load(init)
-    og = orc.Grid(1, n, nz, hord=6)
+    og = orc.Grid(1, n, nz, hord=hord)
     os_ = orc.new_state(og, init)
-    print("hord6 mixed C24", flush=True)
+    print(f"hord{hord} mixed C24", flush=True)
     fv3.acoustic_substeps(s, g, 2000.0, 10)
     assert fv3.check_status(g) == 0
     assert orc.acoustic_substeps(og, os_, 2000.0, 10) == 0
     tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
-    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz"), tol, "hord6 mixed C24")
+    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz"), tol, f"hord{hord} mixed C24")
+
+
+def test_ppm_order_abi(fv3):
+    """hord 7 is a tracer order only; unknown orders are rejected."""
+    import ctypes as C
+
+    base = dict(kind=0, n=16, nz=2, dx=1000.0, f0=0.0, radius=1.0, omega=0.0, ptop=100.0,
+                precision=0, hord=8, d2_bg=0.0, beta=1.0, dddmp=0.0, hord_tr=0, device=0)
+    for hord, hord_tr, want in ((7, 0, -8), (4, 0, -8), (8, 9, -8), (8, 4, -8), (5, 7, 0), (6, 5, 0)):
+        p = fv3.GridParams(**dict(base, hord=hord, hord_tr=hord_tr))
+        h = C.c_void_p()
+        assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, (hord, hord_tr)
+        if want == 0:
+            fv3.lib().fv3_free_grid(h)
 
 
 def test_cfl_flag_latched(fv3):
