@@ -58,7 +58,9 @@ def lib():
         L.orc_set_smag.argtypes = [C.c_void_p, C.c_double]
         L.orc_smag_corner.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_double, dp]
         L.orc_sim1b.restype = C.c_double
-        L.orc_sim1b.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [dp] * 10
+        L.orc_sim1b.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double] + [dp] * 10
+        L.orc_pp_interfaces.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.orc_set_pp_order.argtypes = [C.c_void_p, C.c_int]
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_grid_conn.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_halo_fill.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, C.c_int]
@@ -106,9 +108,11 @@ class Grid:
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
                  d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
-                 hord_tr: int = 0):
+                 hord_tr: int = 0, pp_order: int = 2):
         if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
             raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
+        if pp_order not in (2, 4):
+            raise ValueError("pp_order must be 2 or 4")
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
@@ -122,6 +126,8 @@ class Grid:
         lib().orc_set_smag(h, float(dddmp))
         self.hord, self.hord_tr = hord, hord_tr
         lib().orc_set_hord(h, int(hord), int(hord_tr))
+        self.pp_order = pp_order
+        lib().orc_set_pp_order(h, int(pp_order))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -191,7 +197,7 @@ def fv_tp_2d(g: Grid, t: int, q, crx, cry, xfx, yfx, mx=None, my=None):
     return FX, FY
 
 
-def sim1(dt, ptop, zs, dpi, theta, delz, w, beta: float = 1.0):
+def sim1(dt, ptop, zs, dpi, theta, delz, w, beta: float = 1.0, pp_order: int = 2):
     """One column solve; also returns the interface perturbation P* ("pstar")
     and the unscaled coupling dt x linearised pressure response ("coupling")."""
     nz = len(dpi)
@@ -199,9 +205,18 @@ def sim1(dt, ptop, zs, dpi, theta, delz, w, beta: float = 1.0):
     wo, dzo = np.zeros(nz), np.zeros(nz)
     pf, ph = np.zeros(nz + 1), np.zeros(nz + 1)
     ps, cp = np.zeros(nz + 1), np.zeros(nz + 1)
-    minpiv = lib().orc_sim1b(nz, dt, float(beta), ptop, zs, *[_p(a) for a in ins], _p(wo), _p(dzo),
+    minpiv = lib().orc_sim1b(nz, dt, float(beta), int(pp_order), ptop, zs, *[_p(a) for a in ins], _p(wo), _p(dzo),
                              _p(pf), _p(ph), _p(ps), _p(cp))
     return dict(w=wo, delz=dzo, pfull=pf, phi=ph, min_pivot=minpiv, pstar=ps, coupling=cp)
+
+
+def pp_interfaces(dpi, pp, order: int = 2) -> np.ndarray:
+    """Interface values (nz + 1) of the layer perturbation pp used by the column solve."""
+    d = np.ascontiguousarray(dpi, dtype=np.float64)
+    q = np.ascontiguousarray(pp, dtype=np.float64)
+    out = np.zeros(len(d) + 1)
+    lib().orc_pp_interfaces(len(d), int(order), _p(d), _p(q), _p(out))
+    return out
 
 
 def pgf(dt, L, dpiW, dpiE, phW0, phW1, phE0, phE1, pW0, pW1, pE0, pE1) -> float:

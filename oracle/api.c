@@ -130,12 +130,20 @@ double orc_sim1(int nz, double dt, double ptop, double zs, const double *dpi, co
     return o_sim1(nz, dt, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi);
 }
 
-double orc_sim1b(int nz, double dt, double beta, double ptop, double zs, const double *dpi,
+double orc_sim1b(int nz, double dt, double beta, int pp_order, double ptop, double zs, const double *dpi,
                  const double *theta, const double *delz, const double *w, double *w_out,
                  double *delz_out, double *pfull, double *phi, double *pstar, double *coupling)
 {
-    return o_sim1b(nz, dt, beta, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi, pstar, coupling);
+    return o_sim1b(nz, dt, beta, pp_order, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi, pstar,
+                   coupling);
 }
+
+void orc_pp_interfaces(int nz, int order, const double *dpi, const double *pp, double *pps)
+{
+    o_pp_interfaces(nz, order, dpi, pp, pps);
+}
+
+void orc_set_pp_order(void *gp, int order) { ((OGrid *)gp)->pp_order = order; }
 
 double orc_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
                double phE0, double phE1, double pW0, double pW1, double pE0, double pE1)

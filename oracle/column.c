@@ -22,6 +22,11 @@
  *   scan of m (w_new - w)/dt, the new thickness by inverting the equation of
  *   state, and heights by a bottom-up scan from the surface.
  *
+ * Interface perturbation (order 4): at interfaces with two layers on each
+ * side, the value there of the cubic (in the mass coordinate) whose means
+ * over those four layers are their perturbations, in place of the
+ * mass-weighted mean of the two adjacent layers (order 2).
+ *
  * Off-centring (weight beta in [0.5, 1], 1 = backward Euler above): the
  * momentum equation sees P^b = beta P^{n+1} + (1 - beta) P* and the pressure
  * response is driven by w^b = beta w^{n+1} + (1 - beta) w^n.  Eliminating
@@ -39,8 +44,61 @@
 #include <math.h>
 #include <stdlib.h>
 
+/* Interface values of the layer perturbation pp (K = 0 .. nz): 0 at the top,
+ * the bottom layer's value at the surface; between layers the mass-weighted
+ * mean of the two adjacent layers (order 2), or (order 4, where two layers lie
+ * on each side) the interface value of the cubic whose means over the layers
+ * K-2 .. K+1 equal their pp: a 4 x 4 linear system for the cubic's
+ * coefficients in x = (mass coordinate - interface) / (dpi[K-1] + dpi[K]),
+ * solved by Gaussian elimination with partial pivoting. */
+void o_pp_interfaces(int nz, int order, const double *dpi, const double *pp, double *pps)
+{
+    pps[0] = 0.0;
+    pps[nz] = pp[nz - 1];
+    for (int K = 1; K < nz; K++) {
+        if (order != 4 || K < 2 || K > nz - 2) {
+            pps[K] = (dpi[K] * pp[K - 1] + dpi[K - 1] * pp[K]) / (dpi[K - 1] + dpi[K]);
+            continue;
+        }
+        double sc = dpi[K - 1] + dpi[K];
+        double e[5];
+        e[2] = 0.0;
+        e[1] = -dpi[K - 1] / sc;
+        e[0] = e[1] - dpi[K - 2] / sc;
+        e[3] = dpi[K] / sc;
+        e[4] = e[3] + dpi[K + 1] / sc;
+        double M[4][5];
+        for (int r = 0; r < 4; r++) {
+            double a = e[r], b = e[r + 1];
+            for (int q = 0; q < 4; q++) M[r][q] = (pow(b, q + 1) - pow(a, q + 1)) / ((q + 1) * (b - a));
+            M[r][4] = pp[K - 2 + r];
+        }
+        for (int c = 0; c < 4; c++) {
+            int piv = c;
+            for (int r = c + 1; r < 4; r++)
+                if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+            for (int q = 0; q < 5; q++) {
+                double tmp = M[c][q];
+                M[c][q] = M[piv][q];
+                M[piv][q] = tmp;
+            }
+            for (int r = c + 1; r < 4; r++) {
+                double f = M[r][c] / M[c][c];
+                for (int q = c; q < 5; q++) M[r][q] -= f * M[c][q];
+            }
+        }
+        double co[4];
+        for (int c = 3; c >= 0; c--) {
+            double v = M[c][4];
+            for (int q = c + 1; q < 4; q++) v -= M[c][q] * co[q];
+            co[c] = v / M[c][c];
+        }
+        pps[K] = co[0];   /* the cubic at x = 0 */
+    }
+}
+
 /* Returns the smallest Thomas pivot (positive for a well-posed column). */
-double o_sim1b(int nz, double dt, double beta, double ptop, double zs, const double *dpi,
+double o_sim1b(int nz, double dt, double beta, int pp_order, double ptop, double zs, const double *dpi,
                const double *theta, const double *delz, const double *w, double *w_out,
                double *delz_out, double *pfull, double *phi, double *pstar, double *coupling)
 {
@@ -67,10 +125,7 @@ double o_sim1b(int nz, double dt, double beta, double ptop, double zs, const dou
         double p = p0 * pow(rd * theta[k] * m[k] / (h[k] * p0), gam);
         pp[k] = p - pibar[k];
     }
-    pps[0] = 0.0;
-    for (int K = 1; K < nz; K++)
-        pps[K] = (dpi[K] * pp[K - 1] + dpi[K - 1] * pp[K]) / (dpi[K - 1] + dpi[K]);
-    pps[nz] = pp[nz - 1];
+    o_pp_interfaces(nz, pp_order, dpi, pp, pps);
     /* coupling of interface K: dt times the linearised pressure response to
      * the convergence of w, times beta^2 (see the header) */
     A[0] = 0.0;
@@ -129,7 +184,7 @@ double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, cons
               const double *delz, const double *w, double *w_out, double *delz_out,
               double *pfull, double *phi)
 {
-    return o_sim1b(nz, dt, 1.0, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi, 0, 0);
+    return o_sim1b(nz, dt, 1.0, 2, ptop, zs, dpi, theta, delz, w, w_out, delz_out, pfull, phi, 0, 0);
 }
 
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,

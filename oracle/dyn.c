@@ -256,7 +256,7 @@ static void dzc_riemc_tile(const OGrid *g, int t, double dt2, const double *delz
                 col_t[k] = PL(ptc, t, k, nz)[c];
                 col_w[k] = PL(wc, t, k, nz)[c];
             }
-            o_sim1b(nz, dt2, g->beta, g->ptop, zs[c], col_d, col_t, col_z, col_w, wo, dzo, pf, ph, 0, 0);
+            o_sim1b(nz, dt2, g->beta, g->pp_order, g->ptop, zs[c], col_d, col_t, col_z, col_w, wo, dzo, pf, ph, 0, 0);
             for (int K = 0; K <= nz; K++) {
                 PL(pkc, t, K, nz + 1)[c] = pf[K];
                 PL(gz, t, K, nz + 1)[c] = ph[K];
@@ -742,7 +742,7 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
                         cz[k] = PL(s->delz, t, k, nz)[c];
                         cw[k] = PL(s->w, t, k, nz)[c];
                     }
-                    o_sim1b(nz, bdt, g->beta, g->ptop, zs[(size_t)t * P + c], cd, ct, cz, cw, wo, dzo, pf,
+                    o_sim1b(nz, bdt, g->beta, g->pp_order, g->ptop, zs[(size_t)t * P + c], cd, ct, cz, cw, wo, dzo, pf,
                             ph, 0, 0);
                     for (int k = 0; k < nz; k++) {
                         PL(s->w, t, k, nz)[c] = wo[k];

@@ -297,6 +297,7 @@ OGrid *og_new(int kind, int n, int nz, double delta, double f0, double radius, d
     g->beta = 1.0;
     g->hord = 8;
     g->hord_tr = 0;
+    g->pp_order = 2;
     size_t P = (size_t)g->T * o_plane(g);
     ALLOC_METRICS(g, P);
     if (kind == 0) {

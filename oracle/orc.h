@@ -53,6 +53,8 @@ typedef struct {
      * 5 2dx-filtered; hord_tr that of the tracer transport (0: hord; also
      * 7, positive-definite) */
     int hord, hord_tr;
+    /* interface perturbation of the column solves: 2 mass-linear (default), 4 cubic */
+    int pp_order;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -105,9 +107,10 @@ double o_sim1(int nz, double dt, double ptop, double zs, const double *dpi, cons
 /* off-centred form (beta in [0.5, 1]); pstar / coupling (nz + 1, may be NULL)
  * receive the interface perturbation P* and the unscaled coupling dt x the
  * linearised pressure response */
-double o_sim1b(int nz, double dt, double beta, double ptop, double zs, const double *dpi,
+double o_sim1b(int nz, double dt, double beta, int pp_order, double ptop, double zs, const double *dpi,
                const double *theta, const double *delz, const double *w, double *w_out,
                double *delz_out, double *pfull, double *phi, double *pstar, double *coupling);
+void o_pp_interfaces(int nz, int order, const double *dpi, const double *pp, double *pps);
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
              double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
 

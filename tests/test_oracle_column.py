@@ -8,7 +8,11 @@ the top-down scan of the new perturbation equals the implicitly linearised
 interface pressure (so the returned w solves the discrete momentum equation);
 the thickness inversion reproduces the new pressure through the equation of
 state; all pivots positive; the pressure gradient is zero for identical
-columns, equals -dt*dp/(rho*L) for a uniform offset, and is antisymmetric."""
+columns, equals -dt*dp/(rho*L) for a uniform offset, and is antisymmetric.
+The cubic interface perturbation (pp_order 4): exact interface values of
+cubic profiles on uneven layers, the 7/12, -1/12 weights on even ones, the
+mass-linear rule where one side has a single layer, and its use in both
+column solves of the substep."""
 import math
 
 import numpy as np
@@ -31,9 +35,10 @@ def _column(nz, rng, perturb=0.02):
     return pi, dpi, theta, delz, w
 
 
-def _assemble(dt, pi, dpi, theta, delz, w):
+def _assemble(dt, pi, dpi, theta, delz, w, pps=None):
     """Dense matrix of the implicit system, assembled from the discrete
-    equations (interface pressure linearised in the new w)."""
+    equations (interface pressure linearised in the new w); pps replaces the
+    mass-linear interface perturbation when given."""
     nz = len(dpi)
     m = dpi / G
     h = -delz
@@ -44,6 +49,8 @@ def _assemble(dt, pi, dpi, theta, delz, w):
     for K in range(1, nz):
         PPs[K] = (dpi[K] * pp[K - 1] + dpi[K - 1] * pp[K]) / (dpi[K - 1] + dpi[K])
     PPs[nz] = pp[nz - 1]
+    if pps is not None:
+        PPs = np.asarray(pps, dtype=float)
     d = np.zeros(nz + 1)
     d[1:nz] = 0.5 * (h[:-1] + h[1:])
     d[nz] = 0.5 * h[-1]
@@ -248,3 +255,96 @@ def test_offcentring_weight_changes_the_response(orc):
     b = orc.sim1(10.0, pi[0], 0.0, dpi, theta, dz, np.zeros(nz), beta=0.6)
     assert np.sign(a["w"][4]) == np.sign(b["w"][4]) and np.sign(a["w"][6]) == np.sign(b["w"][6])
     assert np.abs(a["w"] - b["w"]).max() > 1e-6 * np.abs(a["w"]).max()
+
+
+# ---- cubic interface perturbation (pp_order 4) --------------------------
+
+def _cubic_means(coef, x):
+    """Layer means of sum coef[q] s^q, s = x / 1e4, over the layers between
+    the interfaces x, and the profile at the interfaces."""
+    F = lambda xx: sum(c * 1e4 * (xx / 1e4) ** (q + 1) / (q + 1) for q, c in enumerate(coef))
+    f = lambda xx: sum(c * (xx / 1e4) ** q for q, c in enumerate(coef))
+    return (F(x[1:]) - F(x[:-1])) / np.diff(x), f(x)
+
+
+def test_pp_interfaces_cubic_exact(orc):
+    rng = np.random.default_rng(50)
+    for _ in range(10):
+        nz = 12
+        dpi = rng.uniform(300.0, 3000.0, nz)
+        x = np.concatenate([[0.0], np.cumsum(dpi)])
+        coef = rng.normal(size=4) * (50.0, 30.0, 10.0, 5.0)
+        pp, fx = _cubic_means(coef, x)
+        got = orc.pp_interfaces(dpi, pp, order=4)
+        scale = np.abs(pp).max()
+        for K in range(2, nz - 1):
+            assert abs(got[K] - fx[K]) <= 1e-11 * scale, (K, got[K], fx[K])
+        for K in (1, nz - 1):
+            want = (dpi[K] * pp[K - 1] + dpi[K - 1] * pp[K]) / (dpi[K - 1] + dpi[K])
+            assert abs(got[K] - want) <= 1e-14 * scale
+        assert got[0] == 0.0 and got[nz] == pp[nz - 1]
+        two = orc.pp_interfaces(dpi, pp, order=2)
+        mid = (dpi[1:] * pp[:-1] + dpi[:-1] * pp[1:]) / (dpi[:-1] + dpi[1:])
+        np.testing.assert_allclose(two[1:nz], mid, rtol=1e-15, atol=1e-15 * scale)
+        # the mass-linear rule is not exact for curved profiles
+        assert np.abs(two[2:nz - 1] - fx[2:nz - 1]).max() > 1e-6 * scale
+
+
+def test_pp_interfaces_even_layers(orc):
+    rng = np.random.default_rng(51)
+    pp = rng.normal(size=9)
+    got = orc.pp_interfaces(np.full(9, 700.0), pp, order=4)
+    for K in range(2, 8):
+        want = 7 / 12 * (pp[K - 1] + pp[K]) - 1 / 12 * (pp[K - 2] + pp[K + 1])
+        assert abs(got[K] - want) <= 1e-14 * np.abs(pp).max()
+
+
+def test_cubic_interfaces_in_the_solve(orc):
+    """With pp_order 4 the solve's P* is the cubic interface value of the
+    equation-of-state perturbation, and the returned w solves the implicit
+    system assembled with those interface values (dense solve)."""
+    rng = np.random.default_rng(52)
+    nz, dt = 14, 15.0
+    pi, dpi, theta, delz, w = _column(nz, rng)
+    pibar = dpi / (np.log(pi[1:]) - np.log(pi[:-1]))
+    pp = P0 * (RD * theta * (dpi / G) / (-delz * P0)) ** GAM - pibar
+    pps = orc.pp_interfaces(dpi, pp, order=4)
+    r = orc.sim1(dt, pi[0], 0.0, dpi, theta, delz, w, pp_order=4)
+    assert np.abs(r["pstar"] - pps).max() <= 1e-12 * np.abs(pps).max()
+    M, rhs, *_ = _assemble(dt, pi, dpi, theta, delz, w, pps=pps)
+    wd = np.linalg.solve(M, rhs)
+    assert np.abs(r["w"] - wd).max() <= 1e-10 * np.abs(wd).max()
+    r2 = orc.sim1(dt, pi[0], 0.0, dpi, theta, delz, w)
+    assert np.abs(r["w"] - r2["w"]).max() > 1e-8 * np.abs(wd).max()
+
+
+def test_cubic_interfaces_reach_both_solves(orc):
+    """Substep threading: the C-grid solve is the first place the order acts
+    (its interface pressure differs between the orders while the stages
+    before it are bit-equal), and the D-grid solve's w equals the column
+    solve with pp_order 4 applied to the state it receives."""
+    import fv3_inputs as fi
+    n, nz, dt = 12, 10, 300.0
+    init = fi.cube_state(n=n, nz=nz, seed=3)
+    dbg = {}
+    for order in (2, 4):
+        g = orc.Grid(1, n, nz, delta=1.0e5, pp_order=order)
+        s = orc.new_state(g, init)
+        st, d = orc.acoustic_substeps(g, s, dt, 1, stop_stage=3, debug=True)
+        assert st == 0
+        dbg[order] = d
+    np.testing.assert_array_equal(dbg[2]["ptc"], dbg[4]["ptc"])
+    assert np.abs(dbg[2]["pkc"] - dbg[4]["pkc"]).max() > 1e-8 * np.abs(dbg[2]["pkc"]).max()
+    g = orc.Grid(1, n, nz, delta=1.0e5, pp_order=4)
+    s7 = orc.new_state(g, init)
+    assert orc.acoustic_substeps(g, s7, dt, 1, stop_stage=7) == 0
+    s8 = orc.new_state(g, init)
+    assert orc.acoustic_substeps(g, s8, dt, 1, stop_stage=8) == 0
+    H = 3
+    rng = np.random.default_rng(53)
+    for _ in range(12):
+        t, j, i = int(rng.integers(6)), int(rng.integers(n)) + H, int(rng.integers(n)) + H
+        col = lambda k: s7[k][t, :, j, i]
+        r = orc.sim1(dt, g.ptop, 0.0, col("delp"), col("pt"), col("delz"),
+                     col("w"), pp_order=4)
+        assert np.abs(r["w"] - s8["w"][t, :, j, i]).max() <= 1e-13 * max(np.abs(r["w"]).max(), 1e-30)
