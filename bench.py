@@ -153,7 +153,7 @@ def run_precision(fv3, torch, init, args, precision):
     n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
     dt = bdt * ns
     g = fv3.Grid(1, n, nz, precision=precision, beta=args.beta, d2_bg=args.d2_bg, dddmp=args.dddmp,
-                 hord=args.hord, hord_tr=args.hord_tr)
+                 hord=args.hord, hord_tr=args.hord_tr, pp_order=args.pp_order)
     s = fv3.State.allocate(g)
     s.load(init)
     qs = [g.upload(q, nz) for q in init["q"]]
@@ -383,6 +383,8 @@ def main():
                     help="PPM order: 8 monotone, 6 unlimited, 5 2dx-filtered")
     ap.add_argument("--hord-tr", type=int, default=0, choices=[0, 5, 6, 7, 8],
                     help="tracer PPM order (0: as --hord; 7 positive-definite)")
+    ap.add_argument("--pp-order", type=int, default=2, choices=[2, 4],
+                    help="interface pressure perturbation of the column solves: 2 mass-linear, 4 cubic")
     ap.add_argument("--d2-bg", type=float, default=0.0, help="del-2 divergence damping (0 .. 0.25)")
     ap.add_argument("--dddmp", type=float, default=0.0, help="Smagorinsky divergence damping (0 .. 1)")
     args = ap.parse_args()
@@ -436,7 +438,7 @@ def main():
                                f"substeps of {args.bdt:g} s + 4-tracer transport + mass sums per step",
                    "precision": args.precision, "n_split": args.n_split, "cells": cells, "beta": args.beta,
                    "d2_bg": args.d2_bg, "dddmp": args.dddmp, "hord": args.hord,
-                   "hord_tr": args.hord_tr,
+                   "hord_tr": args.hord_tr, "pp_order": args.pp_order,
                    "ms_per_substep": main_res["ms_per_substep"],
                    "device_status": main_res["device_status"]},
         "roofline": main_res["roofline"],

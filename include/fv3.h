@@ -63,7 +63,13 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * if not 0, replaces hord in fv3_tracer_transport and also admits 7, the
  * positive-definite order (order 6 with each parabola of non-negative mean
  * scaled about its mean until its minimum over the cell is 0; non-negative
- * tracers stay non-negative).  Other values: FV3_EUNSUPPORTED.  beta
+ * tracers stay non-negative).  Other values: FV3_EUNSUPPORTED.  pp_order
+ * selects how both column solves carry the layer pressure perturbation to
+ * the interfaces (Sec. IX-B): 2 (0 means the same) the mass-weighted mean of
+ * the two adjacent layers, 4 the interface value of the cubic (in the mass
+ * coordinate) whose means over the two layers on each side are theirs, with
+ * the mass-weighted mean next to the top and the bottom; other values:
+ * FV3_EUNSUPPORTED.  beta
  * in [0.5, 1] off-centres the semi-implicit vertical solve (Sec. IX-B): the
  * momentum equation sees beta P^{n+1} + (1 - beta) P* and the pressure
  * response is driven by beta w^{n+1} + (1 - beta) w^n; 1 is backward Euler
@@ -88,6 +94,8 @@ typedef struct {
     double beta;         /* vertical off-centring, 0.5 .. 1 (1: implicit)  */
     double dddmp;        /* Smagorinsky divergence damping, 0 (off) .. 1   */
     int hord_tr;         /* tracer PPM order: 0 (= hord), 5, 6, 7, 8       */
+    int pp_order;        /* interface p' of the column solves: 2 (or 0)
+                            mass-linear, 4 cubic                          */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

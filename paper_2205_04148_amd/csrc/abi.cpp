@@ -78,6 +78,8 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
         return fail(FV3_EUNSUPPORTED, "PPM order hord must be 8 (monotone), 6 (unlimited) or 5 (2dx-filtered)");
     if (p->hord_tr != 0 && p->hord_tr != 5 && p->hord_tr != 6 && p->hord_tr != 7 && p->hord_tr != 8)
         return fail(FV3_EUNSUPPORTED, "tracer PPM order hord_tr must be 0 (= hord), 5, 6, 7 or 8");
+    if (p->pp_order != 0 && p->pp_order != 2 && p->pp_order != 4)
+        return fail(FV3_EUNSUPPORTED, "pp_order must be 2 (mass-linear; 0 means the same) or 4 (cubic)");
     if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))
         return fail(FV3_EINVAL, "d2_bg must be in [0, 0.25] (explicit del-2 damping)");
     if (!(p->dddmp >= 0.0 && p->dddmp <= 1.0))

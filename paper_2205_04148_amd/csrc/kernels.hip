@@ -819,10 +819,27 @@ DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, co
 constexpr int SU = FV3_SIM1_SU;   // levels per prefetch group, passes 1 and 3
 constexpr int SU2 = 8;            // levels per prefetch group, passes 2 and 4
 
+// Interface value at x = 0 of the cubic whose means over four consecutive
+// layers of thicknesses da, db | dc, dd (the interface between db and dc)
+// are qa, qb | qc, qd: the derivative at the middle node of the quartic
+// through the cumulative contents at the five layer boundaries (Lagrange
+// form, contents and nodes measured from the interface).  Exact for cubics.
+DEVI double cubic_iface(double da, double db, double dc, double dd, double qa, double qb, double qc, double qd)
+{
+    const double x0 = -(da + db), x1 = -db, x3 = dc, x4 = dc + dd;
+    const double Q0 = -(qa * da + qb * db), Q1 = -qb * db, Q3 = qc * dc, Q4 = qc * dc + qd * dd;
+    const double l0 = -(x1 * x3 * x4) / ((x0 - x1) * x0 * (x0 - x3) * (x0 - x4));
+    const double l1 = -(x0 * x3 * x4) / ((x1 - x0) * x1 * (x1 - x3) * (x1 - x4));
+    const double l3 = -(x0 * x1 * x4) / ((x3 - x0) * (x3 - x1) * x3 * (x3 - x4));
+    const double l4 = -(x0 * x1 * x3) / ((x4 - x0) * (x4 - x1) * x4 * (x4 - x3));
+    return Q0 * l0 + Q1 * l1 + Q3 * l3 + Q4 * l4;
+}
+
 // SITE tells the two solves apart in profiles (0 riem_solver_c, 1 riem_solver3);
 // OFFC: off-centred solve (beta < 1), a separate instantiation so that the
-// backward-Euler passes keep their registers
-template <class B, class TW, int PASS, int SITE, bool OFFC = false>
+// backward-Euler passes keep their registers; PPO: interface perturbation
+// (2 mass-linear, 4 cubic where two layers lie on each side; pass 1 only)
+template <class B, class TW, int PASS, int SITE, bool OFFC = false, int PPO = 2>
 DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi,
                                               const B *theta, const double *delz, const TW *w,
                                               const double *phis, double *cpv, double *dpv,
@@ -852,7 +869,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     (void)rgam;
 
     // ---- pass 1: top-down elimination; step k consumes layer k + 1
-    if constexpr (PASS == 1) {
+    if constexpr (PASS == 1 && PPO == 2) {
     double lpi_k = log(ptop);
     double dp0 = (double)dpi[base], th0 = (double)theta[base], h0 = -delz[base], w0 = (double)w[base];
     double pi_k1 = ptop + dp0, lpi_k1 = log(pi_k1);
@@ -924,6 +941,103 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                     dprev = dk;
                     wprev = w0;
                     pi_k1 = pi_k2; lpi_k1 = lpi_k2; dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1; w0 = w1;
+                    pps_k = pps_k1; A_k = A_k1;
+                }
+            }
+            cur = nxt;
+        }
+    }
+    }
+    // ---- pass 1 with the cubic interface perturbation: step k consumes
+    // layer k + 2 (its equation of state), so that the perturbations of the
+    // layers k - 1 .. k + 2 around interface k + 1 are at hand
+    if constexpr (PASS == 1 && PPO == 4) {
+    const double bb = OFFC ? beta * beta : 1.0, ex = (1.0 - beta) / beta;
+    double dp0 = (double)dpi[base], th0 = (double)theta[base], h0 = -delz[base], w0 = (double)w[base];
+    double pi1 = ptop + dp0, lpi1 = log(pi1);
+    double m0 = dp0 / GRAV;
+    double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi1 - log(ptop));
+    double dp1 = 0.0, h1 = 0.0, w1 = 0.0, pp1 = 0.0, pi2 = 0.0, lpi2 = 0.0, m1 = 0.0;
+    if (nz > 1) {
+        const long o = base + lev;
+        dp1 = (double)dpi[o];
+        const double th1 = (double)theta[o];
+        h1 = -delz[o];
+        w1 = (double)w[o];
+        pi2 = pi1 + dp1;
+        lpi2 = log(pi2);
+        m1 = dp1 / GRAV;
+        pp1 = P_REF * exp(gam * log(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi2 - lpi1);
+    }
+    double dpm = 0.0, ppm = 0.0;   // layer k - 1
+    double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0, wprev = 0.0;
+    {
+        G4 cur, nxt;
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            int kk = 2 + u;
+            long o = base + (long)kk * lev;
+            bool in = kk < nz;
+            cur.a[u] = in ? (double)dpi[o] : 0.0;
+            cur.b[u] = in ? (double)theta[o] : 0.0;
+            cur.c[u] = in ? -delz[o] : 0.0;
+            cur.d[u] = in ? (double)w[o] : 0.0;
+        }
+        for (int k0 = 0; k0 < nz; k0 += SU) {
+            if (k0 + SU < nz) {
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    int kk = k0 + SU + 2 + u;
+                    long o = base + (long)kk * lev;
+                    bool in = kk < nz;
+                    nxt.a[u] = in ? (double)dpi[o] : 0.0;
+                    nxt.b[u] = in ? (double)theta[o] : 0.0;
+                    nxt.c[u] = in ? -delz[o] : 0.0;
+                    nxt.d[u] = in ? (double)w[o] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                int k = k0 + u;
+                if (k < nz) {
+                    const double dp2 = cur.a[u], th2 = cur.b[u], h2 = cur.c[u], w2 = cur.d[u];
+                    double pi3 = 0.0, lpi3 = 0.0, m2 = 0.0, pp2 = 0.0;
+                    if (k + 2 < nz) {
+                        pi3 = pi2 + dp2;
+                        lpi3 = log(pi3);
+                        m2 = dp2 / GRAV;
+                        pp2 = P_REF * exp(gam * log(RDGAS * th2 * m2 / (h2 * P_REF))) - dp2 / (lpi3 - lpi2);
+                    }
+                    double pps_k1, A_k1;
+                    if (k < nz - 1) {
+                        if (k >= 1 && k <= nz - 3) pps_k1 = cubic_iface(dpm, dp0, dp1, dp2, ppm, pp0, pp1, pp2);
+                        else pps_k1 = (dp1 * pp0 + dp0 * pp1) / (dp0 + dp1);
+                        A_k1 = bb * gam * (pi1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
+                    } else {
+                        pps_k1 = pp0;
+                        A_k1 = bb * gam * (pi1 + pps_k1) * dt2x / (0.5 * h0);
+                    }
+                    double lower = k > 0 ? -A_k : 0.0;
+                    double diag = m0 + A_k + A_k1;
+                    double upper = k < nz - 1 ? -A_k1 : 0.0;
+                    double rhs = m0 * w0 + dt * (pps_k1 - pps_k);
+                    if constexpr (OFFC) {
+                        double wa = k > 0 ? wprev : 0.0, wb = k < nz - 1 ? w1 : 0.0;
+                        rhs -= ex * (A_k1 * (w0 - wb) - A_k * (wa - w0));
+                        pfull[basei + (long)(k + 1) * lev] = pps_k1;
+                    }
+                    double piv = diag - lower * cprev;
+                    double rpiv = 1.0 / piv;
+                    double ck = upper * rpiv;
+                    double dk = (rhs - lower * dprev) * rpiv;
+                    cpv[base + (long)k * lev] = ck;
+                    dpv[base + (long)k * lev] = dk;
+                    cprev = ck;
+                    dprev = dk;
+                    wprev = w0;
+                    dpm = dp0; ppm = pp0;
+                    dp0 = dp1; m0 = m1; h0 = h1; pp0 = pp1; w0 = w1; pi1 = pi2;
+                    dp1 = dp2; m1 = m2; h1 = h2; pp1 = pp2; w1 = w2; pi2 = pi3; lpi2 = lpi3;
                     pps_k = pps_k1; A_k = A_k1;
                 }
             }
@@ -1954,6 +2068,22 @@ static MetD metrics_d(const fv3_grid *g) { return metrics_b<double>(g); }
 // ====================================================================
 // Host orchestration of one call
 // ====================================================================
+// The first column-solve pass in the instantiation the grid's options ask
+// for: off-centring (beta < 1) and the cubic interface perturbation.
+template <class F>
+static void sim1_pass1(const fv3_grid *g, F &&launch)
+{
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    using P2 = std::integral_constant<int, 2>;
+    using P4 = std::integral_constant<int, 4>;
+    const bool offc = g->p.beta != 1.0, cubic = g->p.pp_order == 4;
+    if (offc && cubic) launch(T_{}, P4{});
+    else if (offc) launch(T_{}, P2{});
+    else if (cubic) launch(F_{}, P4{});
+    else launch(F_{}, P2{});
+}
+
 template <class B>
 static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_split, int stop_stage,
                              hipStream_t st)
@@ -2000,14 +2130,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         // dz_c + riem_solver_c on the half-step cells
         launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
                  (const B *)W.ay, W.delzc);
-        if (g->p.beta != 1.0)
-            launch2d_fn<k_sim1<B, B, 1, 0, true>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
-                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        else
-            launch2d_fn<k_sim1<B, B, 1, 0>>("k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
-                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        sim1_pass1(g, [&](auto offc, auto ppo) {
+            launch2d_fn<k_sim1<B, B, 1, 0, decltype(offc)::value, decltype(ppo)::value>>(
+                "k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
+                (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
+                (double *)nullptr, W.pkc, W.gz, 1);
+        });
         launch2d_sh<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
@@ -2073,14 +2201,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         STOP(7);
         // riem_solver3
-        if (g->p.beta != 1.0)
-            launch2d_fn<k_sim1<B, B, 1, 1, true>>("k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
-                       s->pfull, s->phi, 0);
-        else
-            launch2d_fn<k_sim1<B, B, 1, 1>>("k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
-                       s->pfull, s->phi, 0);
+        sim1_pass1(g, [&](auto offc, auto ppo) {
+            launch2d_fn<k_sim1<B, B, 1, 1, decltype(offc)::value, decltype(ppo)::value>>(
+                "k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
+                (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz, s->pfull,
+                s->phi, 0);
+        });
         launch2d_fn<k_sim1<B, B, 2, 1>>("k_sim1_3.p2", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);

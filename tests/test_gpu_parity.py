@@ -405,17 +405,54 @@ def test_ppm_order_mixed_cube(fv3, orc, hord):
 
 
 def test_ppm_order_abi(fv3):
-    """hord 7 is a tracer order only; unknown orders are rejected."""
+    """hord 7 is a tracer order only; unknown PPM orders and interface orders
+    are rejected."""
     import ctypes as C
 
     base = dict(kind=0, n=16, nz=2, dx=1000.0, f0=0.0, radius=1.0, omega=0.0, ptop=100.0,
                 precision=0, hord=8, d2_bg=0.0, beta=1.0, dddmp=0.0, hord_tr=0, device=0)
-    for hord, hord_tr, want in ((7, 0, -8), (4, 0, -8), (8, 9, -8), (8, 4, -8), (5, 7, 0), (6, 5, 0)):
-        p = fv3.GridParams(**dict(base, hord=hord, hord_tr=hord_tr))
+    for hord, hord_tr, ppo, want in ((7, 0, 2, -8), (4, 0, 2, -8), (8, 9, 2, -8), (8, 4, 2, -8), (5, 7, 2, 0),
+                                     (6, 5, 2, 0), (8, 0, 3, -8), (8, 0, 4, 0), (8, 0, 0, 0)):
+        p = fv3.GridParams(**dict(base, hord=hord, hord_tr=hord_tr, pp_order=ppo))
         h = C.c_void_p()
-        assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, (hord, hord_tr)
+        assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, (hord, hord_tr, ppo)
         if want == 0:
             fv3.lib().fv3_free_grid(h)
+
+
+@pytest.mark.parametrize("kind,n,nz,beta,stop,dt,ns,fields", [
+    (0, 24, 8, 1.0, 4, 0.4, 1, ("uc", "vc")),
+    (1, 12, 9, 1.0, 4, 300.0, 1, ("uc", "vc")),
+    (1, 12, 9, 1.0, 8, 300.0, 1, ("w", "delz", "pfull", "phi")),
+    (0, 48, 8, 1.0, 0, 2.0, 10, ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")),
+    (1, 24, 10, 1.0, 0, 2000.0, 10, ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")),
+    (1, 24, 10, 0.8, 0, 2000.0, 10, ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")),
+])
+def test_cubic_interface_parity(fv3, orc, kind, n, nz, beta, stop, dt, ns, fields):
+    """The cubic interface perturbation (pp_order 4) in both column solves
+    against the oracle: the C-grid winds after p_grad_c, the first output that
+    sees the C-grid solve (stage 4), the D-grid solve's outputs (stage 8; w at
+    the column-solve bar 1e-10), 10 substeps (1e-11), also off-centred.  The
+    oracle's own results differ from the mass-linear ones far above the bars."""
+    g = fv3.Grid(kind, n, nz, beta=beta, pp_order=4)
+    s = fv3.State.allocate(g)
+    init = fi.periodic_state(n=n, nz=nz) if kind == 0 else fi.cube_state(n=n, nz=nz)
+    s.load(init)
+    og = orc.Grid(kind, n, nz, beta=beta, pp_order=4)
+    os_ = orc.new_state(og, init)
+    label = f"pp4 kind{kind} beta{beta} stop{stop}"
+    print(label, flush=True)
+    fv3.acoustic_substeps(s, g, dt, ns, stop_stage=stop)
+    assert orc.acoustic_substeps(og, os_, dt, ns, stop_stage=stop) == 0
+    o2g = orc.Grid(kind, n, nz, beta=beta)
+    o2 = orc.new_state(o2g, init)
+    assert orc.acoustic_substeps(o2g, o2, dt, ns, stop_stage=stop) == 0
+    k0 = fields[0]
+    assert _relerr(_int(o2[k0], n, STAG[k0]), _int(os_[k0], n, STAG[k0])) > 1e3 * 1e-10, k0
+    if stop == 0:
+        assert fv3.check_status(g) == 0
+    tol = {k: (1e-10 if (k == "w" and stop == 8) else (1e-11 if stop == 0 else 1e-13)) for k in fields}
+    _compare(s, os_, n, fields, tol, label)
 
 
 def test_cfl_flag_latched(fv3):
