@@ -77,7 +77,7 @@ def lib():
         L.orc_sim1.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double] + [dp] * 8
         L.orc_pgf.restype = C.c_double
         L.orc_pgf.argtypes = [C.c_double] * 12
-        L.orc_acoustic_substeps.argtypes = [C.c_void_p] + [dp] * 16 + [C.c_double, C.c_int,
+        L.orc_acoustic_substeps.argtypes = [C.c_void_p] + [dp] * 17 + [C.c_double, C.c_int,
                                                                       C.c_int, C.POINTER(dp)]
         L.orc_tracer_transport.argtypes = [C.c_void_p, C.POINTER(dp), C.c_int] + [dp] * 5 + [
             C.c_int, C.POINTER(C.c_int)]
@@ -238,6 +238,8 @@ def new_state(g: Grid, init: dict) -> dict:
     s["pfull"] = g.field(g.nz + 1)
     s["phi"] = g.field(g.nz + 1)
     s["phis"] = np.ascontiguousarray(init.get("phis", np.zeros((g.T, g.N, g.N))), dtype=np.float64)
+    # specific humidity (moist column solves) or None (dry)
+    s["qv"] = np.ascontiguousarray(init["qv"], dtype=np.float64).copy() if init.get("qv") is not None else None
     return s
 
 
@@ -252,7 +254,7 @@ def acoustic_substeps(g: Grid, s: dict, dt: float, n_split: int, stop_stage: int
         dbg = {k: g.field(g.nz + (1 if k in ("pkc", "gz") else 0)) for k in DEBUG_FIELDS}
         dbg_arr = (C.POINTER(C.c_double) * len(DEBUG_FIELDS))(*[_p(dbg[k]) for k in DEBUG_FIELDS])
     st = lib().orc_acoustic_substeps(g._h, *[_p(s[k]) for k in STATE_FIELDS], _p(s["phis"]),
-                                     float(dt), int(n_split), int(stop_stage), dbg_arr)
+                                     _p(s.get("qv")), float(dt), int(n_split), int(stop_stage), dbg_arr)
     return (st, dbg) if debug else st
 
 

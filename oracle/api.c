@@ -154,10 +154,10 @@ double orc_pgf(double dt, double L, double dpiW, double dpiE, double phW0, doubl
 int orc_acoustic_substeps(void *gp, double *u, double *v, double *w, double *delp, double *pt,
                           double *delz, double *uc, double *vc, double *mfx, double *mfy,
                           double *cx, double *cy, double *dp0, double *pfull, double *phi,
-                          const double *phis, double dt, int n_split, int stop_stage,
+                          const double *phis, double *qv, double dt, int n_split, int stop_stage,
                           double **dbg)
 {
-    OState s = {u, v, w, delp, pt, delz, uc, vc, mfx, mfy, cx, cy, dp0, pfull, phi, phis};
+    OState s = {u, v, w, delp, pt, delz, uc, vc, mfx, mfy, cx, cy, dp0, pfull, phi, phis, qv};
     if (n_split < 1 || !(dt > 0)) return -1;
     return orc_substeps_impl((OGrid *)gp, &s, dt, n_split, stop_stage, dbg);
 }

@@ -213,10 +213,16 @@ static void heights(const OGrid *g, int t, const double *delz, const double *zs,
  * The semi-implicit column solve over dt/2 then gives the half-step interface
  * pressure and geopotential used by the C-grid pressure gradient.
  */
+/* virtual potential temperature factor 1 + (Rv/Rd - 1) q of a layer */
+static double o_virt(const double *qv, size_t idx)
+{
+    return qv ? 1.0 + (O_RVGAS / O_RDGAS - 1.0) * qv[idx] : 1.0;
+}
+
 static void dzc_riemc_tile(const OGrid *g, int t, double dt2, const double *delz,
                            const double *zs, const double *ax, const double *ay,
                            const double *delpc, const double *ptc, const double *wc,
-                           double *pkc, double *gz)
+                           const double *qv, double *pkc, double *gz)
 {
     int n = g->n, nz = g->nz;
     size_t P = o_plane(g), o = (size_t)t * P;
@@ -253,7 +259,7 @@ static void dzc_riemc_tile(const OGrid *g, int t, double dt2, const double *delz
             for (int k = 0; k < nz; k++) {
                 col_z[k] = zc[k + 1] - zc[k];
                 col_d[k] = PL(delpc, t, k, nz)[c];
-                col_t[k] = PL(ptc, t, k, nz)[c];
+                col_t[k] = PL(ptc, t, k, nz)[c] * o_virt(qv, (size_t)(t * nz + k) * P + c);
                 col_w[k] = PL(wc, t, k, nz)[c];
             }
             o_sim1b(nz, dt2, g->beta, g->pp_order, g->ptop, zs[c], col_d, col_t, col_z, col_w, wo, dzo, pf, ph, 0, 0);
@@ -677,6 +683,8 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
 
     for (size_t q = 0; q < (size_t)T * P; q++) zs[q] = s->phis ? s->phis[q] / O_GRAV : 0.0;
     og_fill_scalar(g, zs, 1, ST_C, 0);
+    /* humidity is constant over the call: its halo once */
+    if (s->qv) og_fill_scalar(g, s->qv, nz, ST_C, 0);
     /* accumulators restart with every call; delp at entry is kept */
     memset(s->mfx, 0, F3 * sizeof(double));
     memset(s->mfy, 0, F3 * sizeof(double));
@@ -704,7 +712,7 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
         STOP(2);
 #pragma omp parallel for schedule(dynamic)
         for (int t = 0; t < T; t++)
-            dzc_riemc_tile(g, t, dt2, s->delz, zs + (size_t)t * P, ax, ay, delpc, ptc, wc, pkc, gz);
+            dzc_riemc_tile(g, t, dt2, s->delz, zs + (size_t)t * P, ax, ay, delpc, ptc, wc, s->qv, pkc, gz);
         STOP(3);
 #pragma omp parallel for collapse(2) schedule(dynamic)
         for (int t = 0; t < T; t++)
@@ -738,7 +746,7 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
                     size_t c = IX(g, i, j);
                     for (int k = 0; k < nz; k++) {
                         cd[k] = PL(s->delp, t, k, nz)[c];
-                        ct[k] = PL(s->pt, t, k, nz)[c];
+                        ct[k] = PL(s->pt, t, k, nz)[c] * o_virt(s->qv, (size_t)(t * nz + k) * P + c);
                         cz[k] = PL(s->delz, t, k, nz)[c];
                         cw[k] = PL(s->w, t, k, nz)[c];
                     }

@@ -37,6 +37,7 @@ enum { PAIR_SIGNED = 0, PAIR_ABS = 1, PAIR_COS = 2 };
 #define O_RDGAS 287.05
 #define O_CP 1004.6
 #define O_P0 1.0e5
+#define O_RVGAS 461.5
 
 typedef struct {
     int kind;              /* 0 doubly periodic, 1 cubed sphere */
@@ -74,6 +75,7 @@ static inline size_t o_plane(const OGrid *g) { return (size_t)g->N * g->N; }
 typedef struct {
     double *u, *v, *w, *delp, *pt, *delz, *uc, *vc, *mfx, *mfy, *cx, *cy, *dp0, *pfull, *phi;
     const double *phis;
+    double *qv;   /* specific humidity (cell field) or NULL: dry */
 } OState;
 
 /* grid.c */
