@@ -156,6 +156,9 @@ def run_precision(fv3, torch, init, args, precision):
                  hord=args.hord, hord_tr=args.hord_tr, pp_order=args.pp_order)
     s = fv3.State.allocate(g)
     s.load(init)
+    if args.moist:
+        # humidity for the moist column solves: 0.02 x the first tracer (U[0, 1])
+        s.set_humidity(0.02 * init["q"][0])
     qs = [g.upload(q, nz) for q in init["q"]]
     stream = torch.cuda.current_stream()
 
@@ -385,6 +388,8 @@ def main():
                     help="tracer PPM order (0: as --hord; 7 positive-definite)")
     ap.add_argument("--pp-order", type=int, default=2, choices=[2, 4],
                     help="interface pressure perturbation of the column solves: 2 mass-linear, 4 cubic")
+    ap.add_argument("--moist", action="store_true",
+                    help="moist column solves with humidity 0.02 x the first tracer")
     ap.add_argument("--d2-bg", type=float, default=0.0, help="del-2 divergence damping (0 .. 0.25)")
     ap.add_argument("--dddmp", type=float, default=0.0, help="Smagorinsky divergence damping (0 .. 1)")
     args = ap.parse_args()
@@ -438,7 +443,7 @@ def main():
                                f"substeps of {args.bdt:g} s + 4-tracer transport + mass sums per step",
                    "precision": args.precision, "n_split": args.n_split, "cells": cells, "beta": args.beta,
                    "d2_bg": args.d2_bg, "dddmp": args.dddmp, "hord": args.hord,
-                   "hord_tr": args.hord_tr, "pp_order": args.pp_order,
+                   "hord_tr": args.hord_tr, "pp_order": args.pp_order, "moist": args.moist,
                    "ms_per_substep": main_res["ms_per_substep"],
                    "device_status": main_res["device_status"]},
         "roofline": main_res["roofline"],

@@ -135,6 +135,10 @@ typedef struct {
     const double *phis;              /* surface geopotential (2-D) or NULL = flat   */
     void *workspace;
     size_t workspace_bytes;
+    void *qv;                        /* specific humidity [kg/kg] (bulk precision,
+                                        cell field) or NULL = dry: the column
+                                        solves take theta (1 + (Rv/Rd - 1) qv);
+                                        read only, its halo filled at entry    */
 } fv3_state;
 
 /* Build a grid on `p->device`: geometry and metric terms (FP64 on the host),

@@ -73,7 +73,8 @@ class FeatureNorm(C.Structure):
 class StateStruct(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx",
                                           "mfy", "cx", "cy", "dp0", "pfull", "phi", "phis",
-                                          "workspace")] + [("workspace_bytes", C.c_size_t)]
+                                          "workspace")] + [("workspace_bytes", C.c_size_t),
+                                                           ("qv", C.c_void_p)]
 
 
 _lib = None
@@ -273,6 +274,18 @@ class State:
         if "phis" in init:
             g.view(self.f["phis"], 1).copy_(_torch().from_numpy(
                 np.ascontiguousarray(init["phis"]).reshape(g.T, 1, g.N, g.N)))
+        self.set_humidity(init.get("qv"))
+
+    def set_humidity(self, qv) -> None:
+        """Specific humidity for the moist column solves (numpy array in the
+        state's field shape, bulk precision on the device), or None: dry."""
+        g = self.grid
+        if qv is None:
+            self.f.pop("qv", None)
+            return
+        if "qv" not in self.f:
+            self.f["qv"] = g.new_field(g.nz)
+        g.view(self.f["qv"], g.nz).copy_(_torch().from_numpy(np.ascontiguousarray(qv)).to(self.f["qv"].dtype))
 
     def get(self, name: str) -> np.ndarray:
         L = self.grid.nz + 1 if name in IFACE_F64 else self.grid.nz
@@ -284,6 +297,7 @@ class State:
                   "dp0", "pfull", "phi", "phis", "workspace"):
             setattr(s, k, self.f[k].data_ptr())
         s.workspace_bytes = self.f["workspace"].numel()
+        s.qv = self.f["qv"].data_ptr() if "qv" in self.f else None
         return s
 
 

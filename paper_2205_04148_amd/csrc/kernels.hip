@@ -819,6 +819,16 @@ DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, co
 constexpr int SU = FV3_SIM1_SU;   // levels per prefetch group, passes 1 and 3
 constexpr int SU2 = 8;            // levels per prefetch group, passes 2 and 4
 
+// Moist column solves: the equation of state takes the virtual potential
+// temperature theta (1 + (Rv/Rd - 1) q), q the specific humidity (none: dry).
+constexpr double RVGAS = 461.5;
+constexpr double EPSV = RVGAS / RDGAS - 1.0;
+template <class B>
+DEVI double virt(const B *qv, long o)
+{
+    return qv ? 1.0 + EPSV * (double)qv[o] : 1.0;
+}
+
 // Interface value at x = 0 of the cubic whose means over four consecutive
 // layers of thicknesses da, db | dc, dd (the interface between db and dc)
 // are qa, qb | qc, qd: the derivative at the middle node of the quartic
@@ -841,7 +851,7 @@ DEVI double cubic_iface(double da, double db, double dc, double dd, double qa, d
 // (2 mass-linear, 4 cubic where two layers lie on each side; pass 1 only)
 template <class B, class TW, int PASS, int SITE, bool OFFC = false, int PPO = 2>
 DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi,
-                                              const B *theta, const double *delz, const TW *w,
+                                              const B *theta, const B *qv, const double *delz, const TW *w,
                                               const double *phis, double *cpv, double *dpv,
                                               double *wnv, TW *w_out, double *delz_out,
                                               double *pfull, double *phi, int need_cross)
@@ -860,7 +870,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     // of every input are in flight per thread (the column recurrences are
     // sequential; this is what hides HBM latency).
     struct G4 {
-        double a[SU], b[SU], c[SU], d[SU];
+        double a[SU], b[SU], c[SU], d[SU], e[SU];   // e: humidity of the layer (0 when dry)
     };
     struct G2 {
         double a[SU2], b[SU2];
@@ -871,7 +881,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     // ---- pass 1: top-down elimination; step k consumes layer k + 1
     if constexpr (PASS == 1 && PPO == 2) {
     double lpi_k = log(ptop);
-    double dp0 = (double)dpi[base], th0 = (double)theta[base], h0 = -delz[base], w0 = (double)w[base];
+    double dp0 = (double)dpi[base], th0 = (double)theta[base] * virt(qv, base), h0 = -delz[base], w0 = (double)w[base];
     double pi_k1 = ptop + dp0, lpi_k1 = log(pi_k1);
     double m0 = dp0 / GRAV;
     double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi_k1 - lpi_k);
@@ -889,6 +899,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
             bool in = kk < nz;
             cur.a[u] = in ? (double)dpi[o] : 0.0;
             cur.b[u] = in ? (double)theta[o] : 0.0;
+            cur.e[u] = (in && qv) ? (double)qv[o] : 0.0;
             cur.c[u] = in ? -delz[o] : 0.0;
             cur.d[u] = in ? (double)w[o] : 0.0;
         }
@@ -901,6 +912,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                     bool in = kk < nz;
                     nxt.a[u] = in ? (double)dpi[o] : 0.0;
                     nxt.b[u] = in ? (double)theta[o] : 0.0;
+                    nxt.e[u] = (in && qv) ? (double)qv[o] : 0.0;
                     nxt.c[u] = in ? -delz[o] : 0.0;
                     nxt.d[u] = in ? (double)w[o] : 0.0;
                 }
@@ -909,7 +921,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
             for (int u = 0; u < SU; u++) {
                 int k = k0 + u;
                 if (k < nz) {
-                    double dp1 = cur.a[u], th1 = cur.b[u], h1 = cur.c[u], w1 = cur.d[u];
+                    double dp1 = cur.a[u], th1 = cur.b[u] * (1.0 + EPSV * cur.e[u]), h1 = cur.c[u], w1 = cur.d[u];
                     double pps_k1, A_k1, pi_k2 = 0, lpi_k2 = 0, m1 = 0, pp1 = 0;
                     if (k < nz - 1) {
                         pi_k2 = pi_k1 + dp1;
@@ -953,7 +965,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     // layers k - 1 .. k + 2 around interface k + 1 are at hand
     if constexpr (PASS == 1 && PPO == 4) {
     const double bb = OFFC ? beta * beta : 1.0, ex = (1.0 - beta) / beta;
-    double dp0 = (double)dpi[base], th0 = (double)theta[base], h0 = -delz[base], w0 = (double)w[base];
+    double dp0 = (double)dpi[base], th0 = (double)theta[base] * virt(qv, base), h0 = -delz[base], w0 = (double)w[base];
     double pi1 = ptop + dp0, lpi1 = log(pi1);
     double m0 = dp0 / GRAV;
     double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi1 - log(ptop));
@@ -961,7 +973,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     if (nz > 1) {
         const long o = base + lev;
         dp1 = (double)dpi[o];
-        const double th1 = (double)theta[o];
+        const double th1 = (double)theta[o] * virt(qv, o);
         h1 = -delz[o];
         w1 = (double)w[o];
         pi2 = pi1 + dp1;
@@ -980,6 +992,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
             bool in = kk < nz;
             cur.a[u] = in ? (double)dpi[o] : 0.0;
             cur.b[u] = in ? (double)theta[o] : 0.0;
+            cur.e[u] = (in && qv) ? (double)qv[o] : 0.0;
             cur.c[u] = in ? -delz[o] : 0.0;
             cur.d[u] = in ? (double)w[o] : 0.0;
         }
@@ -992,6 +1005,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                     bool in = kk < nz;
                     nxt.a[u] = in ? (double)dpi[o] : 0.0;
                     nxt.b[u] = in ? (double)theta[o] : 0.0;
+                    nxt.e[u] = (in && qv) ? (double)qv[o] : 0.0;
                     nxt.c[u] = in ? -delz[o] : 0.0;
                     nxt.d[u] = in ? (double)w[o] : 0.0;
                 }
@@ -1000,7 +1014,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
             for (int u = 0; u < SU; u++) {
                 int k = k0 + u;
                 if (k < nz) {
-                    const double dp2 = cur.a[u], th2 = cur.b[u], h2 = cur.c[u], w2 = cur.d[u];
+                    const double dp2 = cur.a[u], th2 = cur.b[u] * (1.0 + EPSV * cur.e[u]), h2 = cur.c[u], w2 = cur.d[u];
                     double pi3 = 0.0, lpi3 = 0.0, m2 = 0.0, pp2 = 0.0;
                     if (k + 2 < nz) {
                         pi3 = pi2 + dp2;
@@ -1090,6 +1104,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
             bool in = kk < nz;
             cur.a[u] = in ? (double)dpi[o] : 0.0;
             cur.b[u] = in ? (double)theta[o] : 0.0;
+            cur.e[u] = (in && qv) ? (double)qv[o] : 0.0;
             cur.c[u] = in ? wnv[o] : 0.0;
             cur.d[u] = in ? (double)w[o] : 0.0;
         }
@@ -1102,6 +1117,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                     bool in = kk < nz;
                     nxt.a[u] = in ? (double)dpi[o] : 0.0;
                     nxt.b[u] = in ? (double)theta[o] : 0.0;
+                    nxt.e[u] = (in && qv) ? (double)qv[o] : 0.0;
                     nxt.c[u] = in ? wnv[o] : 0.0;
                     nxt.d[u] = in ? (double)w[o] : 0.0;
                 }
@@ -1110,7 +1126,7 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
             for (int u = 0; u < SU; u++) {
                 int k = k0 + u;
                 if (k < nz) {
-                    double dp = cur.a[u], th = cur.b[u], wk = cur.c[u], wo = cur.d[u];
+                    double dp = cur.a[u], th = cur.b[u] * (1.0 + EPSV * cur.e[u]), wk = cur.c[u], wo = cur.d[u];
                     double m = dp / GRAV;
                     double pik1 = pik + dp, lpik1 = log(pik1);
                     double pib = dp / (lpik1 - lpik);
@@ -2101,7 +2117,10 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
     const double *phis = s->phis;
     double bdt = dt / n_split, dt2 = 0.5 * bdt;
     const B *areaB = M.m[M_AREA];
+    const B *qvp = (const B *)s->qv;
 
+    // humidity is constant over the call: its halo once
+    if (qvp) halo_set<B>(g, FieldSet<B>{{(B *)s->qv, nullptr, nullptr, nullptr}}, 1, nz, st);
     fill(s->mfx, el, 0.0, st);
     fill(s->mfy, el, 0.0, st);
     fill(cx, el, (B)0, st);
@@ -2133,22 +2152,22 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         sim1_pass1(g, [&](auto offc, auto ppo) {
             launch2d_fn<k_sim1<B, B, 1, 0, decltype(offc)::value, decltype(ppo)::value>>(
                 "k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
+                (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
                 (double *)nullptr, W.pkc, W.gz, 1);
         });
         launch2d_sh<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         if (g->p.beta != 1.0)
             launch2d_fn<k_sim1<B, B, 3, 0, true>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         else
             launch2d_fn<k_sim1<B, B, 3, 0>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         launch2d_sh<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
+                       (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         STOP(3);
         launch2d_s(k_pgradc<B>, (Shape{32, 8}), 0, n, 0, n, P, st, G, Md, dt2, (const B *)W.delpc, (const double *)W.pkc,
@@ -2204,22 +2223,22 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         sim1_pass1(g, [&](auto offc, auto ppo) {
             launch2d_fn<k_sim1<B, B, 1, 1, decltype(offc)::value, decltype(ppo)::value>>(
                 "k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz, s->pfull,
+                (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz, s->pfull,
                 s->phi, 0);
         });
         launch2d_fn<k_sim1<B, B, 2, 1>>("k_sim1_3.p2", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
         if (g->p.beta != 1.0)
             launch2d_fn<k_sim1<B, B, 3, 1, true>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
         else
             launch2d_fn<k_sim1<B, B, 3, 1>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
         launch2d_fn<k_sim1<B, B, 4, 1>>("k_sim1_3.p4", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
+                       (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
         STOP(8);
         // H-C
