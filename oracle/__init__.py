@@ -61,6 +61,9 @@ def lib():
         L.orc_sim1b.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double] + [dp] * 10
         L.orc_pp_interfaces.argtypes = [C.c_int, C.c_int, dp, dp, dp]
         L.orc_set_pp_order.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_damp4.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_corner_div.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        L.orc_corner_lap.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_grid_conn.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_halo_fill.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, C.c_int]
@@ -108,11 +111,13 @@ class Grid:
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
                  d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
-                 hord_tr: int = 0, pp_order: int = 2):
+                 hord_tr: int = 0, pp_order: int = 2, nord: int = 0, d4_bg: float = 0.0):
         if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
             raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
         if pp_order not in (2, 4):
             raise ValueError("pp_order must be 2 or 4")
+        if nord not in (0, 1, 2):
+            raise ValueError("nord must be 0, 1 or 2")
         err = C.create_string_buffer(256)
         h = lib().orc_grid_new(kind, n, nz, delta, f0, radius, omega, ptop, err, 256)
         if not h:
@@ -128,6 +133,8 @@ class Grid:
         lib().orc_set_hord(h, int(hord), int(hord_tr))
         self.pp_order = pp_order
         lib().orc_set_pp_order(h, int(pp_order))
+        self.nord, self.d4_bg = nord, d4_bg
+        lib().orc_set_damp4(h, int(nord), float(d4_bg))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -323,3 +330,20 @@ def mass_sums(g: Grid, delp, pt, qs=()) -> np.ndarray:
     arr = (C.POINTER(C.c_double) * max(1, len(qs)))(*[_p(q) for q in qs])
     lib().orc_mass_sums(g._h, _p(delp), _p(pt), arr, len(qs), _p(out))
     return out
+
+
+def corner_div(g: "Grid", U, V) -> np.ndarray:
+    """Corner divergence of D-grid fields U (y-faces), V (x-faces) of shape (T, L, N, N)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    out = np.zeros_like(U)
+    lib().orc_corner_div(g._h, U.shape[1], _p(U), _p(V), _p(out))
+    return out
+
+
+def corner_lap(g: "Grid", D) -> np.ndarray:
+    """Corner Laplacian of a corner field (T, L, N, N); fills D's corner halo in place."""
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    out = np.zeros_like(D)
+    lib().orc_corner_lap(g._h, D.shape[1], _p(D), _p(out))
+    return out, D

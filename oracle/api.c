@@ -41,6 +41,36 @@ void orc_set_damping(void *gp, double d2_bg)
 
 /* Smagorinsky coefficient of the divergence damping */
 void orc_set_smag(void *gp, double dddmp) { ((OGrid *)gp)->dddmp = dddmp; }
+void orc_set_damp4(void *gp, int nord, double d4_bg)
+{
+    ((OGrid *)gp)->nord = nord;
+    ((OGrid *)gp)->d4_bg = d4_bg;
+}
+
+/* corner divergence / Laplacian of whole fields (all tiles, nlev planes);
+ * the Laplacian fills the corner halo of its input first */
+void orc_corner_div(void *gp, int nlev, const double *U, const double *V, double *out)
+{
+    const OGrid *g = (const OGrid *)gp;
+    size_t P = o_plane(g);
+    for (int t = 0; t < g->T; t++)
+        for (int k = 0; k < nlev; k++) {
+            size_t q = ((size_t)t * nlev + k) * P;
+            o_corner_div(g, t, U + q, V + q, out + q);
+        }
+}
+
+void orc_corner_lap(void *gp, int nlev, double *D, double *out)
+{
+    const OGrid *g = (const OGrid *)gp;
+    size_t P = o_plane(g);
+    og_fill_scalar(g, D, nlev, ST_B, 0);
+    for (int t = 0; t < g->T; t++)
+        for (int k = 0; k < nlev; k++) {
+            size_t q = ((size_t)t * nlev + k) * P;
+            o_corner_lap(g, t, D + q, out + q);
+        }
+}
 
 /* Smagorinsky magnitude of one level (oracle plane layout, halos filled) */
 void orc_smag_corner(void *gp, int t, const double *u, const double *v, double dt, double *out)

@@ -359,10 +359,56 @@ void o_smag_corner(const OGrid *g, int t, const double *u, const double *v, doub
     free(shear);
 }
 
+/* Divergence at the corners 0..n of a D-grid pair (U on y-faces, V on
+ * x-faces) over each corner's dual cell: normal components through its four
+ * edges times their lengths over the dual area; at a cube vertex the two
+ * edges next to the missing cell count half. */
+void o_corner_div(const OGrid *g, int t, const double *U, const double *V, double *out)
+{
+    int n = g->n;
+    size_t o = (size_t)t * o_plane(g);
+    const double *dxc = g->dxc + o, *dyc = g->dyc + o, *area_c = g->area_c + o;
+    for (int j = 0; j <= n; j++)
+        for (int i = 0; i <= n; i++) {
+            size_t b = IX(g, i, j);
+            double ws = 1.0, wn = 1.0, ww = 1.0, we = 1.0;
+            if (og_is_vertex(g, i, j)) {
+                if (j == 0) ws = 0.5; else wn = 0.5;
+                if (i == 0) ww = 0.5; else we = 0.5;
+            }
+            out[b] = (we * U[b] * dyc[b] - ww * U[IX(g, i - 1, j)] * dyc[IX(g, i - 1, j)] +
+                      wn * V[b] * dxc[b] - ws * V[IX(g, i, j - 1)] * dxc[IX(g, i, j - 1)]) / area_c[b];
+        }
+}
+
+/* Corner Laplacian of a corner field D (its halo filled): the corner
+ * divergence of its gradient along the cell edges, (D(i+1,j) - D(i,j)) / dx
+ * on y-faces and (D(i,j+1) - D(i,j)) / dy on x-faces. */
+void o_corner_lap(const OGrid *g, int t, const double *D, double *out)
+{
+    int n = g->n;
+    size_t P = o_plane(g), o = (size_t)t * P;
+    const double *dx = g->dx + o, *dy = g->dy + o;
+    double *GU = (double *)calloc(P, sizeof(double)), *GV = (double *)calloc(P, sizeof(double));
+    for (int j = 0; j <= n; j++)
+        for (int i = -1; i <= n; i++) {
+            size_t f = IX(g, i, j);
+            GU[f] = (D[IX(g, i + 1, j)] - D[f]) / dx[f];
+        }
+    for (int j = -1; j <= n; j++)
+        for (int i = 0; i <= n; i++) {
+            size_t f = IX(g, i, j);
+            GV[f] = (D[IX(g, i, j + 1)] - D[f]) / dy[f];
+        }
+    o_corner_div(g, t, GU, GV, out);
+    free(GU);
+    free(GV);
+}
+
 static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, double *v,
                        const double *uc, const double *vc, double *delp, double *pt, double *w,
                        double *mfx, double *mfy, double *cx, double *cy, double *crx,
-                       double *cry, double *xfx, double *yfx, int *cfl)
+                       double *cry, double *xfx, double *yfx, const double *hd, int *cfl)
 {
     int n = g->n;
     size_t P = o_plane(g), o = (size_t)t * P;
@@ -497,6 +543,17 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
                 ke[b] -= nu * flux / area_c[b];
             }
         free(smag);
+    }
+    /* (v'') optional higher-order divergence damping: hd holds the corner
+     * divergence with nord corner Laplacians applied; (-1)^(nord+1) nu_n hd is
+     * added to the kinetic energy, nu_n = (d4_bg da_min)^(nord+1), so that the
+     * divergence obeys dD/dt = (-1)^nord nu_n Lap^(nord+1) D (del-4: nord = 1,
+     * del-6: nord = 2) */
+    if (hd) {
+        double nun = pow(g->d4_bg * g->da_min, g->nord + 1);
+        double sg = (g->nord % 2) ? 1.0 : -1.0;
+        for (int j = 0; j <= n; j++)
+            for (int i = 0; i <= n; i++) ke[IX(g, i, j)] += sg * nun * hd[IX(g, i, j)];
     }
     /* (vi) absolute vorticity at cells and its transport */
     for (int j = -3; j <= n + 2; j++)
@@ -680,6 +737,11 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
            *yfx = dalloc(F3), *pkc = dalloc(F3i), *gz = dalloc(F3i);
     double *zs = dalloc((size_t)T * P);
     int cfl = 0, status = ORC_OK;
+    double *hd = NULL, *hd2 = NULL;
+    if (g->nord > 0 && g->d4_bg > 0.0) {
+        hd = dalloc(F3);
+        hd2 = dalloc(F3);
+    }
 
     for (size_t q = 0; q < (size_t)T * P; q++) zs[q] = s->phis ? s->phis[q] / O_GRAV : 0.0;
     og_fill_scalar(g, zs, 1, ST_C, 0);
@@ -720,6 +782,21 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
         STOP(4);
         og_fill_pair(g, s->uc, ST_X, s->vc, ST_Y, nz, PAIR_SIGNED);
         STOP(5);
+        if (hd) {
+            /* corner divergence of the D-grid winds, then nord corner
+             * Laplacians, each after a fill of the corner halo */
+#pragma omp parallel for collapse(2)
+            for (int t = 0; t < T; t++)
+                for (int k = 0; k < nz; k++)
+                    o_corner_div(g, t, PL(s->u, t, k, nz), PL(s->v, t, k, nz), PL(hd, t, k, nz));
+            for (int r = 0; r < g->nord; r++) {
+                og_fill_scalar(g, hd, nz, ST_B, 0);
+#pragma omp parallel for collapse(2)
+                for (int t = 0; t < T; t++)
+                    for (int k = 0; k < nz; k++) o_corner_lap(g, t, PL(hd, t, k, nz), PL(hd2, t, k, nz));
+                double *sw = hd; hd = hd2; hd2 = sw;
+            }
+        }
 #pragma omp parallel for collapse(2) schedule(dynamic) reduction(| : cfl)
         for (int t = 0; t < T; t++)
             for (int k = 0; k < nz; k++) {
@@ -729,7 +806,7 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
                            PL(s->pt, t, k, nz), PL(s->w, t, k, nz), PL(s->mfx, t, k, nz),
                            PL(s->mfy, t, k, nz), PL(s->cx, t, k, nz), PL(s->cy, t, k, nz),
                            PL(crx, t, k, nz), PL(cry, t, k, nz), PL(xfx, t, k, nz),
-                           PL(yfx, t, k, nz), &c);
+                           PL(yfx, t, k, nz), hd ? PL(hd, t, k, nz) : NULL, &c);
                 cfl |= c;
             }
         STOP(6);
@@ -773,6 +850,8 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
 #undef STOP
     }
 done:
+    free(hd);
+    free(hd2);
     if (dbg) {
         double *src[] = {delpc, ptc, wc, ax, ay, crx, cry, xfx, yfx};
         for (int q = 0; q < 9; q++)

@@ -56,6 +56,9 @@ typedef struct {
     int hord, hord_tr;
     /* interface perturbation of the column solves: 2 mass-linear (default), 4 cubic */
     int pp_order;
+    /* higher-order divergence damping: order nord (1 del-4, 2 del-6, 0 off), coefficient d4_bg */
+    int nord;
+    double d4_bg;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -113,6 +116,8 @@ double o_sim1b(int nz, double dt, double beta, int pp_order, double ptop, double
                const double *theta, const double *delz, const double *w, double *w_out,
                double *delz_out, double *pfull, double *phi, double *pstar, double *coupling);
 void o_pp_interfaces(int nz, int order, const double *dpi, const double *pp, double *pps);
+void o_corner_div(const OGrid *g, int t, const double *U, const double *V, double *out);
+void o_corner_lap(const OGrid *g, int t, const double *D, double *out);
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
              double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
 
