@@ -81,7 +81,14 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * per corner to min(0.2, dddmp dt sqrt(DT^2 + DS^2)) where larger (the
  * Smagorinsky magnitude of the paper's Sec. VII-C case study; DT the tension
  * at the corner, DS the shear of its cells, dt the substep; it applies with
- * d2_bg = 0 too). */
+ * d2_bg = 0 too).  nord 1 or 2 with d4_bg in (0, 0.25] adds del-4 or del-6
+ * damping: the corner divergence D of the D-grid winds gets nord corner
+ * Laplacians (the same divergence operator applied to the gradient along
+ * the cell edges, corner halo exchanged before each), and (-1)^(nord+1) nu
+ * times the result is added to the kinetic energy, nu = (d4_bg x smallest
+ * dual-cell area)^(nord+1), so that dD/dt = (-1)^nord nu Lap^(nord+1) D
+ * (nord outside [0, 2]: FV3_EUNSUPPORTED; d4_bg outside [0, 0.25]:
+ * FV3_EINVAL). */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -96,6 +103,9 @@ typedef struct {
     int hord_tr;         /* tracer PPM order: 0 (= hord), 5, 6, 7, 8       */
     int pp_order;        /* interface p' of the column solves: 2 (or 0)
                             mass-linear, 4 cubic                          */
+    int nord;            /* higher-order divergence damping: 0 off,
+                            1 del-4, 2 del-6                              */
+    double d4_bg;        /* its coefficient, 0 .. 0.25                    */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

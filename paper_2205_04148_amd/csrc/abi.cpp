@@ -78,6 +78,9 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
         return fail(FV3_EUNSUPPORTED, "PPM order hord must be 8 (monotone), 6 (unlimited) or 5 (2dx-filtered)");
     if (p->hord_tr != 0 && p->hord_tr != 5 && p->hord_tr != 6 && p->hord_tr != 7 && p->hord_tr != 8)
         return fail(FV3_EUNSUPPORTED, "tracer PPM order hord_tr must be 0 (= hord), 5, 6, 7 or 8");
+    if (p->nord < 0 || p->nord > 2) return fail(FV3_EUNSUPPORTED, "nord must be 0, 1 (del-4) or 2 (del-6)");
+    if (!std::isfinite(p->d4_bg) || p->d4_bg < 0.0 || p->d4_bg > 0.25)
+        return fail(FV3_EINVAL, "d4_bg must be in [0, 0.25]");
     if (p->pp_order != 0 && p->pp_order != 2 && p->pp_order != 4)
         return fail(FV3_EUNSUPPORTED, "pp_order must be 2 (mass-linear; 0 means the same) or 4 (cubic)");
     if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))
@@ -123,6 +126,7 @@ fv3_status fv3_free_grid(fv3_grid *g)
     if (g->planD.d) (void)hipFree(g->planD.d);
     if (g->planCv.d) (void)hipFree(g->planCv.d);
     if (g->planA.d) (void)hipFree(g->planA.d);
+    if (g->planB.d) (void)hipFree(g->planB.d);
     if (g->flags) (void)hipFree(g->flags);
     if (g->red) (void)hipFree(g->red);
     delete g;

@@ -94,6 +94,7 @@ struct fv3_grid {
     float *metf[fv3::M_ALL] = {};             // device, FP32 copies (mixed precision)
     std::vector<double> hmet[fv3::M_ALL];     // host copies
     fv3::Plan planC, planD, planCv, planA;    // scalar, D-grid pair, C-grid pair, cell pair
+    fv3::Plan planB;                          // corner (B-grid) scalar
     int *flags = nullptr;                     // device error latch [3]: cfl, nonfinite, remap
     double *red = nullptr;                    // device reduction scratch
     long red_elems = 0;

@@ -418,8 +418,9 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
                     m = std::min(m, ac[g->off0 + (long)t * g->lev + (long)j * g->pitch + i]);
         g->da_min = m;
     }
-    std::vector<HaloEnt> pc, pd, pcv, pa;
+    std::vector<HaloEnt> pc, pd, pcv, pa, pb;
     make_plan(G, g, SC, SC, false, pc);
+    make_plan(G, g, SB, SB, false, pb);   // corner scalar
     make_plan(G, g, SC, SC, true, pa);    // cell-centred vector
     make_plan(G, g, SY, SX, true, pd);    // D grid: u (x comp) on y-faces, v on x-faces
     make_plan(G, g, SX, SY, true, pcv);   // C grid: uc on x-faces, vc on y-faces
@@ -432,6 +433,8 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
     g->planCv.count = (int)pcv.size();
     if ((s = upload(&g->planA.d, pa, err)) != FV3_OK) return s;
     g->planA.count = (int)pa.size();
+    if ((s = upload(&g->planB.d, pb, err)) != FV3_OK) return s;
+    g->planB.count = (int)pb.size();
     if (hipMalloc((void **)&g->flags, 4 * sizeof(int)) != hipSuccess) return FV3_ENOMEM;
     if (hipMemset(g->flags, 0, 4 * sizeof(int)) != hipSuccess) return FV3_EDEVICE;
     return FV3_OK;

@@ -476,6 +476,14 @@ static void halo_scalar(const fv3_grid *g, T *f, int L, hipStream_t st)
     launch_fn<k_halo_scalar<T>>("k_halo_scalar", dim3((g->planC.count + 255) / 256, L), dim3(256), st,
                  g->geo, (const HaloEnt *)g->planC.d, g->planC.count, f, L);
 }
+// corner (B-grid) scalar field
+template <class T>
+static void halo_corner(const fv3_grid *g, T *f, int L, hipStream_t st)
+{
+    if (g->planB.count == 0) return;
+    launch_fn<k_halo_scalar<T>>("k_halo_corner", dim3((g->planB.count + 255) / 256, L), dim3(256), st,
+                 g->geo, (const HaloEnt *)g->planB.d, g->planB.count, f, L);
+}
 template <class T>
 static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hipStream_t st)
 {
@@ -1580,7 +1588,7 @@ DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc
 // corner displacements of the contravariant C-grid winds)
 template <class B, int ORD>
 DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const B *u, const B *v,
-                           const B *ut, const B *vt, B *om, B *ke)
+                           const B *ut, const B *vt, const B *hd, B hc, B *om, B *ke)
 {
     KBEGIN(G.nz);
     int n = G.n;
@@ -1634,8 +1642,62 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const 
             }
             kev -= c2 * damin * (fe - fw + fn - fs) * rac;
         }
+        // higher-order damping: hc = (-1)^(nord+1) nu_n times the divergence
+        // after nord corner Laplacians
+        if (hd) kev += hc * AT(hd + o, i, j);
         AT(ke + o, i, j) = kev;
     }
+}
+
+// Divergence at corner (i, j) of a D-grid pair (U on y-faces, V on x-faces)
+// over the corner's dual cell: normal components through its four edges
+// times their lengths over the dual area, half weights for the two edges
+// next to the missing cell at a cube vertex.
+template <class B>
+DEVI B corner_div_at(const Geo &G, const Mets<B> &M, const B *U, const B *V, int t, int i, int j)
+{
+    B ws = 1, wn = 1, ww = 1, we = 1;
+    if (is_vertex(G, i, j)) {
+        if (j == 0) ws = 0.5; else wn = 0.5;
+        if (i == 0) ww = 0.5; else we = 0.5;
+    }
+    const B *dxc = MP(M, M_DXC), *dyc = MP(M, M_DYC);
+    return (we * AT(U, i, j) * AT(dyc, i, j) - ww * AT(U, i - 1, j) * AT(dyc, i - 1, j) +
+            wn * AT(V, i, j) * AT(dxc, i, j) - ws * AT(V, i, j - 1) * AT(dxc, i, j - 1)) *
+           AT(MP(M, M_RAREA_C), i, j);
+}
+
+// Higher-order divergence damping: the corner divergence of the D-grid
+// winds (corners 0..n of every level) ...
+template <class B>
+DEVI void k_cdiv(KARGS, Geo G, Mets<B> M, const B *u, const B *v, B *dg)
+{
+    KBEGIN(G.nz);
+    long o = pidx(G, G.nz, t, k);
+    AT(dg + o, i, j) = corner_div_at(G, M, u + o, v + o, t, i, j);
+}
+
+// ... and the corner Laplacian of a corner field whose halo is filled: the
+// corner divergence of its gradient along the cell edges, (D(i+1,j) -
+// D(i,j)) / dx on y-faces and (D(i,j+1) - D(i,j)) / dy on x-faces.
+template <class B>
+DEVI void k_clap(KARGS, Geo G, Mets<B> M, const B *d, B *out)
+{
+    KBEGIN(G.nz);
+    long o = pidx(G, G.nz, t, k);
+    const B *D = d + o, *rdx = MP(M, M_RDX), *rdy = MP(M, M_RDY);
+    const B c = AT(D, i, j);
+    const B ge = (AT(D, i + 1, j) - c) * AT(rdx, i, j), gw = (c - AT(D, i - 1, j)) * AT(rdx, i - 1, j);
+    const B gn = (AT(D, i, j + 1) - c) * AT(rdy, i, j), gs = (c - AT(D, i, j - 1)) * AT(rdy, i, j - 1);
+    B ws = 1, wn = 1, ww = 1, we = 1;
+    if (is_vertex(G, i, j)) {
+        if (j == 0) ws = 0.5; else wn = 0.5;
+        if (i == 0) ww = 0.5; else we = 0.5;
+    }
+    const B *dxc = MP(M, M_DXC), *dyc = MP(M, M_DYC);
+    AT(out + o, i, j) = (we * ge * AT(dyc, i, j) - ww * gw * AT(dyc, i - 1, j) + wn * gn * AT(dxc, i, j) -
+                         ws * gs * AT(dxc, i, j - 1)) *
+                        AT(MP(M, M_RAREA_C), i, j);
 }
 
 // D-grid wind update from kinetic-energy differences and vorticity fluxes;
@@ -2191,11 +2253,26 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             b.q = w; b.qout = W.wn;
             fvtp(g, P, b, st);
         }
+        // higher-order divergence damping (nord 1, 2): the C-grid half-step
+        // arrays ax, ay are free after p_grad_c and hold the corner fields
+        const B *hd = nullptr;
+        double hc = 0.0;
+        if (g->p.nord > 0 && g->p.d4_bg > 0.0) {
+            launch2d(k_cdiv<B>, 0, n, 0, n, P, st, G, M, (const B *)u, (const B *)v, W.ax);
+            B *a = W.ax, *b = W.ay;
+            for (int r = 0; r < g->p.nord; r++) {
+                halo_corner(g, a, nz, st);
+                launch2d(k_clap<B>, 0, n, 0, n, P, st, G, M, (const B *)a, b);
+                std::swap(a, b);
+            }
+            hd = a;
+            hc = (g->p.nord % 2 ? 1.0 : -1.0) * std::pow(g->p.d4_bg * g->da_min, g->p.nord + 1);
+        }
         auto omke = [&](auto lim) {
             launch2d_sh<k_dsw_omke<B, decltype(lim)::value>>(
                 "k_dsw_omke<B>", (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M,
                 (B)bdt, (B)g->p.d2_bg, (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v,
-                (const B *)W.ut, (const B *)W.vt, W.om, W.ke);
+                (const B *)W.ut, (const B *)W.vt, (const B *)hd, (B)hc, W.om, W.ke);
         };
         if (g->p.hord == 6) omke(std::integral_constant<int, 6>{});
         else if (g->p.hord == 5) omke(std::integral_constant<int, 5>{});
