@@ -62,6 +62,7 @@ def lib():
         L.orc_pp_interfaces.argtypes = [C.c_int, C.c_int, dp, dp, dp]
         L.orc_set_pp_order.argtypes = [C.c_void_p, C.c_int]
         L.orc_set_damp4.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_set_vtdm.argtypes = [C.c_void_p, C.c_double]
         L.orc_corner_div.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
         L.orc_corner_lap.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
@@ -111,7 +112,8 @@ class Grid:
     def __init__(self, kind: int, n: int, nz: int, delta: float = 1000.0, f0: float = 0.0,
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
                  d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
-                 hord_tr: int = 0, pp_order: int = 2, nord: int = 0, d4_bg: float = 0.0):
+                 hord_tr: int = 0, pp_order: int = 2, nord: int = 0, d4_bg: float = 0.0,
+                 vtdm: float = 0.0):
         if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
             raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
         if pp_order not in (2, 4):
@@ -135,6 +137,8 @@ class Grid:
         lib().orc_set_pp_order(h, int(pp_order))
         self.nord, self.d4_bg = nord, d4_bg
         lib().orc_set_damp4(h, int(nord), float(d4_bg))
+        self.vtdm = vtdm
+        lib().orc_set_vtdm(h, float(vtdm))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1

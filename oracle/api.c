@@ -41,6 +41,8 @@ void orc_set_damping(void *gp, double d2_bg)
 
 /* Smagorinsky coefficient of the divergence damping */
 void orc_set_smag(void *gp, double dddmp) { ((OGrid *)gp)->dddmp = dddmp; }
+void orc_set_vtdm(void *gp, double vtdm) { ((OGrid *)gp)->vtdm = vtdm; }
+
 void orc_set_damp4(void *gp, int nord, double d4_bg)
 {
     ((OGrid *)gp)->nord = nord;

@@ -566,6 +566,25 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
     og_view_scalar(g, om, ST_C, MODE_X, 0, qx);
     og_view_scalar(g, om, ST_C, MODE_Y, 0, qy);
     o_fv_tp_2d(g, t, om, qx, qy, crx, cry, xfx, yfx, NULL, NULL, VX, VY);
+    /* (vii) optional del-2 vorticity damping: a diffusive flux of the
+     * relative vorticity joins the vorticity fluxes, nu_v times its
+     * difference across the face over the centre distance times the face
+     * length (into the cell on the low side), so that the vorticity of the
+     * updated winds diffuses with nu_v = vtdm times the smallest dual area */
+    if (g->vtdm > 0.0) {
+        double nuv = g->vtdm * g->da_min;
+        const double *dxc = g->dxc + o, *dyc = g->dyc + o;
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i <= n; i++) {
+                size_t f = IX(g, i, j), w_ = IX(g, i - 1, j);
+                VX[f] += nuv * ((om[w_] - fC[w_]) - (om[f] - fC[f])) * dy[f] / dxc[f];
+            }
+        for (int j = 0; j <= n; j++)
+            for (int i = 0; i < n; i++) {
+                size_t f = IX(g, i, j), s_ = IX(g, i, j - 1);
+                VY[f] += nuv * ((om[s_] - fC[s_]) - (om[f] - fC[f])) * dx[f] / dyc[f];
+            }
+    }
     /* (viii) D-grid wind update (pressure gradient follows after riem_solver3) */
     for (int j = 0; j <= n; j++)
         for (int i = 0; i < n; i++) {

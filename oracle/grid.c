@@ -300,6 +300,7 @@ OGrid *og_new(int kind, int n, int nz, double delta, double f0, double radius, d
     g->pp_order = 2;
     g->nord = 0;
     g->d4_bg = 0.0;
+    g->vtdm = 0.0;
     size_t P = (size_t)g->T * o_plane(g);
     ALLOC_METRICS(g, P);
     if (kind == 0) {

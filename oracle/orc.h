@@ -59,6 +59,8 @@ typedef struct {
     /* higher-order divergence damping: order nord (1 del-4, 2 del-6, 0 off), coefficient d4_bg */
     int nord;
     double d4_bg;
+    /* del-2 vorticity damping coefficient (0 = off) */
+    double vtdm;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */

@@ -124,3 +124,113 @@ def test_corner_laplacian_conserves_and_is_self_adjoint(orc):
     b = float((wts * LE[sl] * D[sl]).sum())
     assert abs(a - b) <= 1e-10 * max(abs(a), abs(b)), (a, b)
     assert abs(a) > 0
+
+
+# ---- del-2 vorticity damping (vtdm) -------------------------------------
+
+def _one_v(orc, st, n, nz, vtdm, dt=0.2):
+    g = orc.Grid(0, n, nz, vtdm=vtdm)
+    s = orc.new_state(g, st)
+    assert orc.acoustic_substeps(g, s, dt, 1) == 0
+    return s
+
+
+@pytest.mark.parametrize("m", [1, 4, 8])
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_vorticity_damping_closed_form(orc, m, axis):
+    """A purely rotational mode, v = cos(2 pi m i / n) on x-faces (or
+    u = cos(2 pi m j / n) on y-faces), the other wind 0: its vorticity is a
+    Fourier mode of the 1-D cell Laplacian, and the damping changes that wind
+    by -4 vtdm sin^2(pi m / n) times itself (del-2 diffusion of the vorticity;
+    nu_v = vtdm dx^2), the other wind not at all."""
+    n, nz, vt = 16, 2, 0.1
+    i = np.arange(n)
+    col = np.cos(2 * np.pi * m * i / n)
+    z = np.zeros((nz, n, n))
+    if axis == "x":
+        w = np.broadcast_to(col, (nz, n, n)).copy()
+        st = _pure_wind_state(n, nz, z, w)
+        k, o = "v", "u"
+    else:
+        w = np.broadcast_to(col[:, None], (nz, n, n)).copy()
+        st = _pure_wind_state(n, nz, w, z)
+        k, o = "u", "v"
+    a = _one_v(orc, st, n, nz, 0.0)
+    b = _one_v(orc, st, n, nz, vt)
+    d = (b[k] - a[k])[0, :, H:H + n, H:H + n]
+    want = -(4 * vt) * np.sin(np.pi * m / n) ** 2 * w
+    np.testing.assert_allclose(d, want, rtol=0, atol=1e-13)
+    np.testing.assert_allclose((b[o] - a[o])[0, :, H:H + n, H:H + n], 0.0, atol=1e-13)
+
+
+def test_vorticity_damping_on_the_cube(orc):
+    """On the cube (uneven metrics) the change of the D-grid winds in the
+    momentum update is the diffusive vorticity flux alone: for v on x-face
+    (i, j), -nu_v (w(i-1, j) - w(i, j)) / dxc, for u on y-face (i, j),
+    nu_v (w(i, j-1) - w(i, j)) / dyc, w the relative vorticity (circulation
+    of the halo-filled winds over the cell area)."""
+    n, nz, vt = 10, 2, 0.15
+    st = fi.cube_state(n=n, nz=nz, seed=8)
+    g0 = orc.Grid(1, n, nz, delta=1.0e5)
+    g1 = orc.Grid(1, n, nz, delta=1.0e5, vtdm=vt)
+    out = []
+    for g in (g0, g1):
+        s = orc.new_state(g, st)
+        assert orc.acoustic_substeps(g, s, 300.0, 1, stop_stage=6) == 0
+        out.append(s)
+    U, V = st["u"].copy(), st["v"].copy()
+    orc.halo_fill_pair(g0, U, "Y", V, "X")
+    dx, dy, dxc, dyc = (g0.metric(k) for k in ("dx", "dy", "dxc", "dyc"))
+    area = g0.metric("area")
+    nuv = vt * g0.metric("area_c")[:, H:H + n + 1, H:H + n + 1].min()
+    c = slice(H - 1, H + n)
+    w = np.zeros_like(U)
+    e = slice(H, H + n + 1)
+    with np.errstate(divide="ignore", invalid="ignore"):   # the cube-corner halo cells have no area
+        w[:, :, c, c] = (U[:, :, c, c] * dx[:, None, c, c] - U[:, :, e, c] * dx[:, None, e, c] -
+                         V[:, :, c, c] * dy[:, None, c, c] + V[:, :, c, e] * dy[:, None, c, e]) / area[:, None, c, c]
+    I = slice(H, H + n)
+    dv = (out[1]["v"] - out[0]["v"])[:, :, I, I]
+    want_v = -nuv * (w[:, :, I, H - 1:H + n - 1] - w[:, :, I, I]) / dxc[:, None, I, I]
+    du = (out[1]["u"] - out[0]["u"])[:, :, I, I]
+    want_u = nuv * (w[:, :, H - 1:H + n - 1, I] - w[:, :, I, I]) / dyc[:, None, I, I]
+    scale = max(np.abs(want_v).max(), np.abs(want_u).max())
+    assert scale > 1e-6
+    assert np.abs(dv - want_v).max() <= 1e-8 * scale
+    assert np.abs(du - want_u).max() <= 1e-8 * scale
+
+
+def test_vorticity_damping_leaves_divergent_flow(orc):
+    """D-grid winds that are differences of a corner potential have zero
+    relative vorticity in every cell: the damping changes nothing."""
+    n, nz = 16, 2
+    rng = np.random.default_rng(29)
+    chi = rng.standard_normal((nz, n, n)) * 1000.0          # potential at corners
+    dx = 1000.0
+    u = (np.roll(chi, -1, axis=2) - chi) / dx               # y-face (i, j): corners (i, j), (i+1, j)
+    v = (np.roll(chi, -1, axis=1) - chi) / dx               # x-face (i, j): corners (i, j), (i, j+1)
+    st = _pure_wind_state(n, nz, u, v)
+    a = _one_v(orc, st, n, nz, 0.0)
+    b = _one_v(orc, st, n, nz, 0.2)
+    scale = np.abs(a["u"]).max()
+    assert np.abs(b["u"] - a["u"]).max() <= 1e-12 * scale
+    assert np.abs(b["v"] - a["v"]).max() <= 1e-12 * scale
+
+
+def test_vorticity_damping_ignores_coriolis(orc):
+    """On the cube f varies (its Laplacian is not zero): D-grid winds at rest
+    have zero relative vorticity, so the momentum update with the damping
+    equals the one without bit for bit (stage 6), which would not hold if the
+    absolute vorticity were diffused."""
+    n, nz = 10, 3
+    st = fi.cube_state(n=n, nz=nz, noise=0.0)
+    st["u"][:] = 0.0
+    st["v"][:] = 0.0
+    out = []
+    for vt in (0.0, 0.2):
+        g = orc.Grid(1, n, nz, delta=1.0e5, vtdm=vt)
+        s = orc.new_state(g, st)
+        assert orc.acoustic_substeps(g, s, 300.0, 1, stop_stage=6) == 0
+        out.append((s["u"].copy(), s["v"].copy()))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
