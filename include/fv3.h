@@ -88,7 +88,11 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * times the result is added to the kinetic energy, nu = (d4_bg x smallest
  * dual-cell area)^(nord+1), so that dD/dt = (-1)^nord nu Lap^(nord+1) D
  * (nord outside [0, 2]: FV3_EUNSUPPORTED; d4_bg outside [0, 0.25]:
- * FV3_EINVAL). */
+ * FV3_EINVAL).  vtdm in (0, 0.25] adds del-2 vorticity damping: the
+ * diffusive flux nu_v (w(upwind side) - w(cell)) x face length / centre
+ * distance of the relative vorticity w joins the vorticity fluxes of the
+ * momentum update, nu_v = vtdm x smallest dual-cell area (outside
+ * [0, 0.25]: FV3_EINVAL). */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -106,6 +110,7 @@ typedef struct {
     int nord;            /* higher-order divergence damping: 0 off,
                             1 del-4, 2 del-6                              */
     double d4_bg;        /* its coefficient, 0 .. 0.25                    */
+    double vtdm;         /* del-2 vorticity damping, 0 (off) .. 0.25       */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

@@ -81,6 +81,8 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
     if (p->nord < 0 || p->nord > 2) return fail(FV3_EUNSUPPORTED, "nord must be 0, 1 (del-4) or 2 (del-6)");
     if (!std::isfinite(p->d4_bg) || p->d4_bg < 0.0 || p->d4_bg > 0.25)
         return fail(FV3_EINVAL, "d4_bg must be in [0, 0.25]");
+    if (!std::isfinite(p->vtdm) || p->vtdm < 0.0 || p->vtdm > 0.25)
+        return fail(FV3_EINVAL, "vtdm must be in [0, 0.25]");
     if (p->pp_order != 0 && p->pp_order != 2 && p->pp_order != 4)
         return fail(FV3_EUNSUPPORTED, "pp_order must be 2 (mass-linear; 0 means the same) or 4 (cubic)");
     if (!(p->d2_bg >= 0.0 && p->d2_bg <= 0.25))

@@ -856,10 +856,11 @@ DEVI double cubic_iface(double da, double db, double dc, double dd, double qa, d
 // SITE tells the two solves apart in profiles (0 riem_solver_c, 1 riem_solver3);
 // OFFC: off-centred solve (beta < 1), a separate instantiation so that the
 // backward-Euler passes keep their registers; PPO: interface perturbation
-// (2 mass-linear, 4 cubic where two layers lie on each side; pass 1 only)
-template <class B, class TW, int PASS, int SITE, bool OFFC = false, int PPO = 2>
+// (2 mass-linear, 4 cubic where two layers lie on each side; pass 1 only);
+// MOIST: humidity in the equation of state (passes 1 and 3)
+template <class B, class TW, int PASS, int SITE, bool OFFC = false, int PPO = 2, bool MOIST = false>
 DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi,
-                                              const B *theta, const B *qv, const double *delz, const TW *w,
+                                              const B *theta, const B *qv_, const double *delz, const TW *w,
                                               const double *phis, double *cpv, double *dpv,
                                               double *wnv, TW *w_out, double *delz_out,
                                               double *pfull, double *phi, int need_cross)
@@ -873,6 +874,8 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     const long base = pidx(G, nz, t, 0) + (long)j * G.pitch + i, lev = G.lev;
     const long basei = pidx(G, nz + 1, t, 0) + (long)j * G.pitch + i;
     const double dt2x = dt * dt;
+    // humidity only in the moist instantiation: the dry one folds the factor away
+    const B *qv = MOIST ? qv_ : nullptr;
     // Each pass walks the column in groups of SU levels and issues the loads
     // of the next group before computing the current one, so that SU levels
     // of every input are in flight per thread (the column recurrences are
@@ -1702,16 +1705,27 @@ DEVI void k_clap(KARGS, Geo G, Mets<B> M, const B *d, B *out)
 
 // D-grid wind update from kinetic-energy differences and vorticity fluxes;
 // commit the transported delp, pt, w.
+// Optional del-2 vorticity damping (nuv > 0): the diffusive flux of the
+// relative vorticity (om - f) across each face joins the vorticity flux, so
+// u gains nuv (w(i, j-1) - w(i, j)) / dyc and v loses nuv (w(i-1, j) - w(i, j)) / dxc.
 template <class B>
 DEVI void k_dsw_update(KARGS, Geo G, Mets<B> M, const B *ke, const B *VX, const B *VY,
-                             const B *dn, const B *pn, const B *wn, B *u, B *v, B *delp, B *pt, B *w)
+                             const B *dn, const B *pn, const B *wn, const B *om, B nuv, B *u, B *v, B *delp,
+                             B *pt, B *w)
 {
     KBEGIN(G.nz);
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
     const B *KE = ke + o;
-    if (i < n) AT(u + o, i, j) = AT(u + o, i, j) + (AT(KE, i, j) - AT(KE, i + 1, j) + AT(VY + o, i, j)) * AT(MP(M, M_RDX), i, j);
-    if (j < n) AT(v + o, i, j) = AT(v + o, i, j) + (AT(KE, i, j) - AT(KE, i, j + 1) - AT(VX + o, i, j)) * AT(MP(M, M_RDY), i, j);
+    B du = 0, dv = 0;
+    if (nuv > (B)0) {
+        const B *OM = om + o, *fc = MP(M, M_FC);
+        const B wc = AT(OM, i, j) - AT(fc, i, j);
+        if (i < n) du = nuv * ((AT(OM, i, j - 1) - AT(fc, i, j - 1)) - wc) * AT(MP(M, M_RDYC), i, j);
+        if (j < n) dv = -nuv * ((AT(OM, i - 1, j) - AT(fc, i - 1, j)) - wc) * AT(MP(M, M_RDXC), i, j);
+    }
+    if (i < n) AT(u + o, i, j) = AT(u + o, i, j) + (AT(KE, i, j) - AT(KE, i + 1, j) + AT(VY + o, i, j)) * AT(MP(M, M_RDX), i, j) + du;
+    if (j < n) AT(v + o, i, j) = AT(v + o, i, j) + (AT(KE, i, j) - AT(KE, i, j + 1) - AT(VX + o, i, j)) * AT(MP(M, M_RDY), i, j) + dv;
     if (i < n && j < n) {
         AT(delp + o, i, j) = AT(dn + o, i, j);
         AT(pt + o, i, j) = AT(pn + o, i, j);
@@ -2149,17 +2163,34 @@ static MetD metrics_d(const fv3_grid *g) { return metrics_b<double>(g); }
 // The first column-solve pass in the instantiation the grid's options ask
 // for: off-centring (beta < 1) and the cubic interface perturbation.
 template <class F>
-static void sim1_pass1(const fv3_grid *g, F &&launch)
+static void sim1_pass1(const fv3_grid *g, bool moist, F &&launch)
 {
     using T_ = std::true_type;
     using F_ = std::false_type;
     using P2 = std::integral_constant<int, 2>;
     using P4 = std::integral_constant<int, 4>;
     const bool offc = g->p.beta != 1.0, cubic = g->p.pp_order == 4;
-    if (offc && cubic) launch(T_{}, P4{});
-    else if (offc) launch(T_{}, P2{});
-    else if (cubic) launch(F_{}, P4{});
-    else launch(F_{}, P2{});
+    auto go = [&](auto m) {
+        if (offc && cubic) launch(T_{}, P4{}, m);
+        else if (offc) launch(T_{}, P2{}, m);
+        else if (cubic) launch(F_{}, P4{}, m);
+        else launch(F_{}, P2{}, m);
+    };
+    if (moist) go(T_{});
+    else go(F_{});
+}
+
+// the third column-solve pass: off-centring and humidity
+template <class F>
+static void sim1_pass3(const fv3_grid *g, bool moist, F &&launch)
+{
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    const bool offc = g->p.beta != 1.0;
+    if (offc && moist) launch(T_{}, T_{});
+    else if (offc) launch(T_{}, F_{});
+    else if (moist) launch(F_{}, T_{});
+    else launch(F_{}, F_{});
 }
 
 template <class B>
@@ -2211,8 +2242,8 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         // dz_c + riem_solver_c on the half-step cells
         launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
                  (const B *)W.ay, W.delzc);
-        sim1_pass1(g, [&](auto offc, auto ppo) {
-            launch2d_fn<k_sim1<B, B, 1, 0, decltype(offc)::value, decltype(ppo)::value>>(
+        sim1_pass1(g, qvp != nullptr, [&](auto offc, auto ppo, auto moist) {
+            launch2d_fn<k_sim1<B, B, 1, 0, decltype(offc)::value, decltype(ppo)::value, decltype(moist)::value>>(
                 "k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                 (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
                 (double *)nullptr, W.pkc, W.gz, 1);
@@ -2220,14 +2251,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d_sh<k_sim1<B, B, 2, 0>>("k_sim1_c.p2", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        if (g->p.beta != 1.0)
-            launch2d_fn<k_sim1<B, B, 3, 0, true>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
-                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
-        else
-            launch2d_fn<k_sim1<B, B, 3, 0>>("k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
-                       (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
-                       (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
+        sim1_pass3(g, qvp != nullptr, [&](auto offc, auto moist) {
+            launch2d_fn<k_sim1<B, B, 3, 0, decltype(offc)::value, 2, decltype(moist)::value>>(
+                "k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
+                (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
+                (double *)nullptr, W.pkc, W.gz, 1);
+        });
         launch2d_sh<k_sim1<B, B, 4, 0>>("k_sim1_c.p4", Shape{128, 2}, -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                        (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
@@ -2284,7 +2313,8 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             fvtp(g, P, a, st);
         }
         launch2d_s(k_dsw_update<B>, (Shape{32, 8}), 0, n, 0, n, P, st, G, M, (const B *)W.ke, (const B *)W.VX, (const B *)W.VY,
-                 (const B *)W.dn, (const B *)W.pn, (const B *)W.wn, u, v, delp, pt, w);
+                 (const B *)W.dn, (const B *)W.pn, (const B *)W.wn, (const B *)W.om, (B)(g->p.vtdm * g->da_min), u, v,
+                 delp, pt, w);
         STOP(6);
         // dz_d
         launch2d(k_heights, -3, n + 2, -3, n + 2, T, st, G, (const double *)delz, phis, W.zh);
@@ -2297,8 +2327,8 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         STOP(7);
         // riem_solver3
-        sim1_pass1(g, [&](auto offc, auto ppo) {
-            launch2d_fn<k_sim1<B, B, 1, 1, decltype(offc)::value, decltype(ppo)::value>>(
+        sim1_pass1(g, qvp != nullptr, [&](auto offc, auto ppo, auto moist) {
+            launch2d_fn<k_sim1<B, B, 1, 1, decltype(offc)::value, decltype(ppo)::value, decltype(moist)::value>>(
                 "k_sim1_3.p1", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                 (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz, s->pfull,
                 s->phi, 0);
@@ -2306,14 +2336,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d_fn<k_sim1<B, B, 2, 1>>("k_sim1_3.p2", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
-        if (g->p.beta != 1.0)
-            launch2d_fn<k_sim1<B, B, 3, 1, true>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
-                       s->pfull, s->phi, 0);
-        else
-            launch2d_fn<k_sim1<B, B, 3, 1>>("k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
-                       (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
-                       s->pfull, s->phi, 0);
+        sim1_pass3(g, qvp != nullptr, [&](auto offc, auto moist) {
+            launch2d_fn<k_sim1<B, B, 3, 1, decltype(offc)::value, 2, decltype(moist)::value>>(
+                "k_sim1_3.p3", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
+                (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz, s->pfull,
+                s->phi, 0);
+        });
         launch2d_fn<k_sim1<B, B, 4, 1>>("k_sim1_3.p4", 0, n - 1, 0, n - 1, T, st, G, bdt, g->p.beta, g->p.ptop, (const B *)delp,
                        (const B *)pt, qvp, (const double *)delz, (const B *)w, phis, W.s1, W.s2, W.s3, w, delz,
                        s->pfull, s->phi, 0);
