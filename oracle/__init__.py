@@ -63,6 +63,8 @@ def lib():
         L.orc_set_pp_order.argtypes = [C.c_void_p, C.c_int]
         L.orc_set_damp4.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_vtdm.argtypes = [C.c_void_p, C.c_double]
+        L.orc_set_edge_fix.argtypes = [C.c_void_p, C.c_int]
+        L.orc_edge_partner.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
         L.orc_corner_div.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
         L.orc_corner_lap.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.orc_grid_metric.argtypes = [C.c_void_p, C.c_int, dp]
@@ -113,7 +115,7 @@ class Grid:
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
                  d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
                  hord_tr: int = 0, pp_order: int = 2, nord: int = 0, d4_bg: float = 0.0,
-                 vtdm: float = 0.0):
+                 vtdm: float = 0.0, edge_fix: bool = False):
         if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
             raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
         if pp_order not in (2, 4):
@@ -139,6 +141,8 @@ class Grid:
         lib().orc_set_damp4(h, int(nord), float(d4_bg))
         self.vtdm = vtdm
         lib().orc_set_vtdm(h, float(vtdm))
+        self.edge_fix = edge_fix
+        lib().orc_set_edge_fix(h, int(bool(edge_fix)))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -351,3 +355,11 @@ def corner_lap(g: "Grid", D) -> np.ndarray:
     out = np.zeros_like(D)
     lib().orc_corner_lap(g._h, D.shape[1], _p(D), _p(out))
     return out, D
+
+
+def edge_partner(g: "Grid", t: int, stagger: str, i: int, j: int):
+    """The other tile's copy of a face on a tile edge of the cube: (tile,
+    stagger, i, j, sign of its flux along ours)."""
+    out = (C.c_int * 4)()
+    sg = lib().orc_edge_partner(g._h, t, 1 if stagger == "X" else 2, i, j, out)
+    return out[0], "X" if out[1] == 1 else "Y", out[2], out[3], sg

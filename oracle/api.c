@@ -42,6 +42,12 @@ void orc_set_damping(void *gp, double d2_bg)
 /* Smagorinsky coefficient of the divergence damping */
 void orc_set_smag(void *gp, double dddmp) { ((OGrid *)gp)->dddmp = dddmp; }
 void orc_set_vtdm(void *gp, double vtdm) { ((OGrid *)gp)->vtdm = vtdm; }
+void orc_set_edge_fix(void *gp, int on) { ((OGrid *)gp)->edge_fix = on; }
+
+int orc_edge_partner(void *gp, int t, int st, int i, int j, int *out4)
+{
+    return og_edge_partner((const OGrid *)gp, t, st, i, j, out4, out4 + 1, out4 + 2, out4 + 3);
+}
 
 void orc_set_damp4(void *gp, int nord, double d4_bg)
 {

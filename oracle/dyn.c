@@ -359,6 +359,98 @@ void o_smag_corner(const OGrid *g, int t, const double *u, const double *v, doub
     free(shear);
 }
 
+/* Edge-flux fix-up on the cube.  A face on a tile edge is stored by both
+ * tiles and each computes its own flux through it; both fluxes are replaced
+ * by their mean (the partner's counted along our direction), and the cell
+ * next to the face takes the difference, so that what leaves one tile enters
+ * the other.  edge_faces lists, for cell (i, j) of a tile, its faces on the
+ * tile edge: stagger, face indices and the sign with which a flux along +x or
+ * +y enters the cell. */
+static int edge_faces(const OGrid *g, int i, int j, int st[2], int fi[2], int fj[2], int sg[2])
+{
+    int n = g->n, m = 0;
+    if (i == 0) { st[m] = ST_X; fi[m] = 0; fj[m] = j; sg[m] = 1; m++; }
+    if (i == n - 1) { st[m] = ST_X; fi[m] = n; fj[m] = j; sg[m] = -1; m++; }
+    if (j == 0) { st[m] = ST_Y; fi[m] = i; fj[m] = 0; sg[m] = 1; m++; }
+    if (j == n - 1) { st[m] = ST_Y; fi[m] = i; fj[m] = n; sg[m] = -1; m++; }
+    return m;
+}
+
+/* the mean flux through a shared face minus our own, for one quantity */
+static double edge_delta(const OGrid *g, int nlev, const double *FX, const double *FY, int t, int k, int st,
+                         int i, int j)
+{
+    size_t P = o_plane(g);
+    int tp, stp, ip, jp;
+    int sg = og_edge_partner(g, t, st, i, j, &tp, &stp, &ip, &jp);
+    const double *own = st == ST_X ? FX : FY, *par = stp == ST_X ? FX : FY;
+    double fo = own[((size_t)t * nlev + k) * P + IX(g, i, j)];
+    double fp = sg * par[((size_t)tp * nlev + k) * P + IX(g, ip, jp)];
+    return 0.5 * (fo + fp) - fo;
+}
+
+void o_edge_fix_dsw(const OGrid *g, const double *FXm, const double *FYm, const double *FXp,
+                    const double *FYp, const double *FXw, const double *FYw, double *delp, double *pt,
+                    double *w, double *mfx, double *mfy)
+{
+    int n = g->n, nz = g->nz;
+    size_t P = o_plane(g);
+    if (g->kind != 1) return;
+    /* all deltas from the unmodified fluxes first, then the updates */
+    size_t F3 = (size_t)g->T * nz * P;
+    double *dM = dalloc(F3), *dP = dalloc(F3), *dW = dalloc(F3);
+    for (int t = 0; t < g->T; t++)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++) {
+                    int st[2], fi[2], fj[2], sg[2];
+                    int m = edge_faces(g, i, j, st, fi, fj, sg);
+                    size_t c = PL(dM, t, k, nz) - dM + IX(g, i, j);
+                    for (int q = 0; q < m; q++) {
+                        double em = edge_delta(g, nz, FXm, FYm, t, k, st[q], fi[q], fj[q]);
+                        dM[c] += sg[q] * em;
+                        dP[c] += sg[q] * edge_delta(g, nz, FXp, FYp, t, k, st[q], fi[q], fj[q]);
+                        dW[c] += sg[q] * edge_delta(g, nz, FXw, FYw, t, k, st[q], fi[q], fj[q]);
+                        double *acc = st[q] == ST_X ? mfx : mfy;
+                        acc[PL(acc, t, k, nz) - acc + IX(g, fi[q], fj[q])] += em;
+                    }
+                }
+    for (int t = 0; t < g->T; t++)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++) {
+                    if (i > 0 && i < n - 1 && j > 0 && j < n - 1) continue;
+                    size_t c = PL(dM, t, k, nz) - dM + IX(g, i, j);
+                    double a = g->area[(size_t)t * P + IX(g, i, j)];
+                    double d0 = delp[c], d1 = d0 + dM[c] / a;
+                    pt[c] = (pt[c] * d0 * a + dP[c]) / (d1 * a);
+                    w[c] = (w[c] * d0 * a + dW[c]) / (d1 * a);
+                    delp[c] = d1;
+                }
+    free(dM); free(dP); free(dW);
+}
+
+void o_edge_fix_tracer(const OGrid *g, const double *FX, const double *FY, const double *dp2, double *q)
+{
+    int n = g->n, nz = g->nz;
+    size_t P = o_plane(g);
+    if (g->kind != 1) return;
+    size_t F3 = (size_t)g->T * nz * P;
+    double *dQ = dalloc(F3);
+    for (int t = 0; t < g->T; t++)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++) {
+                    int st[2], fi[2], fj[2], sg[2];
+                    int m = edge_faces(g, i, j, st, fi, fj, sg);
+                    size_t c = PL(dQ, t, k, nz) - dQ + IX(g, i, j);
+                    for (int r = 0; r < m; r++) dQ[c] += sg[r] * edge_delta(g, nz, FX, FY, t, k, st[r], fi[r], fj[r]);
+                }
+    for (size_t c = 0; c < F3; c++)
+        if (dQ[c] != 0.0) q[c] += dQ[c] / (dp2[c] * g->area[(c / ((size_t)nz * P)) * P + c % P]);
+    free(dQ);
+}
+
 /* Divergence at the corners 0..n of a D-grid pair (U on y-faces, V on
  * x-faces) over each corner's dual cell: normal components through its four
  * edges times their lengths over the dual area; at a cube vertex the two
@@ -408,7 +500,7 @@ void o_corner_lap(const OGrid *g, int t, const double *D, double *out)
 static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, double *v,
                        const double *uc, const double *vc, double *delp, double *pt, double *w,
                        double *mfx, double *mfy, double *cx, double *cy, double *crx,
-                       double *cry, double *xfx, double *yfx, const double *hd, int *cfl)
+                       double *cry, double *xfx, double *yfx, const double *hd, double *const *ef, int *cfl)
 {
     int n = g->n;
     size_t P = o_plane(g), o = (size_t)t * P;
@@ -462,6 +554,11 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             size_t c = IX(g, i, j);
             dn[c] = delp[c] + (FX[c] - FX[IX(g, i + 1, j)] + FY[c] - FY[IX(g, i, j + 1)]) / area[c];
         }
+    /* fluxes kept for the edge-flux fix-up */
+    if (ef) {
+        memcpy(ef[0], FX, P * sizeof(double));
+        memcpy(ef[1], FY, P * sizeof(double));
+    }
     /* (iii) pt and w with the mass fluxes */
     og_view_scalar(g, pt, ST_C, MODE_X, 0, qx);
     og_view_scalar(g, pt, ST_C, MODE_Y, 0, qy);
@@ -472,6 +569,10 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             pn[c] = (pt[c] * delp[c] * area[c] + GX[c] - GX[IX(g, i + 1, j)] + GY[c] -
                      GY[IX(g, i, j + 1)]) / (dn[c] * area[c]);
         }
+    if (ef) {
+        memcpy(ef[2], GX, P * sizeof(double));
+        memcpy(ef[3], GY, P * sizeof(double));
+    }
     og_view_scalar(g, w, ST_C, MODE_X, 0, qx);
     og_view_scalar(g, w, ST_C, MODE_Y, 0, qy);
     o_fv_tp_2d(g, t, w, qx, qy, crx, cry, xfx, yfx, FX, FY, GX, GY);
@@ -481,6 +582,10 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             wn[c] = (w[c] * delp[c] * area[c] + GX[c] - GX[IX(g, i + 1, j)] + GY[c] -
                      GY[IX(g, i, j + 1)]) / (dn[c] * area[c]);
         }
+    if (ef) {
+        memcpy(ef[4], GX, P * sizeof(double));
+        memcpy(ef[5], GY, P * sizeof(double));
+    }
     /* (iv) accumulate mass fluxes and Courant numbers on the interior faces */
     for (int j = 0; j < n; j++)
         for (int i = 0; i <= n; i++) {
@@ -761,6 +866,11 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
         hd = dalloc(F3);
         hd2 = dalloc(F3);
     }
+    double *efb[6] = {0, 0, 0, 0, 0, 0}, **ef = NULL;
+    if (g->edge_fix && g->kind == 1) {
+        for (int q = 0; q < 6; q++) efb[q] = dalloc(F3);
+        ef = efb;
+    }
 
     for (size_t q = 0; q < (size_t)T * P; q++) zs[q] = s->phis ? s->phis[q] / O_GRAV : 0.0;
     og_fill_scalar(g, zs, 1, ST_C, 0);
@@ -820,14 +930,18 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
         for (int t = 0; t < T; t++)
             for (int k = 0; k < nz; k++) {
                 int c = 0;
+                double *efp[6];
+                for (int q = 0; q < 6; q++) efp[q] = ef ? PL(ef[q], t, k, nz) : NULL;
                 d_sw_plane(g, t, k, bdt, PL(s->u, t, k, nz), PL(s->v, t, k, nz),
                            PL(s->uc, t, k, nz), PL(s->vc, t, k, nz), PL(s->delp, t, k, nz),
                            PL(s->pt, t, k, nz), PL(s->w, t, k, nz), PL(s->mfx, t, k, nz),
                            PL(s->mfy, t, k, nz), PL(s->cx, t, k, nz), PL(s->cy, t, k, nz),
                            PL(crx, t, k, nz), PL(cry, t, k, nz), PL(xfx, t, k, nz),
-                           PL(yfx, t, k, nz), hd ? PL(hd, t, k, nz) : NULL, &c);
+                           PL(yfx, t, k, nz), hd ? PL(hd, t, k, nz) : NULL, ef ? efp : NULL, &c);
                 cfl |= c;
             }
+        if (ef)
+            o_edge_fix_dsw(g, ef[0], ef[1], ef[2], ef[3], ef[4], ef[5], s->delp, s->pt, s->w, s->mfx, s->mfy);
         STOP(6);
 #pragma omp parallel for schedule(dynamic)
         for (int t = 0; t < T; t++)
@@ -871,6 +985,7 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
 done:
     free(hd);
     free(hd2);
+    for (int q = 0; q < 6; q++) free(efb[q]);
     if (dbg) {
         double *src[] = {delpc, ptc, wc, ax, ay, crx, cry, xfx, yfx};
         for (int q = 0; q < 9; q++)
@@ -929,6 +1044,11 @@ int orc_tracer_impl(const OGrid *g, double **q, int nq, const double *dp0, const
     double rs = (double)nsplt;
     double *xfx = dalloc(F3), *yfx = dalloc(F3), *dp1 = dalloc(F3), *dp2 = dalloc(F3);
     double *crs = dalloc(F3), *crys = dalloc(F3), *mxs = dalloc(F3), *mys = dalloc(F3);
+    double *efx = NULL, *efy = NULL;
+    if (g->edge_fix && g->kind == 1) {
+        efx = dalloc(F3);
+        efy = dalloc(F3);
+    }
     memcpy(dp1, dp0, F3 * sizeof(double));
 #pragma omp parallel for collapse(2)
     for (int t = 0; t < T; t++)
@@ -978,6 +1098,7 @@ int orc_tracer_impl(const OGrid *g, double **q, int nq, const double *dp0, const
                     size_t o = (size_t)t * P;
                     double *Q = PL(q[m], t, k, nz);
                     double *qx = dalloc(P), *qy = dalloc(P), *FX = dalloc(P), *FY = dalloc(P);
+                    double *keepX = efx ? PL(efx, t, k, nz) : NULL, *keepY = efy ? PL(efy, t, k, nz) : NULL;
                     og_view_scalar(g, Q, ST_C, MODE_X, 0, qx);
                     og_view_scalar(g, Q, ST_C, MODE_Y, 0, qy);
                     o_fv_tp_2d_ord(g, g->hord_tr ? g->hord_tr : g->hord, t, Q, qx, qy, PL(crs, t, k, nz), PL(crys, t, k, nz),
@@ -991,13 +1112,18 @@ int orc_tracer_impl(const OGrid *g, double **q, int nq, const double *dp0, const
                             Q[c] = (Q[c] * d1[c] * a + FX[c] - FX[IX(g, i + 1, j)] + FY[c] -
                                     FY[IX(g, i, j + 1)]) / (d2[c] * a);
                         }
+                    if (keepX) {
+                        memcpy(keepX, FX, P * sizeof(double));
+                        memcpy(keepY, FY, P * sizeof(double));
+                    }
                     free(qx); free(qy); free(FX); free(FY);
                 }
+            if (efx) o_edge_fix_tracer(g, efx, efy, dp2, q[m]);
         }
         double *tmp = dp1; dp1 = dp2; dp2 = tmp;
     }
     free(cx); free(cy); free(xfx); free(yfx); free(dp1); free(dp2); free(crs); free(crys);
-    free(mxs); free(mys);
+    free(mxs); free(mys); free(efx); free(efy);
     return 0;
 }
 

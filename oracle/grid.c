@@ -301,6 +301,7 @@ OGrid *og_new(int kind, int n, int nz, double delta, double f0, double radius, d
     g->nord = 0;
     g->d4_bg = 0.0;
     g->vtdm = 0.0;
+    g->edge_fix = 0;
     size_t P = (size_t)g->T * o_plane(g);
     ALLOC_METRICS(g, P);
     if (kind == 0) {

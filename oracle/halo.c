@@ -243,3 +243,28 @@ void og_view_pair(const OGrid *g, const double *px, int stx, const double *py, i
             }
     }
 }
+
+/* The other tile's copy of a face on a tile edge of the cube: x-face (st =
+ * ST_X, i = 0 or n) or y-face (ST_Y, j = 0 or n).  Writes the partner tile,
+ * stagger and indices; returns the sign with which the partner's flux
+ * (positive along its own +x or +y) counts along our +x or +y. */
+int og_edge_partner(const OGrid *g, int t, int st, int i, int j, int *tp, int *stp, int *ip, int *jp)
+{
+    int n2 = 2 * g->n, x2 = 2 * i + SX[st], y2 = 2 * j + SY[st];
+    int e;
+    if (st == ST_X) e = x2 == 0 ? 0 : 1;
+    else e = y2 == 0 ? 2 : 3;
+    (void)n2;
+    int R[2][2];
+    memcpy(R, g->R[t][e], sizeof(int) * 4);
+    int dx = x2 - 2 * g->P0[t][e][0], dy = y2 - 2 * g->P0[t][e][1];
+    int qx2 = R[0][0] * dx + R[0][1] * dy + 2 * g->Q0[t][e][0];
+    int qy2 = R[1][0] * dx + R[1][1] * dy + 2 * g->Q0[t][e][1];
+    *tp = g->nbr[t][e];
+    *stp = stag_of(qx2, qy2);
+    *ip = floordiv2(qx2);
+    *jp = floordiv2(qy2);
+    int comp, sign;
+    rot_dir(R, st == ST_X ? 0 : 1, &comp, &sign);
+    return sign;
+}

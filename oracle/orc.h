@@ -61,6 +61,8 @@ typedef struct {
     double d4_bg;
     /* del-2 vorticity damping coefficient (0 = off) */
     double vtdm;
+    /* cube: replace both tiles' fluxes through a shared edge face by their mean */
+    int edge_fix;
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -96,6 +98,7 @@ void og_view_scalar(const OGrid *g, const double *plane, int st, int mode, int c
 void og_view_pair(const OGrid *g, const double *px, int stx, const double *py, int sty,
                   int mode, int kind, double *ox, double *oy);
 int og_is_vertex(const OGrid *g, int i, int j);
+int og_edge_partner(const OGrid *g, int t, int st, int i, int j, int *tp, int *stp, int *ip, int *jp);
 
 /* ppm.c */
 double o_ppm_face(const double q[6], double c);
@@ -120,6 +123,10 @@ double o_sim1b(int nz, double dt, double beta, int pp_order, double ptop, double
 void o_pp_interfaces(int nz, int order, const double *dpi, const double *pp, double *pps);
 void o_corner_div(const OGrid *g, int t, const double *U, const double *V, double *out);
 void o_corner_lap(const OGrid *g, int t, const double *D, double *out);
+void o_edge_fix_dsw(const OGrid *g, const double *FXm, const double *FYm, const double *FXp,
+                    const double *FYp, const double *FXw, const double *FYw, double *delp, double *pt,
+                    double *w, double *mfx, double *mfy);
+void o_edge_fix_tracer(const OGrid *g, const double *FX, const double *FY, const double *dp2, double *q);
 double o_pgf(double dt, double L, double dpiW, double dpiE, double phW0, double phW1,
              double phE0, double phE1, double pW0, double pW1, double pE0, double pE1);
 
