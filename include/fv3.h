@@ -92,7 +92,13 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * diffusive flux nu_v (w(upwind side) - w(cell)) x face length / centre
  * distance of the relative vorticity w joins the vorticity fluxes of the
  * momentum update, nu_v = vtdm x smallest dual-cell area (outside
- * [0, 0.25]: FV3_EINVAL). */
+ * [0, 0.25]: FV3_EINVAL).  edge_fix = 1 on the cube: a face on a tile edge
+ * is stored by both tiles; after each flux-form transport (delp, pt delp,
+ * w delp in d_sw, each tracer sub-cycle) both copies of its flux take their
+ * mean and the cell next to the face takes the difference, so the global
+ * sums of mass, pt mass and tracer masses are exact; the accumulated mass
+ * fluxes take the mean too (no effect on the doubly periodic grid; other
+ * values: FV3_EINVAL). */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -111,6 +117,7 @@ typedef struct {
                             1 del-4, 2 del-6                              */
     double d4_bg;        /* its coefficient, 0 .. 0.25                    */
     double vtdm;         /* del-2 vorticity damping, 0 (off) .. 0.25       */
+    int edge_fix;        /* cube: edge-flux fix-up, 0 (off) or 1          */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

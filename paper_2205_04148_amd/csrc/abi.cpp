@@ -81,6 +81,7 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
     if (p->nord < 0 || p->nord > 2) return fail(FV3_EUNSUPPORTED, "nord must be 0, 1 (del-4) or 2 (del-6)");
     if (!std::isfinite(p->d4_bg) || p->d4_bg < 0.0 || p->d4_bg > 0.25)
         return fail(FV3_EINVAL, "d4_bg must be in [0, 0.25]");
+    if (p->edge_fix != 0 && p->edge_fix != 1) return fail(FV3_EINVAL, "edge_fix must be 0 or 1");
     if (!std::isfinite(p->vtdm) || p->vtdm < 0.0 || p->vtdm > 0.25)
         return fail(FV3_EINVAL, "vtdm must be in [0, 0.25]");
     if (p->pp_order != 0 && p->pp_order != 2 && p->pp_order != 4)
@@ -129,6 +130,7 @@ fv3_status fv3_free_grid(fv3_grid *g)
     if (g->planCv.d) (void)hipFree(g->planCv.d);
     if (g->planA.d) (void)hipFree(g->planA.d);
     if (g->planB.d) (void)hipFree(g->planB.d);
+    if (g->edge_cells) (void)hipFree(g->edge_cells);
     if (g->flags) (void)hipFree(g->flags);
     if (g->red) (void)hipFree(g->red);
     delete g;

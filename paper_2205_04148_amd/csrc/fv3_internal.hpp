@@ -48,6 +48,16 @@ struct Plan {
     int count = 0;
 };
 
+// A cell next to a tile edge of the cube and its faces on that edge (one, or
+// two at a tile corner): our flux (array 0: x-faces, 1: y-faces, in-plane
+// offset), the sign with which it enters the cell, and the other tile's copy
+// of the face with the sign that maps its flux onto ours.
+struct EdgeCell {
+    int t, cell, nf;
+    int arr[2], off[2], sin[2];
+    int pt[2], parr[2], poff[2], spar[2];
+};
+
 // Block index handed to a kernel body explicitly (the hardware index when a
 // kernel runs alone, the member-local index in an ensemble launch).
 struct Bk {
@@ -95,6 +105,8 @@ struct fv3_grid {
     std::vector<double> hmet[fv3::M_ALL];     // host copies
     fv3::Plan planC, planD, planCv, planA;    // scalar, D-grid pair, C-grid pair, cell pair
     fv3::Plan planB;                          // corner (B-grid) scalar
+    fv3::EdgeCell *edge_cells = nullptr;      // cube: cells next to tile edges (edge-flux fix-up)
+    int edge_count = 0;
     int *flags = nullptr;                     // device error latch [3]: cfl, nonfinite, remap
     double *red = nullptr;                    // device reduction scratch
     long red_elems = 0;

@@ -137,6 +137,17 @@ class Geometry {
         qy2 = m.r[1][0] * x2 + m.r[1][1] * y2 + m.ay2;
     }
 
+    // The affine map of edge e of tile t applied to a point (doubled lattice
+    // coordinates) on that edge: the same point in the neighbour tile.
+    void edge_map(int t, int e, int x2, int y2, int &tb, int &qx2, int &qy2, int r[2][2]) const
+    {
+        const EdgeMap &m = em[t][e];
+        tb = m.nb;
+        std::memcpy(r, m.r, sizeof(m.r));
+        qx2 = m.r[0][0] * x2 + m.r[0][1] * y2 + m.ax2;
+        qy2 = m.r[1][0] * x2 + m.r[1][1] * y2 + m.ay2;
+    }
+
     // Position of lattice corner (I, J) of tile t, halo corners via the owner.
     V3 corner_ext(int t, int I, int J) const
     {
@@ -322,6 +333,52 @@ void make_plan(const Geometry &G, const fv3_grid *g, int stx, int sty, bool pair
     }
 }
 
+// Edge cells of the cube for the edge-flux fix-up: every cell with a face on
+// a tile edge, each such face with its partner copy on the neighbour tile.
+bool make_edge_cells(const Geometry &G, const fv3_grid *g, std::vector<EdgeCell> &out)
+{
+    if (!G.cube) return true;
+    const int n = G.n;
+    for (int t = 0; t < g->T; t++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                if (i > 0 && i < n - 1 && j > 0 && j < n - 1) continue;
+                EdgeCell c{};
+                c.t = t;
+                c.cell = (int)((long)j * g->pitch + i);
+                // (edge, face stagger x = 0 / y = 1, face i, j, inflow sign)
+                int faces[4][5], m = 0;
+                if (i == 0) { int f[5] = {0, 0, 0, j, 1}; std::memcpy(faces[m++], f, sizeof(f)); }
+                if (i == n - 1) { int f[5] = {1, 0, n, j, -1}; std::memcpy(faces[m++], f, sizeof(f)); }
+                if (j == 0) { int f[5] = {2, 1, i, 0, 1}; std::memcpy(faces[m++], f, sizeof(f)); }
+                if (j == n - 1) { int f[5] = {3, 1, i, n, -1}; std::memcpy(faces[m++], f, sizeof(f)); }
+                c.nf = m;
+                for (int q = 0; q < m; q++) {
+                    const int e = faces[q][0], ax = faces[q][1], fi = faces[q][2], fj = faces[q][3];
+                    const int x2 = 2 * fi + (ax == 0 ? 0 : 1), y2 = 2 * fj + (ax == 0 ? 1 : 0);
+                    int tb, qx2, qy2, r[2][2];
+                    G.edge_map(t, e, x2, y2, tb, qx2, qy2, r);
+                    // our normal direction (x for x-faces, y for y-faces) in the neighbour's frame
+                    const int vx = ax == 0 ? r[0][0] : r[0][1], vy = ax == 0 ? r[1][0] : r[1][1];
+                    c.arr[q] = ax;
+                    c.off[q] = (int)((long)fj * g->pitch + fi);
+                    c.sin[q] = faces[q][4];
+                    c.pt[q] = tb;
+                    c.parr[q] = vx != 0 ? 0 : 1;
+                    c.spar[q] = vx != 0 ? vx : vy;
+                    // the partner is a face on one of the neighbour's edges
+                    const int pi = fdiv2(qx2), pj = fdiv2(qy2);
+                    const bool xf = (qx2 & 1) == 0 && (qy2 & 1) == 1, yf = (qx2 & 1) == 1 && (qy2 & 1) == 0;
+                    if (tb < 0 || tb >= g->T || pi < 0 || pi > n || pj < 0 || pj > n || !(xf || yf) ||
+                        (xf && pi != 0 && pi != n) || (yf && pj != 0 && pj != n) || xf != (c.parr[q] == 0))
+                        return false;
+                    c.poff[q] = (int)((long)pj * g->pitch + pi);
+                }
+                out.push_back(c);
+            }
+    return true;
+}
+
 }  // namespace
 
 static void set_layout(const fv3_grid_params *p, fv3_grid *g)
@@ -435,6 +492,15 @@ fv3_status build_grid(const fv3_grid_params *p, fv3_grid *g, std::string &err)
     g->planA.count = (int)pa.size();
     if ((s = upload(&g->planB.d, pb, err)) != FV3_OK) return s;
     g->planB.count = (int)pb.size();
+    std::vector<EdgeCell> ec;
+    if (!make_edge_cells(G, g, ec)) {
+        err = "edge-cell plan: a tile-edge face has no partner face on the neighbour's edge";
+        return FV3_EINTERNAL;
+    }
+    if (!ec.empty()) {
+        if ((s = upload(&g->edge_cells, ec, err)) != FV3_OK) return s;
+        g->edge_count = (int)ec.size();
+    }
     if (hipMalloc((void **)&g->flags, 4 * sizeof(int)) != hipSuccess) return FV3_ENOMEM;
     if (hipMemset(g->flags, 0, 4 * sizeof(int)) != hipSuccess) return FV3_EDEVICE;
     return FV3_OK;

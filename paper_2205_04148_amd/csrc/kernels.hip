@@ -1263,6 +1263,7 @@ struct FvArgs {
     const T *area;         // area metric (type T)
     int epi;
     T *FX, *FY;            // flux outputs (may be null)
+    int edges_only;        // write the flux outputs on tile-edge faces only
     T *qout;               // cell output, Lq levels
     const T *dold, *dnew;  // EPI_MASSW
     const double *dp1, *dp2;            // EPI_TRACER
@@ -1445,7 +1446,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             T F = (T)0.5 * (fx + sFx[s]) * wgt;
             sFx[s] = F;
             if (c < FTX || i == n) {
-                if (A.FX) A.FX[oc + fi] = F;
+                if (A.FX && (!A.edges_only || i == 0 || i == n)) A.FX[oc + fi] = F;
                 if (EPI == EPI_DELP) {
                     A.mfx[oc + fi] += (double)F;
                     A.cxa[oc + fi] += (C)sCX[s];
@@ -1468,7 +1469,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             T F = (T)0.5 * (fy + sFy[s]) * wgt;
             sFy[s] = F;
             if (r < FTY || j == n) {
-                if (A.FY) A.FY[oc + fi] = F;
+                if (A.FY && (!A.edges_only || j == 0 || j == n)) A.FY[oc + fi] = F;
                 if (EPI == EPI_DELP) {
                     A.mfy[oc + fi] += (double)F;
                     A.cya[oc + fi] += (C)sCY[s];
@@ -1650,6 +1651,61 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const 
         if (hd) kev += hc * AT(hd + o, i, j);
         AT(ke + o, i, j) = kev;
     }
+}
+
+// Edge-flux fix-up on the cube, one thread per (cell next to a tile edge,
+// level): each of the cell's faces on the edge takes the mean of our flux and
+// the neighbour tile's copy (mapped onto our direction); the cell takes the
+// difference.  After d_sw: mass fluxes FXm/FYm (delp), content fluxes of pt
+// and w, the committed delp, pt, w and the mass-flux accumulators.
+template <class B>
+DEVI B edge_mean_delta(const Geo &G, const EdgeCell &c, int q, int k, const B *FX, const B *FY)
+{
+    const B *own = c.arr[q] == 0 ? FX : FY, *par = c.parr[q] == 0 ? FX : FY;
+    const B fo = own[pidx(G, G.nz, c.t, k) + c.off[q]];
+    const B fp = (B)c.spar[q] * par[pidx(G, G.nz, c.pt[q], k) + c.poff[q]];
+    return (B)0.5 * (fo + fp) - fo;
+}
+
+template <class B>
+DEVI void k_edgefix_dsw(Bk bk, Geo G, const EdgeCell *__restrict__ cells, int count, const B *area,
+                        const B *FXm, const B *FYm, const B *FXp, const B *FYp, const B *FXw, const B *FYw,
+                        B *delp, B *pt, B *w, double *mfx, double *mfy)
+{
+    const int e = (int)(bk.x * blockDim.x + threadIdx.x);
+    if (e >= count) return;
+    const int k = (int)bk.y;
+    const EdgeCell c = cells[e];
+    B dM = 0, dP = 0, dW = 0;
+    for (int q = 0; q < c.nf; q++) {
+        const B em = edge_mean_delta(G, c, q, k, FXm, FYm);
+        dM += (B)c.sin[q] * em;
+        dP += (B)c.sin[q] * edge_mean_delta(G, c, q, k, FXp, FYp);
+        dW += (B)c.sin[q] * edge_mean_delta(G, c, q, k, FXw, FYw);
+        double *acc = c.arr[q] == 0 ? mfx : mfy;
+        acc[pidx(G, G.nz, c.t, k) + c.off[q]] += (double)em;
+    }
+    const long o = pidx(G, G.nz, c.t, k) + c.cell;
+    const B a = area[pidx(G, 1, c.t, 0) + c.cell];
+    const B d0 = delp[o], d1 = d0 + dM / a;
+    pt[o] = (pt[o] * d0 * a + dP) / (d1 * a);
+    w[o] = (w[o] * d0 * a + dW) / (d1 * a);
+    delp[o] = d1;
+}
+
+// ... and after a tracer sub-cycle: tracer fluxes, the sub-cycle's new mass dp2.
+template <class B>
+DEVI void k_edgefix_q(Bk bk, Geo G, const EdgeCell *__restrict__ cells, int count, const B *area, const B *FX,
+                      const B *FY, const double *dp2, B *qf)
+{
+    const int e = (int)(bk.x * blockDim.x + threadIdx.x);
+    if (e >= count) return;
+    const int k = (int)bk.y;
+    const EdgeCell c = cells[e];
+    B dQ = 0;
+    for (int q = 0; q < c.nf; q++) dQ += (B)c.sin[q] * edge_mean_delta(G, c, q, k, FX, FY);
+    const long o = pidx(G, G.nz, c.t, k) + c.cell;
+    qf[o] = qf[o] + (B)((double)dQ / (dp2[o] * (double)area[pidx(G, 1, c.t, 0) + c.cell]));
 }
 
 // Divergence at corner (i, j) of a D-grid pair (U on y-faces, V on x-faces)
@@ -2211,6 +2267,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
     double bdt = dt / n_split, dt2 = 0.5 * bdt;
     const B *areaB = M.m[M_AREA];
     const B *qvp = (const B *)s->qv;
+    const bool efix = g->p.edge_fix && g->edge_count > 0;
 
     // humidity is constant over the call: its halo once
     if (qvp) halo_set<B>(g, FieldSet<B>{{(B *)s->qv, nullptr, nullptr, nullptr}}, 1, nz, st);
@@ -2278,8 +2335,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             FvArgs<B, B, B> b{};
             b.q = pt; b.Lq = nz; b.crx = W.crx; b.cry = W.cry; b.xfx = W.xfx; b.yfx = W.yfx; b.Lc = nz;
             b.mx = W.FX; b.my = W.FY; b.area = areaB; b.epi = EPI_MASSW; b.qout = W.pn; b.dold = delp; b.dnew = W.dn;
+            // edge-flux fix-up: keep the content fluxes (the C-grid half-step
+            // arrays are free after p_grad_c)
+            if (efix) { b.FX = W.delpc; b.FY = W.ptc; b.edges_only = 1; }
             fvtp(g, P, b, st);
             b.q = w; b.qout = W.wn;
+            if (efix) { b.FX = W.wc; b.FY = W.qo; }
             fvtp(g, P, b, st);
         }
         // higher-order divergence damping (nord 1, 2): the C-grid half-step
@@ -2315,6 +2376,11 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         launch2d_s(k_dsw_update<B>, (Shape{32, 8}), 0, n, 0, n, P, st, G, M, (const B *)W.ke, (const B *)W.VX, (const B *)W.VY,
                  (const B *)W.dn, (const B *)W.pn, (const B *)W.wn, (const B *)W.om, (B)(g->p.vtdm * g->da_min), u, v,
                  delp, pt, w);
+        if (efix)
+            launch_fn<k_edgefix_dsw<B>>("k_edgefix", dim3((g->edge_count + 255) / 256, nz), dim3(256), st, G,
+                                        (const EdgeCell *)g->edge_cells, g->edge_count, areaB, (const B *)W.FX,
+                                        (const B *)W.FY, (const B *)W.delpc, (const B *)W.ptc, (const B *)W.wc,
+                                        (const B *)W.qo, delp, pt, w, s->mfx, s->mfy);
         STOP(6);
         // dz_d
         launch2d(k_heights, -3, n + 2, -3, n + 2, T, st, G, (const double *)delz, phis, W.zh);
@@ -2429,6 +2495,7 @@ static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid 
         if (nsplt < 1) nsplt = 1;
     }
     double rs = (double)nsplt;
+    const bool efix = g->p.edge_fix && g->edge_count > 0;
     launch2d_s(k_tracer_flux<B>, (Shape{128, 2}), -3, n + 3, -3, n + 3, P, st, G, Md, rs, (const B *)cx, (const B *)cy,
              (const double *)s->mfx, (const double *)s->mfy, W.crx, W.cry, W.xfx, W.yfx, W.mxs, W.mys);
     copy(s->dp0, W.dp1, el, st);
@@ -2443,8 +2510,13 @@ static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid 
             a.q = Q; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
             a.mx = W.mxs; a.my = W.mys; a.area = M.m[M_AREA]; a.epi = EPI_TRACER; a.qout = W.qo;
             a.dp1 = dp1; a.dp2 = dp2;
+            if (efix) { a.FX = W.delpc; a.FY = W.ptc; a.edges_only = 1; }
             fvtp(g, P, a, st);
             copy((const B *)W.qo, Q, el, st);
+            if (efix)
+                launch_fn<k_edgefix_q<B>>("k_edgefix_q", dim3((g->edge_count + 255) / 256, nz), dim3(256), st, G,
+                                          (const EdgeCell *)g->edge_cells, g->edge_count, (const B *)M.m[M_AREA],
+                                          (const B *)W.delpc, (const B *)W.ptc, (const double *)dp2, Q);
         }
         double *tmp = dp1;
         dp1 = dp2;

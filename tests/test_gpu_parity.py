@@ -576,16 +576,90 @@ def test_vorticity_damping_parity(fv3, orc, kind, n, nz, stop, dt, ns, precision
     _compare(s, os_, n, fields, tol, label)
 
 
+@pytest.mark.parametrize("n,nz,stop,dt,ns,precision", [
+    (12, 5, 6, 300.0, 1, "fp64"),
+    (24, 10, 0, 2000.0, 10, "fp64"),
+    (24, 10, 0, 2000.0, 10, "mixed"),
+])
+def test_edge_fix_parity(fv3, orc, n, nz, stop, dt, ns, precision):
+    """Edge-flux fix-up on the cube against the oracle: after one d_sw
+    (1e-13), after 10 substeps (1e-11; mixed: the mixed bars) and the tracer
+    transport; with the fix the device's compensated global sums of mass,
+    pt mass and tracer mass are exact in FP64 (1e-14)."""
+    import torch
+
+    init = fi.cube_state(n=n, nz=nz, nq=1)
+    g = fv3.Grid(1, n, nz, dx=1.0e5, precision=precision, edge_fix=True)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(1, n, nz, delta=1.0e5, edge_fix=True)
+    os_ = orc.new_state(og, init)
+    label = f"edgefix n{n} stop{stop} {precision}"
+    print(label, flush=True)
+    qd = [g.upload(q, nz) for q in init["q"]]
+    m0 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)
+    fv3.acoustic_substeps(s, g, dt, ns, stop_stage=stop)
+    assert orc.acoustic_substeps(og, os_, dt, ns, stop_stage=stop) == 0
+    if precision == "mixed":
+        tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
+        fields = tuple(tol)
+    elif stop == 6:
+        fields, tol = ("u", "v", "delp", "pt", "w", "mfx", "mfy"), 1e-13
+    else:
+        fields, tol = ("u", "v", "w", "delp", "pt", "delz", "mfx", "mfy", "pfull", "phi"), 1e-11
+    _compare(s, os_, n, fields, tol, label)
+    if stop != 0:
+        return
+    assert fv3.check_status(g) == 0
+    qh = [q.copy() for q in init["q"]]
+    fv3.tracer_transport(qd, s, g)
+    orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+    torch.cuda.synchronize()
+    e = _relerr(_int(g.download(qd[0], nz), n, "C"), _int(qh[0], n, "C"))
+    print(f"{label} tracer {e:.2e}", flush=True)
+    assert e <= (1e-11 if precision == "fp64" else 1e-4)
+    if precision == "fp64":
+        m1 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)
+        rel = np.abs(m1 / m0 - 1)
+        print(f"{label} sums {rel}", flush=True)
+        assert rel.max() <= 1e-14, rel
+
+
+def test_edge_fix_periodic_untouched(fv3):
+    """The doubly periodic grid has no tile edges: edge_fix changes nothing."""
+    import torch
+
+    n, nz = 24, 4
+    init = fi.periodic_state(n=n, nz=nz)
+    out = []
+    for ef in (False, True):
+        g = fv3.Grid(0, n, nz, edge_fix=ef)
+        s = fv3.State.allocate(g)
+        s.load(init)
+        fv3.acoustic_substeps(s, g, 2.0, 5)
+        torch.cuda.synchronize()
+        out.append({k: s.get(k) for k in ("u", "v", "delp", "pt", "w")})
+    for k in out[0]:
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
 def test_higher_order_damping_abi(fv3):
     import ctypes as C
 
     base = dict(kind=0, n=16, nz=2, dx=1000.0, f0=0.0, radius=1.0, omega=0.0, ptop=100.0, precision=0, hord=8,
-                d2_bg=0.0, beta=1.0, dddmp=0.0, hord_tr=0, pp_order=2, nord=0, d4_bg=0.0, vtdm=0.0, device=0)
+                d2_bg=0.0, beta=1.0, dddmp=0.0, hord_tr=0, pp_order=2, nord=0, d4_bg=0.0, vtdm=0.0, edge_fix=0,
+                device=0)
     for nord, d4, vt, want in ((3, 0.1, 0, -8), (-1, 0.1, 0, -8), (1, 0.3, 0, -1), (1, -0.1, 0, -1),
                                (2, 0.25, 0, 0), (1, 0.0, 0, 0), (0, 0, 0.3, -1), (0, 0, -0.1, -1), (0, 0, 0.2, 0)):
         p = fv3.GridParams(**dict(base, nord=nord, d4_bg=d4, vtdm=vt))
         h = C.c_void_p()
         assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, (nord, d4, vt)
+        if want == 0:
+            fv3.lib().fv3_free_grid(h)
+    for ef, want in ((2, -1), (-1, -1), (1, 0)):
+        p = fv3.GridParams(**dict(base, edge_fix=ef))
+        h = C.c_void_p()
+        assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, ef
         if want == 0:
             fv3.lib().fv3_free_grid(h)
 
