@@ -508,7 +508,14 @@ static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hip
 // per-stage kernels; a view source outside the staged region is read (or,
 // for the A-grid winds, recomputed) from global memory.
 // --------------------------------------------------------------------
-constexpr int CTX = 32, CNT = 256;
+// Tile width: the points i in [-1, n + 1] split into ceil((n + 3) / CTX)
+// tiles from i = -1; 33 covers C192's 195 points in 6 tiles (32 needed 7, the
+// last with 3 useful columns: a mostly empty tile still issues every
+// instruction of the kernel).
+#ifndef FV3_CSW_CTX
+#define FV3_CSW_CTX 33
+#endif
+constexpr int CTX = FV3_CSW_CTX, CNT = 256;
 // tile rows per precision: the FP64 tile is shorter so that its LDS allows
 // five blocks per CU
 template <class B>
@@ -569,7 +576,7 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
     B *sVC = sFw + HF * WF, *sGm = sVC + HF * WF, *sGp = sGm + HF * WF, *sGw = sGp + HF * WF;
     B *sKE = sGw + HF * WF, *sVO = sKE + HK * WK;
     const int n = G.n, tid = threadIdx.x;
-    const int i0 = -CTX + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;   // i0: 32-aligned, first tile holds i = -1
+    const int i0 = -1 + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
     const int t = bk.z / G.nz, k = bk.z % G.nz;
     const long o = pidx(G, G.nz, t, k);
     const B *U = u + o, *V = v + o, *D = delp + o, *PT = pt + o, *Wf = w + o;
@@ -753,7 +760,7 @@ DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B 
     // and the interpolation stencils around it) reach a cube corner block
     constexpr int CTY = CswRows<B>::Y;
     const int n = G.n;
-    const int i0 = -CTX + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
+    const int i0 = -1 + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
     const bool nx = i0 - 6 < 0 || i0 + CTX + 5 > n, ny = j0 - 6 < 0 || j0 + CTY + 5 > n;
     __shared__ B L[csw_lds<CTY>()];
     if (G.cube && nx && ny)
@@ -2291,7 +2298,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         }
         STOP(1);
         // c_sw
-        launch_fn<k_csw<B>>("k_csw", dim3((unsigned)((n + 1 + CTX + CTX) / CTX),
+        launch_fn<k_csw<B>>("k_csw", dim3((unsigned)((n + 3 + CTX - 1) / CTX),
                                           (unsigned)((n + 3 + CswRows<B>::Y - 1) / CswRows<B>::Y), P),
                             dim3(CNT), st, G, M, (B)dt2, (const B *)u, (const B *)v, (const B *)delp, (const B *)pt,
                             (const B *)w, uc, vc, W.delpc, W.ptc, W.wc, W.ax, W.ay);
