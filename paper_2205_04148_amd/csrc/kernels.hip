@@ -1816,6 +1816,44 @@ DEVI void k_heights(KARGS, Geo G, const double *delz, const double *phis, double
     }
 }
 
+// Mixed precision: the heights travel as FP32 deviations from a reference
+// per (tile, interface), the height at cell (0, 0).  The transport is exactly
+// translation-equivariant (PPM faces, advective inner and outer updates), so
+// only the deviations' rounding enters, not that of the full height.  Every
+// thread scans the reference column beside its own (the same loads for the
+// whole tile, served by the cache); the thread of cell (0, 0) stores it.
+DEVI void k_heights_dev(KARGS, Geo G, const double *delz, const double *phis, double *zref, float *zd)
+{
+    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+    if (i < ilo || i > ihi || j > jhi) return;
+    int nz = G.nz, t = bk.z;
+    if (in_corner(G, SC, i, j)) return;
+    long c = (long)j * G.pitch + i;
+    const bool keep = i == 0 && j == 0;
+    double z = phis ? phis[pidx(G, 1, t, 0) + c] / GRAV : 0.0;
+    double zr = phis ? phis[pidx(G, 1, t, 0)] / GRAV : 0.0;
+    zd[pidx(G, nz + 1, t, nz) + c] = (float)(z - zr);
+    if (keep) zref[t * (nz + 1) + nz] = zr;
+    for (int k = nz - 1; k >= 0; k--) {
+        z -= delz[pidx(G, nz, t, k) + c];
+        zr -= delz[pidx(G, nz, t, k)];
+        zd[pidx(G, nz + 1, t, k) + c] = (float)(z - zr);
+        if (keep) zref[t * (nz + 1) + k] = zr;
+    }
+}
+
+DEVI void k_delz_from_zdev(KARGS, Geo G, const float *zn, const double *zref, const double *phis, double *delz)
+{
+    KBEGIN(G.nz);
+    int nz = G.nz;
+    const double *zr = zref + t * (nz + 1);
+    double top = zr[k] + (double)AT(zn + pidx(G, nz + 1, t, k), i, j);
+    double below = k == nz - 1 ? (phis ? AT(phis + pidx(G, 1, t, 0), i, j) / GRAV : 0.0)
+                               : zr[k + 1] + (double)AT(zn + pidx(G, nz + 1, t, k + 1), i, j);
+    AT(delz + pidx(G, nz, t, k), i, j) = below - top;
+}
+
 DEVI void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phis, double *delz)
 {
     KBEGIN(G.nz);
@@ -2390,14 +2428,28 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
                                         (const B *)W.qo, delp, pt, w, s->mfx, s->mfy);
         STOP(6);
         // dz_d
-        launch2d(k_heights, -3, n + 2, -3, n + 2, T, st, G, (const double *)delz, phis, W.zh);
-        {
+        if constexpr (std::is_same<B, float>::value) {
+            // FP32 deviations from per-interface reference heights: the input
+            // and the references in the FP64 height scratch zh (the input
+            // fills half of it), the output in zn
+            const long ei = alloc_elems(g, nz + 1);
+            float *zd = (float *)W.zh, *zdn = (float *)W.zn;
+            double *zref = (double *)((float *)W.zh + ((ei + 63) / 64) * 64);
+            launch2d(k_heights_dev, -3, n + 2, -3, n + 2, T, st, G, (const double *)delz, phis, zref, zd);
+            FvArgs<float, B, double> a{};
+            a.q = zd; a.Lq = nz + 1; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
+            a.iface = 1; a.area = M.m[M_AREA]; a.epi = EPI_ADV; a.qout = zdn;
+            fvtp(g, P, a, st);
+            launch2d(k_delz_from_zdev, 0, n - 1, 0, n - 1, P, st, G, (const float *)zdn, (const double *)zref, phis,
+                     delz);
+        } else {
+            launch2d(k_heights, -3, n + 2, -3, n + 2, T, st, G, (const double *)delz, phis, W.zh);
             FvArgs<double, B, double> a{};
             a.q = W.zh; a.Lq = nz + 1; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
             a.iface = 1; a.area = Md.m[M_AREA]; a.epi = EPI_ADV; a.qout = W.zn;
             fvtp(g, P, a, st);
+            launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         }
-        launch2d(k_delz_from_zh, 0, n - 1, 0, n - 1, P, st, G, (const double *)W.zn, phis, delz);
         STOP(7);
         // riem_solver3
         sim1_pass1(g, qvp != nullptr, [&](auto offc, auto ppo, auto moist) {
