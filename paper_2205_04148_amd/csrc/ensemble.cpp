@@ -53,16 +53,15 @@ dim3 site_table(const fv3_ensemble *e, size_t s, std::vector<MemberBlk> &tab)
     const Site &S = e->rec.sites[s];
     dim3 b = S.tunable ? kShapes[e->shape[s]] : S.blk;
     tab.resize(e->members);
-    int z = 0, gx = 0, gy = 0;
+    long total = 0;
     for (int m = 0; m < e->members; m++) {
         int x = S.tunable ? (S.ex[m] + (int)b.x - 1) / (int)b.x : S.ex[m];
         int y = S.tunable ? (S.ey[m] + (int)b.y - 1) / (int)b.y : S.ey[m];
-        tab[m] = MemberBlk{z, x, y, 0};
-        z += S.ez[m];
-        gx = std::max(gx, x);
-        gy = std::max(gy, y);
+        tab[m] = MemberBlk{(int)total, x, y, S.ez[m]};
+        total += (long)x * y * S.ez[m];
     }
-    return dim3((unsigned)std::max(gx, 1), (unsigned)std::max(gy, 1), (unsigned)std::max(z, 1));
+    // one-dimensional grid: every member's blocks back to back
+    return dim3((unsigned)std::max(total, 1L), 1, 1);
 }
 
 fv3_status upload_table(fv3_ensemble *e, size_t s)

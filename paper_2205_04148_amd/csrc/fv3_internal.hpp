@@ -64,10 +64,10 @@ struct Bk {
     unsigned x, y, z;
 };
 
-// Ensemble launches: per member, the first grid-z index of its planes and its
-// own x/y grid extent.
+// Ensemble launches: per member, its first block in the one-dimensional
+// launch grid and its own x/y/z block extents.
 struct MemberBlk {
-    int z0, gx, gy, pad;
+    int b0, gx, gy, gz;
 };
 
 // One recorded kernel launch of the substep sequence, for all members:

@@ -216,17 +216,21 @@ template <auto F, class... A>
 __global__ void __launch_bounds__(256) k_multi(const Tup<A...> *__restrict__ args, const MemberBlk *__restrict__ tab,
                                                int members)
 {
-    const Bk b = xcd_block();
-    const int z = (int)b.z;
+    // one-dimensional grid over every member's own blocks back to back (no
+    // block outside a member's extent): find the member, then its block
+    const int L = (int)xcd_block().x;
     int lo = 0, hi = members - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].z0 <= z) lo = mid;
+        if (tab[mid].b0 <= L) lo = mid;
         else hi = mid - 1;
     }
     const MemberBlk mb = tab[lo];
-    if ((int)b.x >= mb.gx || (int)b.y >= mb.gy) return;
-    tcall<F>(Bk{b.x, b.y, (unsigned)(z - mb.z0)}, args[lo], std::index_sequence_for<A...>{});
+    const int gxy = mb.gx * mb.gy, local = L - mb.b0;
+    if (gxy <= 0) return;
+    const int bz = local / gxy, rem = local - bz * gxy, by = rem / mb.gx, bx = rem - by * mb.gx;
+    if (bz >= mb.gz) return;
+    tcall<F>(Bk{(unsigned)bx, (unsigned)by, (unsigned)bz}, args[lo], std::index_sequence_for<A...>{});
 }
 
 // Recording of the launch sequence of one call per member (ensemble mode).
