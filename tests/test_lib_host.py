@@ -72,3 +72,21 @@ def test_host_metrics_match_oracle(fv3, orc, kind, n):
         scale = max(np.abs(b).max(), 1e-300)
         err = np.abs(a - b).max() / scale
         assert err <= 1e-13, (name, err)
+
+
+def test_pmc_launch_names():
+    """Counter rows map to the launch names of the timing hooks: fv_tp_2d by its
+    epilogue (not its PPM order), the column solves by pass and site."""
+    from paper_2205_04148_amd import pmc
+
+    fvtp = ("_ZN3fv35k_oneITnDaXadL_ZNS_6k_fvtpIfffLi{e}ELi{o}EEEvNS_2BkENS_3GeoENS_6FvArgs"
+            "IT_T0_T1_EEEEJS3_NS4_IfffEEEEEvDpT0_")
+    for e, want in pmc.FVTP_EPI.items():
+        for o in (5, 6, 7, 8):
+            assert pmc.launch_name(fvtp.format(e=e, o=o)) == want
+    sim1 = ("_ZN3fv35k_oneITnDaXadL_ZNS_6k_sim1IffLi{p}ELi{s}ELb0ELi2ELb0EEEvNS_2BkEiiiiiNS_3GeoE"
+            "dddPKT_S6_S6_PKdPKT0_S8_PdSC_SC_PS9_SC_SC_SC_iEEJiiiiiS3_dddPKfSF_SF_S8_SF_S8_SC_SC_SC_"
+            "PfSC_SC_SC_iEEEvDpT0_")
+    assert pmc.launch_name(sim1.format(p=1, s=0)) == "k_sim1_c.p1"
+    assert pmc.launch_name(sim1.format(p=4, s=1)) == "k_sim1_3.p4"
+    assert pmc.launch_name("_ZN2at6native18elementwise_kernelIiEEvv") is None
