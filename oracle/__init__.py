@@ -64,6 +64,9 @@ def lib():
         L.orc_set_damp4.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_vtdm.argtypes = [C.c_void_p, C.c_double]
         L.orc_set_edge_fix.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_edge_ppm.argtypes = [C.c_void_p, C.c_int]
+        L.orc_ppm_face_edge.restype = C.c_double
+        L.orc_ppm_face_edge.argtypes = [dp, dp, C.c_double, C.c_int, C.c_int, C.c_int]
         L.orc_edge_partner.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
         L.orc_corner_div.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
         L.orc_corner_lap.argtypes = [C.c_void_p, C.c_int, dp, dp]
@@ -115,7 +118,8 @@ class Grid:
                  radius: float = RADIUS, omega: float = OMEGA, ptop: float = 100.0,
                  d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
                  hord_tr: int = 0, pp_order: int = 2, nord: int = 0, d4_bg: float = 0.0,
-                 vtdm: float = 0.0, edge_fix: bool = False):
+                 vtdm: float = 0.0, edge_fix: bool = False,
+                 edge_ppm: bool = False):
         if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
             raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
         if pp_order not in (2, 4):
@@ -143,6 +147,8 @@ class Grid:
         lib().orc_set_vtdm(h, float(vtdm))
         self.edge_fix = edge_fix
         lib().orc_set_edge_fix(h, int(bool(edge_fix)))
+        self.edge_ppm = edge_ppm
+        lib().orc_set_edge_ppm(h, int(bool(edge_ppm)))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -201,6 +207,16 @@ def ppm_face(q6, c: float, hord: int = 8) -> float:
     if hord == 8:
         return lib().orc_ppm_face(_p(q), float(c))
     return lib().orc_ppm_face_order(_p(q), float(c), int(hord))
+
+
+def ppm_face_edge(q6, w6, c: float, hord: int, pe: int, west: bool) -> float:
+    """Face value between window cells 2 and 3 when window interface pe
+    (1..5, between cells pe-1 and pe) is a cube tile edge; w6 are the cell
+    widths along the sweep, west says the tile lies at cells >= pe."""
+    q = np.ascontiguousarray(q6, dtype=np.float64)
+    w = np.ascontiguousarray(w6, dtype=np.float64)
+    assert q.shape == (6,) and w.shape == (6,) and 1 <= pe <= 5
+    return lib().orc_ppm_face_edge(_p(q), _p(w), float(c), int(hord), int(pe), int(bool(west)))
 
 
 def fv_tp_2d(g: Grid, t: int, q, crx, cry, xfx, yfx, mx=None, my=None):

@@ -43,6 +43,7 @@ void orc_set_damping(void *gp, double d2_bg)
 void orc_set_smag(void *gp, double dddmp) { ((OGrid *)gp)->dddmp = dddmp; }
 void orc_set_vtdm(void *gp, double vtdm) { ((OGrid *)gp)->vtdm = vtdm; }
 void orc_set_edge_fix(void *gp, int on) { ((OGrid *)gp)->edge_fix = on; }
+void orc_set_edge_ppm(void *gp, int on) { ((OGrid *)gp)->edge_ppm = on; }
 
 int orc_edge_partner(void *gp, int t, int st, int i, int j, int *out4)
 {
@@ -141,6 +142,10 @@ int orc_corner_view_pair(void *gp, const double *px, int stx, const double *py, 
 
 double orc_ppm_face(const double *q6, double c) { return o_ppm_face(q6, c); }
 double orc_ppm_face_order(const double *q6, double c, int ord) { return o_ppm_face_order(q6, c, ord); }
+double orc_ppm_face_edge(const double *q6, const double *w6, double c, int ord, int pe, int west)
+{
+    return o_ppm_face_edge(q6, w6, c, ord, pe, west);
+}
 void orc_set_hord(void *gp, int hord, int hord_tr)
 {
     ((OGrid *)gp)->hord = hord;

@@ -63,6 +63,7 @@ typedef struct {
     double vtdm;
     /* cube: replace both tiles' fluxes through a shared edge face by their mean */
     int edge_fix;
+    int edge_ppm;          /* one-sided PPM edge values at cube tile edges */
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -102,6 +103,7 @@ int og_edge_partner(const OGrid *g, int t, int st, int i, int j, int *tp, int *s
 
 /* ppm.c */
 double o_ppm_face(const double q[6], double c);
+double o_ppm_face_edge(const double q[6], const double w[6], double c, int ord, int pe, int west);
 double o_ppm_face_order(const double q[6], double c, int ord);
 void o_fv_tp_2d_ord(const OGrid *g, int ord, int t, const double *q, const double *qx, const double *qy,
                     const double *crx, const double *cry, const double *xfx, const double *yfx,
