@@ -98,7 +98,16 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * mean and the cell next to the face takes the difference, so the global
  * sums of mass, pt mass and tracer masses are exact; the accumulated mass
  * fluxes take the mean too (no effect on the doubly periodic grid; other
- * values: FV3_EINVAL). */
+ * values: FV3_EINVAL).  edge_ppm = 1 on the cube: every flux-form transport
+ * (fv_tp_2d of delp, pt, w, the vorticity, the dz_d heights and the
+ * tracers) builds the PPM edge values at the three interfaces around each
+ * tile edge from one side only, the edge value itself as the mean of the two
+ * width-weighted linear extrapolations to the edge (the panel-edge treatment
+ * of Putman & Lin 2007); order 8 constrains the two cells beside the edge
+ * and the second cell inside the tile to monotone parabolas (Colella &
+ * Woodward 1984) instead of clipping to twice the slope.  Sweeps through the
+ * corner halo keep the centred stencil.  No effect on the doubly periodic
+ * grid; other values: FV3_EINVAL. */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -118,6 +127,7 @@ typedef struct {
     double d4_bg;        /* its coefficient, 0 .. 0.25                    */
     double vtdm;         /* del-2 vorticity damping, 0 (off) .. 0.25       */
     int edge_fix;        /* cube: edge-flux fix-up, 0 (off) or 1          */
+    int edge_ppm;        /* cube: one-sided PPM at tile edges, 0 or 1     */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

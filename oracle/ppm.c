@@ -44,7 +44,9 @@
  *    the parabola when the mean is not between its edge values, else move
  *    the edge opposite an interior extremum so the extremum sits on the
  *    cell boundary.
- * Only faces 0, 1, 2 and n-2, n-1, n have an edge cell upwind.
+ * Only faces 0, 1, 2 and n-2, n-1, n have an edge cell upwind.  Linear exactness
+ * fixes the one-sided weights up to one free parameter; the published value
+ * taken for it has no independent check (parity unpinned for that weight).
  */
 #include "orc.h"
 #include <math.h>

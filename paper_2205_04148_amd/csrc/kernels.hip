@@ -422,6 +422,94 @@ DEVI T ppm_lds(const T *p, T c)
     return ppm_up<ORD>(u[0], u[S], u[2 * S], u[3 * S], u[4 * S], c);
 }
 
+// Face value next to a cube tile edge (option edge_ppm, Putman & Lin 2007).
+// p holds the six cells m-3..m+2 of the sweep, S apart; w their widths along
+// the sweep, ws apart.  Window interface pe (between window cells pe-1 and
+// pe, 1 <= pe <= 5) is the edge; the tile lies at cells >= pe (west) or
+// below pe.  The edge values of the three interfaces around the edge are
+// one-sided: at the edge, the mean of the linear extrapolations from the two
+// cells on either side (by distance); next to it, three cells of its own
+// side, (3 q_near + 11 q_far) / 14 -+ (4/7) times the far cell's slope.
+// Order 8 leaves the deviations of the two cells beside the edge and of the
+// second cell inside the tile unclipped and makes their parabolas monotone
+// (Colella & Woodward 1984).  Written without dynamically indexed arrays.
+template <int ORD, class T>
+DEVI T ppm_edge(const T *p, int S, const T *w, int ws, T c, int pe, bool west)
+{
+    T q[6], x[6], dm[6], al[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        q[k] = p[k * S];
+        x[k] = w[k * ws];
+    }
+    const bool pos = c > 0;
+    if constexpr (ORD == 5) {
+        const bool x1 = (q[1] - q[0]) * (q[2] - q[1]) < (T)0, x2 = (q[2] - q[1]) * (q[3] - q[2]) < (T)0;
+        const bool x3 = (q[3] - q[2]) * (q[4] - q[3]) < (T)0, x4 = (q[4] - q[3]) * (q[5] - q[4]) < (T)0;
+        if (pos ? (x2 && (x1 || x3)) : (x3 && (x2 || x4))) return pos ? q[2] : q[3];
+    }
+#pragma unroll
+    for (int k = 1; k <= 4; k++)
+        dm[k] = ORD == 8 ? lslope(q[k - 1], q[k], q[k + 1]) : (q[k + 1] - q[k - 1]) * (T)0.25;
+    const T third = (T)1 / (T)3, r14 = (T)1 / (T)14, f47 = (T)4 / (T)7;
+#pragma unroll
+    for (int k = 2; k <= 4; k++) {
+        T v = (T)0.5 * (q[k - 1] + q[k]) + (dm[k - 1] - dm[k]) * third;
+        if (k == pe) {
+            const T lo = (((T)2 * x[k - 1] + x[k - 2]) * q[k - 1] - x[k - 1] * q[k - 2]) / (x[k - 2] + x[k - 1]);
+            const T hi = (((T)2 * x[k] + x[k + 1]) * q[k] - x[k] * q[k + 1]) / (x[k] + x[k + 1]);
+            v = (T)0.5 * (lo + hi);
+        } else if (k == pe - 1) {
+            v = ((T)3 * q[k] + (T)11 * q[k - 1]) * r14 + f47 * dm[k - 1];
+        } else if (k == pe + 1) {
+            v = ((T)3 * q[k - 1] + (T)11 * q[k]) * r14 - f47 * dm[k];
+        }
+        al[k] = v;
+    }
+    const int s = pos ? 2 : 3;
+    const T qs = pos ? q[2] : q[3], ds = pos ? dm[2] : dm[3];
+    const T aL = pos ? al[2] : al[3], aR = pos ? al[3] : al[4];
+    const bool edge_cell = s == pe - 1 || s == pe || s == (west ? pe + 1 : pe - 2);
+    T bl = aL - qs, br = aR - qs;
+    if constexpr (ORD == 8) {
+        if (!edge_cell) {
+            const T a2 = (T)2 * fabs(ds);
+            bl = copysign(fmin(a2, fabs(bl)), -ds);
+            br = copysign(fmin(a2, fabs(br)), ds);
+        } else if (bl * br >= (T)0) {
+            bl = br = (T)0;
+        } else {
+            const T da = br - bl, a6 = (T)-3 * (bl + br);
+            if (a6 * da > da * da) bl = (T)-2 * br;
+            else if (a6 * da < -(da * da)) br = (T)-2 * bl;
+        }
+    }
+    if constexpr (ORD == 7) {
+        if (qs >= (T)0) {
+            const T eL = qs + bl, eR = qs + br, a6 = (T)-3 * (bl + br), da = eR - eL;
+            T mn = fmin(eL, eR);
+            if (a6 < (T)0 && fabs(da) < -a6) mn = fmin(mn, qs + da * da / ((T)4 * a6) + a6 / (T)12);
+            if (mn < (T)0) {
+                const T th = qs / (qs - mn);
+                bl *= th;
+                br *= th;
+            }
+        }
+    }
+    const T cc = fabs(c);
+    return qs + ((T)1 - cc) * ((pos ? br : bl) - cc * (bl + br));
+}
+
+// Window position of a tile edge for face m of a sweep over n cells, or 0
+// when the face has no edge cell upwind (faces 0, 1, 2 and n-2, n-1, n do).
+DEVI int edge_pe(int m, int n, bool &west)
+{
+    west = m <= 2;
+    if (m >= 0 && m <= 2) return 3 - m;
+    if (m >= n - 2 && m <= n) return n - m + 3;
+    return 0;
+}
+
 // ====================================================================
 // Halo exchange: plan-driven copies from the neighbour tile's interior
 // (orientation transform folded into the plan for vector pairs).
@@ -1272,6 +1360,7 @@ struct FvArgs {
     int Lc, iface;
     const M *mx, *my;      // optional flux weights (mass fluxes)
     const T *area;         // area metric (type T)
+    const T *dxa, *dya;    // cell widths along x and y (type T; tile-edge PPM)
     int epi;
     T *FX, *FY;            // flux outputs (may be null)
     int edges_only;        // write the flux outputs on tile-edge faces only
@@ -1289,7 +1378,7 @@ DEVI T ccr(const C *a, const C *a0, int idx, int avg)
     return (T)a[idx];
 }
 
-template <class T, class C, class M, int EPI, int ORD>
+template <class T, class C, class M, int EPI, int ORD, int EDGE>
 DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
 {
     constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
@@ -1312,6 +1401,8 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     const int avg = A.iface && k > 0;
     const long ob = avg ? pidx(G, A.Lc, t, k - 1) : oc;
     const T *AR = A.area + G.off0 + (long)t * G.lev;
+    const T *DXA = EDGE ? A.dxa + G.off0 + (long)t * G.lev : nullptr;
+    const T *DYA = EDGE ? A.dya + G.off0 + (long)t * G.lev : nullptr;
     const int P = (int)G.pitch;
     const C *cry = A.cry + oc, *yfx = A.yfx + oc, *crx = A.crx + oc, *xfx = A.xfx + oc;
     const C *cry0 = A.cry + ob, *yfx0 = A.yfx + ob, *crx0 = A.crx + ob, *xfx0 = A.xfx + ob;
@@ -1403,6 +1494,11 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (i <= n + 2 && j <= n) {
             const T *col = sQy + r * QW + c;
             f = ppm_lds<QW, ORD>(col, sCY[e]);
+            if constexpr (EDGE) {
+                bool west;
+                const int pe = (i >= 0 && i < n) ? edge_pe(j, n, west) : 0;
+                if (pe) f = ppm_edge<ORD>(col, QW, DYA + (j - 3) * P + i, P, sCY[e], pe, west);
+            }
         }
         sFy[e] = f;
     }
@@ -1413,6 +1509,11 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (i <= n && j <= n + 2) {
             const T *row = sQ + r * QW + c;
             f = ppm_lds<1, ORD>(row, sCX[e]);
+            if constexpr (EDGE) {
+                bool west;
+                const int pe = (j >= 0 && j < n) ? edge_pe(i, n, west) : 0;
+                if (pe) f = ppm_edge<ORD>(row, 1, DXA + j * P + i - 3, 1, sCX[e], pe, west);
+            }
         }
         sFx[e] = f;
     }
@@ -1453,6 +1554,11 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             int s = (r + 3) * XW + c;
             const T *row = sQi + r * QW + c;
             T fx = ppm_lds<1, ORD>(row, sCX[s]);
+            if constexpr (EDGE) {
+                bool west;
+                const int pe = edge_pe(i, n, west);
+                if (pe) fx = ppm_edge<ORD>(row, 1, DXA + j * P + i - 3, 1, sCX[s], pe, west);
+            }
             T wgt = A.mx ? (T)wx[m] : sXF[s];
             T F = (T)0.5 * (fx + sFx[s]) * wgt;
             sFx[s] = F;
@@ -1476,6 +1582,11 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             int s = r * YW + c + 3;
             const T *col = sQj + r * FTX + c;
             T fy = ppm_lds<FTX, ORD>(col, sCY[s]);
+            if constexpr (EDGE) {
+                bool west;
+                const int pe = edge_pe(j, n, west);
+                if (pe) fy = ppm_edge<ORD>(col, FTX, DYA + (j - 3) * P + i, P, sCY[s], pe, west);
+            }
             T wgt = A.my ? (T)wy[m] : sYF[s];
             T F = (T)0.5 * (fy + sFy[s]) * wgt;
             sFy[s] = F;
@@ -1521,7 +1632,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     }
 }
 
-template <class T, class C, class M, int ORD>
+template <class T, class C, class M, int ORD, int EDGE>
 static void fvtp_order(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
 {
     static const char *names[] = {"k_fvtp_flux", "k_fvtp_delp", "k_fvtp_massw", "k_fvtp_adv", "k_fvtp_tracer"};
@@ -1529,30 +1640,49 @@ static void fvtp_order(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, 
     dim3 grd((unsigned)((g->n + FTX - 1) / FTX), (unsigned)((g->n + FTY - 1) / FTY), (unsigned)planes);
     if constexpr (ORD == 7) {
         // the positive-definite order exists for the tracer transport only
-        launch_fn<k_fvtp<T, C, M, EPI_TRACER, ORD>>(names[EPI_TRACER], grd, dim3(FNT), st, g->geo, a);
+        launch_fn<k_fvtp<T, C, M, EPI_TRACER, ORD, EDGE>>(names[EPI_TRACER], grd, dim3(FNT), st, g->geo, a);
     } else {
         switch (a.epi) {
-        case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-        case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-        case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-        case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
-        default: launch_fn<k_fvtp<T, C, M, EPI_TRACER, ORD>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_FLUX: launch_fn<k_fvtp<T, C, M, EPI_FLUX, ORD, EDGE>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_DELP: launch_fn<k_fvtp<T, C, M, EPI_DELP, ORD, EDGE>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_MASSW: launch_fn<k_fvtp<T, C, M, EPI_MASSW, ORD, EDGE>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        case EPI_ADV: launch_fn<k_fvtp<T, C, M, EPI_ADV, ORD, EDGE>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
+        default: launch_fn<k_fvtp<T, C, M, EPI_TRACER, ORD, EDGE>>(names[a.epi], grd, dim3(FNT), st, g->geo, a); break;
         }
     }
 }
 
+template <class T, class C, class M, int EDGE>
+static void fvtp_ord(const fv3_grid *g, int ord, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
+{
+    switch (ord) {
+    case 5: fvtp_order<T, C, M, 5, EDGE>(g, planes, a, st); break;
+    case 6: fvtp_order<T, C, M, 6, EDGE>(g, planes, a, st); break;
+    case 7: fvtp_order<T, C, M, 7, EDGE>(g, planes, a, st); break;
+    default: fvtp_order<T, C, M, 8, EDGE>(g, planes, a, st); break;
+    }
+}
+
 // the grid's PPM order applies to every transport of the call; the tracer
-// transport takes hord_tr when that is set
+// transport takes hord_tr when that is set.  On the cube with edge_ppm the
+// tile-edge instantiation runs, with the cell widths in the field's type.
 template <class T, class C, class M>
 static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStream_t st)
 {
     int ord = g->p.hord;
     if (a.epi == EPI_TRACER && g->p.hord_tr != 0) ord = g->p.hord_tr;
-    switch (ord) {
-    case 5: fvtp_order<T, C, M, 5>(g, planes, a, st); break;
-    case 6: fvtp_order<T, C, M, 6>(g, planes, a, st); break;
-    case 7: fvtp_order<T, C, M, 7>(g, planes, a, st); break;
-    default: fvtp_order<T, C, M, 8>(g, planes, a, st); break;
+    if (g->p.edge_ppm && g->p.kind == FV3_GRID_CUBED_SPHERE) {
+        FvArgs<T, C, M> b = a;
+        if constexpr (std::is_same<T, double>::value) {
+            b.dxa = g->met[M_DXA];
+            b.dya = g->met[M_DYA];
+        } else {
+            b.dxa = g->metf[M_DXA];
+            b.dya = g->metf[M_DYA];
+        }
+        fvtp_ord<T, C, M, 1>(g, ord, planes, b, st);
+    } else {
+        fvtp_ord<T, C, M, 0>(g, ord, planes, a, st);
     }
 }
 

@@ -44,8 +44,9 @@ def launch_name(symbol: str):
     name, targs = rest[:ln], rest[ln:]
     ints = [int(x) for x in re.findall(r"Li(\d+)E", targs.split("EEvNS_")[0])]
     if name == "k_fvtp" and ints:
-        # template integers: the epilogue, then the PPM order
-        return FVTP_EPI.get(ints[-2] if len(ints) >= 2 else ints[-1], name)
+        # template integers: the epilogue first (then the PPM order and the
+        # tile-edge switch)
+        return FVTP_EPI.get(ints[0], name)
     if name == "k_sim1" and len(ints) >= 2:
         return f"k_sim1_{'c' if ints[1] == 0 else '3'}.p{ints[0]}"
     if name in ("k_csw", "k_nhpgrad", "k_halo_scalar", "k_halo_pair", "k_fill"):

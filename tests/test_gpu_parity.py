@@ -643,6 +643,75 @@ def test_edge_fix_periodic_untouched(fv3):
         np.testing.assert_array_equal(out[0][k], out[1][k])
 
 
+@pytest.mark.parametrize("n,nz,stop,dt,ns,precision,hord,hord_tr", [
+    (12, 5, 6, 300.0, 1, "fp64", 8, 0),
+    (12, 5, 6, 300.0, 1, "fp64", 6, 0),
+    (12, 5, 6, 300.0, 1, "fp64", 5, 0),
+    (24, 10, 0, 2000.0, 10, "fp64", 8, 7),
+    (24, 10, 0, 2000.0, 10, "mixed", 8, 0),
+])
+def test_edge_ppm_parity(fv3, orc, n, nz, stop, dt, ns, precision, hord, hord_tr):
+    """One-sided PPM at the cube's tile edges against the oracle: after one
+    d_sw (1e-13) and after 10 substeps and the tracer transport (1e-11;
+    mixed: the mixed bars).  After one d_sw the device also differs from the
+    oracle without the option by far more than the bar, so the tile-edge
+    instantiation is the one that ran."""
+    import torch
+
+    init = fi.cube_state(n=n, nz=nz, nq=1)
+    g = fv3.Grid(1, n, nz, dx=1.0e5, precision=precision, hord=hord, hord_tr=hord_tr, edge_ppm=True)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(1, n, nz, delta=1.0e5, hord=hord, hord_tr=hord_tr, edge_ppm=True)
+    os_ = orc.new_state(og, init)
+    label = f"edgeppm n{n} stop{stop} {precision} hord{hord}/{hord_tr}"
+    print(label, flush=True)
+    qd = [g.upload(q, nz) for q in init["q"]]
+    fv3.acoustic_substeps(s, g, dt, ns, stop_stage=stop)
+    assert orc.acoustic_substeps(og, os_, dt, ns, stop_stage=stop) == 0
+    if precision == "mixed":
+        tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
+        fields = tuple(tol)
+    elif stop == 6:
+        fields, tol = ("u", "v", "delp", "pt", "w", "mfx", "mfy"), 1e-13
+    else:
+        fields, tol = ("u", "v", "w", "delp", "pt", "delz", "mfx", "mfy", "pfull", "phi"), 1e-11
+    _compare(s, os_, n, fields, tol, label)
+    if stop == 6:
+        og0 = orc.Grid(1, n, nz, delta=1.0e5, hord=hord, hord_tr=hord_tr)
+        os0 = orc.new_state(og0, init)
+        assert orc.acoustic_substeps(og0, os0, dt, ns, stop_stage=stop) == 0
+        d = max(_relerr(_int(s.get(k), n, "C"), _int(os0[k], n, "C")) for k in ("delp", "pt"))
+        print(f"{label} vs no edge_ppm {d:.2e}", flush=True)
+        assert d > 1e-9
+        return
+    assert fv3.check_status(g) == 0
+    qh = [q.copy() for q in init["q"]]
+    fv3.tracer_transport(qd, s, g)
+    orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+    torch.cuda.synchronize()
+    e = _relerr(_int(g.download(qd[0], nz), n, "C"), _int(qh[0], n, "C"))
+    print(f"{label} tracer {e:.2e}", flush=True)
+    assert e <= (1e-11 if precision == "fp64" else 1e-4)
+
+
+def test_edge_ppm_periodic_untouched(fv3):
+    """The doubly periodic grid has no tile edges: edge_ppm changes nothing."""
+    import torch
+
+    init = fi.periodic_state(n=16, nz=3)
+    out = []
+    for ep in (False, True):
+        g = fv3.Grid(0, 16, 3, edge_ppm=ep)
+        s = fv3.State.allocate(g)
+        s.load(init)
+        fv3.acoustic_substeps(s, g, 2.0, 5)
+        torch.cuda.synchronize()
+        out.append({k: s.get(k) for k in ("u", "v", "delp", "pt", "w")})
+    for k in out[0]:
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
 def test_higher_order_damping_abi(fv3):
     import ctypes as C
 
@@ -660,6 +729,12 @@ def test_higher_order_damping_abi(fv3):
         p = fv3.GridParams(**dict(base, edge_fix=ef))
         h = C.c_void_p()
         assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, ef
+        if want == 0:
+            fv3.lib().fv3_free_grid(h)
+    for ep, want in ((2, -1), (-1, -1), (1, 0)):
+        p = fv3.GridParams(**dict(base, edge_ppm=ep))
+        h = C.c_void_p()
+        assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == want, ep
         if want == 0:
             fv3.lib().fv3_free_grid(h)
 

@@ -79,11 +79,12 @@ def test_pmc_launch_names():
     epilogue (not its PPM order), the column solves by pass and site."""
     from paper_2205_04148_amd import pmc
 
-    fvtp = ("_ZN3fv35k_oneITnDaXadL_ZNS_6k_fvtpIfffLi{e}ELi{o}EEEvNS_2BkENS_3GeoENS_6FvArgs"
+    fvtp = ("_ZN3fv35k_oneITnDaXadL_ZNS_6k_fvtpIfffLi{e}ELi{o}ELi{x}EEEvNS_2BkENS_3GeoENS_6FvArgs"
             "IT_T0_T1_EEEEJS3_NS4_IfffEEEEEvDpT0_")
     for e, want in pmc.FVTP_EPI.items():
         for o in (5, 6, 7, 8):
-            assert pmc.launch_name(fvtp.format(e=e, o=o)) == want
+            for x in (0, 1):
+                assert pmc.launch_name(fvtp.format(e=e, o=o, x=x)) == want
     sim1 = ("_ZN3fv35k_oneITnDaXadL_ZNS_6k_sim1IffLi{p}ELi{s}ELb0ELi2ELb0EEEvNS_2BkEiiiiiNS_3GeoE"
             "dddPKT_S6_S6_PKdPKT0_S8_PdSC_SC_PS9_SC_SC_SC_iEEJiiiiiS3_dddPKfSF_SF_S8_SF_S8_SC_SC_SC_"
             "PfSC_SC_SC_iEEEvDpT0_")
