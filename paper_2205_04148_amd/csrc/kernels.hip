@@ -509,6 +509,9 @@ DEVI int edge_pe(int m, int n, bool &west)
     if (m >= n - 2 && m <= n) return n - m + 3;
     return 0;
 }
+DEVI bool edge_face(int m, int n) { return m <= 2 || m >= n - 2; }
+// the k-th (0..5) face with an edge cell upwind: 0, 1, 2, n-2, n-1, n
+DEVI int edge_face_at(int k, int n) { return k < 3 ? k : n - 5 + k; }
 
 // ====================================================================
 // Halo exchange: plan-driven copies from the neighbour tile's interior
@@ -1494,11 +1497,6 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (i <= n + 2 && j <= n) {
             const T *col = sQy + r * QW + c;
             f = ppm_lds<QW, ORD>(col, sCY[e]);
-            if constexpr (EDGE) {
-                bool west;
-                const int pe = (i >= 0 && i < n) ? edge_pe(j, n, west) : 0;
-                if (pe) f = ppm_edge<ORD>(col, QW, DYA + (j - 3) * P + i, P, sCY[e], pe, west);
-            }
         }
         sFy[e] = f;
     }
@@ -1509,13 +1507,30 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (i <= n && j <= n + 2) {
             const T *row = sQ + r * QW + c;
             f = ppm_lds<1, ORD>(row, sCX[e]);
-            if constexpr (EDGE) {
-                bool west;
-                const int pe = (j >= 0 && j < n) ? edge_pe(i, n, west) : 0;
-                if (pe) f = ppm_edge<ORD>(row, 1, DXA + j * P + i - 3, 1, sCX[e], pe, west);
-            }
         }
         sFx[e] = f;
+    }
+    if constexpr (EDGE) {
+        // faces with an edge cell upwind, on sweeps whose cross index lies
+        // inside the tile (at most six per row or column): the one-sided
+        // values replace the centred ones
+        __syncthreads();
+        for (int e = tid; e < XH * 6; e += FNT) {
+            const int r = e / 6, i = edge_face_at(e - r * 6, n), c = i - i0, j = j0 - 3 + r;
+            if (c < 0 || c >= XW || j < 0 || j >= n) continue;
+            bool west;
+            const int pe = edge_pe(i, n, west);
+            const int f = r * XW + c;
+            sFx[f] = ppm_edge<ORD>(sQ + r * QW + c, 1, DXA + j * P + i - 3, 1, sCX[f], pe, west);
+        }
+        for (int e = tid; e < YW * 6; e += FNT) {
+            const int c = e / 6, j = edge_face_at(e - c * 6, n), r = j - j0, i = i0 - 3 + c;
+            if (r < 0 || r >= YH || i < 0 || i >= n) continue;
+            bool west;
+            const int pe = edge_pe(j, n, west);
+            const int f = r * YW + c;
+            sFy[f] = ppm_edge<ORD>(sQy + r * QW + c, QW, DYA + (j - 3) * P + i, P, sCY[f], pe, west);
+        }
     }
     __syncthreads();
     // 3. inner advective half updates
@@ -1543,32 +1558,50 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     }
     __syncthreads();
     // 4. final fluxes (in place over the outer fluxes)
+    auto put_x = [&](int i, int c, int fi, int s, T fx, T wgt) {
+        const T F = (T)0.5 * (fx + sFx[s]) * wgt;
+        sFx[s] = F;
+        if (c < FTX || i == n) {
+            if (A.FX && (!A.edges_only || i == 0 || i == n)) A.FX[oc + fi] = F;
+            if (EPI == EPI_DELP) {
+                A.mfx[oc + fi] += (double)F;
+                A.cxa[oc + fi] += (C)sCX[s];
+            }
+        }
+    };
+    auto put_y = [&](int j, int r, int fi, int s, T fy, T wgt) {
+        const T F = (T)0.5 * (fy + sFy[s]) * wgt;
+        sFy[s] = F;
+        if (r < FTY || j == n) {
+            if (A.FY && (!A.edges_only || j == 0 || j == n)) A.FY[oc + fi] = F;
+            if (EPI == EPI_DELP) {
+                A.mfy[oc + fi] += (double)F;
+                A.cya[oc + fi] += (C)sCY[s];
+            }
+        }
+    };
 #pragma unroll
     for (int m = 0; m < N4X; m++) {
         int e = tid + m * FNT;
         if (e >= FTY * XW) break;
         int r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 + r;
-        if (i <= n && j < n) {
-            int fi = j * P + i;
-            int s = (r + 3) * XW + c;
-            const T *row = sQi + r * QW + c;
-            T fx = ppm_lds<1, ORD>(row, sCX[s]);
-            if constexpr (EDGE) {
-                bool west;
-                const int pe = edge_pe(i, n, west);
-                if (pe) fx = ppm_edge<ORD>(row, 1, DXA + j * P + i - 3, 1, sCX[s], pe, west);
-            }
-            T wgt = A.mx ? (T)wx[m] : sXF[s];
-            T F = (T)0.5 * (fx + sFx[s]) * wgt;
-            sFx[s] = F;
-            if (c < FTX || i == n) {
-                if (A.FX && (!A.edges_only || i == 0 || i == n)) A.FX[oc + fi] = F;
-                if (EPI == EPI_DELP) {
-                    A.mfx[oc + fi] += (double)F;
-                    A.cxa[oc + fi] += (C)sCX[s];
-                }
-            }
+        if (i <= n && j < n && !(EDGE && edge_face(i, n))) {
+            const int s = (r + 3) * XW + c;
+            T fx = ppm_lds<1, ORD>(sQi + r * QW + c, sCX[s]);
+            put_x(i, c, j * P + i, s, fx, A.mx ? (T)wx[m] : sXF[s]);
+        }
+    }
+    if constexpr (EDGE) {
+        // the faces with an edge cell upwind, at most six per row
+        for (int e = tid; e < FTY * 6; e += FNT) {
+            const int r = e / 6, i = edge_face_at(e - r * 6, n), c = i - i0, j = j0 + r;
+            if (c < 0 || c >= XW || j >= n) continue;
+            const int fi = j * P + i, s = (r + 3) * XW + c;
+            bool west;
+            const int pe = edge_pe(i, n, west);
+            T fx = ppm_edge<ORD>(sQi + r * QW + c, 1, DXA + j * P + i - 3, 1, sCX[s], pe, west);
+            put_x(i, c, fi, s, fx, A.mx ? (T)A.mx[oc + fi] : sXF[s]);
         }
     }
 #pragma unroll
@@ -1577,26 +1610,22 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (e >= YH * FTX) break;
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
-        if (i < n && j <= n) {
-            int fi = j * P + i;
-            int s = r * YW + c + 3;
-            const T *col = sQj + r * FTX + c;
-            T fy = ppm_lds<FTX, ORD>(col, sCY[s]);
-            if constexpr (EDGE) {
-                bool west;
-                const int pe = edge_pe(j, n, west);
-                if (pe) fy = ppm_edge<ORD>(col, FTX, DYA + (j - 3) * P + i, P, sCY[s], pe, west);
-            }
-            T wgt = A.my ? (T)wy[m] : sYF[s];
-            T F = (T)0.5 * (fy + sFy[s]) * wgt;
-            sFy[s] = F;
-            if (r < FTY || j == n) {
-                if (A.FY && (!A.edges_only || j == 0 || j == n)) A.FY[oc + fi] = F;
-                if (EPI == EPI_DELP) {
-                    A.mfy[oc + fi] += (double)F;
-                    A.cya[oc + fi] += (C)sCY[s];
-                }
-            }
+        if (i < n && j <= n && !(EDGE && edge_face(j, n))) {
+            const int s = r * YW + c + 3;
+            T fy = ppm_lds<FTX, ORD>(sQj + r * FTX + c, sCY[s]);
+            put_y(j, r, j * P + i, s, fy, A.my ? (T)wy[m] : sYF[s]);
+        }
+    }
+    if constexpr (EDGE) {
+        // the faces with an edge cell upwind, at most six per column
+        for (int e = tid; e < FTX * 6; e += FNT) {
+            const int c = e / 6, j = edge_face_at(e - c * 6, n), r = j - j0, i = i0 + c;
+            if (r < 0 || r >= YH || i >= n) continue;
+            const int fi = j * P + i, s = r * YW + c + 3;
+            bool west;
+            const int pe = edge_pe(j, n, west);
+            T fy = ppm_edge<ORD>(sQj + r * FTX + c, FTX, DYA + (j - 3) * P + i, P, sCY[s], pe, west);
+            put_y(j, r, fi, s, fy, A.my ? (T)A.my[oc + fi] : sYF[s]);
         }
     }
     if constexpr (EPI == EPI_FLUX) return;
