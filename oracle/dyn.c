@@ -605,13 +605,19 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             size_t b = IX(g, i, j);
             double ub = 0.5 * bdt * (ut[IX(g, i, j - 1)] + ut[b]);
             double vb = 0.5 * bdt * (vt[IX(g, i - 1, j)] + vt[b]);
-            double a6[6];
+            double a6[6], w6[6];
             double cxu = ub / dx[ub > 0.0 ? IX(g, i - 1, j) : b];
-            for (int s = 0; s < 6; s++) a6[s] = u[IX(g, i - 3 + s, j)];
-            double ubv = o_ppm_face_order(a6, cxu, g->hord);
+            for (int s = 0; s < 6; s++) {
+                a6[s] = u[IX(g, i - 3 + s, j)];
+                w6[s] = dx[IX(g, i - 3 + s, j)];
+            }
+            double ubv = o_ppm_face_wind(g, a6, w6, cxu, g->hord, i);
             double cyv = vb / dy[vb > 0.0 ? IX(g, i, j - 1) : b];
-            for (int s = 0; s < 6; s++) a6[s] = v[IX(g, i, j - 3 + s)];
-            double vbv = o_ppm_face_order(a6, cyv, g->hord);
+            for (int s = 0; s < 6; s++) {
+                a6[s] = v[IX(g, i, j - 3 + s)];
+                w6[s] = dy[IX(g, i, j - 3 + s)];
+            }
+            double vbv = o_ppm_face_wind(g, a6, w6, cyv, g->hord, j);
             ke[b] = 0.5 * (ub * ubv + vb * vbv);
         }
     /* (v') optional del-2 divergence damping: nu times the divergence of the

@@ -104,6 +104,7 @@ int og_edge_partner(const OGrid *g, int t, int st, int i, int j, int *tp, int *s
 /* ppm.c */
 double o_ppm_face(const double q[6], double c);
 double o_ppm_face_edge(const double q[6], const double w[6], double c, int ord, int pe, int west);
+double o_ppm_face_wind(const OGrid *g, const double q[6], const double w[6], double c, int ord, int m);
 double o_ppm_face_order(const double q[6], double c, int ord);
 void o_fv_tp_2d_ord(const OGrid *g, int ord, int t, const double *q, const double *qx, const double *qy,
                     const double *crx, const double *cry, const double *xfx, const double *yfx,

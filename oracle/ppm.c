@@ -171,12 +171,28 @@ double o_ppm_face_edge(const double q[6], const double w[6], double c, int ord, 
  * x lies inside the tile take the one-sided values: the sweeps through the
  * corner halo (which feed only the cross-direction updates of halo cells)
  * keep the centred stencil, there being no cell widths in the corner halo. */
-static int edge_window(const OGrid *g, int m, int x, int *pe, int *west)
+static int edge_faces(const OGrid *g, int m, int *pe, int *west)
 {
-    if (!g->edge_ppm || g->kind != 1 || x < 0 || x >= g->n) return 0;
+    if (!g->edge_ppm || g->kind != 1) return 0;
     if (m >= 0 && m <= 2) { *pe = 3 - m; *west = 1; return 1; }
     if (m >= g->n - 2 && m <= g->n) { *pe = g->n - m + 3; *west = 0; return 1; }
     return 0;
+}
+static int edge_window(const OGrid *g, int m, int x, int *pe, int *west)
+{
+    if (x < 0 || x >= g->n) return 0;
+    return edge_faces(g, m, pe, west);
+}
+
+/* The kinetic-energy upwinding of d_sw sweeps the D-grid winds along their
+ * own rows (u along x, v along y), the cells being the winds' faces with
+ * widths dx (dy); its rows 0..n all lie on the tile, so the one-sided edge
+ * values apply at faces 0-2 and n-2..n of every row. */
+double o_ppm_face_wind(const OGrid *g, const double q[6], const double w[6], double c, int ord, int m)
+{
+    int pe, west;
+    if (edge_faces(g, m, &pe, &west)) return o_ppm_face_edge(q, w, c, ord, pe, west);
+    return o_ppm_face_order(q, c, ord);
 }
 
 static double ppm_x(const OGrid *g, int t, const double *q, int i, int j, double c, int ord)

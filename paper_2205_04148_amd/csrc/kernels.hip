@@ -1837,6 +1837,54 @@ DEVI B edge_mean_delta(const Geo &G, const EdgeCell &c, int q, int k, const B *F
     return (B)0.5 * (fo + fp) - fo;
 }
 
+// Tile-edge kinetic energy (edge_ppm): at the corners whose wind sweeps have
+// an edge cell upwind (i or j in 0, 1, 2, n-2, n-1, n) the upwinded winds take
+// the one-sided face values, the widths being the face lengths dx (dy); the
+// difference from the centred values k_dsw_omke used is added to ke.  One
+// thread per corner of the six lines of each direction (corners on both a
+// column and a row line counted once), levels in y, tiles in z.
+template <class B, int ORD>
+DEVI void k_ke_edge(Bk bk, Geo G, Mets<B> M, B bdt, const B *u, const B *v, const B *ut, const B *vt, B *ke)
+{
+    const int n = G.n, e = (int)(bk.x * blockDim.x + threadIdx.x), k = (int)bk.y, t = (int)bk.z;
+    int i, j;
+    if (e < 6 * (n + 1)) {
+        const int q = e / (n + 1);
+        j = e - q * (n + 1);
+        i = edge_face_at(q, n);
+    } else {
+        const int e2 = e - 6 * (n + 1);
+        if (e2 >= 6 * (n - 5)) return;
+        const int q = e2 / (n - 5);
+        i = 3 + e2 - q * (n - 5);
+        j = edge_face_at(q, n);
+    }
+    const long o = pidx(G, G.nz, t, k);
+    const B *U = u + o, *V = v + o;
+    const B *dx = MP(M, M_DX), *dy = MP(M, M_DY);
+    B d = 0;
+    bool west;
+    if (edge_face(i, n)) {
+        const B ub = (B)0.5 * bdt * (AT(ut + o, i, j - 1) + AT(ut + o, i, j));
+        const B cu = ub / AT(dx, ub > 0 ? i - 1 : i, j);
+        const int pe = edge_pe(i, n, west);
+        const B ue = ppm_edge<ORD>(&AT(U, i - 3, j), 1, &AT(dx, i - 3, j), 1, cu, pe, west);
+        const B uc = ppm6<ORD>(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j),
+                               AT(U, i + 2, j), cu);
+        d += ub * (ue - uc);
+    }
+    if (edge_face(j, n)) {
+        const B vb = (B)0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
+        const B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
+        const int pe = edge_pe(j, n, west);
+        const B ve = ppm_edge<ORD>(&AT(V, i, j - 3), (int)G.pitch, &AT(dy, i, j - 3), (int)G.pitch, cv, pe, west);
+        const B vc = ppm6<ORD>(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1),
+                               AT(V, i, j + 2), cv);
+        d += vb * (ve - vc);
+    }
+    AT(ke + o, i, j) += (B)0.5 * d;
+}
+
 template <class B>
 DEVI void k_edgefix_dsw(Bk bk, Geo G, const EdgeCell *__restrict__ cells, int count, const B *area,
                         const B *FXm, const B *FYm, const B *FXp, const B *FYp, const B *FXw, const B *FYw,
@@ -2566,6 +2614,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
             hd = a;
             hc = (g->p.nord % 2 ? 1.0 : -1.0) * std::pow(g->p.d4_bg * g->da_min, g->p.nord + 1);
         }
+        const bool eppm = g->p.edge_ppm && g->p.kind == FV3_GRID_CUBED_SPHERE;
         auto omke = [&](auto lim) {
             launch2d_sh<k_dsw_omke<B, decltype(lim)::value>>(
                 "k_dsw_omke<B>", (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M,
@@ -2575,6 +2624,17 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         if (g->p.hord == 6) omke(std::integral_constant<int, 6>{});
         else if (g->p.hord == 5) omke(std::integral_constant<int, 5>{});
         else omke(std::integral_constant<int, 8>{});
+        if (eppm) {
+            const int cnt = 12 * (n + 1) - 36;
+            auto kee = [&](auto lim) {
+                launch_fn<k_ke_edge<B, decltype(lim)::value>>("k_ke_edge", dim3((cnt + 255) / 256, nz, 6), dim3(256),
+                                                             st, G, M, (B)bdt, (const B *)u, (const B *)v,
+                                                             (const B *)W.ut, (const B *)W.vt, W.ke);
+            };
+            if (g->p.hord == 6) kee(std::integral_constant<int, 6>{});
+            else if (g->p.hord == 5) kee(std::integral_constant<int, 5>{});
+            else kee(std::integral_constant<int, 8>{});
+        }
         {
             FvArgs<B, B, B> a{};
             a.q = W.om; a.Lq = nz; a.crx = W.crx; a.cry = W.cry; a.xfx = W.xfx; a.yfx = W.yfx; a.Lc = nz;
