@@ -303,7 +303,11 @@ const char *fv3_last_error(void);
 /* Run n_split acoustic substeps of dt / n_split on each of `members`
  * (state, grid) pairs, exactly as fv3_acoustic_substeps would on each alone
  * (same kernels, bit-identical results), with one launch per kernel for all
- * members.  All grids must share one precision and be on the current device.
+ * members.  All grids must share one precision and be on the current device
+ * (else FV3_EDTYPE / FV3_EDEVICE), and the options that choose kernels: PPM
+ * orders, damping switches, off-centring, the tile-edge options and humidity
+ * (a member whose launch sequence differs from the first member's:
+ * FV3_EUNSUPPORTED).  Grid kinds and sizes may differ.
  * Convenience form: builds an ensemble, runs it and synchronises `stream`. */
 fv3_status fv3_acoustic_substeps_batched(fv3_state *const *states, const fv3_grid *const *grids,
                                          int members, double dt, int n_split, void *stream);

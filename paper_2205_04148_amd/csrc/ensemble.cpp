@@ -168,6 +168,13 @@ fv3_status fv3_ensemble_create(fv3_state *const *states, const fv3_grid *const *
     for (int m = 0; m < members; m++) {
         e->rec.member = m;
         fv3_status r = fv3::record_substeps(states[m], grids[m], dt / n_split, &e->rec);
+        if (r == FV3_EUNSUPPORTED) {
+            delete e;
+            return fv3::set_error(r, "member " + std::to_string(m) +
+                                         ": its options choose a launch sequence other than member 0's (PPM "
+                                         "orders, damping switches, off-centring, tile-edge options and "
+                                         "humidity must agree)");
+        }
         if (r != FV3_OK) {
             delete e;
             return fv3::set_error(r, "recording of member " + std::to_string(m) + " failed");

@@ -1849,9 +1849,9 @@ DEVI void k_ke_edge(Bk bk, Geo G, Mets<B> M, B bdt, const B *u, const B *v, cons
     const int n = G.n, e = (int)(bk.x * blockDim.x + threadIdx.x), k = (int)bk.y, t = (int)bk.z;
     int i, j;
     if (e < 6 * (n + 1)) {
-        const int q = e / (n + 1);
-        j = e - q * (n + 1);
-        i = edge_face_at(q, n);
+        // the six edge columns of one row are neighbouring threads
+        j = e / 6;
+        i = edge_face_at(e - 6 * j, n);
     } else {
         const int e2 = e - 6 * (n + 1);
         if (e2 >= 6 * (n - 5)) return;
@@ -2723,7 +2723,8 @@ fv3_status record_substeps(fv3_state *s, const fv3_grid *g, double bdt, Recorder
                                       : substeps_t<double>(s, g, bdt, 1, 0, nullptr);
     g_rec = nullptr;
     if (r != FV3_OK) return r;
-    if (rec->bad || rec->pos != rec->sites.size() || rec->mark != 2) return FV3_EINTERNAL;
+    // a member whose options choose other kernels than the first member's
+    if (rec->bad || rec->pos != rec->sites.size() || rec->mark != 2) return FV3_EUNSUPPORTED;
     return FV3_OK;
 }
 

@@ -163,3 +163,12 @@ def test_ensemble_errors(fv3):
     assert e.value.status == -3
     with pytest.raises(fv3.FV3Error):
         fv3.acoustic_substeps_batched([s1], [g1], -1.0, 2)
+    # a member whose options choose other kernels (tile-edge PPM on a cube,
+    # a different PPM order) is refused with its own status
+    for opts in ({"edge_ppm": True}, {"hord": 6}):
+        g3 = fv3.Grid(1, 12, 3, precision="fp64", **opts)
+        g4 = fv3.Grid(1, 12, 3, precision="fp64")
+        s3, s4 = fv3.State.allocate(g3), fv3.State.allocate(g4)
+        with pytest.raises(fv3.FV3Error) as e:
+            fv3.acoustic_substeps_batched([s4, s3], [g4, g3], 1.0, 2)
+        assert e.value.status == -8, opts
