@@ -188,3 +188,25 @@ def test_diagonal_reflection_of_a_tile(orc):
     sl = (slice(H, H + n), slice(H, H + n + 1))
     np.testing.assert_allclose(gy.T[sl], fx[sl], rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(gx.T[sl[::-1]], fy[sl[::-1]], rtol=1e-12, atol=1e-14)
+
+
+def test_one_dsw_changes_winds_only_near_tile_edges(orc):
+    # the kinetic-energy upwinding and every fv_tp_2d of d_sw take the edge
+    # values only next to a tile edge: after one d_sw the winds
+    # of the tile interior are bit-equal with and without the option, and the
+    # winds next to the edges differ (through the edge-corner kinetic energy)
+    import fv3_inputs as fi
+
+    n, nz = 24, 2
+    init = fi.cube_state(n=n, nz=nz, nq=0)
+    out = []
+    for on in (False, True):
+        g = orc.Grid(1, n, nz, delta=1.0e5, edge_ppm=on)
+        s = orc.new_state(g, init)
+        assert orc.acoustic_substeps(g, s, 300.0, 1, stop_stage=6) == 0
+        out.append(s)
+    lo, hi = H + 5, H + n - 4    # measured: bit-equal from four cells in
+    for k in ("u", "v"):
+        a, b = out[0][k], out[1][k]
+        np.testing.assert_array_equal(a[:, :, lo:hi, lo:hi], b[:, :, lo:hi, lo:hi])
+        assert np.abs(a[:, :, H:H + n, H:H + 2] - b[:, :, H:H + n, H:H + 2]).max() > 1e-8
