@@ -695,6 +695,40 @@ def test_edge_ppm_parity(fv3, orc, n, nz, stop, dt, ns, precision, hord, hord_tr
     assert e <= (1e-11 if precision == "fp64" else 1e-4)
 
 
+def test_edge_ppm_with_edge_fix(fv3, orc):
+    """Both tile-edge options on the cube: 10 substeps and the tracer
+    transport match the oracle (1e-11) and the device's global sums of mass,
+    pt mass and tracer mass stay exact (1e-14)."""
+    import torch
+
+    n, nz, dt, ns = 24, 10, 2000.0, 10
+    init = fi.cube_state(n=n, nz=nz, nq=1)
+    g = fv3.Grid(1, n, nz, dx=1.0e5, precision="fp64", edge_fix=True, edge_ppm=True)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(1, n, nz, delta=1.0e5, edge_fix=True, edge_ppm=True)
+    os_ = orc.new_state(og, init)
+    label = "edgeppm+edgefix n24"
+    print(label, flush=True)
+    qd = [g.upload(q, nz) for q in init["q"]]
+    m0 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)
+    fv3.acoustic_substeps(s, g, dt, ns)
+    assert orc.acoustic_substeps(og, os_, dt, ns) == 0
+    _compare(s, os_, n, ("u", "v", "w", "delp", "pt", "delz", "mfx", "mfy", "pfull", "phi"), 1e-11, label)
+    assert fv3.check_status(g) == 0
+    qh = [q.copy() for q in init["q"]]
+    fv3.tracer_transport(qd, s, g)
+    orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+    torch.cuda.synchronize()
+    e = _relerr(_int(g.download(qd[0], nz), n, "C"), _int(qh[0], n, "C"))
+    print(f"{label} tracer {e:.2e}", flush=True)
+    assert e <= 1e-11
+    m1 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)
+    rel = np.abs(m1 / m0 - 1)
+    print(f"{label} sums {rel}", flush=True)
+    assert rel.max() <= 1e-14, rel
+
+
 def test_edge_ppm_periodic_untouched(fv3):
     """The doubly periodic grid has no tile edges: edge_ppm changes nothing."""
     import torch
