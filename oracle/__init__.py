@@ -256,7 +256,8 @@ def pgf(dt, L, dpiW, dpiE, phW0, phW1, phE0, phE1, pW0, pW1, pE0, pE1) -> float:
 
 STATE_FIELDS = ["u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "cx", "cy",
                 "dp0", "pfull", "phi"]
-DEBUG_FIELDS = ["delpc", "ptc", "wc", "ax", "ay", "crx", "cry", "xfx", "yfx", "pkc", "gz"]
+DEBUG_FIELDS = ["delpc", "ptc", "wc", "ax", "ay", "crx", "cry", "xfx", "yfx", "pkc", "gz", "vortc",
+                "vortd"]
 
 
 def new_state(g: Grid, init: dict) -> dict:

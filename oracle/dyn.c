@@ -56,7 +56,7 @@ static int skip_corner(const OGrid *g, int st, int i, int j)
 static void c_sw_plane(const OGrid *g, int t, double dt2, const double *u, const double *v,
                        const double *delp, const double *pt, const double *w, double *ucp_out,
                        double *vcp_out, double *delpc, double *ptc, double *wc, double *ax,
-                       double *ay)
+                       double *ay, double *vort_out)
 {
     int n = g->n;
     size_t P = o_plane(g), o = (size_t)t * P;
@@ -171,6 +171,7 @@ static void c_sw_plane(const OGrid *g, int t, double dt2, const double *u, const
                           ww * vcp[IX(g, i - 1, j)] * dyc[IX(g, i - 1, j)] +
                           we * vcp[IX(g, i, j)] * dyc[IX(g, i, j)];
             vort[b] = fB[b] + circ / area_c[b];
+            if (vort_out) vort_out[b] = vort[b];
         }
 
     /* C-grid wind update on the interior faces */
@@ -500,7 +501,8 @@ void o_corner_lap(const OGrid *g, int t, const double *D, double *out)
 static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, double *v,
                        const double *uc, const double *vc, double *delp, double *pt, double *w,
                        double *mfx, double *mfy, double *cx, double *cy, double *crx,
-                       double *cry, double *xfx, double *yfx, const double *hd, double *const *ef, int *cfl)
+                       double *cry, double *xfx, double *yfx, const double *hd, double *const *ef, int *cfl,
+                       double *om_out)
 {
     int n = g->n;
     size_t P = o_plane(g), o = (size_t)t * P;
@@ -673,6 +675,7 @@ static void d_sw_plane(const OGrid *g, int t, int k, double bdt, double *u, doub
             size_t c = IX(g, i, j);
             om[c] = fC[c] + (u[c] * dx[c] - u[IX(g, i, j + 1)] * dx[IX(g, i, j + 1)] -
                              v[c] * dy[c] + v[IX(g, i + 1, j)] * dy[IX(g, i + 1, j)]) / area[c];
+            if (om_out && i >= 0 && i < n && j >= 0 && j < n) om_out[c] = om[c];
         }
     og_view_scalar(g, om, ST_C, MODE_X, 0, qx);
     og_view_scalar(g, om, ST_C, MODE_Y, 0, qy);
@@ -866,6 +869,9 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
            *ay = dalloc(F3), *crx = dalloc(F3), *cry = dalloc(F3), *xfx = dalloc(F3),
            *yfx = dalloc(F3), *pkc = dalloc(F3i), *gz = dalloc(F3i);
     double *zs = dalloc((size_t)T * P);
+    /* debug outputs of the last substep: c_sw's corner and d_sw's cell
+     * absolute vorticity (each substep overwrites them) */
+    double *vortc = dbg ? dbg[11] : NULL, *vortd = dbg ? dbg[12] : NULL;
     int cfl = 0, status = ORC_OK;
     double *hd = NULL, *hd2 = NULL;
     if (g->nord > 0 && g->d4_bg > 0.0) {
@@ -905,7 +911,7 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
                            PL(s->delp, t, k, nz), PL(s->pt, t, k, nz), PL(s->w, t, k, nz),
                            PL(s->uc, t, k, nz), PL(s->vc, t, k, nz), PL(delpc, t, k, nz),
                            PL(ptc, t, k, nz), PL(wc, t, k, nz), PL(ax, t, k, nz),
-                           PL(ay, t, k, nz));
+                           PL(ay, t, k, nz), vortc ? PL(vortc, t, k, nz) : NULL);
         STOP(2);
 #pragma omp parallel for schedule(dynamic)
         for (int t = 0; t < T; t++)
@@ -943,7 +949,8 @@ int orc_substeps_impl(const OGrid *g, OState *s, double dt, int n_split, int sto
                            PL(s->pt, t, k, nz), PL(s->w, t, k, nz), PL(s->mfx, t, k, nz),
                            PL(s->mfy, t, k, nz), PL(s->cx, t, k, nz), PL(s->cy, t, k, nz),
                            PL(crx, t, k, nz), PL(cry, t, k, nz), PL(xfx, t, k, nz),
-                           PL(yfx, t, k, nz), hd ? PL(hd, t, k, nz) : NULL, ef ? efp : NULL, &c);
+                           PL(yfx, t, k, nz), hd ? PL(hd, t, k, nz) : NULL, ef ? efp : NULL, &c,
+                           vortd ? PL(vortd, t, k, nz) : NULL);
                 cfl |= c;
             }
         if (ef)
