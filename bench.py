@@ -9,8 +9,9 @@ accumulated fluxes, then the compensated global mass sums.
 The headline line is the mixed-precision build (FP32 stencil bulk; FP64
 column solves, vertical scans, pressure gradients, mass-flux accumulators and
 sums); the FP64 build is measured on the same state beside it ("mixed vs
-FP64"), and the per-field difference between the two after one step (100
-substeps) from the same initial state is reported.
+FP64").  Each build's fields after one call of 100 substeps from the initial
+state, with the benchmarked options, are compared with the FP64 oracle's
+("error_vs_fp64_oracle": per field max |device - oracle| / max |oracle|).
 
 metric  acoustic-substep cell-updates/s = 6 * 192^2 * 79 * 100 / (seconds per step)
         (the tracer transport and the sums are inside the timed step)
@@ -19,9 +20,13 @@ roofline  the kernel with the largest share of the step, timed live with HIP
           algorithmic bytes per launch / mean launch time, where algorithmic
           bytes = (distinct fields the kernel reads or writes, each counted
           once, at their element sizes) x (cells per launch), the paper's
-          bandwidth model of Sec. VII-C.
+          bandwidth model of Sec. VII-C.  copy_roof_GBs: the library's own
+          streaming copy kernel (fv3_device_copy) over 2 GiB.
 cpu_baseline  the oracle (plain C, OpenMP) on a bounded sample of the same
-          workload: 10 acoustic substeps of C192 x 79 in FP64.
+          workload: the first substep of C192 x 79 on one thread, the next
+          10 on all usable threads (at most 16); the host's CPU model and
+          counts are reported with it.  The oracle then finishes the 100
+          substeps (untimed) to serve as the FP64 reference above.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--precision mixed|fp64]
        python bench.py --ensemble     (batched uneven ensemble instead: one JSON line)
@@ -115,38 +120,83 @@ def committed_traffic(precision, n, nz, kernel):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def copy_roof(torch, nbytes=2 << 30, reps=10):
-    """Achievable HBM bandwidth of a plain device-to-device copy (torch's
-    copy kernel, 2 GiB, read + write counted), the practical roof next to
-    the 8 TB/s peak."""
+def copy_roof(fv3, torch, nbytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device-to-device copy with the
+    library's streaming copy kernel (fv3_device_copy, 2 GiB, read + write
+    counted, HIP events around each launch), the practical roof next to the
+    8 TB/s peak."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    fv3.device_copy(a, b)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    fv3.timing_start("k_stream_copy")
     for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / reps
+        fv3.device_copy(a, b)
+    per = fv3.timing_stop()
+    ms, cnt = per["k_stream_copy"]
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / sec / 1e9
+    return 2 * nbytes / (ms / cnt / 1000.0) / 1e9
 
 
-def cpu_baseline(init, n, nz, bdt, substeps):
+def host_cpu():
+    """CPU model name and logical CPU counts of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def oracle_reference(init, args, opts):
+    """The oracle (plain C, FP64, OpenMP over planes and columns) on the
+    benchmarked state and options.  Its first substep runs on one thread and
+    the next 10 on all usable threads (at most 16), both timed: those are the
+    CPU baseline.  The remaining substeps of the n_split run follow, untimed,
+    on all threads, so that the final state is the oracle's after n_split
+    substeps (the prognostics do not depend on how the substeps are split
+    into calls).  Returns (cpu_baseline dict, final oracle state)."""
     import oracle
 
+    n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
     threads = min(16, len(os.sched_getaffinity(0)))
-    oracle.set_threads(threads)
-    g = oracle.Grid(1, n, nz)
-    s = oracle.new_state(g, init)
+    og = oracle.Grid(1, n, nz, **opts)
+    s = oracle.new_state(og, init)
+    cells = 6 * n * n * nz
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    st = oracle.acoustic_substeps(g, s, bdt * substeps, substeps)
-    dt = time.perf_counter() - t0
-    cells = 6 * n * n * nz * substeps
-    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"C{n}x{nz} cubed sphere FP64, {substeps} acoustic substeps of {bdt:g} s, "
-                      f"{dt:.1f} s wall, status {st}"}
+    st1 = oracle.acoustic_substeps(og, s, bdt, 1)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    nall = min(10, ns - 1)
+    t0 = time.perf_counter()
+    st2 = oracle.acoustic_substeps(og, s, bdt * nall, nall) if nall > 0 else 0
+    tall = time.perf_counter() - t0
+    rest = ns - 1 - nall
+    t0 = time.perf_counter()
+    st3, done = 0, 0
+    while done < rest and st3 == 0:
+        m = min(30, rest - done)      # in chunks, with a progress line each
+        st3 = oracle.acoustic_substeps(og, s, bdt * m, m)
+        done += m
+        log(f"oracle: {1 + nall + done} of {ns} substeps, status {st3}")
+    trest = time.perf_counter() - t0
+    model, ncpu, usable = host_cpu()
+    rate_all = cells * nall / tall if nall > 0 else None
+    cpu = {"value": rate_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"C{n}x{nz} cubed sphere FP64 from the benchmark's state: substep 1 on 1 thread "
+                     f"({t1:.1f} s), substeps 2-{1 + nall} on {threads} threads ({tall:.1f} s); "
+                     f"status {st1}, {st2}",
+           "rate_1_thread": cells / t1, "rate_all_threads": rate_all,
+           "threads_all": threads, "nproc": ncpu, "usable_cpus": usable, "cpu_model": model}
+    log(f"oracle: 1 substep on 1 thread {t1:.1f} s, {nall} on {threads} threads {tall:.1f} s, "
+        f"{rest} more {trest:.1f} s (status {st3})")
+    return cpu, s
 
 
 def run_precision(fv3, torch, init, args, precision):
@@ -211,27 +261,47 @@ def run_precision(fv3, torch, init, args, precision):
             "device_status": int(st), "ms_per_substep": 1000 * sec / ns}
 
 
-def precision_error(fv3, torch, init, args):
-    """Per-field max |mixed - fp64| / max |fp64| over the interior after one step."""
+PREC_FIELDS = ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")
+
+
+def grid_opts(args):
+    """The options of the benchmarked configuration (same names in the
+    library binding and the oracle)."""
+    return {"beta": args.beta, "d2_bg": args.d2_bg, "dddmp": args.dddmp, "hord": args.hord,
+            "hord_tr": args.hord_tr, "pp_order": args.pp_order, "nord": args.nord, "d4_bg": args.d4_bg,
+            "vtdm": args.vtdm, "edge_fix": args.edge_fix, "edge_ppm": args.edge_ppm}
+
+
+def gpu_final_fields(fv3, torch, init, args, precision):
+    """One call of n_split substeps from the initial state with the
+    benchmarked options; the interior of each field of PREC_FIELDS."""
     n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
+    g = fv3.Grid(1, n, nz, precision=precision, **grid_opts(args))
+    s = fv3.State.allocate(g)
+    s.load(init)
+    if args.moist:
+        s.set_humidity(0.02 * init["q"][0])
+    fv3.acoustic_substeps(s, g, bdt * ns, ns)
+    torch.cuda.synchronize()
+    st = fv3.check_status(g)
+    res = {k: interior(s.get(k), n, k) for k in PREC_FIELDS}
+    del s, g
+    torch.cuda.empty_cache()
+    return res, st
+
+
+def interior(a, n, k, H=3):
+    ni = n + 1 if k == "v" else n
+    nj = n + 1 if k == "u" else n
+    return a[..., H:H + nj, H:H + ni]
+
+
+def field_errors(res, ref_state, n):
+    """max |device - oracle| / max |oracle| over the interior, per field."""
     out = {}
-    res = {}
-    for prec in ("fp64", "mixed"):
-        g = fv3.Grid(1, n, nz, precision=prec)
-        s = fv3.State.allocate(g)
-        s.load(init)
-        fv3.acoustic_substeps(s, g, bdt * ns, ns)
-        torch.cuda.synchronize()
-        res[prec] = {k: s.get(k) for k in ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")}
-        del s, g
-        torch.cuda.empty_cache()
-    H = 3
-    for k, a in res["fp64"].items():
-        ni = n + 1 if k == "v" else n
-        nj = n + 1 if k == "u" else n
-        ref = a[..., H:H + nj, H:H + ni]
-        mix = res["mixed"][k][..., H:H + nj, H:H + ni]
-        out[k] = float(abs(mix - ref).max() / max(abs(ref).max(), 1e-300))
+    for k in PREC_FIELDS:
+        ref = interior(ref_state[k], n, k)
+        out[k] = float(abs(res[k] - ref).max() / max(abs(ref).max(), 1e-300))
     return out
 
 
@@ -423,8 +493,8 @@ def main():
     init = fi.cube_state(n=n, nz=nz)
     log(f"initial state C{n}x{nz}: {time.perf_counter() - t0:.1f} s")
 
-    roof_copy = copy_roof(torch)
-    log(f"device copy roof: {roof_copy:.0f} GB/s")
+    roof_copy = copy_roof(fv3, torch)
+    log(f"device copy roof (library streaming copy): {roof_copy:.0f} GB/s")
     main_res = run_precision(fv3, torch, init, args, args.precision)
     main_res["roofline"]["copy_roof_GBs"] = roof_copy
     main_res["roofline"]["frac_of_copy_roof"] = (main_res["roofline"]["achieved"] or 0) / roof_copy
@@ -434,11 +504,26 @@ def main():
         r = run_precision(fv3, torch, init, args, other_prec)
         other = {"precision": other_prec, "value": r["value"], "ms_per_step": r["ms_per_step"],
                  "roofline": r["roofline"]}
-    err = precision_error(fv3, torch, init, args) if not args.no_compare else None
     cpu = None
+    err = None
     if not args.no_cpu:
-        log("oracle CPU baseline ...")
-        cpu = cpu_baseline(init, n, nz, args.bdt, 10)
+        # the device's fields after one call of n_split substeps, each
+        # precision, then the oracle from the same state with the same options
+        precs = [args.precision] + ([] if args.no_compare else [other["precision"]])
+        final = {p: gpu_final_fields(fv3, torch, init, args, p) for p in precs}
+        log("oracle: CPU baseline and FP64 reference ...")
+        oinit = dict(init)
+        if args.moist:
+            oinit["qv"] = 0.02 * init["q"][0]
+        cpu, ref = oracle_reference(oinit, args, grid_opts(args))
+        err = {"reference": "FP64 oracle", "substeps": args.n_split,
+               "measure": "max |device - oracle| / max |oracle| over the interior"}
+        for p, (res, st) in final.items():
+            err[p] = field_errors(res, ref, n)
+            err[p]["device_status"] = int(st)
+            log(f"[{p}] vs FP64 oracle after {args.n_split} substeps: "
+                + ", ".join(f"{k} {v:.1e}" for k, v in err[p].items() if k != "device_status"))
+        del ref
     cells = 6 * n * n * nz
     out = {
         "metric": "acoustic-substep cell-updates/s at C192x79, mixed vs FP64; % HBM peak",
@@ -460,7 +545,7 @@ def main():
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
         "compare": other,
-        "mixed_vs_fp64_max_rel_error_after_1_step": err,
+        "error_vs_fp64_oracle": err,
     }
     print(json.dumps(out), flush=True)
 

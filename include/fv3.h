@@ -230,7 +230,11 @@ fv3_status fv3_acoustic_substeps_debug(fv3_state *s, const fv3_grid *g, double d
  * halo fill of the tracers and a mass-weighted fv_tp_2d update.  q[m] are
  * device pointers to nq bulk-precision cell fields, updated in place; s->cx
  * and s->cy get their halos filled.  Errors: FV3_EINVAL (NULL pointers,
- * nq < 1 or > 64). */
+ * nq < 1 or > 64, nsplt > FV3_MAX_TRACER_SUBCYCLES); with nsplt <= 0,
+ * FV3_ENONFINITE when a Courant number is not finite and FV3_ECFL when the
+ * count would exceed FV3_MAX_TRACER_SUBCYCLES (nothing is enqueued after
+ * the read in either case). */
+#define FV3_MAX_TRACER_SUBCYCLES 1024
 fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_grid *g,
                                 int nsplt, void *stream);
 
@@ -259,6 +263,21 @@ fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_
 fv3_status fv3_remap(fv3_state *s, const fv3_grid *g, const double *ak, const double *bk,
                      void *const *q, int nq, void *stream);
 
+/* One pass of the remapping loop, the middle of FV3's three nested loops
+ * (Sec. II; its share of the run is Table III's "Lagrangian contrib."),
+ * over the span dt: k_split times, n_split acoustic substeps of
+ * dt / (k_split n_split) (fv3_acoustic_substeps over dt / k_split), then the
+ * tracer transport of the nq tracers q[m] with the fluxes those substeps
+ * accumulated (fv3_tracer_transport with nsplt; skipped when nq = 0), then the
+ * vertical remapping of the state and the tracers to ak + bk ps (fv3_remap).
+ * Arguments and their conditions as in those three calls; the accumulators,
+ * dp0, pfull and phi hold the last pass's values.  Asynchronous on `stream`
+ * except for the sub-cycle count read of each tracer transport when
+ * nsplt <= 0.  Errors: those of the three calls (FV3_EINVAL also for
+ * k_split < 1); the first failing pass stops the loop. */
+fv3_status fv3_dynamics(fv3_state *s, const fv3_grid *g, void *const *q, int nq, const double *ak,
+                        const double *bk, double dt, int k_split, int n_split, int nsplt, void *stream);
+
 /* Compensated (Neumaier) FP64 global sums over the interior cells:
  * out[0] = sum delp*area, out[1] = sum pt*delp*area, out[2+m] = sum
  * q[m]*delp*area.  `delp` and `pt` are bulk-precision fields; out is a
@@ -285,6 +304,12 @@ fv3_status fv3_check_status(const fv3_grid *g, void *stream);
  * are written NUL-separated into `names` (names_cap bytes).  Returns the
  * number of kernels reported, or a negative fv3_status.  Not thread-safe. */
 fv3_status fv3_timing_start(const char *filter);
+/* Measurement support: copy `bytes` (a multiple of 16, both addresses
+ * 16-byte aligned, no overlap) from device memory src to dst with the
+ * library's streaming copy kernel (16-byte accesses), the practical HBM roof
+ * that kernel timings are set against.  Asynchronous on `stream`; timed as
+ * "k_stream_copy".  Errors: FV3_EINVAL. */
+fv3_status fv3_device_copy(const void *src, void *dst, size_t bytes, void *stream);
 int fv3_timing_stop(char *names, int names_cap, double *total_ms, long *counts, int cap);
 
 const char *fv3_status_string(fv3_status s);

@@ -350,6 +350,24 @@ def remap(g: Grid, s: dict, ak, bk, qs=()) -> int:
                            len(qs), _p(ak), _p(bk))
 
 
+def dynamics(g: Grid, s: dict, qs, ak, bk, dt: float, k_split: int, n_split: int, nsplt: int = 0) -> int:
+    """One pass of the remapping loop (the middle of FV3's three nested
+    loops, Sec. II): k_split times, n_split acoustic substeps over dt /
+    k_split, the tracer transport of qs with the fluxes they accumulated,
+    and the vertical remap of the state and qs to ak + bk * ps.  Returns the
+    first non-zero status, else 0."""
+    for _ in range(k_split):
+        st = acoustic_substeps(g, s, dt / k_split, n_split)
+        if st != 0:
+            return st
+        if len(qs):
+            tracer_transport(g, qs, s["dp0"], s["mfx"], s["mfy"], s["cx"], s["cy"], nsplt)
+        st = remap(g, s, ak, bk, qs)
+        if st != 0:
+            return st
+    return 0
+
+
 def mass_sums(g: Grid, delp, pt, qs=()) -> np.ndarray:
     out = np.zeros(2 + len(qs))
     arr = (C.POINTER(C.c_double) * max(1, len(qs)))(*[_p(q) for q in qs])

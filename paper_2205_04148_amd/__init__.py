@@ -31,8 +31,8 @@ METRICS = ["dx", "dy", "dxc", "dyc", "dxa", "dya", "area", "area_c", "fC", "fB",
            "cos_u", "sin_v", "cos_v", "sin_a", "cos_a"]
 EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_bytes",
            "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
-           "fv3_tracer_transport", "fv3_remap", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
-           "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start",
+           "fv3_tracer_transport", "fv3_remap", "fv3_dynamics", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
+           "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start", "fv3_device_copy",
            "fv3_timing_stop", "fv3_acoustic_substeps_batched", "fv3_ensemble_create",
            "fv3_ensemble_run", "fv3_ensemble_free", "fv3_ensemble_tune", "fv3_ensemble_shapes",
            "fv3_coarsen", "fv3_column_features", "fv3_apply_correction",
@@ -106,9 +106,12 @@ def lib():
         L.fv3_remap.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(vp), C.c_int, vp]
         L.fv3_mass_sums.argtypes = [vp, vp, vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double), vp]
+        L.fv3_dynamics.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.c_double, C.c_int, C.c_int, C.c_int, vp]
         L.fv3_halo_fill.argtypes = [vp, C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp]
         L.fv3_check_status.argtypes = [vp, vp]
         L.fv3_timing_start.argtypes = [C.c_char_p]
+        L.fv3_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.fv3_timing_stop.argtypes = [C.c_char_p, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_long), C.c_int]
         L.fv3_acoustic_substeps_batched.argtypes = [C.POINTER(C.POINTER(StateStruct)), C.POINTER(vp),
@@ -346,6 +349,21 @@ def remap(state: State, grid: Grid, ak, bk, qs=(), stream=None) -> None:
                            bk.ctypes.data_as(C.POINTER(C.c_double)), arr, len(qs), _stream(stream)))
 
 
+def dynamics(state: State, grid: Grid, qs, ak, bk, dt: float, k_split: int, n_split: int, nsplt: int = 0,
+             stream=None) -> None:
+    """fv3_dynamics: k_split x (n_split acoustic substeps, tracer transport of
+    qs, vertical remap to ak + bk * ps) over the span dt."""
+    ak = np.ascontiguousarray(ak, dtype=np.float64)
+    bk = np.ascontiguousarray(bk, dtype=np.float64)
+    if ak.shape != (grid.nz + 1,) or bk.shape != (grid.nz + 1,):
+        raise ValueError("ak and bk need nz + 1 values")
+    st = state.struct()
+    arr = (C.c_void_p * max(1, len(qs)))(*[q.data_ptr() for q in qs])
+    _check(lib().fv3_dynamics(C.byref(st), grid.handle, arr, len(qs), ak.ctypes.data_as(C.POINTER(C.c_double)),
+                              bk.ctypes.data_as(C.POINTER(C.c_double)), float(dt), int(k_split), int(n_split),
+                              int(nsplt), _stream(stream)))
+
+
 def mass_sums(grid: Grid, delp, pt, qs=(), stream=None) -> np.ndarray:
     out = np.zeros(2 + len(qs))
     arr = (C.c_void_p * max(1, len(qs)))(*[q.data_ptr() for q in qs])
@@ -353,6 +371,14 @@ def mass_sums(grid: Grid, delp, pt, qs=(), stream=None) -> np.ndarray:
                                arr, len(qs), out.ctypes.data_as(C.POINTER(C.c_double)),
                                _stream(stream)))
     return out
+
+
+def device_copy(src, dst, stream=None) -> None:
+    """fv3_device_copy of the bytes of device tensor src into dst (same size)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst must hold the same number of bytes")
+    _check(lib().fv3_device_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb, _stream(stream)))
 
 
 def halo_fill(grid: Grid, fields, levels: int, fp64: bool = False, stream=None) -> None:

@@ -36,6 +36,16 @@ fv3_status check_state(const fv3_state *s, const fv3_grid *g)
     if (!device_ok(g)) return fail(FV3_EDEVICE, "current HIP device differs from the grid's device");
     return FV3_OK;
 }
+fv3_status check_remap_coeffs(const fv3_grid *g, const double *ak, const double *bk)
+{
+    const int nz = g->nz;
+    if (nz > FV3_REMAP_MAX_LEVELS) return fail(FV3_ESHAPE, "nz exceeds FV3_REMAP_MAX_LEVELS");
+    for (int K = 0; K <= nz; K++)
+        if (!std::isfinite(ak[K]) || !std::isfinite(bk[K])) return fail(FV3_EINVAL, "non-finite ak or bk");
+    if (ak[0] != g->p.ptop || bk[0] != 0.0 || ak[nz] != 0.0 || bk[nz] != 1.0)
+        return fail(FV3_EINVAL, "need ak[0] = ptop, bk[0] = 0, ak[nz] = 0, bk[nz] = 1");
+    return FV3_OK;
+}
 }  // namespace
 
 namespace fv3 {
@@ -208,7 +218,11 @@ fv3_status fv3_tracer_transport(void *const *q, int nq, fv3_state *s, const fv3_
         if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
     fv3_status st = check_state(s, g);
     if (st != FV3_OK) return st;
+    if (nsplt > FV3_MAX_TRACER_SUBCYCLES)
+        return fail(FV3_EINVAL, "nsplt above FV3_MAX_TRACER_SUBCYCLES (" +
+                                    std::to_string(FV3_MAX_TRACER_SUBCYCLES) + ")");
     st = fv3::run_tracer(q, nq, s, g, nsplt, (hipStream_t)stream);
+    if (st == FV3_ENONFINITE || st == FV3_ECFL) return st;   // message set where it was found
     if (st != FV3_OK) return fail(st, "tracer transport failed");
     return FV3_OK;
 }
@@ -222,14 +236,41 @@ fv3_status fv3_remap(fv3_state *s, const fv3_grid *g, const double *ak, const do
         if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
     fv3_status st = check_state(s, g);
     if (st != FV3_OK) return st;
-    const int nz = g->nz;
-    if (nz > FV3_REMAP_MAX_LEVELS) return fail(FV3_ESHAPE, "nz exceeds FV3_REMAP_MAX_LEVELS");
-    for (int K = 0; K <= nz; K++)
-        if (!std::isfinite(ak[K]) || !std::isfinite(bk[K])) return fail(FV3_EINVAL, "non-finite ak or bk");
-    if (ak[0] != g->p.ptop || bk[0] != 0.0 || ak[nz] != 0.0 || bk[nz] != 1.0)
-        return fail(FV3_EINVAL, "need ak[0] = ptop, bk[0] = 0, ak[nz] = 0, bk[nz] = 1");
+    st = check_remap_coeffs(g, ak, bk);
+    if (st != FV3_OK) return st;
     st = fv3::run_remap(s, g, ak, bk, q, nq, (hipStream_t)stream);
     if (st != FV3_OK) return fail(st, "remap failed");
+    return FV3_OK;
+}
+
+fv3_status fv3_dynamics(fv3_state *s, const fv3_grid *g, void *const *q, int nq, const double *ak,
+                        const double *bk, double dt, int k_split, int n_split, int nsplt, void *stream)
+{
+    if (!ak || !bk) return fail(FV3_EINVAL, "NULL ak or bk");
+    if (nq < 0 || nq > 64 || (nq > 0 && !q)) return fail(FV3_EINVAL, "need 0..64 tracers");
+    for (int m = 0; m < nq; m++)
+        if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
+    fv3_status st = check_state(s, g);
+    if (st != FV3_OK) return st;
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV3_EINVAL, "dt must be finite and positive");
+    if (k_split < 1 || n_split < 1) return fail(FV3_EINVAL, "k_split and n_split must be >= 1");
+    if (nsplt > FV3_MAX_TRACER_SUBCYCLES)
+        return fail(FV3_EINVAL, "nsplt above FV3_MAX_TRACER_SUBCYCLES");
+    st = check_remap_coeffs(g, ak, bk);
+    if (st != FV3_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const double dtk = dt / k_split;
+    for (int it = 0; it < k_split; it++) {
+        st = fv3::run_substeps(s, g, dtk, n_split, 0, hs);
+        if (st != FV3_OK) return fail(st, "substep launch failed");
+        if (nq > 0) {
+            st = fv3::run_tracer(q, nq, s, g, nsplt, hs);
+            if (st == FV3_ENONFINITE || st == FV3_ECFL) return st;
+            if (st != FV3_OK) return fail(st, "tracer transport failed");
+        }
+        st = fv3::run_remap(s, g, ak, bk, q, nq, hs);
+        if (st != FV3_OK) return fail(st, "remap failed");
+    }
     return FV3_OK;
 }
 
@@ -256,6 +297,16 @@ fv3_status fv3_halo_fill(const fv3_grid *g, void *const *fields, int n_fields, i
     for (int m = 0; m < n_fields; m++)
         if (!fields[m]) return fail(FV3_EINVAL, "NULL field pointer");
     return fv3::run_halo_cells(g, fields, n_fields, levels, fp64, (hipStream_t)stream);
+}
+
+fv3_status fv3_device_copy(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (!src || !dst) return fail(FV3_EINVAL, "NULL pointer");
+    if (bytes % 16 != 0 || ((size_t)src | (size_t)dst) % 16 != 0)
+        return fail(FV3_EINVAL, "bytes and both addresses must be multiples of 16");
+    const char *a = (const char *)src, *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes) return fail(FV3_EINVAL, "source and destination overlap");
+    return fv3::run_device_copy(src, dst, bytes, (hipStream_t)stream);
 }
 
 fv3_status fv3_timing_start(const char *filter)

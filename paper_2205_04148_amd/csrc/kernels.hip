@@ -2273,6 +2273,10 @@ DEVI void k_tracer_dp(KARGS, Geo G, MetD M, const double *dp1, const double *mxs
                                                 AT(MP(M, M_AREA), i, j);
 }
 
+// maximum that keeps a NaN (fmax drops it), so a non-finite Courant number
+// reaches the host's sub-cycle count
+DEVI double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
+
 // max |cx|, |cy| over the interior faces: block maximum, one atomic per block
 template <class B>
 __global__ void k_absmax(int ilo, int ihi, int jlo, int jhi, Geo G, const B *cx, const B *cy, unsigned long long *out)
@@ -2289,17 +2293,18 @@ __global__ void k_absmax(int ilo, int ihi, int jlo, int jhi, Geo G, const B *cx,
         for (int z = (int)blockIdx.z; z < planes; z += (int)gridDim.z) {
             int t = z / G.nz, k = z % G.nz;
             long o = pidx(G, G.nz, t, k);
-            if (j < n) m = fmax(m, fabs((double)AT(cx + o, i, j)));
-            if (i < n) m = fmax(m, fabs((double)AT(cy + o, i, j)));
+            if (j < n) m = nanmax(m, fabs((double)AT(cx + o, i, j)));
+            if (i < n) m = nanmax(m, fabs((double)AT(cy + o, i, j)));
         }
     }
     sm[tid] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) sm[tid] = fmax(sm[tid], sm[tid + w]);
+        if (tid < w) sm[tid] = nanmax(sm[tid], sm[tid + w]);
         __syncthreads();
     }
-    // non-negative doubles order like their bit patterns
+    // non-negative doubles order like their bit patterns, and a NaN's bits
+    // lie above those of +inf, so a NaN survives the atomic too
     if (tid == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
@@ -2774,6 +2779,11 @@ static fv3_status tracer_t(void *const *q, int nq, fv3_state *s, const fv3_grid 
         if (hipStreamSynchronize(st) != hipSuccess) return FV3_EDEVICE;
         double cmax;
         std::memcpy(&cmax, &h, sizeof(cmax));
+        if (!std::isfinite(cmax))
+            return set_error(FV3_ENONFINITE, "accumulated Courant numbers cx, cy are not finite");
+        if (cmax > (double)FV3_MAX_TRACER_SUBCYCLES)
+            return set_error(FV3_ECFL, "max |cx|, |cy| = " + std::to_string(cmax) + " needs more than " +
+                                           std::to_string(FV3_MAX_TRACER_SUBCYCLES) + " tracer sub-cycles");
         nsplt = (int)std::ceil(cmax);
         if (nsplt < 1) nsplt = 1;
     }
@@ -2844,6 +2854,44 @@ static fv3_status mass_sums_t(const fv3_grid *g, const void *delp, const void *p
         out[which] = s + c;
     }
     return FV3_OK;
+}
+
+// Streaming copy for the bandwidth roof: 16-byte loads and stores; a block
+// moves 16 KiB per iteration (four loads per thread issued before the four
+// stores), grid-stride over 16 KiB chunks with at most 2048 blocks (8 per
+// compute unit).
+__global__ void __launch_bounds__(256) k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                     long n16)
+{
+    const long stride = (long)gridDim.x * 1024;
+    for (long base = (long)blockIdx.x * 1024; base < n16; base += stride) {
+        uint4 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            long e = base + u * 256 + threadIdx.x;
+            if (e < n16) r[u] = src[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            long e = base + u * 256 + threadIdx.x;
+            if (e < n16) dst[e] = r[u];
+        }
+    }
+}
+
+fv3_status run_device_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
+{
+    long n16 = (long)(bytes / 16);
+    bool tm = timing_wanted("k_stream_copy");
+    TimingRec r;
+    if (tm) timing_begin("k_stream_copy", st, r);
+    if (n16 > 0) {
+        long chunks = (n16 + 1023) / 1024;
+        unsigned blocks = (unsigned)(chunks < 2048 ? chunks : 2048);
+        hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16);
+    }
+    if (tm) timing_end(st, r);
+    return hipGetLastError() == hipSuccess ? FV3_OK : FV3_EDEVICE;
 }
 
 fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,

@@ -1,6 +1,7 @@
 """HBM traffic per kernel launch from two rocprofv3 counter databases.
 
     python -m paper_2205_04148_amd.pmc FETCH_DIR WRITE_DIR OUT.json WORKLOAD
+    python -m paper_2205_04148_amd.pmc counters DIR OUT.json WORKLOAD [DIR2 ...]
 
 FETCH_DIR / WRITE_DIR hold the rocpd databases of one ``rocprofv3 --pmc
 FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of the same command.  Both
@@ -84,8 +85,60 @@ def calibrate(rows, counter: str) -> float:
     raise KeyError("no copy kernel in the counter run")
 
 
+def load_all(dirname: str):
+    """Every counter of a rocpd database: {launch name: {counter: [values]}}."""
+    db = glob.glob(os.path.join(dirname, "**", "*.db"), recursive=True)
+    if not db:
+        raise FileNotFoundError(f"no rocpd database under {dirname}")
+    con = sqlite3.connect(db[0])
+    out = collections.defaultdict(lambda: collections.defaultdict(list))
+    for sym, cname, val in con.execute("select kernel_name, counter_name, value from counters_collection"):
+        name = launch_name(sym)
+        if name:
+            out[name][cname].append(float(val))
+    return out
+
+
+SIMDS = 1024          # 256 compute units x 4 SIMDs (MI355X)
+VALU_CYCLES = 4       # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+
+
+def counters_main(a):
+    """counters DIR OUT.json WORKLOAD [DIR2 ...]: per launch name, the mean
+    per dispatch of every counter in the databases, plus derived figures:
+    valu_busy = SQ_ACTIVE_INST_VALU x 4 / SIMDs / GRBM_GUI_ACTIVE (share of
+    the kernel's cycles in which the average SIMD issued VALU work),
+    valu_per_wave = SQ_INSTS_VALU / SQ_WAVES, lds_conflict_per_inst =
+    SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (conflict cycles per LDS
+    instruction)."""
+    dirs, out, workload = [a[0]] + a[3:], a[1], a[2]
+    merged = collections.defaultdict(dict)
+    for d in dirs:
+        for name, cs in load_all(d).items():
+            for c, v in cs.items():
+                merged[name][c] = v
+    kern = {}
+    for name, cs in sorted(merged.items()):
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        m["dispatches"] = max(len(v) for v in cs.values())
+        g = m.get("GRBM_GUI_ACTIVE")
+        if g and "SQ_ACTIVE_INST_VALU" in m:
+            m["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] * VALU_CYCLES / SIMDS / g
+        if m.get("SQ_WAVES") and "SQ_INSTS_VALU" in m:
+            m["valu_per_wave"] = m["SQ_INSTS_VALU"] / m["SQ_WAVES"]
+        if m.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in m:
+            m["lds_conflict_per_inst"] = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_INSTS_LDS"]
+        kern[name] = m
+    doc = {"workload": workload, "kernel_source_sha256": source_sha256(), "kernels": kern}
+    with open(out, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(f"{len(kern)} kernels -> {out}")
+
+
 def main(argv=None):
     a = argv if argv is not None else sys.argv[1:]
+    if a and a[0] == "counters":
+        return counters_main(a[1:])
     fdir, wdir, out, workload = a[0], a[1], a[2], a[3]
     f = load(fdir, "FETCH_SIZE")
     w = load(wdir, "WRITE_SIZE")

@@ -1,0 +1,107 @@
+"""GPU parity at sizes where the kernels run many blocks per cube tile.
+
+The smaller cube cases elsewhere (C12 .. C24) fit one 32- or 33-wide block
+across a tile in x, so no block there is free of tile edges.  Here:
+
+* C64 x 8 (two transport blocks and two c_sw tiles per tile row, faces
+  n-2..n of the edge treatments in the last block, face n on its right
+  boundary): 10 substeps and a 4-tracer transport, with and without the
+  tile-edge options, against the oracle built with the same options; with
+  the edge-flux fix-up the device's mass, pt-mass and tracer-mass sums stay
+  exact.
+* C96 x 79, FP64, 10 substeps of 30 s plus the 4-tracer transport (the
+  C96 baroclinic-jet configuration of the paper's test case, Sec. X).
+* C192 x 79, FP64, 2 substeps of 15 s plus the 4-tracer transport (the
+  launch configuration the benchmark times, in FP64), every field compared
+  over the whole interior.
+
+Bar: 1e-11 relative (max |gpu - oracle| / max |oracle| per field) after
+several substeps in FP64, as for the smaller cases: each stage differs by
+FMA contraction and one-ulp differences of pow/log between the two math
+libraries, amplified most in w (see test_gpu_parity)."""
+import numpy as np
+import pytest
+
+import fv3_inputs as fi
+
+pytestmark = pytest.mark.gpu
+H = 3
+STAG = {"u": "Y", "v": "X", "w": "C", "delp": "C", "pt": "C", "delz": "C", "uc": "X", "vc": "Y",
+        "mfx": "X", "mfy": "Y", "cx": "X", "cy": "Y", "dp0": "C", "pfull": "C", "phi": "C"}
+FIELDS = ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "cx", "cy", "dp0", "pfull", "phi")
+
+
+def _int(a, n, st):
+    ni = n + 1 if st in ("X", "B") else n
+    nj = n + 1 if st in ("Y", "B") else n
+    return a[..., H:H + nj, H:H + ni]
+
+
+def _relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fv3():
+    import torch
+
+    import paper_2205_04148_amd as m
+
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _run_pair(fv3, orc, n, nz, bdt, ns, opts, tol=1e-11, label=""):
+    """ns substeps and a tracer transport of every tracer of the C{n} x nz
+    jet on the device and in the oracle; returns the device grid, state and
+    tracers."""
+    import torch
+
+    init = fi.cube_state(n=n, nz=nz)
+    g = fv3.Grid(1, n, nz, **opts)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    qd = [g.upload(q, nz) for q in init["q"]]
+    m0 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)
+    fv3.acoustic_substeps(s, g, bdt * ns, ns)
+    fv3.tracer_transport(qd, s, g)
+    torch.cuda.synchronize()
+    assert fv3.check_status(g) == 0
+    m1 = fv3.mass_sums(g, s.f["delp"], s.f["pt"], qd)
+
+    og = orc.Grid(1, n, nz, **opts)
+    os_ = orc.new_state(og, init)
+    assert orc.acoustic_substeps(og, os_, bdt * ns, ns) == 0
+    qh = [q.copy() for q in init["q"]]
+    orc.tracer_transport(og, qh, os_["dp0"], os_["mfx"], os_["mfy"], os_["cx"], os_["cy"])
+
+    errs = {k: _relerr(_int(s.get(k), n, STAG[k]), _int(os_[k], n, STAG[k])) for k in FIELDS}
+    for m, (a, b) in enumerate(zip(qd, qh)):
+        errs[f"q{m}"] = _relerr(_int(g.download(a, nz), n, "C"), _int(b, n, "C"))
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+    return g, s, qd, m0, m1
+
+
+@pytest.mark.parametrize("edge_ppm,edge_fix", [(False, False), (True, False), (False, True), (True, True)])
+def test_cube_c64_multiblock(fv3, orc, edge_ppm, edge_fix):
+    opts = {"edge_ppm": edge_ppm, "edge_fix": edge_fix}
+    g, s, qd, m0, m1 = _run_pair(fv3, orc, 64, 8, 60.0, 10, opts, label=f"C64x8 {opts}")
+    if edge_fix:
+        # the fix-up makes the device's global sums exact on the cube
+        rel = np.abs(m1 - m0) / np.abs(m0)
+        print("C64 sums relative change", rel, flush=True)
+        assert np.all(rel <= 1e-14), rel
+
+
+def test_cfg2_c96x79_fp64(fv3, orc):
+    """C96 x 79 in FP64: 10 substeps of 30 s and the 4-tracer transport."""
+    _run_pair(fv3, orc, 96, 79, 30.0, 10, {}, label="C96x79 fp64")
+
+
+def test_c192x79_fp64_two_substeps(fv3, orc):
+    """The benchmark's grid in FP64: 2 substeps of 15 s and the 4-tracer
+    transport, every interior point of every field."""
+    _run_pair(fv3, orc, 192, 79, 15.0, 2, {}, label="C192x79 fp64")

@@ -842,3 +842,30 @@ def test_mixed_precision_cube(fv3, orc):
     m = fv3.mass_sums(g, s.f["delp"], s.f["pt"])
     ref = orc.mass_sums(og, os_["delp"], os_["pt"])
     assert abs(m[0] / ref[0] - 1) <= 1e-6
+
+
+def test_nonfinite_flag_latched(fv3, orc):
+    """A NaN in pt gives FV3_ENONFINITE once (the flag then clears), in the
+    library as in the oracle; the tracer transport then refuses the
+    non-finite Courant numbers with the same status instead of sub-cycling."""
+    n, nz = 16, 2
+    init = fi.periodic_state(n=n, nz=nz)
+    init["pt"][0, 1, H + 5, H + 7] = np.nan
+    g = fv3.Grid(0, n, nz)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    fv3.acoustic_substeps(s, g, 1.0, 2)
+    assert fv3.check_status(g) == -7
+    assert fv3.check_status(g) == 0   # cleared
+    q = g.upload(np.ones_like(init["delp"]), nz)
+    with pytest.raises(fv3.FV3Error) as e:
+        fv3.tracer_transport([q], s, g, nsplt=0)
+    assert e.value.status == -7
+    og = orc.Grid(0, n, nz)
+    assert orc.acoustic_substeps(og, orc.new_state(og, init), 1.0, 2) == -7
+    # a clean state on the same grid reports ok again
+    s.load(fi.periodic_state(n=n, nz=nz))
+    fv3.acoustic_substeps(s, g, 1.0, 2)
+    assert fv3.check_status(g) == 0
+    fv3.tracer_transport([q], s, g, nsplt=0)
+    assert fv3.check_status(g) == 0

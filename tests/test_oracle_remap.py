@@ -253,3 +253,40 @@ def test_monotone_data_give_monotone_parabolas_and_result(seed):
     assert np.all(aR >= aL - tol)
     out = orc.remap_column(pe1, _shifted(pe1, seed + 7, frac=0.49), a)
     assert np.all(np.diff(out) >= -1e-12 * np.abs(a).max())
+
+
+def test_dynamics_loop_conserves_and_lands_on_reference():
+    """The oracle's remapping loop (k_split passes of substeps, tracer
+    transport and remap) on the doubly periodic grid: the global sums of
+    mass, pt mass and tracer masses are those of the start (each of the three
+    steps conserves them there), every column ends on the reference
+    interfaces, and with k_split = 1 the loop is the three calls in order,
+    bit for bit."""
+    n, nz = 16, 6
+    init = fi.periodic_state(n=n, nz=nz, seed=5, nq=2)
+    ak, bk = fi.hybrid_coefficients(nz, 100.0)
+    og = orc.Grid(0, n, nz)
+    s = orc.new_state(og, init)
+    qs = [np.ascontiguousarray(q, dtype=np.float64).copy() for q in init["q"]]
+    before = orc.mass_sums(og, s["delp"], s["pt"], qs)
+    assert orc.dynamics(og, s, qs, ak, bk, 3 * 4 * 0.3, 3, 4) == 0
+    after = orc.mass_sums(og, s["delp"], s["pt"], qs)
+    assert np.all(np.abs(after - before) <= 1e-13 * np.abs(before)), (before, after)
+    cs = np.s_[..., H:H + n, H:H + n]
+    ps = og.ptop + s["delp"][cs].sum(axis=1)
+    pe = og.ptop + np.concatenate([np.zeros_like(ps[:, None]), np.cumsum(s["delp"][cs], axis=1)], axis=1)
+    ref = ak[None, :, None, None] + bk[None, :, None, None] * ps[:, None]
+    assert np.abs(pe - ref).max() <= 1e-9
+    # k_split = 1: the loop is substeps, tracer transport, remap
+    a = orc.new_state(og, init)
+    b = orc.new_state(og, init)
+    qa = [np.ascontiguousarray(q, dtype=np.float64).copy() for q in init["q"]]
+    qb = [q.copy() for q in qa]
+    assert orc.dynamics(og, a, qa, ak, bk, 4 * 0.3, 1, 4) == 0
+    assert orc.acoustic_substeps(og, b, 4 * 0.3, 4) == 0
+    orc.tracer_transport(og, qb, b["dp0"], b["mfx"], b["mfy"], b["cx"], b["cy"])
+    assert orc.remap(og, b, ak, bk, qb) == 0
+    for k in ("u", "v", "w", "delp", "pt", "delz"):
+        assert np.array_equal(a[k], b[k]), k
+    for x, y in zip(qa, qb):
+        assert np.array_equal(x, y)
