@@ -285,6 +285,29 @@ fv3_status fv3_dynamics(fv3_state *s, const fv3_grid *g, void *const *q, int nq,
 fv3_status fv3_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
                          int nq, double *host_out, void *stream);
 
+/* Size of the fixed device scratch of fv3_mass_sums_noalloc: 4 MiB per GPU,
+ * held from the first fv3_init_grid on that GPU until the process ends. */
+#define FV3_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same sums as
+ * fv3_mass_sums, with no device or host allocation and no synchronisation.
+ * The per-block partials go to a fixed device array of
+ * FV3_NOALLOC_SCRATCH_BYTES instead of the grid's reduction buffer, and are
+ * combined on the device in the same order and with the same compensated
+ * additions, so the results are bit-identical to fv3_mass_sums.
+ * dev_out: DEVICE array of 2 + nq doubles (caller-owned), written
+ * asynchronously on `stream` in fv3_mass_sums' order.  Every call on one GPU
+ * shares that GPU's scratch array: calls that overlap on one GPU (on
+ * different streams or host threads) race and give wrong sums; calls in
+ * stream order are safe (each fully overwrites the partials it reads).
+ * Errors: FV3_EINVAL (NULL pointers, nq outside 0..64), FV3_EDEVICE (the
+ * current device is not the grid's), FV3_ESHAPE (the grid needs more block
+ * partials than the scratch holds: 2 doubles per 64 x 4 block of every tile,
+ * which fits any doubly periodic tile and cubes up to about C3300). */
+fv3_status fv3_mass_sums_noalloc(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                                 int nq, double *dev_out, void *stream);
+
 /* Fill the halos of n_fields cell-centred fields (L levels each, bulk
  * precision unless fp64 != 0) from the neighbouring tiles.  Exposed for
  * tests of the halo exchange. */

@@ -31,7 +31,7 @@ METRICS = ["dx", "dy", "dxc", "dyc", "dxa", "dya", "area", "area_c", "fC", "fB",
            "cos_u", "sin_v", "cos_v", "sin_a", "cos_a"]
 EXPORTS = ["fv3_init_grid", "fv3_free_grid", "fv3_grid_layout", "fv3_workspace_bytes",
            "fv3_grid_metric", "fv3_acoustic_substeps", "fv3_acoustic_substeps_debug",
-           "fv3_tracer_transport", "fv3_remap", "fv3_dynamics", "fv3_mass_sums", "fv3_halo_fill", "fv3_check_status",
+           "fv3_tracer_transport", "fv3_remap", "fv3_dynamics", "fv3_mass_sums", "fv3_mass_sums_noalloc", "fv3_halo_fill", "fv3_check_status",
            "fv3_status_string", "fv3_last_error", "fv3_host_grid_metric", "fv3_timing_start", "fv3_device_copy",
            "fv3_timing_stop", "fv3_acoustic_substeps_batched", "fv3_ensemble_create",
            "fv3_ensemble_run", "fv3_ensemble_free", "fv3_ensemble_tune", "fv3_ensemble_shapes",
@@ -108,6 +108,7 @@ def lib():
         L.fv3_mass_sums.argtypes = [vp, vp, vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double), vp]
         L.fv3_dynamics.argtypes = [C.POINTER(StateStruct), vp, C.POINTER(vp), C.c_int, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.c_double, C.c_int, C.c_int, C.c_int, vp]
+        L.fv3_mass_sums_noalloc.argtypes = [vp, vp, vp, C.POINTER(vp), C.c_int, vp, vp]
         L.fv3_halo_fill.argtypes = [vp, C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp]
         L.fv3_check_status.argtypes = [vp, vp]
         L.fv3_timing_start.argtypes = [C.c_char_p]
@@ -379,6 +380,16 @@ def device_copy(src, dst, stream=None) -> None:
     if dst.numel() * dst.element_size() != nb:
         raise ValueError("src and dst must hold the same number of bytes")
     _check(lib().fv3_device_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb, _stream(stream)))
+
+
+def mass_sums_noalloc(grid: Grid, delp, pt, qs, out, stream=None) -> None:
+    """fv3_mass_sums_noalloc: the sums into `out`, a device float64 tensor of
+    2 + len(qs) elements; nothing is allocated and nothing synchronised."""
+    if out.dtype != _torch().float64 or not out.is_cuda or out.numel() < 2 + len(qs) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 device tensor of 2 + nq elements")
+    arr = (C.c_void_p * max(1, len(qs)))(*[q.data_ptr() for q in qs])
+    _check(lib().fv3_mass_sums_noalloc(grid.handle, C.c_void_p(delp.data_ptr()), C.c_void_p(pt.data_ptr()),
+                                       arr, len(qs), C.c_void_p(out.data_ptr()), _stream(stream)))
 
 
 def halo_fill(grid: Grid, fields, levels: int, fp64: bool = False, stream=None) -> None:

@@ -118,6 +118,12 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
         fv3_free_grid(g);
         return fail(s, "grid construction: " + err);
     }
+    // the allocation-free entry point's scratch address on this device
+    // (hipSetDevice above made it current)
+    if (fv3::noalloc_setup(p->device) != FV3_OK) {
+        fv3_free_grid(g);
+        return fail(FV3_EDEVICE, "hipGetSymbolAddress of the fixed scratch array failed");
+    }
     g->ws_bytes = fv3::workspace_bytes(g);
     g->red_elems = fv3::reduction_elems(g);
     if (hipMalloc((void **)&g->red, g->red_elems * sizeof(double)) != hipSuccess) {
@@ -286,6 +292,26 @@ fv3_status fv3_mass_sums(const fv3_grid *g, const void *delp, const void *pt, vo
     std::lock_guard<std::mutex> lock(mu);
     fv3_status st = fv3::run_mass_sums(g, delp, pt, q, nq, host_out, (hipStream_t)stream);
     if (st != FV3_OK) return fail(st, "mass sums failed");
+    return FV3_OK;
+}
+
+fv3_status fv3_mass_sums_noalloc(const fv3_grid *g, const void *delp, const void *pt, void *const *q, int nq,
+                                 double *dev_out, void *stream)
+{
+    if (!g || !delp || !pt || !dev_out || nq < 0 || (nq > 0 && !q))
+        return fail(FV3_EINVAL, "NULL argument");
+    if (nq > 64) return fail(FV3_EINVAL, "need 0..64 tracers");
+    for (int m = 0; m < nq; m++)
+        if (!q[m]) return fail(FV3_EINVAL, "NULL tracer pointer");
+    if (!device_ok(g)) return fail(FV3_EDEVICE, "current HIP device differs from the grid's device");
+    long need = fv3::noalloc_mass_doubles(g);
+    long cap = (long)(FV3_NOALLOC_SCRATCH_BYTES / sizeof(double));
+    if (need > cap)
+        return fail(FV3_ESHAPE, "grid needs " + std::to_string(need * (long)sizeof(double)) +
+                                    " bytes of block partials; the fixed scratch holds " +
+                                    std::to_string((long)FV3_NOALLOC_SCRATCH_BYTES));
+    fv3_status st = fv3::run_mass_sums_noalloc(g, delp, pt, q, nq, dev_out, (hipStream_t)stream);
+    if (st != FV3_OK) return fail(st, "allocation-free mass sums failed");
     return FV3_OK;
 }
 

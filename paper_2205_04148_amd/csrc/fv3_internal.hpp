@@ -149,6 +149,12 @@ fv3_status run_tracer(void *const *q, int nq, fv3_state *s, const fv3_grid *g, i
 fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
                          int nq, double *out, hipStream_t st);
 fv3_status run_device_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+// allocation-free variant: scratch in a fixed device array resolved per device
+constexpr int FV3_MAX_DEVICES = 64;
+fv3_status noalloc_setup(int device);
+long noalloc_mass_doubles(const fv3_grid *g);
+fv3_status run_mass_sums_noalloc(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                                 int nq, double *dev_out, hipStream_t st);
 fv3_status run_halo_cells(const fv3_grid *g, void *const *f, int nf, int levels, int fp64,
                           hipStream_t st);
 // halo of a cell-centred vector (x, y components in tile coordinates)

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 #include <string>
@@ -2899,6 +2900,80 @@ fv3_status run_mass_sums(const fv3_grid *g, const void *delp, const void *pt, vo
 {
     if (g->bulk_bytes == 4) return mass_sums_t<float>(g, delp, pt, q, nq, out, st);
     return mass_sums_t<double>(g, delp, pt, q, nq, out, st);
+}
+
+// ====================================================================
+// Allocation-free mass sums.  The per-block partials go to a fixed
+// file-scope device array instead of the grid's reduction buffer, and one
+// thread combines them on the device into the caller's device output, so
+// the call allocates nothing (device or host) and does not synchronise.
+// Each GPU holds its own copy of the array; host code only ever uses the
+// address that hipGetSymbolAddress returned for the current device.
+// ====================================================================
+static __device__ __align__(256) double scratch[FV3_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[FV3_MAX_DEVICES];   // device address of `scratch`, per HIP ordinal
+
+fv3_status noalloc_setup(int device)
+{
+    if (device < 0 || device >= FV3_MAX_DEVICES) return FV3_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return FV3_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FV3_EDEVICE;
+    g_scratch_dev[device] = (double *)p;
+    return FV3_OK;
+}
+
+long noalloc_mass_doubles(const fv3_grid *g) { return 2 * part_count(g); }
+
+// The block partials added in block order with the same Neumaier steps as
+// the host-side combine of run_mass_sums, so both give the same bits.
+__global__ void k_mass_final(const double *part, long np, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (long b = 0; b < np; b++) {
+        c += part[2 * b + 1];
+        double x = part[2 * b], t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    }
+    *out = s + c;
+}
+
+template <class B>
+static fv3_status mass_sums_noalloc_t(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                                      int nq, double *dev_out, double *part, hipStream_t st)
+{
+    MetD M = metrics_d(g);
+    const Geo &G = g->geo;
+    int n = g->n;
+    long np = part_count(g);
+    // every block of k_mass_partial writes its own two slots (zero outside
+    // the interior), so nothing in the scratch has to be cleared first
+    for (int which = 0; which < 2 + nq; which++) {
+        const B *qq = which >= 2 ? (const B *)q[which - 2] : nullptr;
+        launch2d_native("k_mass_partial", k_mass_partial<B>, 0, n - 1, 0, n - 1, g->T, st, G, M, (const B *)delp,
+                        (const B *)pt, qq, which < 2 ? which : 2, part);
+        hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, st, (const double *)part, np, dev_out + which);
+    }
+    return hipGetLastError() == hipSuccess ? FV3_OK : FV3_EDEVICE;
+}
+
+fv3_status run_mass_sums_noalloc(const fv3_grid *g, const void *delp, const void *pt, void *const *q,
+                                 int nq, double *dev_out, hipStream_t st)
+{
+    double *part = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (g->p.device >= 0 && g->p.device < FV3_MAX_DEVICES) part = g_scratch_dev[g->p.device];
+    }
+    if (!part) return FV3_EINTERNAL;   // fv3_init_grid resolves it for the grid's device
+    if (g->bulk_bytes == 4) return mass_sums_noalloc_t<float>(g, delp, pt, q, nq, dev_out, part, st);
+    return mass_sums_noalloc_t<double>(g, delp, pt, q, nq, dev_out, part, st);
 }
 
 }  // namespace fv3
