@@ -2,6 +2,7 @@
 
     python -m paper_2205_04148_amd.pmc FETCH_DIR WRITE_DIR OUT.json WORKLOAD
     python -m paper_2205_04148_amd.pmc counters DIR OUT.json WORKLOAD [DIR2 ...]
+    python -m paper_2205_04148_amd.pmc trace DIR OUT.md TITLE COMMAND
 
 FETCH_DIR / WRITE_DIR hold the rocpd databases of one ``rocprofv3 --pmc
 FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of the same command.  Both
@@ -100,14 +101,16 @@ def load_all(dirname: str):
 
 
 SIMDS = 1024          # 256 compute units x 4 SIMDs (MI355X)
+XCDS = 8              # GRBM_GUI_ACTIVE comes summed over the 8 accelerator dies
 VALU_CYCLES = 4       # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
 
 
 def counters_main(a):
     """counters DIR OUT.json WORKLOAD [DIR2 ...]: per launch name, the mean
     per dispatch of every counter in the databases, plus derived figures:
-    valu_busy = SQ_ACTIVE_INST_VALU x 4 / SIMDs / GRBM_GUI_ACTIVE (share of
-    the kernel's cycles in which the average SIMD issued VALU work),
+    valu_busy = SQ_ACTIVE_INST_VALU x 4 / SIMDs / (GRBM_GUI_ACTIVE / XCDs)
+    (share of the kernel's cycles in which the average SIMD issues VALU
+    work; GRBM_GUI_ACTIVE / XCDs is the kernel's duration in cycles),
     valu_per_wave = SQ_INSTS_VALU / SQ_WAVES, lds_conflict_per_inst =
     SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (conflict cycles per LDS
     instruction)."""
@@ -123,7 +126,8 @@ def counters_main(a):
         m["dispatches"] = max(len(v) for v in cs.values())
         g = m.get("GRBM_GUI_ACTIVE")
         if g and "SQ_ACTIVE_INST_VALU" in m:
-            m["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] * VALU_CYCLES / SIMDS / g
+            m["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] * VALU_CYCLES / SIMDS / (g / XCDS)
+            m["duration_us_at_2400MHz"] = g / XCDS / 2400.0
         if m.get("SQ_WAVES") and "SQ_INSTS_VALU" in m:
             m["valu_per_wave"] = m["SQ_INSTS_VALU"] / m["SQ_WAVES"]
         if m.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in m:
@@ -135,10 +139,52 @@ def counters_main(a):
     print(f"{len(kern)} kernels -> {out}")
 
 
+def short_name(sym: str) -> str:
+    """Readable kernel name with its template arguments from a k_one symbol:
+    bulk / Courant / weight types (f, d) and the integer arguments."""
+    m = re.search(r"k_oneITnDaXadL_ZNS_(\d+)(k_\w+)", sym)
+    if not m:
+        return sym[:60]
+    ln = int(m.group(1))
+    rest = m.group(2)
+    name, targs = rest[:ln], rest[ln:]
+    head = targs.split("EEvNS_")[0]
+    types = "".join(re.findall(r"(?<=I)([fd]+)(?=L|E|$)", head)[:1])
+    ints = re.findall(r"Li(\d+)E", head)
+    args = ",".join([types] + ints) if types else ",".join(ints)
+    return f"{name}<{args}>" if args else name
+
+
+def trace_main(a):
+    """trace DIR OUT.md TITLE COMMAND: the top_kernels view of a rocprofv3
+    kernel-trace database as a markdown table."""
+    dirname, out, title, command = a[0], a[1], a[2], a[3]
+    db = glob.glob(os.path.join(dirname, "**", "*.db"), recursive=True)
+    if not db:
+        raise FileNotFoundError(f"no rocpd database under {dirname}")
+    con = sqlite3.connect(db[0])
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    lines = [f"# {title}", "", "Command (GPU box, from the repository root; rocprofv3 run from /tmp with TMPDIR=/tmp):",
+             "", "    " + command, "",
+             "rocprofv3 top_kernels view (durations in microseconds; template arguments: bulk/Courant/weight "
+             "types, then the epilogue of fv_tp_2d (0 flux, 1 delp, 2 mass-weighted, 3 interface heights, "
+             "4 tracer) or the pass and site of k_sim1).", "",
+             "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for name, calls, tot, avg, pct in rows:
+        if pct < 0.05:
+            continue
+        lines.append(f"| {short_name(name)} | {calls} | {tot:.1f} | {avg:.1f} | {pct:.2f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"{len(rows)} kernels -> {out}")
+
+
 def main(argv=None):
     a = argv if argv is not None else sys.argv[1:]
     if a and a[0] == "counters":
         return counters_main(a[1:])
+    if a and a[0] == "trace":
+        return trace_main(a[1:])
     fdir, wdir, out, workload = a[0], a[1], a[2], a[3]
     f = load(fdir, "FETCH_SIZE")
     w = load(wdir, "WRITE_SIZE")
