@@ -65,6 +65,10 @@ def lib():
         L.orc_set_vtdm.argtypes = [C.c_void_p, C.c_double]
         L.orc_set_edge_fix.argtypes = [C.c_void_p, C.c_int]
         L.orc_set_edge_ppm.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_edge_interp.argtypes = [C.c_void_p, C.c_int]
+        L.orc_interp.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_interp.restype = C.c_double
+        L.orc_corner_values.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_ppm_face_edge.restype = C.c_double
         L.orc_ppm_face_edge.argtypes = [dp, dp, C.c_double, C.c_int, C.c_int, C.c_int]
         L.orc_edge_partner.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
@@ -119,7 +123,7 @@ class Grid:
                  d2_bg: float = 0.0, beta: float = 1.0, dddmp: float = 0.0, hord: int = 8,
                  hord_tr: int = 0, pp_order: int = 2, nord: int = 0, d4_bg: float = 0.0,
                  vtdm: float = 0.0, edge_fix: bool = False,
-                 edge_ppm: bool = False):
+                 edge_ppm: bool = False, edge_interp: bool = False):
         if hord not in (5, 6, 8) or hord_tr not in (0, 5, 6, 7, 8):
             raise ValueError("PPM orders: hord 5, 6 or 8; hord_tr 0, 5, 6, 7 or 8")
         if pp_order not in (2, 4):
@@ -149,6 +153,8 @@ class Grid:
         lib().orc_set_edge_fix(h, int(bool(edge_fix)))
         self.edge_ppm = edge_ppm
         lib().orc_set_edge_ppm(h, int(bool(edge_ppm)))
+        self.edge_interp = edge_interp
+        lib().orc_set_edge_interp(h, int(bool(edge_interp)))
         self.kind, self.n, self.nz = kind, n, nz
         self.T = 6 if kind == 1 else 1
         self.N = n + 2 * H + 1
@@ -326,6 +332,27 @@ def ppm_profile(d, a):
     aL, aR, a6 = np.zeros_like(a), np.zeros_like(a), np.zeros_like(a)
     lib().orc_ppm_profile(len(a), _p(d), _p(a), _p(aL), _p(aR), _p(a6))
     return aL, aR, a6
+
+
+INTERP_KINDS = {"face_pt": 0, "cell_pt": 1, "face_mean": 2}
+
+
+def interp(kind: str, x, m0: int, m: int, n: int, edge: bool) -> float:
+    """One interpolation of c_sw (kind "cell_pt": D -> A, "face_pt": A -> C)
+    or of nh_p_grad's corner values ("face_mean") at index m along a sweep
+    whose tile edges are the interfaces 0 and n; x[k - m0] is the value at
+    index k.  edge: the one-sided stencils of the option edge_interp."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().orc_interp(INTERP_KINDS[kind], _p(x), len(x), int(m0), int(m), int(n), int(bool(edge)))
+
+
+def corner_values(g: Grid, q) -> np.ndarray:
+    """nh_p_grad's corner values of one level, q [T][N][N] with filled halos
+    (the cell-to-corner interpolation of the D-grid pressure gradient)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    out = np.zeros_like(q)
+    lib().orc_corner_values(g._h, _p(q), _p(out))
+    return out
 
 
 def remap_column(pe1, pe2, q1) -> np.ndarray:

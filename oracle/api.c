@@ -44,6 +44,15 @@ void orc_set_smag(void *gp, double dddmp) { ((OGrid *)gp)->dddmp = dddmp; }
 void orc_set_vtdm(void *gp, double vtdm) { ((OGrid *)gp)->vtdm = vtdm; }
 void orc_set_edge_fix(void *gp, int on) { ((OGrid *)gp)->edge_fix = on; }
 void orc_set_edge_ppm(void *gp, int on) { ((OGrid *)gp)->edge_ppm = on; }
+void orc_set_edge_interp(void *gp, int on) { ((OGrid *)gp)->edge_interp = on; }
+
+void orc_corner_values(void *gp, const double *q, double *qB) { o_corner_values((const OGrid *)gp, q, qB); }
+
+double orc_interp(int kind, const double *x, int len, int m0, int m, int n, int edge)
+{
+    (void)len;
+    return o_interp(kind, x, 1, m0, m, n, edge);
+}
 
 int orc_edge_partner(void *gp, int t, int st, int i, int j, int *out4)
 {

@@ -42,6 +42,53 @@ static int skip_corner(const OGrid *g, int st, int i, int j)
     return g->kind == 1 && og_region(g, st, i, j) == 2;
 }
 
+/* ------------------------------------------- interpolations along a sweep */
+/*
+ * Along a sweep with interfaces m (interface m between cells m - 1 and m,
+ * cell m centred at m + 1/2), x0[(k - m0) s] is the value at index k:
+ *  OI_CELL_PT   point value at the centre of cell m from the point values
+ *               at the interfaces m - 1 .. m + 2: the cubic's (-1,9,9,-1)/16;
+ *  OI_FACE_PT   point value at interface m from the point values at the
+ *               centres of cells m - 2 .. m + 1: (-1,9,9,-1)/16;
+ *  OI_FACE_MEAN value at interface m from the means of cells m - 2 .. m + 1:
+ *               (-1,7,7,-1)/12, the interface value of the cubic whose cell
+ *               means they are.
+ * With `edge` (the option edge_interp, on sweeps through a cube tile whose
+ * tile edges are the interfaces 0 and n), a stencil that would reach across
+ * an edge uses only the points on its own side: the interpolant of the
+ * three nearest points there (quadratic; for OI_FACE_PT and OI_CELL_PT the
+ * weights 3/8, 3/4, -1/8 from the point next to the edge outwards, for
+ * OI_FACE_MEAN the cell-mean weights 1/3, 5/6, -1/6), and an interface on
+ * the edge itself takes the mean of the two linear extrapolations through
+ * the two nearest points (centres, or cell means) of each side,
+ * 3/4 (a_{-1} + a_0) - 1/4 (a_{-2} + a_1).  The weights assume evenly spaced
+ * points, as the centred ones do.
+ */
+double o_interp(int kind, const double *x0, ptrdiff_t s, int m0, int m, int n, int edge)
+{
+#define X(k) x0[(ptrdiff_t)((k) - m0) * s]
+    if (kind == OI_CELL_PT) {
+        if (edge && (m == 0 || m == n)) return 0.375 * X(m) + 0.75 * X(m + 1) - 0.125 * X(m + 2);
+        if (edge && (m == -1 || m == n - 1)) return 0.375 * X(m + 1) + 0.75 * X(m) - 0.125 * X(m - 1);
+        return (-X(m - 1) + 9.0 * X(m) + 9.0 * X(m + 1) - X(m + 2)) / 16.0;
+    }
+    if (edge && (m == 0 || m == n)) return 0.75 * (X(m - 1) + X(m)) - 0.25 * (X(m - 2) + X(m + 1));
+    if (kind == OI_FACE_PT) {
+        if (edge && (m == 1 || m == n + 1)) return 0.375 * X(m - 1) + 0.75 * X(m) - 0.125 * X(m + 1);
+        if (edge && (m == -1 || m == n - 1)) return 0.375 * X(m) + 0.75 * X(m - 1) - 0.125 * X(m - 2);
+        return (-X(m - 2) + 9.0 * X(m - 1) + 9.0 * X(m) - X(m + 1)) / 16.0;
+    }
+    if (edge && (m == 1 || m == n + 1)) return (2.0 * X(m - 1) + 5.0 * X(m) - X(m + 1)) / 6.0;
+    if (edge && (m == -1 || m == n - 1)) return (2.0 * X(m) + 5.0 * X(m - 1) - X(m - 2)) / 6.0;
+    {
+        static const double c4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
+        double r = 0.0;
+        for (int a = 0; a < 4; a++) r += c4[a] * X(m - 2 + a);
+        return r;
+    }
+#undef X
+}
+
 /* ------------------------------------------------------------------ c_sw */
 /*
  * Half-step C-grid update on one level of one tile.  D-grid winds are
@@ -77,18 +124,20 @@ static void c_sw_plane(const OGrid *g, int t, double dt2, const double *u, const
 
     og_view_pair(g, u, ST_Y, v, ST_X, MODE_X, PAIR_SIGNED, uX, vX);
     og_view_pair(g, u, ST_Y, v, ST_X, MODE_Y, PAIR_SIGNED, uY, vY);
+    /* one-sided stencils at tile edges only on sweeps whose cross index lies
+     * inside the tile (option edge_interp, cube) */
+    const int ei = g->edge_interp && g->kind == 1;
+    const ptrdiff_t N = g->N;
     /* D -> A: u along y, v along x */
     for (int j = -2; j <= n + 1; j++)
         for (int i = -3; i <= n + 2; i++) {
             if (skip_corner(g, ST_C, i, j)) continue;
-            ua[IX(g, i, j)] = (-uY[IX(g, i, j - 1)] + 9.0 * uY[IX(g, i, j)] +
-                               9.0 * uY[IX(g, i, j + 1)] - uY[IX(g, i, j + 2)]) / 16.0;
+            ua[IX(g, i, j)] = o_interp(OI_CELL_PT, uY + IX(g, i, 0), N, 0, j, n, ei && i >= 0 && i < n);
         }
     for (int j = -3; j <= n + 2; j++)
         for (int i = -2; i <= n + 1; i++) {
             if (skip_corner(g, ST_C, i, j)) continue;
-            va[IX(g, i, j)] = (-vX[IX(g, i - 1, j)] + 9.0 * vX[IX(g, i, j)] +
-                               9.0 * vX[IX(g, i + 1, j)] - vX[IX(g, i + 2, j)]) / 16.0;
+            va[IX(g, i, j)] = o_interp(OI_CELL_PT, vX + IX(g, 0, j), 1, 0, i, n, ei && j >= 0 && j < n);
         }
     og_view_pair(g, ua, ST_C, va, ST_C, MODE_X, PAIR_SIGNED, uaX, vaX);
     og_view_pair(g, ua, ST_C, va, ST_C, MODE_Y, PAIR_SIGNED, uaY, vaY);
@@ -99,8 +148,7 @@ static void c_sw_plane(const OGrid *g, int t, double dt2, const double *u, const
             int inrow = (j >= 0 && j < n);
             if (!inrow && (i < 0 || i > n)) continue;
             size_t f = IX(g, i, j);
-            ucp[f] = (-uaX[IX(g, i - 2, j)] + 9.0 * uaX[IX(g, i - 1, j)] + 9.0 * uaX[f] -
-                      uaX[IX(g, i + 1, j)]) / 16.0;
+            ucp[f] = o_interp(OI_FACE_PT, uaX + IX(g, 0, j), 1, 0, i, n, ei && inrow);
             ax[f] = dt2 * (ucp[f] - v[f] * cos_u[f]) / sin_u[f] * dy[f];
         }
     for (int j = -1; j <= n + 1; j++)
@@ -108,8 +156,7 @@ static void c_sw_plane(const OGrid *g, int t, double dt2, const double *u, const
             int incol = (i >= 0 && i < n);
             if (!incol && (j < 0 || j > n)) continue;
             size_t f = IX(g, i, j);
-            vcp[f] = (-vaY[IX(g, i, j - 2)] + 9.0 * vaY[IX(g, i, j - 1)] + 9.0 * vaY[f] -
-                      vaY[IX(g, i, j + 1)]) / 16.0;
+            vcp[f] = o_interp(OI_FACE_PT, vaY + IX(g, i, 0), N, 0, j, n, ei && incol);
             ay[f] = dt2 * (vcp[f] - u[f] * cos_v[f]) / sin_v[f] * dx[f];
         }
 
@@ -781,10 +828,13 @@ static void dzd_tile(const OGrid *g, int t, double *delz, const double *zs, cons
  */
 static void corner_interp(const OGrid *g, const double *q, double *qB)
 {
-    static const double c4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
     int n = g->n;
     size_t P = o_plane(g);
     double *qx = dalloc(P);
+    /* one-sided stencils at tile edges (option edge_interp, cube): the pass
+     * along x on rows inside the tile, the pass along y on every corner
+     * column (all lie on or inside the tile) */
+    const int ei = g->edge_interp && g->kind == 1;
     og_view_scalar(g, q, ST_C, MODE_X, 0, qx);
     for (int j = 0; j <= n; j++)
         for (int i = 0; i <= n; i++) {
@@ -798,15 +848,22 @@ static void corner_interp(const OGrid *g, const double *q, double *qB)
                 qB[IX(g, i, j)] = s / 3.0;
                 continue;
             }
-            double acc = 0.0;
+            /* inner pass along x on the rows j - 2 .. j + 1, then along y */
+            double rows[4];
             for (int b = 0; b < 4; b++) {
-                double row = 0.0;
-                for (int a = 0; a < 4; a++) row += c4[a] * qx[IX(g, i + a - 2, j + b - 2)];
-                acc += c4[b] * row;
+                int r = j + b - 2;
+                rows[b] = o_interp(OI_FACE_MEAN, qx + IX(g, 0, r), 1, 0, i, n, ei && r >= 0 && r < n);
             }
-            qB[IX(g, i, j)] = acc;
+            qB[IX(g, i, j)] = o_interp(OI_FACE_MEAN, rows, 1, j - 2, j, n, ei);
         }
     free(qx);
+}
+
+/* corner values of one level of every tile (halos already filled) */
+void o_corner_values(const OGrid *g, const double *q, double *qB)
+{
+    size_t P = o_plane(g);
+    for (int t = 0; t < g->T; t++) corner_interp(g, q + (size_t)t * P, qB + (size_t)t * P);
 }
 
 static void nhpgrad_tile(const OGrid *g, int t, double bdt, double *u, double *v,

@@ -64,6 +64,7 @@ typedef struct {
     /* cube: replace both tiles' fluxes through a shared edge face by their mean */
     int edge_fix;
     int edge_ppm;          /* one-sided PPM edge values at cube tile edges */
+    int edge_interp;       /* one-sided c_sw and nh_p_grad interpolations at cube tile edges */
     /* cube connectivity: per tile, per edge (0 W, 1 E, 2 S, 3 N) */
     int nbr[6][4];
     int R[6][4][2][2];     /* lattice rotation from this tile into the neighbour */
@@ -77,6 +78,11 @@ typedef struct {
 } OGrid;
 
 static inline size_t o_plane(const OGrid *g) { return (size_t)g->N * g->N; }
+
+/* one-dimensional interpolations of c_sw and nh_p_grad (see dyn.c) */
+enum { OI_FACE_PT = 0, OI_CELL_PT = 1, OI_FACE_MEAN = 2 };
+double o_interp(int kind, const double *x0, ptrdiff_t s, int m0, int m, int n, int edge);
+void o_corner_values(const OGrid *g, const double *q, double *qB);
 #define IX(g, i, j) ((size_t)((j) + H) * (size_t)(g)->N + (size_t)((i) + H))
 
 /* caller-owned state arrays of the substep loop */

@@ -37,7 +37,17 @@ namespace fv3 {
 
 // ------------------------------------------------------------ indexing
 DEVI long pidx(const Geo &G, int L, int t, int k) { return G.off0 + ((long)t * L + k) * G.lev; }
-#define AT(P, i, j) (P)[(int)(j) * (int)G.pitch + (int)(i)]
+// Element (i, j) of a plane whose interior origin is P (i, j >= -3): the
+// address is the plane's halo corner (-3, -3) plus a non-negative 32-bit
+// byte offset, so that a block-uniform P becomes a scalar base with one
+// 32-bit vector offset instead of per-lane 64-bit address arithmetic.
+template <class T>
+DEVI T &at_(T *p, int i, int j, int pitch)
+{
+    char *b = (char *)(p - (3 * pitch + 3));
+    return *(T *)(b + (unsigned)((j + 3) * pitch + (i + 3)) * (unsigned)sizeof(T));
+}
+#define AT(P, i, j) at_((P), (int)(i), (int)(j), (int)G.pitch)
 
 DEVI int stx_(int st) { return (st == SC || st == SY) ? 1 : 0; }
 DEVI int sty_(int st) { return (st == SC || st == SX) ? 1 : 0; }
@@ -658,8 +668,9 @@ constexpr int csw_lds()
 }
 
 template <class B, bool CORNER>
-DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *delp, const B *pt,
-                   const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc, B *ax, B *ay)
+DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Mets<B> &M, B dt2, const B *u,
+                   const B *v, const B *delp, const B *pt, const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc,
+                   B *ax, B *ay)
 {
     constexpr int CTY = CswRows<B>::Y;
     constexpr int WA = CTX + 5, HA = CTY + 5;   // A-grid cells i0-3.., j0-3..
@@ -673,7 +684,6 @@ DEVI void csw_body(Bk bk, B *L, Geo G, Mets<B> M, B dt2, const B *u, const B *v,
     B *sKE = sGw + HF * WF, *sVO = sKE + HK * WK;
     const int n = G.n, tid = threadIdx.x;
     const int i0 = -1 + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
-    const int t = bk.z / G.nz, k = bk.z % G.nz;
     const long o = pidx(G, G.nz, t, k);
     const B *U = u + o, *V = v + o, *D = delp + o, *PT = pt + o, *Wf = w + o;
 
@@ -859,10 +869,11 @@ DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B 
     const int i0 = -1 + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
     const bool nx = i0 - 6 < 0 || i0 + CTX + 5 > n, ny = j0 - 6 < 0 || j0 + CTY + 5 > n;
     __shared__ B L[csw_lds<CTY>()];
+    const int t = (int)bk.z / G.nz, k = (int)bk.z % G.nz;
     if (G.cube && nx && ny)
-        csw_body<B, true>(bk, L, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+        csw_body<B, true>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
     else
-        csw_body<B, false>(bk, L, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+        csw_body<B, false>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
 }
 
 // ====================================================================
@@ -892,24 +903,49 @@ DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, co
     double zw = zs_at(G, phis, t, i - 1, j, 0), ze = zs_at(G, phis, t, i + 1, j, 0);
     double zsou = zs_at(G, phis, t, i, j - 1, 1), znor = zs_at(G, phis, t, i, j + 1, 1);
     double zprev = zc;   // new height of the interface below
+    // Walk bottom-up.  Level K needs the thicknesses of layer K at the cell
+    // and its four neighbours and the area fluxes of layers K and K - 1 (the
+    // interface mean); the layer K - 1 values are loaded one step ahead and
+    // carried, so every value is loaded once and the next level's loads are
+    // in flight while the current one computes.
+    long o = pidx(G, nz, t, nz - 1);
+    const double *D = delz + o;
+    double dc = AT(D, i, j), dw = sv(G, D, SC, i - 1, j, 0), de = sv(G, D, SC, i + 1, j, 0);
+    double ds = sv(G, D, SC, i, j - 1, 1), dn = sv(G, D, SC, i, j + 1, 1);
+    double ax0 = (double)AT(ax + o, i, j), ax1 = (double)AT(ax + o, i + 1, j);
+    double ay0 = (double)AT(ay + o, i, j), ay1 = (double)AT(ay + o, i, j + 1);
     for (int K = nz - 1; K >= 0; K--) {
-        long o = pidx(G, nz, t, K);
-        const double *D = delz + o;
-        zc -= AT(D, i, j);
-        zw -= sv(G, D, SC, i - 1, j, 0);
-        ze -= sv(G, D, SC, i + 1, j, 0);
-        zsou -= sv(G, D, SC, i, j - 1, 1);
-        znor -= sv(G, D, SC, i, j + 1, 1);
-        long ob = K > 0 ? pidx(G, nz, t, K - 1) : o;
-        double a0 = K == 0 ? (double)AT(ax + o, i, j) : 0.5 * ((double)AT(ax + ob, i, j) + (double)AT(ax + o, i, j));
-        double a1 = K == 0 ? (double)AT(ax + o, i + 1, j) : 0.5 * ((double)AT(ax + ob, i + 1, j) + (double)AT(ax + o, i + 1, j));
-        double b0 = K == 0 ? (double)AT(ay + o, i, j) : 0.5 * ((double)AT(ay + ob, i, j) + (double)AT(ay + o, i, j));
-        double b1 = K == 0 ? (double)AT(ay + o, i, j + 1) : 0.5 * ((double)AT(ay + ob, i, j + 1) + (double)AT(ay + o, i, j + 1));
+        double ndc = 0, ndw = 0, nde = 0, nds = 0, ndn = 0, nax0 = 0, nax1 = 0, nay0 = 0, nay1 = 0;
+        const long on = K > 0 ? pidx(G, nz, t, K - 1) : o;
+        if (K > 0) {
+            const double *Dn = delz + on;
+            ndc = AT(Dn, i, j);
+            ndw = sv(G, Dn, SC, i - 1, j, 0);
+            nde = sv(G, Dn, SC, i + 1, j, 0);
+            nds = sv(G, Dn, SC, i, j - 1, 1);
+            ndn = sv(G, Dn, SC, i, j + 1, 1);
+            nax0 = (double)AT(ax + on, i, j);
+            nax1 = (double)AT(ax + on, i + 1, j);
+            nay0 = (double)AT(ay + on, i, j);
+            nay1 = (double)AT(ay + on, i, j + 1);
+        }
+        zc -= dc;
+        zw -= dw;
+        ze -= de;
+        zsou -= ds;
+        znor -= dn;
+        double a0 = K == 0 ? ax0 : 0.5 * (nax0 + ax0);
+        double a1 = K == 0 ? ax1 : 0.5 * (nax1 + ax1);
+        double b0 = K == 0 ? ay0 : 0.5 * (nay0 + ay0);
+        double b1 = K == 0 ? ay1 : 0.5 * (nay1 + ay1);
         double z0 = a0 > 0 ? zw : zc, z1 = a1 > 0 ? zc : ze;
         double y0 = b0 > 0 ? zsou : zc, y1 = b1 > 0 ? zc : znor;
         double zn = (zc * area + a0 * z0 - a1 * z1 + b0 * y0 - b1 * y1) / (area + a0 - a1 + b0 - b1);
         AT(delzc + o, i, j) = zprev - zn;
         zprev = zn;
+        o = on;
+        dc = ndc; dw = ndw; de = nde; ds = nds; dn = ndn;
+        ax0 = nax0; ax1 = nax1; ay0 = nay0; ay1 = nay1;
     }
 }
 
@@ -1306,26 +1342,46 @@ DEVI double pgf(double dt, double L, double dW, double dE, double zW0, double zW
 }
 
 // p_grad_c on the interior C-grid faces with the half-step cells' pressure
-// and geopotential; layer mass weights from delpc.
+// and geopotential; layer mass weights from delpc.  Each thread walks PGK
+// consecutive layers of its point: the interface below one layer is the
+// interface above the next, so its pressure and geopotential are carried
+// instead of loaded again (the face metric too).
+#ifndef FV3_PGK
+#define FV3_PGK 4
+#endif
+constexpr int PGK = FV3_PGK;
 template <class B>
 DEVI void k_pgradc(KARGS, Geo G, MetD M, double dt2, const B *delpc, const double *pkc,
                          const double *gz, B *uc, B *vc)
 {
-    KBEGIN(G.nz);
-    int n = G.n, nz = G.nz;
-    long o = pidx(G, nz, t, k), o0 = pidx(G, nz + 1, t, k), o1 = pidx(G, nz + 1, t, k + 1);
-    const B *D = delpc + o;
-    if (j < n) {
-        int iw = i - 1, ie = i;
-        AT(uc + o, i, j) += (B)pgf(dt2, AT(MP(M, M_DXC), i, j), (double)AT(D, iw, j), (double)AT(D, ie, j),
-                                   AT(gz + o0, iw, j), AT(gz + o1, iw, j), AT(gz + o0, ie, j), AT(gz + o1, ie, j),
-                                   AT(pkc + o0, iw, j), AT(pkc + o1, iw, j), AT(pkc + o0, ie, j), AT(pkc + o1, ie, j));
-    }
-    if (i < n) {
-        int js = j - 1, jn = j;
-        AT(vc + o, i, j) += (B)pgf(dt2, AT(MP(M, M_DYC), i, j), (double)AT(D, i, js), (double)AT(D, i, jn),
-                                   AT(gz + o0, i, js), AT(gz + o1, i, js), AT(gz + o0, i, jn), AT(gz + o1, i, jn),
-                                   AT(pkc + o0, i, js), AT(pkc + o1, i, js), AT(pkc + o0, i, jn), AT(pkc + o1, i, jn));
+    const int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+    const int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+    if (i < ilo || i > ihi || j > jhi) return;
+    const int n = G.n, nz = G.nz, nzb = (nz + PGK - 1) / PGK;
+    const int t = (int)bk.z / nzb, k0 = ((int)bk.z % nzb) * PGK;
+    const bool fx = j < n, fy = i < n;   // x-face (i, j) and y-face (i, j) of this point
+    if (!fx && !fy) return;
+    const double dxc = fx ? AT(MP(M, M_DXC), i, j) : 0.0, dyc = fy ? AT(MP(M, M_DYC), i, j) : 0.0;
+    // cells W = (i - 1, j), C = (i, j), S = (i, j - 1) at the interface above the layer
+    long oi = pidx(G, nz + 1, t, k0);
+    double zW = 0, pW = 0, zS = 0, pS = 0;
+    if (fx) { zW = AT(gz + oi, i - 1, j); pW = AT(pkc + oi, i - 1, j); }
+    if (fy) { zS = AT(gz + oi, i, j - 1); pS = AT(pkc + oi, i, j - 1); }
+    double zC = AT(gz + oi, i, j), pC = AT(pkc + oi, i, j);
+    const int k1 = k0 + PGK < nz ? k0 + PGK : nz;
+    for (int k = k0; k < k1; k++) {
+        const long o = pidx(G, nz, t, k), o1 = pidx(G, nz + 1, t, k + 1);
+        const B *D = delpc + o;
+        double zW1 = 0, pW1 = 0, zS1 = 0, pS1 = 0;
+        if (fx) { zW1 = AT(gz + o1, i - 1, j); pW1 = AT(pkc + o1, i - 1, j); }
+        if (fy) { zS1 = AT(gz + o1, i, j - 1); pS1 = AT(pkc + o1, i, j - 1); }
+        const double zC1 = AT(gz + o1, i, j), pC1 = AT(pkc + o1, i, j);
+        const double dC = (double)AT(D, i, j);
+        if (fx)
+            AT(uc + o, i, j) += (B)pgf(dt2, dxc, (double)AT(D, i - 1, j), dC, zW, zW1, zC, zC1, pW, pW1, pC, pC1);
+        if (fy)
+            AT(vc + o, i, j) += (B)pgf(dt2, dyc, (double)AT(D, i, j - 1), dC, zS, zS1, zC, zC1, pS, pS1, pC, pC1);
+        zW = zW1; pW = pW1; zS = zS1; pS = pS1; zC = zC1; pC = pC1;
     }
 }
 
@@ -1375,31 +1431,72 @@ struct FvArgs {
     C *cxa, *cya;
 };
 
-template <class T, class C>
-DEVI T ccr(const C *a, const C *a0, int idx, int avg)
+// Loads and stores through a block-uniform base pointer and a 32-bit
+// unsigned element offset (one VALU add per access instead of 64-bit
+// address arithmetic).
+template <class T>
+DEVI T ldo(const T *base, unsigned e)
 {
-    if (avg) return (T)(0.5 * ((double)a0[idx] + (double)a[idx]));
-    return (T)a[idx];
+    return *(const T *)((const char *)base + e * (unsigned)sizeof(T));
+}
+template <class T>
+DEVI void sto(T *base, unsigned e, T v)
+{
+    *(T *)((char *)base + e * (unsigned)sizeof(T)) = v;
 }
 
-template <class T, class C, class M, int EPI, int ORD, int EDGE>
-DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
+template <class T, class C>
+DEVI T ccr(const C *a, const C *a0, unsigned idx, int avg)
+{
+    if (avg) return (T)(0.5 * ((double)ldo(a0, idx) + (double)ldo(a, idx)));
+    return (T)ldo(a, idx);
+}
+
+// a / b for the flux-divergence updates: FP32 through the hardware
+// reciprocal (about 1 ulp, far below the FP32 bulk's rounding), FP64 exact
+template <class T>
+DEVI T rdiv(T a, T b)
+{
+    if constexpr (std::is_same<T, float>::value) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+
+// The transport tile in LDS (one instance per block, shared by both
+// instantiations of the body).
+template <class T>
+struct FvLds {
+    static constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
+    static constexpr int QW = FTX + 6, QH = FTY + 6;
+    static constexpr int YW = FTX + 6, YH = FTY + 1;   // y-faces: cols i0-3..i0+FTX+2, rows j0..j0+FTY
+    static constexpr int XW = FTX + 1, XH = FTY + 6;   // x-faces: cols i0..i0+FTX, rows j0-3..j0+FTY+2
+    T sQ[QH * QW], sQy[QH * QW], sAR[QH * QW];
+    T sCY[YH * YW], sYF[YH * YW], sFy[YH * YW];
+    T sCX[XH * XW], sXF[XH * XW], sFx[XH * XW];
+    T sQi[FTY * QW];                // cells: cols i0-3..i0+FTX+2, rows j0..j0+FTY-1
+    T sQj[QH * FTX];                // cells: cols i0..i0+FTX-1, rows j0-3..j0+FTY+2
+};
+
+// CORNER: the block's staging window reaches a cube corner block (only
+// blocks at the four corners of a tile), so its field reads go through the
+// corner views; every other block reads the plane directly.
+template <class T, class C, class M, int EPI, int ORD, int EDGE, bool CORNER>
+DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
 {
     constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
-    constexpr int QW = FTX + 6, QH = FTY + 6;
-    constexpr int YW = FTX + 6, YH = FTY + 1;   // y-faces: cols i0-3..i0+FTX+2, rows j0..j0+FTY
-    constexpr int XW = FTX + 1, XH = FTY + 6;   // x-faces: cols i0..i0+FTX, rows j0-3..j0+FTY+2
+    constexpr int QW = FvLds<T>::QW, QH = FvLds<T>::QH;
+    constexpr int YW = FvLds<T>::YW, YH = FvLds<T>::YH;
+    constexpr int XW = FvLds<T>::XW, XH = FvLds<T>::XH;
     constexpr int N4X = (FTY * XW + FNT - 1) / FNT, N4Y = (YH * FTX + FNT - 1) / FNT;
     constexpr int N5 = (FTY * FTX + FNT - 1) / FNT;
-    __shared__ T sQ[QH * QW], sQy[QH * QW], sAR[QH * QW];
-    __shared__ T sCY[YH * YW], sYF[YH * YW], sFy[YH * YW];
-    __shared__ T sCX[XH * XW], sXF[XH * XW], sFx[XH * XW];
-    __shared__ T sQi[FTY * QW];                // cells: cols i0-3..i0+FTX+2, rows j0..j0+FTY-1
-    __shared__ T sQj[QH * FTX];                // cells: cols i0..i0+FTX-1, rows j0-3..j0+FTY+2
+    T *sQ = L.sQ, *sQy = L.sQy, *sAR = L.sAR, *sCY = L.sCY, *sYF = L.sYF, *sFy = L.sFy;
+    T *sCX = L.sCX, *sXF = L.sXF, *sFx = L.sFx, *sQi = L.sQi, *sQj = L.sQj;
     const int n = G.n, tid = threadIdx.x;
     const int i0 = bk.x * FTX, j0 = bk.y * FTY;
     const int t = bk.z / A.Lc, k = bk.z % A.Lc;
-    // plane pointers (block-uniform) and 32-bit in-plane offsets
+    // plane pointers (block-uniform); the staged ones are rebased to the
+    // halo corner (-3, -3) so that every offset is a non-negative 32-bit value
+    const int P = (int)G.pitch;
+    const unsigned hb = 3u * (unsigned)P + 3u;   // rebase of the staging windows
     const T *Q = A.q + pidx(G, A.Lq, t, k);
     const long oc = pidx(G, A.Lc, t, k);
     const int avg = A.iface && k > 0;
@@ -1407,9 +1504,10 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     const T *AR = A.area + G.off0 + (long)t * G.lev;
     const T *DXA = EDGE ? A.dxa + G.off0 + (long)t * G.lev : nullptr;
     const T *DYA = EDGE ? A.dya + G.off0 + (long)t * G.lev : nullptr;
-    const int P = (int)G.pitch;
-    const C *cry = A.cry + oc, *yfx = A.yfx + oc, *crx = A.crx + oc, *xfx = A.xfx + oc;
-    const C *cry0 = A.cry + ob, *yfx0 = A.yfx + ob, *crx0 = A.crx + ob, *xfx0 = A.xfx + ob;
+    const T *Qh = Q - hb, *ARh = AR - hb;
+    const C *cryh = A.cry + oc - hb, *yfxh = A.yfx + oc - hb, *crxh = A.crx + oc - hb, *xfxh = A.xfx + oc - hb;
+    const C *cry0h = A.cry + ob - hb, *yfx0h = A.yfx + ob - hb, *crx0h = A.crx + ob - hb, *xfx0h = A.xfx + ob - hb;
+    const M *MX = A.mx ? A.mx + oc : nullptr, *MY = A.my ? A.my + oc : nullptr;
     using PT = typename std::conditional<EPI == EPI_TRACER, double, T>::type;
 
     // 0. per-thread prefetch of the global operands of phases 4 and 5, in
@@ -1420,31 +1518,31 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
     for (int m = 0; m < N4X; m++) {
         int e = tid + m * FNT, r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 + r;
-        wx[m] = (A.mx && e < FTY * XW && i <= n && j < n) ? A.mx[oc + j * P + i] : (M)0;
+        wx[m] = (MX && e < FTY * XW && i <= n && j < n) ? ldo(MX, (unsigned)(j * P + i)) : (M)0;
     }
 #pragma unroll
     for (int m = 0; m < N4Y; m++) {
         int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
-        wy[m] = (A.my && e < YH * FTX && i < n && j <= n) ? A.my[oc + j * P + i] : (M)0;
+        wy[m] = (MY && e < YH * FTX && i < n && j <= n) ? ldo(MY, (unsigned)(j * P + i)) : (M)0;
     }
 #pragma unroll
     for (int m = 0; m < N5; m++) {
         int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
         bool in = e < FTY * FTX && i < n && j < n;
-        int ci = j * P + i;
+        unsigned ci = (unsigned)(j * P + i);
         pa[m] = (PT)0;
         pb[m] = (PT)0;
         if constexpr (EPI == EPI_MASSW) {
             if (in) {
-                pa[m] = A.dold[oc + ci];
-                pb[m] = A.dnew[oc + ci];
+                pa[m] = ldo(A.dold + oc, ci);
+                pb[m] = ldo(A.dnew + oc, ci);
             }
         } else if constexpr (EPI == EPI_TRACER) {
             if (in) {
-                pa[m] = A.dp1[oc + ci];
-                pb[m] = A.dp2[oc + ci];
+                pa[m] = ldo(A.dp1 + oc, ci);
+                pb[m] = ldo(A.dp2 + oc, ci);
             }
         }
     }
@@ -1455,12 +1553,13 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int i = i0 - 3 + c, j = j0 - 3 + r;
         T vx = 0, vy = 0, ar = 0;
         if (i <= n + 2 && j <= n + 2) {
-            if (in_corner(G, SC, i, j)) {
+            if (CORNER && in_corner(G, SC, i, j)) {
                 vx = sv(G, Q, SC, i, j, 0);
                 vy = sv(G, Q, SC, i, j, 1);
             } else {
-                vx = vy = Q[j * P + i];
-                ar = AR[j * P + i];
+                const unsigned u = (unsigned)((j + 3) * P + (i + 3));
+                vx = vy = ldo(Qh, u);
+                ar = ldo(ARh, u);
             }
         }
         sQ[e] = vx;
@@ -1472,8 +1571,9 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int i = i0 - 3 + c, j = j0 + r;
         T cr = 0, fl = 0;
         if (i <= n + 2 && j <= n) {
-            cr = ccr<T>(cry, cry0, j * P + i, avg);
-            fl = ccr<T>(yfx, yfx0, j * P + i, avg);
+            const unsigned u = (unsigned)((j + 3) * P + (i + 3));
+            cr = ccr<T>(cryh, cry0h, u, avg);
+            fl = ccr<T>(yfxh, yfx0h, u, avg);
         }
         sCY[e] = cr;
         sYF[e] = fl;
@@ -1483,8 +1583,9 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         int i = i0 + c, j = j0 - 3 + r;
         T cr = 0, fl = 0;
         if (i <= n && j <= n + 2) {
-            cr = ccr<T>(crx, crx0, j * P + i, avg);
-            fl = ccr<T>(xfx, xfx0, j * P + i, avg);
+            const unsigned u = (unsigned)((j + 3) * P + (i + 3));
+            cr = ccr<T>(crxh, crx0h, u, avg);
+            fl = ccr<T>(xfxh, xfx0h, u, avg);
         }
         sCX[e] = cr;
         sXF[e] = fl;
@@ -1542,7 +1643,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (i <= n + 2 && j < n) {
             T ar = sAR[(r + 3) * QW + c];
             T y0 = sYF[r * YW + c], y1 = sYF[(r + 1) * YW + c];
-            v = (sQ[(r + 3) * QW + c] * ar + y0 * sFy[r * YW + c] - y1 * sFy[(r + 1) * YW + c]) / (ar + y0 - y1);
+            v = rdiv(sQ[(r + 3) * QW + c] * ar + y0 * sFy[r * YW + c] - y1 * sFy[(r + 1) * YW + c], ar + y0 - y1);
         }
         sQi[e] = v;
     }
@@ -1553,7 +1654,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         if (i < n && j <= n + 2) {
             T ar = sAR[r * QW + c + 3];
             T x0 = sXF[r * XW + c], x1 = sXF[r * XW + c + 1];
-            v = (sQ[r * QW + c + 3] * ar + x0 * sFx[r * XW + c] - x1 * sFx[r * XW + c + 1]) / (ar + x0 - x1);
+            v = rdiv(sQ[r * QW + c + 3] * ar + x0 * sFx[r * XW + c] - x1 * sFx[r * XW + c + 1], ar + x0 - x1);
         }
         sQj[e] = v;
     }
@@ -1563,10 +1664,10 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         const T F = (T)0.5 * (fx + sFx[s]) * wgt;
         sFx[s] = F;
         if (c < FTX || i == n) {
-            if (A.FX && (!A.edges_only || i == 0 || i == n)) A.FX[oc + fi] = F;
+            if (A.FX && (!A.edges_only || i == 0 || i == n)) sto(A.FX + oc, (unsigned)fi, F);
             if (EPI == EPI_DELP) {
-                A.mfx[oc + fi] += (double)F;
-                A.cxa[oc + fi] += (C)sCX[s];
+                sto(A.mfx + oc, (unsigned)fi, ldo(A.mfx + oc, (unsigned)fi) + (double)F);
+                sto(A.cxa + oc, (unsigned)fi, (C)(ldo(A.cxa + oc, (unsigned)fi) + (C)sCX[s]));
             }
         }
     };
@@ -1574,10 +1675,10 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         const T F = (T)0.5 * (fy + sFy[s]) * wgt;
         sFy[s] = F;
         if (r < FTY || j == n) {
-            if (A.FY && (!A.edges_only || j == 0 || j == n)) A.FY[oc + fi] = F;
+            if (A.FY && (!A.edges_only || j == 0 || j == n)) sto(A.FY + oc, (unsigned)fi, F);
             if (EPI == EPI_DELP) {
-                A.mfy[oc + fi] += (double)F;
-                A.cya[oc + fi] += (C)sCY[s];
+                sto(A.mfy + oc, (unsigned)fi, ldo(A.mfy + oc, (unsigned)fi) + (double)F);
+                sto(A.cya + oc, (unsigned)fi, (C)(ldo(A.cya + oc, (unsigned)fi) + (C)sCY[s]));
             }
         }
     };
@@ -1602,7 +1703,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             bool west;
             const int pe = edge_pe(i, n, west);
             T fx = ppm_edge<ORD>(sQi + r * QW + c, 1, DXA + j * P + i - 3, 1, sCX[s], pe, west);
-            put_x(i, c, fi, s, fx, A.mx ? (T)A.mx[oc + fi] : sXF[s]);
+            put_x(i, c, fi, s, fx, MX ? (T)ldo(MX, (unsigned)fi) : sXF[s]);
         }
     }
 #pragma unroll
@@ -1626,7 +1727,7 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
             bool west;
             const int pe = edge_pe(j, n, west);
             T fy = ppm_edge<ORD>(sQj + r * FTX + c, FTX, DYA + (j - 3) * P + i, P, sCY[s], pe, west);
-            put_y(j, r, fi, s, fy, A.my ? (T)A.my[oc + fi] : sYF[s]);
+            put_y(j, r, fi, s, fy, MY ? (T)ldo(MY, (unsigned)fi) : sYF[s]);
         }
     }
     if constexpr (EPI == EPI_FLUX) return;
@@ -1647,19 +1748,31 @@ DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
         T qc = sQ[(r + 3) * QW + c + 3];
         T out;
         if constexpr (EPI == EPI_DELP) {
-            out = qc + (fw - fe + fs - fn) / ar;
+            out = qc + rdiv(fw - fe + fs - fn, ar);
         } else if constexpr (EPI == EPI_MASSW) {
-            out = (qc * (T)pa[m] * ar + fw - fe + fs - fn) / ((T)pb[m] * ar);
+            out = rdiv(qc * (T)pa[m] * ar + fw - fe + fs - fn, (T)pb[m] * ar);
         } else if constexpr (EPI == EPI_ADV) {
             T x0 = sXF[(r + 3) * XW + c], x1 = sXF[(r + 3) * XW + c + 1];
             T y0 = sYF[r * YW + c + 3], y1 = sYF[(r + 1) * YW + c + 3];
-            out = (qc * ar + fw - fe + fs - fn) / (ar + x0 - x1 + y0 - y1);
+            out = rdiv(qc * ar + fw - fe + fs - fn, ar + x0 - x1 + y0 - y1);
         } else {
             out = (T)(((double)qc * pa[m] * (double)ar + (double)fw - (double)fe + (double)fs - (double)fn) /
                       (pb[m] * (double)ar));
         }
-        A.qout[oq + ci] = out;
+        sto(A.qout + oq, (unsigned)ci, out);
     }
+}
+
+
+template <class T, class C, class M, int EPI, int ORD, int EDGE>
+DEVI void k_fvtp(Bk bk, Geo G, FvArgs<T, C, M> A)
+{
+    constexpr int FTX = FvTile<T>::X, FTY = FvTile<T>::Y;
+    __shared__ FvLds<T> L;
+    const int n = G.n, i0 = bk.x * FTX, j0 = bk.y * FTY;
+    const bool corner = G.cube && (i0 - 3 < 0 || i0 + FTX + 2 >= n) && (j0 - 3 < 0 || j0 + FTY + 2 >= n);
+    if (corner) fvtp_body<T, C, M, EPI, ORD, EDGE, true>(bk, G, A, L);
+    else fvtp_body<T, C, M, EPI, ORD, EDGE, false>(bk, G, A, L);
 }
 
 template <class T, class C, class M, int ORD, int EDGE>
@@ -2580,7 +2693,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
                        (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         STOP(3);
-        launch2d_s(k_pgradc<B>, (Shape{32, 8}), 0, n, 0, n, P, st, G, Md, dt2, (const B *)W.delpc, (const double *)W.pkc,
+        launch2d_s(k_pgradc<B>, (Shape{32, 8}), 0, n, 0, n, T * ((nz + PGK - 1) / PGK), st, G, Md, dt2, (const B *)W.delpc, (const double *)W.pkc,
                  (const double *)W.gz, uc, vc);
         STOP(4);
         halo_pair(g, g->planCv, uc, vc, nz, st);

@@ -3,8 +3,8 @@
 // FP32 accumulation, Adam in FP32, and the application of the predicted
 // tendencies to a coarse state.
 //
-// Matrix products use v_mfma_f32_16x16x16_bf16: one wavefront computes one
-// 16 x 16 output tile, stepping K by 16.  Operand strides are explicit so the
+// Matrix products use gfx950's v_mfma_f32_16x16x32_bf16: one instruction
+// adds a 16 x 32 by 32 x 16 BF16 product to a 16 x 16 FP32 tile.  Operand strides are explicit so the
 // transposed products of the backward pass (X^T dZ, dZ W^T) read the stored
 // row-major matrices in place.  The network is small (395 -> 256 -> 256 ->
 // 237), so these are plain register-tiled products, not a library GEMM.
@@ -22,7 +22,8 @@ namespace fv3 {
 #define DEVI __device__ __forceinline__
 
 typedef uint16_t bf16_t;
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // round to nearest even, the bit-exact rounding the oracle applies
@@ -46,9 +47,10 @@ enum { GE_NONE = 0, GE_TANH = 1 };
 // staged through LDS 32 at a time.  Operands are loaded with the thread
 // index running along whichever of their two dimensions is contiguous, and
 // stored in LDS k-contiguous (A as [m][k], B as [n][k]) so that each lane
-// reads its four k-consecutive values of an MFMA operand as one 8-byte word.
-// Accumulation runs over K in ascending chunks of 16 as one MFMA chain per
-// output tile.
+// reads its eight k-consecutive values of an MFMA operand (lane group g of
+// 16 lanes holds k = 8g .. 8g + 7 of its row or column) as one 16-byte word.
+// Accumulation runs over K in ascending chunks of 32, one MFMA per chunk
+// and output tile.
 constexpr int GBM = 64, GBN = 64, GBK = 32, GKP = GBK + 8;
 
 __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const bf16_t *A, long sam, long sak,
@@ -103,23 +105,20 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const bf
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GBK; kk += 16) {
-            v4s a[2], b[2];
+        static_assert(GBK == 32, "one 16x16x32 MFMA per K chunk");
+        {
+            v8bf a[2], b[2];
 #pragma unroll
             for (int x = 0; x < 2; x++) {
-                const bf16_t *pa = sA + (wm + 16 * x + r) * GKP + kk + 4 * g;
-                const bf16_t *pb = sB + (wn + 16 * x + r) * GKP + kk + 4 * g;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    a[x][q] = (short)pa[q];
-                    b[x][q] = (short)pb[q];
-                }
+                const v8s va = *(const v8s *)(sA + (wm + 16 * x + r) * GKP + 8 * g);
+                const v8s vb = *(const v8s *)(sB + (wn + 16 * x + r) * GKP + 8 * g);
+                a[x] = __builtin_bit_cast(v8bf, va);
+                b[x] = __builtin_bit_cast(v8bf, vb);
             }
 #pragma unroll
             for (int x = 0; x < 2; x++)
 #pragma unroll
-                for (int y = 0; y < 2; y++) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[x], b[y], acc[x][y], 0, 0, 0);
+                for (int y = 0; y < 2; y++) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
         }
         __syncthreads();
     }

@@ -35,7 +35,7 @@ import time
 import numpy as np
 
 from . import (MLP, Grid, State, acoustic_substeps, apply_correction, check_status, coarsen,
-               column_features)
+               column_features, dynamics)
 
 H = 3
 
@@ -47,15 +47,28 @@ def log(*a):
 class Config:
     def __init__(self, fine_n=192, coarse_n=48, nz=79, fine_bdt=15.0, coarse_bdt=60.0,
                  window=10800.0, windows=4, precision="mixed", hidden=256, bumps=4,
-                 epochs=20, batch=4096, lr=1e-3, seed0=5000):
+                 epochs=20, batch=4096, lr=1e-3, seed0=5000, remap=900.0):
         self.fine_n, self.coarse_n, self.nz = fine_n, coarse_n, nz
         self.fine_bdt, self.coarse_bdt = fine_bdt, coarse_bdt
         self.window, self.windows = window, windows
         self.precision, self.hidden, self.bumps = precision, hidden, bumps
         self.epochs, self.batch, self.lr, self.seed0 = epochs, batch, lr, seed0
+        # seconds between vertical remaps (0: Lagrangian layers for the whole run)
+        self.remap = remap
 
 
-def _advance(s: State, g: Grid, seconds: float, bdt: float, stream=None) -> None:
+def _advance(s: State, g: Grid, seconds: float, bdt: float, remap: float = 0.0, stream=None) -> None:
+    """Advance by `seconds` in acoustic substeps of about bdt; with remap > 0
+    through the remapping loop (fv3_dynamics: a vertical remap to the hybrid
+    reference coordinate every `remap` seconds)."""
+    if remap > 0.0:
+        import fv3_inputs as fi
+
+        k_split = max(1, int(round(seconds / remap)))
+        n_split = max(1, int(round(seconds / k_split / bdt)))
+        ak, bk = fi.hybrid_coefficients(g.nz, g.ptop)
+        dynamics(s, g, [], ak, bk, seconds, k_split, n_split, stream=stream)
+        return
     n_split = max(1, int(round(seconds / bdt)))
     acoustic_substeps(s, g, seconds, n_split, stream=stream)
 
@@ -99,8 +112,8 @@ def generate(cfg: Config, seeds, fields=None):
         sf.load(init)
         for w in range(cfg.windows):
             coarsen(sf, gf, sc, gc)
-            _advance(sf, gf, cfg.window, cfg.fine_bdt)
-            _advance(sc, gc, cfg.window, cfg.coarse_bdt)
+            _advance(sf, gf, cfg.window, cfg.fine_bdt, cfg.remap)
+            _advance(sc, gc, cfg.window, cfg.coarse_bdt, cfg.remap)
             coarsen(sf, gf, st, gc)
             ok = check_status(gf) == 0 and check_status(gc) == 0
             if not ok:
@@ -214,9 +227,9 @@ def gain_test(cfg: Config, model: Model, seeds):
         coarsen(sf, gf, sp, gc)
         coarsen(sf, gf, sq, gc)
         for w in range(cfg.windows):
-            _advance(sf, gf, cfg.window, cfg.fine_bdt)
-            _advance(sp, gc, cfg.window, cfg.coarse_bdt)
-            _advance(sq, gc, cfg.window, cfg.coarse_bdt)
+            _advance(sf, gf, cfg.window, cfg.fine_bdt, cfg.remap)
+            _advance(sp, gc, cfg.window, cfg.coarse_bdt, cfg.remap)
+            _advance(sq, gc, cfg.window, cfg.coarse_bdt, cfg.remap)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             flag.zero_()
@@ -259,10 +272,14 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--bumps", type=int, default=4)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--remap", type=float, default=900.0,
+                    help="seconds between vertical remaps (0: no remapping)")
+    ap.add_argument("--fine-bdt", type=float, default=15.0)
+    ap.add_argument("--coarse-bdt", type=float, default=60.0)
     a = ap.parse_args(argv)
     cfg = Config(fine_n=a.fine_n, coarse_n=a.coarse_n, nz=a.nz, window=3600.0 * a.window_hours,
                  windows=a.windows, precision=a.precision, epochs=a.epochs, batch=a.batch,
-                 lr=a.lr, bumps=a.bumps)
+                 lr=a.lr, bumps=a.bumps, remap=a.remap, fine_bdt=a.fine_bdt, coarse_bdt=a.coarse_bdt)
     train_seeds = list(range(cfg.seed0, cfg.seed0 + a.train_seeds))
     test_seeds = list(range(cfg.seed0 + 64, cfg.seed0 + 64 + a.test_seeds))
     t0 = time.perf_counter()
@@ -273,7 +290,8 @@ def main(argv=None):
     res = gain_test(cfg, model, test_seeds)
     out = {"config": {"fine": f"C{cfg.fine_n}x{cfg.nz}", "coarse": f"C{cfg.coarse_n}x{cfg.nz}",
                       "window_h": a.window_hours, "windows": cfg.windows, "train_seeds": train_seeds,
-                      "test_seeds": test_seeds, "precision": cfg.precision, "bumps": cfg.bumps},
+                      "test_seeds": test_seeds, "precision": cfg.precision, "bumps": cfg.bumps,
+                      "remap_seconds": cfg.remap, "fine_bdt": cfg.fine_bdt, "coarse_bdt": cfg.coarse_bdt},
            "data_seconds": gen_s, "dropped_windows": bad, "training": rep, "gain_test": res}
     print(json.dumps(out), flush=True)
 
