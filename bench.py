@@ -202,10 +202,7 @@ def oracle_reference(init, args, opts):
 def run_precision(fv3, torch, init, args, precision):
     n, nz, ns, bdt = args.n, args.nz, args.n_split, args.bdt
     dt = bdt * ns
-    g = fv3.Grid(1, n, nz, precision=precision, beta=args.beta, d2_bg=args.d2_bg, dddmp=args.dddmp,
-                 hord=args.hord, hord_tr=args.hord_tr, pp_order=args.pp_order, nord=args.nord,
-                 d4_bg=args.d4_bg, vtdm=args.vtdm, edge_fix=args.edge_fix,
-                 edge_ppm=args.edge_ppm)
+    g = fv3.Grid(1, n, nz, precision=precision, **grid_opts(args))
     s = fv3.State.allocate(g)
     s.load(init)
     if args.moist:
@@ -269,7 +266,8 @@ def grid_opts(args):
     library binding and the oracle)."""
     return {"beta": args.beta, "d2_bg": args.d2_bg, "dddmp": args.dddmp, "hord": args.hord,
             "hord_tr": args.hord_tr, "pp_order": args.pp_order, "nord": args.nord, "d4_bg": args.d4_bg,
-            "vtdm": args.vtdm, "edge_fix": args.edge_fix, "edge_ppm": args.edge_ppm}
+            "vtdm": args.vtdm, "edge_fix": args.edge_fix, "edge_ppm": args.edge_ppm,
+            "edge_interp": args.edge_interp}
 
 
 def gpu_final_fields(fv3, torch, init, args, precision):
@@ -466,6 +464,8 @@ def main():
     ap.add_argument("--vtdm", type=float, default=0.0, help="del-2 vorticity damping (0 .. 0.25)")
     ap.add_argument("--edge-fix", action="store_true", help="edge-flux fix-up at the tile edges")
     ap.add_argument("--edge-ppm", action="store_true", help="one-sided PPM edge values at the tile edges")
+    ap.add_argument("--edge-interp", action="store_true",
+                    help="one-sided c_sw and nh_p_grad interpolations at the tile edges")
     ap.add_argument("--moist", action="store_true",
                     help="moist column solves with humidity 0.02 x the first tracer")
     ap.add_argument("--d2-bg", type=float, default=0.0, help="del-2 divergence damping (0 .. 0.25)")
@@ -539,7 +539,7 @@ def main():
                    "hord_tr": args.hord_tr, "pp_order": args.pp_order, "moist": args.moist,
                    "nord": args.nord, "d4_bg": args.d4_bg, "vtdm": args.vtdm,
                    "edge_fix": args.edge_fix,
-                   "edge_ppm": args.edge_ppm,
+                   "edge_ppm": args.edge_ppm, "edge_interp": args.edge_interp,
                    "ms_per_substep": main_res["ms_per_substep"],
                    "device_status": main_res["device_status"]},
         "roofline": main_res["roofline"],

@@ -107,7 +107,17 @@ typedef enum { FV3_FP64 = 0, FV3_MIXED = 1 } fv3_precision;
  * and the second cell inside the tile to monotone parabolas (Colella &
  * Woodward 1984) instead of clipping to twice the slope.  Sweeps through the
  * corner halo keep the centred stencil.  No effect on the doubly periodic
- * grid; other values: FV3_EINVAL. */
+ * grid; other values: FV3_EINVAL.  edge_interp = 1 on the cube (the edge
+ * corrections of Sec. V-B): c_sw's D-grid to cell-centre and cell-centre to
+ * C-grid interpolations and nh_p_grad's cell-to-corner interpolation, where
+ * their four-point stencils would reach across a tile edge, use the
+ * quadratic through the three nearest points on their own side (weights
+ * 3/8, 3/4, -1/8 for the point values of c_sw, 1/3, 5/6, -1/6 for the cell
+ * means of nh_p_grad), and a face or corner on the edge takes the mean of
+ * the two linear extrapolations from the two nearest points of each side;
+ * sweeps outside the tile keep the centred stencils, the cube vertices the
+ * three-cell mean.  No effect on the doubly periodic grid; other values:
+ * FV3_EINVAL. */
 typedef struct {
     int kind;            /* fv3_grid_kind                                  */
     int n, nz;           /* cells per tile edge, layers                    */
@@ -128,6 +138,8 @@ typedef struct {
     double vtdm;         /* del-2 vorticity damping, 0 (off) .. 0.25       */
     int edge_fix;        /* cube: edge-flux fix-up, 0 (off) or 1          */
     int edge_ppm;        /* cube: one-sided PPM at tile edges, 0 or 1     */
+    int edge_interp;     /* cube: one-sided c_sw / nh_p_grad interpolation
+                            at tile edges, 0 or 1                         */
     int device;          /* HIP device ordinal                             */
 } fv3_grid_params;
 

@@ -52,7 +52,7 @@ class GridParams(C.Structure):
                 ("ptop", C.c_double), ("precision", C.c_int), ("hord", C.c_int),
                 ("d2_bg", C.c_double), ("beta", C.c_double), ("dddmp", C.c_double), ("hord_tr", C.c_int),
                 ("pp_order", C.c_int), ("nord", C.c_int), ("d4_bg", C.c_double),
-                ("vtdm", C.c_double), ("edge_fix", C.c_int), ("edge_ppm", C.c_int),
+                ("vtdm", C.c_double), ("edge_fix", C.c_int), ("edge_ppm", C.c_int), ("edge_interp", C.c_int),
                 ("device", C.c_int)]
 
 
@@ -153,12 +153,12 @@ def _check(st):
 
 def _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg=0.0, beta=1.0, dddmp=0.0,
             hord=8, hord_tr=0, pp_order=2, nord=0, d4_bg=0.0, vtdm=0.0, edge_fix=False,
-            edge_ppm=False):
+            edge_ppm=False, edge_interp=False):
     return GridParams(kind=kind, n=n, nz=nz, dx=dx, f0=f0, radius=radius, omega=omega, ptop=ptop,
                       precision=0 if precision == "fp64" else 1, hord=hord, d2_bg=d2_bg, beta=beta,
                       dddmp=dddmp, hord_tr=hord_tr, pp_order=pp_order, nord=nord, d4_bg=d4_bg,
                       vtdm=vtdm, edge_fix=int(bool(edge_fix)), edge_ppm=int(bool(edge_ppm)),
-                      device=device)
+                      edge_interp=int(bool(edge_interp)), device=device)
 
 
 def host_metric(kind, n, nz, name, dx=1000.0, f0=0.0, radius=RADIUS, omega=OMEGA, ptop=100.0,
@@ -187,11 +187,11 @@ class Grid:
                  precision: str = "fp64", device: int = 0, d2_bg: float = 0.0, beta: float = 1.0,
                  dddmp: float = 0.0, hord: int = 8, hord_tr: int = 0, pp_order: int = 2, nord: int = 0,
                  d4_bg: float = 0.0, vtdm: float = 0.0, edge_fix: bool = False,
-                 edge_ppm: bool = False):
+                 edge_ppm: bool = False, edge_interp: bool = False):
         torch = _torch()
         torch.cuda.set_device(device)
         p = _params(kind, n, nz, dx, f0, radius, omega, ptop, precision, device, d2_bg, beta, dddmp, hord,
-                    hord_tr, pp_order, nord, d4_bg, vtdm, edge_fix, edge_ppm)
+                    hord_tr, pp_order, nord, d4_bg, vtdm, edge_fix, edge_ppm, edge_interp)
         h = C.c_void_p()
         _check(lib().fv3_init_grid(C.byref(p), C.byref(h)))
         self._h = h

@@ -93,6 +93,7 @@ fv3_status fv3_init_grid(const fv3_grid_params *p, fv3_grid **out)
         return fail(FV3_EINVAL, "d4_bg must be in [0, 0.25]");
     if (p->edge_fix != 0 && p->edge_fix != 1) return fail(FV3_EINVAL, "edge_fix must be 0 or 1");
     if (p->edge_ppm != 0 && p->edge_ppm != 1) return fail(FV3_EINVAL, "edge_ppm must be 0 or 1");
+    if (p->edge_interp != 0 && p->edge_interp != 1) return fail(FV3_EINVAL, "edge_interp must be 0 or 1");
     if (!std::isfinite(p->vtdm) || p->vtdm < 0.0 || p->vtdm > 0.25)
         return fail(FV3_EINVAL, "vtdm must be in [0, 0.25]");
     if (p->pp_order != 0 && p->pp_order != 2 && p->pp_order != 4)

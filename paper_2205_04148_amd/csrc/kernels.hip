@@ -635,7 +635,37 @@ struct CswRows<double> {
 
 // A-grid winds at a cell from the D-grid winds; CORNER = false for blocks
 // whose reads cannot reach a cube corner block (no view checks)
-template <class B, bool CORNER>
+// One-sided stencils at cube tile edges (option edge_interp).  Along a
+// sweep with tile edges at the interfaces 0 and n, the four points a, b, c,
+// d are the stencil of the centred interpolation; where it would reach
+// across an edge, the quadratic through the three nearest points on the own
+// side (3/8, 3/4, -1/8 from the point next to the edge), and on the edge the
+// mean of the two linear extrapolations of the two nearest points per side.
+// cell_pt: centre of cell m from the interfaces m-1 .. m+2 (D -> A);
+// face_pt: interface m from the centres m-2 .. m+1 (A -> C).
+template <class B>
+DEVI B cell_pt(B a, B b, B c, B d, int m, int n, bool edge)
+{
+    if (edge) {
+        if (m == 0 || m == n) return (B)0.375 * b + (B)0.75 * c - (B)0.125 * d;
+        if (m == -1 || m == n - 1) return (B)0.375 * c + (B)0.75 * b - (B)0.125 * a;
+    }
+    return (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+}
+template <class B>
+DEVI B face_pt(B a, B b, B c, B d, int m, int n, bool edge)
+{
+    if (edge) {
+        if (m == 0 || m == n) return (B)0.75 * (b + c) - (B)0.25 * (a + d);
+        if (m == 1 || m == n + 1) return (B)0.375 * b + (B)0.75 * c - (B)0.125 * d;
+        if (m == -1 || m == n - 1) return (B)0.375 * c + (B)0.75 * b - (B)0.125 * a;
+    }
+    return (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+}
+
+// the sweep of ua runs along j in column i, that of va along i in row j;
+// the edge rule applies on sweeps whose cross index lies inside the tile
+template <class B, bool CORNER, bool EI = false>
 DEVI B ua_at(const Geo &G, const B *U, const B *V, int i, int j)
 {
     B a, b, c, d;
@@ -645,9 +675,9 @@ DEVI B ua_at(const Geo &G, const B *U, const B *V, int i, int j)
     } else {
         a = AT(U, i, j - 1), b = AT(U, i, j), c = AT(U, i, j + 1), d = AT(U, i, j + 2);
     }
-    return (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+    return cell_pt(a, b, c, d, j, G.n, EI && i >= 0 && i < G.n);
 }
-template <class B, bool CORNER>
+template <class B, bool CORNER, bool EI = false>
 DEVI B va_at(const Geo &G, const B *U, const B *V, int i, int j)
 {
     B a, b, c, d;
@@ -657,7 +687,7 @@ DEVI B va_at(const Geo &G, const B *U, const B *V, int i, int j)
     } else {
         a = AT(V, i - 1, j), b = AT(V, i, j), c = AT(V, i + 1, j), d = AT(V, i + 2, j);
     }
-    return (-a + (B)9 * b + (B)9 * c - d) / (B)16;
+    return cell_pt(a, b, c, d, i, G.n, EI && j >= 0 && j < G.n);
 }
 
 // LDS elements of one c_sw block
@@ -667,7 +697,7 @@ constexpr int csw_lds()
     return 2 * (CTY + 5) * (CTX + 5) + 3 * (CTY + 3) * (CTX + 3) + 8 * (CTY + 2) * (CTX + 2) + 2 * (CTY + 1) * (CTX + 1);
 }
 
-template <class B, bool CORNER>
+template <class B, bool CORNER, bool EI>
 DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Mets<B> &M, B dt2, const B *u,
                    const B *v, const B *delp, const B *pt, const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc,
                    B *ax, B *ay)
@@ -702,7 +732,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
             int qi, qj;
             bool cw;
             corner_src(G, SC, i, j, mode, qi, qj, cw);
-            B val = inA(qi, qj) ? sVA[aA(qi, qj)] : va_at<B, true>(G, U, V, qi, qj);
+            B val = inA(qi, qj) ? sVA[aA(qi, qj)] : va_at<B, true, EI>(G, U, V, qi, qj);
             return cw ? -val : val;
         }
         return sUA[aA(i, j)];
@@ -712,7 +742,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
             int qi, qj;
             bool cw;
             corner_src(G, SC, i, j, mode, qi, qj, cw);
-            B val = inA(qi, qj) ? sUA[aA(qi, qj)] : ua_at<B, true>(G, U, V, qi, qj);
+            B val = inA(qi, qj) ? sUA[aA(qi, qj)] : ua_at<B, true, EI>(G, U, V, qi, qj);
             return !cw ? -val : val;
         }
         return sVA[aA(i, j)];
@@ -734,8 +764,8 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         int i = i0 - 3 + c, j = j0 - 3 + r;
         B a = 0, b = 0;
         if (i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2 && !(CORNER && in_corner(G, SC, i, j))) {
-            if (j >= -2 && j <= n + 1) a = ua_at<B, CORNER>(G, U, V, i, j);
-            if (i >= -2 && i <= n + 1) b = va_at<B, CORNER>(G, U, V, i, j);
+            if (j >= -2 && j <= n + 1) a = ua_at<B, CORNER, EI>(G, U, V, i, j);
+            if (i >= -2 && i <= n + 1) b = va_at<B, CORNER, EI>(G, U, V, i, j);
         }
         sUA[e] = a;
         sVA[e] = b;
@@ -764,7 +794,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         B uc0 = 0, fm = 0, fp = 0, fw = 0;
         if (xf) {
             B a = UAx(i - 2, j, 0), b = UAx(i - 1, j, 0), c1 = UAx(i, j, 0), d = UAx(i + 1, j, 0);
-            uc0 = (-a + (B)9 * b + (B)9 * c1 - d) / (B)16;
+            uc0 = face_pt(a, b, c1, d, i, n, EI && j >= 0 && j < n);
             B fl = dt2 * (uc0 - AT(V, i, j) * AT(MP(M, M_COS_U), i, j)) * AT(MP(M, M_RSIN_U), i, j) *
                    AT(MP(M, M_DY), i, j);
             int up = fl > 0 ? i - 1 : i;
@@ -780,7 +810,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         B vc0 = 0, gm = 0, gp = 0, gw = 0;
         if (yf) {
             B a = VAy(i, j - 2, 1), b = VAy(i, j - 1, 1), c1 = VAy(i, j, 1), d = VAy(i, j + 1, 1);
-            vc0 = (-a + (B)9 * b + (B)9 * c1 - d) / (B)16;
+            vc0 = face_pt(a, b, c1, d, j, n, EI && i >= 0 && i < n);
             B fl = dt2 * (vc0 - AT(U, i, j) * AT(MP(M, M_COS_V), i, j)) * AT(MP(M, M_RSIN_V), i, j) *
                    AT(MP(M, M_DX), i, j);
             int up = fl > 0 ? j - 1 : j;
@@ -858,7 +888,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
     }
 }
 
-template <class B>
+template <class B, bool EI = false>
 DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B *delp, const B *pt,
                 const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc, B *ax, B *ay)
 {
@@ -871,9 +901,11 @@ DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B 
     __shared__ B L[csw_lds<CTY>()];
     const int t = (int)bk.z / G.nz, k = (int)bk.z % G.nz;
     if (G.cube && nx && ny)
-        csw_body<B, true>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+        csw_body<B, true, EI>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+    else if (EI && (nx || ny))
+        csw_body<B, false, EI>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
     else
-        csw_body<B, false>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+        csw_body<B, false, false>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
 }
 
 // ====================================================================
@@ -2204,7 +2236,27 @@ DEVI void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phis, dou
 constexpr int NPX = FV3_NHP_TX, NPY = FV3_NHP_TY;   // nh_p_grad corner tile
 constexpr int NCW = NPX + 5, NCH = NPY + 5;   // cells i0-2..i0+NPX+2, j0-2..j0+NPY+2
 
-template <class B>
+// cell means x0..x3 of the cells m-2 .. m+1 to interface m: (-1,7,7,-1)/12,
+// or with `edge` next to a tile edge (interfaces 0, n) the interface value
+// of the quadratic with the three nearest cell means on the own side
+// (1/3, 5/6, -1/6), on the edge the mean of the two sides' linear
+// extrapolations (option edge_interp)
+DEVI double face_mean(double x0, double x1, double x2, double x3, int m, int n, bool edge, const double *w4)
+{
+    if (edge) {
+        if (m == 0 || m == n) return 0.75 * (x1 + x2) - 0.25 * (x0 + x3);
+        if (m == 1 || m == n + 1) return (2.0 * x1 + 5.0 * x2 - x3) / 6.0;
+        if (m == -1 || m == n - 1) return (2.0 * x2 + 5.0 * x1 - x0) / 6.0;
+    }
+    double r = 0.0;
+    r += w4[0] * x0;
+    r += w4[1] * x1;
+    r += w4[2] * x2;
+    r += w4[3] * x3;
+    return r;
+}
+
+template <class B, bool EI = false>
 DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
                                                  const double *phi, const B *delp, B *u, B *v)
 {
@@ -2240,6 +2292,10 @@ DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
     }
     __syncthreads();
     const double w4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
+    // with the edge rule, only blocks with corner columns (rows) within one
+    // cell of a tile edge (0, 1, n - 1, n) take the one-sided branches of
+    // the x (y) pass
+    const bool ebx = EI && (i0 <= 1 || i0 + NPX >= n - 1), eby = EI && (j0 <= 1 || j0 + NPY >= n - 1);
     // The tensor interpolation in two passes: along x for every staged row at
     // every corner column (into registers), then along y at each corner.
     constexpr int NRX = (NPY + 4) * (NPX + 1), NRP = (NRX + 255) / 256;
@@ -2247,12 +2303,18 @@ DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
 #pragma unroll
     for (int m = 0; m < NRP; m++) {
         int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
+        // the edge rule on rows inside the tile (row j = j0 - 2 + rr)
+        const int jr = j0 - 2 + rr;
+        const bool ex = EI && jr >= 0 && jr < n;
 #pragma unroll
         for (int f = 0; f < 5; f++) {
             double rw = 0.0;
             if (e < NRX) {
                 const double *row = &sc[f][rr * NCW + c];
-                for (int a = 0; a < 4; a++) rw += w4[a] * row[a];
+                if (EI && ebx)
+                    rw = face_mean(row[0], row[1], row[2], row[3], i0 + c, n, ex, w4);
+                else
+                    for (int a = 0; a < 4; a++) rw += w4[a] * row[a];
             }
             xr[m][f] = rw;
         }
@@ -2287,7 +2349,12 @@ DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
         if (i > n || j > n || is_vertex(G, i, j)) continue;
         for (int f = 0; f < 5; f++) {
             double acc = 0.0;
-            for (int b = 0; b < 4; b++) acc += w4[b] * sc[f][(r + b) * NCW + c];
+            if (EI && eby) {
+                const double *col = &sc[f][r * NCW + c];
+                acc = face_mean(col[0], col[NCW], col[2 * NCW], col[3 * NCW], j, n, true, w4);
+            } else {
+                for (int b = 0; b < 4; b++) acc += w4[b] * sc[f][(r + b) * NCW + c];
+            }
             sb[f][e] = acc;
         }
     }
@@ -2666,10 +2733,18 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         }
         STOP(1);
         // c_sw
-        launch_fn<k_csw<B>>("k_csw", dim3((unsigned)((n + 3 + CTX - 1) / CTX),
-                                          (unsigned)((n + 3 + CswRows<B>::Y - 1) / CswRows<B>::Y), P),
-                            dim3(CNT), st, G, M, (B)dt2, (const B *)u, (const B *)v, (const B *)delp, (const B *)pt,
-                            (const B *)w, uc, vc, W.delpc, W.ptc, W.wc, W.ax, W.ay);
+        {
+            const dim3 cgrd((unsigned)((n + 3 + CTX - 1) / CTX), (unsigned)((n + 3 + CswRows<B>::Y - 1) / CswRows<B>::Y),
+                            P);
+            if (g->p.edge_interp && g->p.kind == FV3_GRID_CUBED_SPHERE)
+                launch_fn<k_csw<B, true>>("k_csw", cgrd, dim3(CNT), st, G, M, (B)dt2, (const B *)u, (const B *)v,
+                                          (const B *)delp, (const B *)pt, (const B *)w, uc, vc, W.delpc, W.ptc,
+                                          W.wc, W.ax, W.ay);
+            else
+                launch_fn<k_csw<B>>("k_csw", cgrd, dim3(CNT), st, G, M, (B)dt2, (const B *)u, (const B *)v,
+                                    (const B *)delp, (const B *)pt, (const B *)w, uc, vc, W.delpc, W.ptc, W.wc,
+                                    W.ax, W.ay);
+        }
         STOP(2);
         // dz_c + riem_solver_c on the half-step cells
         launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
@@ -2818,8 +2893,15 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         halo_scalar(g, delp, nz, st);
         STOP(9);
         // nh_p_grad
-        launch_fn<k_nhpgrad<B>>("k_nhpgrad", dim3((n + NPX) / NPX, (n + NPY) / NPY, P), dim3(256), st, G, Md,
-                     bdt, (const double *)s->pfull, (const double *)s->phi, (const B *)delp, u, v);
+        {
+            const dim3 ngrd((n + NPX) / NPX, (n + NPY) / NPY, P);
+            if (g->p.edge_interp && g->p.kind == FV3_GRID_CUBED_SPHERE)
+                launch_fn<k_nhpgrad<B, true>>("k_nhpgrad", ngrd, dim3(256), st, G, Md, bdt, (const double *)s->pfull,
+                                              (const double *)s->phi, (const B *)delp, u, v);
+            else
+                launch_fn<k_nhpgrad<B>>("k_nhpgrad", ngrd, dim3(256), st, G, Md, bdt, (const double *)s->pfull,
+                                        (const double *)s->phi, (const B *)delp, u, v);
+        }
 #undef STOP
     }
     rec_mark();

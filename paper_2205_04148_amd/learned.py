@@ -47,7 +47,7 @@ def log(*a):
 class Config:
     def __init__(self, fine_n=192, coarse_n=48, nz=79, fine_bdt=15.0, coarse_bdt=60.0,
                  window=10800.0, windows=4, precision="mixed", hidden=256, bumps=4,
-                 epochs=20, batch=4096, lr=1e-3, seed0=5000, remap=900.0):
+                 epochs=20, batch=4096, lr=1e-3, seed0=5000, remap=900.0, test_windows=0):
         self.fine_n, self.coarse_n, self.nz = fine_n, coarse_n, nz
         self.fine_bdt, self.coarse_bdt = fine_bdt, coarse_bdt
         self.window, self.windows = window, windows
@@ -55,6 +55,8 @@ class Config:
         self.epochs, self.batch, self.lr, self.seed0 = epochs, batch, lr, seed0
         # seconds between vertical remaps (0: Lagrangian layers for the whole run)
         self.remap = remap
+        # windows of the gain test (0: as many as for training)
+        self.test_windows = test_windows if test_windows > 0 else windows
 
 
 def _advance(s: State, g: Grid, seconds: float, bdt: float, remap: float = 0.0, stream=None) -> None:
@@ -94,11 +96,52 @@ class Features:
         return self.X.cpu().numpy().astype(np.float64)
 
 
-def generate(cfg: Config, seeds, fields=None):
-    """Training pairs (inputs, targets) as host float64 arrays, one block of
-    (6 coarse_n^2) rows per window and seed."""
+def _initial(cfg: Config, seed: int) -> dict:
     import fv3_inputs as fi
 
+    return fi.cube_state(n=cfg.fine_n, nz=cfg.nz, seed=seed, nq=0, bumps=cfg.bumps)
+
+
+def _initial_states(cfg: Config, seeds, pool=None):
+    """The seeds' initial fine states in order; with a process pool they are
+    built on the host ahead of the device runs (a few in flight)."""
+    if pool is None:
+        for seed in seeds:
+            yield _initial(cfg, seed)
+        return
+    import collections
+
+    ahead = collections.deque()
+    it = iter(seeds)
+    for seed in it:
+        ahead.append(pool.submit(_initial, cfg, seed))
+        if len(ahead) >= pool._max_workers:
+            break
+    for seed in it:
+        done = ahead.popleft().result()
+        ahead.append(pool.submit(_initial, cfg, seed))
+        yield done
+    while ahead:
+        yield ahead.popleft().result()
+
+
+def make_pool(workers: int):
+    """Host process pool for the initial states.  Create it before the
+    process touches the GPU: its workers come from a fork server started
+    now, so none of them is forked from a process holding a device context."""
+    if workers <= 0:
+        return None
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    pool = cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("forkserver"))
+    pool.submit(int, 0).result()
+    return pool
+
+
+def generate(cfg: Config, seeds, fields=None, pool=None):
+    """Training pairs (inputs, targets) as host float64 arrays, one block of
+    (6 coarse_n^2) rows per window and seed."""
     gf = Grid(1, cfg.fine_n, cfg.nz, precision=cfg.precision)
     gc = Grid(1, cfg.coarse_n, cfg.nz, precision=cfg.precision)
     sf, sc, st = State.allocate(gf), State.allocate(gc), State.allocate(gc)
@@ -106,10 +149,10 @@ def generate(cfg: Config, seeds, fields=None):
     nz = cfg.nz
     Xs, Ts = [], []
     bad = 0
-    for seed in seeds:
-        t0 = time.perf_counter()
-        init = fi.cube_state(n=cfg.fine_n, nz=nz, seed=seed, nq=0, bumps=cfg.bumps)
+    t0 = time.perf_counter()
+    for seed, init in zip(seeds, _initial_states(cfg, seeds, pool)):
         sf.load(init)
+        del init
         for w in range(cfg.windows):
             coarsen(sf, gf, sc, gc)
             _advance(sf, gf, cfg.window, cfg.fine_bdt, cfg.remap)
@@ -124,7 +167,7 @@ def generate(cfg: Config, seeds, fields=None):
             y = feat.raw(st, gc)
             Xs.append(x.astype(np.float32))
             Ts.append(((y[:, :3 * nz] - x[:, :3 * nz]) / cfg.window).astype(np.float32))
-        log(f"seed {seed}: {time.perf_counter() - t0:.1f} s")
+        log(f"seed {seed}: done at {time.perf_counter() - t0:.1f} s")
     return np.concatenate(Xs), np.concatenate(Ts), bad
 
 
@@ -202,7 +245,7 @@ def _rmse(a: np.ndarray, b: np.ndarray, nz: int):
     return [float(np.sqrt(np.mean(d[:, f * nz:(f + 1) * nz] ** 2))) for f in range(3)]
 
 
-def gain_test(cfg: Config, model: Model, seeds):
+def gain_test(cfg: Config, model: Model, seeds, pool=None):
     """RMSE of (ua, va, pt) against the coarsened truth after each window,
     plain vs corrected coarse runs from the same start."""
     import torch
@@ -218,15 +261,15 @@ def gain_test(cfg: Config, model: Model, seeds):
     Xn = _zeros((rows, 5 * nz))
     Y = _zeros((rows, 3 * nz))
     flag = torch.zeros(1, dtype=torch.int32, device="cuda")
-    per = {"plain": np.zeros((cfg.windows, 3)), "corrected": np.zeros((cfg.windows, 3))}
+    per = {"plain": np.zeros((cfg.test_windows, 3)), "corrected": np.zeros((cfg.test_windows, 3))}
     fallbacks = 0
     infer_s = 0.0
-    for seed in seeds:
-        init = fi.cube_state(n=cfg.fine_n, nz=nz, seed=seed, nq=0, bumps=cfg.bumps)
+    for seed, init in zip(seeds, _initial_states(cfg, seeds, pool)):
         sf.load(init)
+        del init
         coarsen(sf, gf, sp, gc)
         coarsen(sf, gf, sq, gc)
-        for w in range(cfg.windows):
+        for w in range(cfg.test_windows):
             _advance(sf, gf, cfg.window, cfg.fine_bdt, cfg.remap)
             _advance(sp, gc, cfg.window, cfg.coarse_bdt, cfg.remap)
             _advance(sq, gc, cfg.window, cfg.coarse_bdt, cfg.remap)
@@ -251,8 +294,8 @@ def gain_test(cfg: Config, model: Model, seeds):
     for k, a in per.items():
         out[k] = np.sqrt(a / len(seeds)).tolist()
     gain = (1.0 - np.array(out["corrected"]) / np.array(out["plain"])).tolist()
-    n_inf = len(seeds) * cfg.windows
-    return {"hours": [(w + 1) * cfg.window / 3600.0 for w in range(cfg.windows)],
+    n_inf = len(seeds) * cfg.test_windows
+    return {"hours": [(w + 1) * cfg.window / 3600.0 for w in range(cfg.test_windows)],
             "rmse_plain_ua_va_pt": out["plain"], "rmse_corrected_ua_va_pt": out["corrected"],
             "gain_ua_va_pt": gain, "fallback_windows": fallbacks, "windows": n_inf,
             "inference_columns_per_s": rows * n_inf / infer_s if infer_s > 0 else None}
@@ -276,20 +319,24 @@ def main(argv=None):
                     help="seconds between vertical remaps (0: no remapping)")
     ap.add_argument("--fine-bdt", type=float, default=15.0)
     ap.add_argument("--coarse-bdt", type=float, default=60.0)
+    ap.add_argument("--workers", type=int, default=0, help="host processes building initial states ahead")
+    ap.add_argument("--test-windows", type=int, default=0, help="windows of the gain test (0: --windows)")
     a = ap.parse_args(argv)
+    pool = make_pool(a.workers)   # before any device work
     cfg = Config(fine_n=a.fine_n, coarse_n=a.coarse_n, nz=a.nz, window=3600.0 * a.window_hours,
                  windows=a.windows, precision=a.precision, epochs=a.epochs, batch=a.batch,
-                 lr=a.lr, bumps=a.bumps, remap=a.remap, fine_bdt=a.fine_bdt, coarse_bdt=a.coarse_bdt)
+                 lr=a.lr, bumps=a.bumps, remap=a.remap, fine_bdt=a.fine_bdt, coarse_bdt=a.coarse_bdt,
+                 test_windows=a.test_windows)
     train_seeds = list(range(cfg.seed0, cfg.seed0 + a.train_seeds))
     test_seeds = list(range(cfg.seed0 + 64, cfg.seed0 + 64 + a.test_seeds))
     t0 = time.perf_counter()
-    X, T, bad = generate(cfg, train_seeds)
+    X, T, bad = generate(cfg, train_seeds, pool=pool)
     gen_s = time.perf_counter() - t0
     log(f"training data {X.shape} -> {T.shape} in {gen_s:.1f} s ({bad} windows dropped)")
     model, rep = train(cfg, X, T)
-    res = gain_test(cfg, model, test_seeds)
+    res = gain_test(cfg, model, test_seeds, pool=pool)
     out = {"config": {"fine": f"C{cfg.fine_n}x{cfg.nz}", "coarse": f"C{cfg.coarse_n}x{cfg.nz}",
-                      "window_h": a.window_hours, "windows": cfg.windows, "train_seeds": train_seeds,
+                      "window_h": a.window_hours, "windows": cfg.windows, "test_windows": cfg.test_windows, "train_seeds": train_seeds,
                       "test_seeds": test_seeds, "precision": cfg.precision, "bumps": cfg.bumps,
                       "remap_seconds": cfg.remap, "fine_bdt": cfg.fine_bdt, "coarse_bdt": cfg.coarse_bdt},
            "data_seconds": gen_s, "dropped_windows": bad, "training": rep, "gain_test": res}

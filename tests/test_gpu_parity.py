@@ -869,3 +869,74 @@ def test_nonfinite_flag_latched(fv3, orc):
     assert fv3.check_status(g) == 0
     fv3.tracer_transport([q], s, g, nsplt=0)
     assert fv3.check_status(g) == 0
+
+
+# ------------------------------------------------- one-sided interpolations
+@pytest.mark.parametrize("n,nz,stop,dt,ns,precision", [
+    (12, 5, 2, 300.0, 1, "fp64"),      # c_sw: the half-step C-grid winds
+    (12, 5, 10, 300.0, 1, "fp64"),     # a whole substep: nh_p_grad's corner values
+    (24, 10, 0, 2000.0, 10, "fp64"),   # 10 substeps
+    (64, 8, 0, 600.0, 10, "fp64"),     # several blocks per tile row
+    (24, 10, 0, 2000.0, 10, "mixed"),
+])
+def test_edge_interp_parity(fv3, orc, n, nz, stop, dt, ns, precision):
+    """One-sided c_sw and nh_p_grad interpolations at the cube's tile edges
+    (edge_interp) against the oracle built with them: after c_sw (1e-13),
+    after one whole substep (1e-13; w 1e-10, the column-solve bar), after 10
+    substeps (1e-11; mixed: the mixed bars).  The oracle without the option
+    differs by far more than the bars, so the edge instantiations ran."""
+    init = fi.cube_state(n=n, nz=nz)
+    g = fv3.Grid(1, n, nz, dx=1.0e5, precision=precision, edge_interp=True)
+    s = fv3.State.allocate(g)
+    s.load(init)
+    og = orc.Grid(1, n, nz, delta=1.0e5, edge_interp=True)
+    os_ = orc.new_state(og, init)
+    label = f"edgeinterp C{n}x{nz} stop{stop} ns{ns} {precision}"
+    print(label, flush=True)
+    fv3.acoustic_substeps(s, g, dt, ns, stop_stage=stop)
+    assert orc.acoustic_substeps(og, os_, dt, ns, stop_stage=stop) == 0
+    if precision == "mixed":
+        fields = ("u", "v", "w", "delp", "pt", "delz")
+        tol = {"u": 1e-4, "v": 1e-4, "w": 1e-2, "delp": 1e-4, "pt": 1e-4, "delz": 1e-4}
+    elif stop == 2:
+        fields, tol = ("uc", "vc"), 1e-13
+    elif stop == 10:
+        fields = ("u", "v", "w", "delp", "pt", "delz", "pfull", "phi")
+        tol = {k: (1e-10 if k == "w" else 1e-13) for k in fields}
+    else:
+        fields = ("u", "v", "w", "delp", "pt", "delz", "uc", "vc", "mfx", "mfy", "pfull", "phi")
+        tol = 1e-11
+    _compare(s, os_, n, fields, tol, label)
+    if stop:
+        og0 = orc.Grid(1, n, nz, delta=1.0e5)
+        os0 = orc.new_state(og0, init)
+        assert orc.acoustic_substeps(og0, os0, dt, ns, stop_stage=stop) == 0
+        ks = ("uc", "vc") if stop == 2 else ("u", "v")
+        d = max(_relerr(_int(s.get(k), n, STAG[k]), _int(os0[k], n, STAG[k])) for k in ks)
+        print(f"{label} vs no edge_interp {d:.2e}", flush=True)
+        assert d > 1e-9
+    assert fv3.check_status(g) == 0
+
+
+def test_edge_interp_periodic_untouched_and_abi(fv3):
+    """The doubly periodic grid has no tile edges: edge_interp changes
+    nothing; values other than 0 and 1 are refused."""
+    import ctypes as C
+
+    import torch
+
+    init = fi.periodic_state(n=16, nz=3)
+    out = []
+    for ei in (False, True):
+        g = fv3.Grid(0, 16, 3, edge_interp=ei)
+        s = fv3.State.allocate(g)
+        s.load(init)
+        fv3.acoustic_substeps(s, g, 2.0, 5)
+        torch.cuda.synchronize()
+        out.append({k: s.get(k) for k in ("u", "v", "delp", "pt", "w")})
+    for k in out[0]:
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+    p = fv3._params(1, 16, 2, 1000.0, 0.0, fv3.RADIUS, fv3.OMEGA, 100.0, "fp64", 0)
+    p.edge_interp = 2
+    h = C.c_void_p()
+    assert fv3.lib().fv3_init_grid(C.byref(p), C.byref(h)) == -1
