@@ -69,6 +69,8 @@ def lib():
         L.orc_interp.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.orc_interp.restype = C.c_double
         L.orc_corner_values.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_corner_vort.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
         L.orc_ppm_face_edge.restype = C.c_double
         L.orc_ppm_face_edge.argtypes = [dp, dp, C.c_double, C.c_int, C.c_int, C.c_int]
         L.orc_edge_partner.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
@@ -352,6 +354,16 @@ def corner_values(g: Grid, q) -> np.ndarray:
     q = np.ascontiguousarray(q, dtype=np.float64)
     out = np.zeros_like(q)
     lib().orc_corner_values(g._h, _p(q), _p(out))
+    return out
+
+
+def corner_vorticity(g: Grid, uc, vc) -> np.ndarray:
+    """c_sw's absolute vorticity at the corners of one level of every tile
+    from C-grid winds uc (x-faces) and vc (y-faces), [T][N][N] each."""
+    uc = np.ascontiguousarray(uc, dtype=np.float64)
+    vc = np.ascontiguousarray(vc, dtype=np.float64)
+    out = np.zeros_like(uc)
+    lib().orc_corner_vort(g._h, _p(uc), _p(vc), _p(out))
     return out
 
 

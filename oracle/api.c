@@ -47,6 +47,10 @@ void orc_set_edge_ppm(void *gp, int on) { ((OGrid *)gp)->edge_ppm = on; }
 void orc_set_edge_interp(void *gp, int on) { ((OGrid *)gp)->edge_interp = on; }
 
 void orc_corner_values(void *gp, const double *q, double *qB) { o_corner_values((const OGrid *)gp, q, qB); }
+void orc_corner_vort(void *gp, const double *uc, const double *vc, double *out)
+{
+    o_corner_vort_all((const OGrid *)gp, uc, vc, out);
+}
 
 double orc_interp(int kind, const double *x, int len, int m0, int m, int n, int edge)
 {

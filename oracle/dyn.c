@@ -89,6 +89,29 @@ double o_interp(int kind, const double *x0, ptrdiff_t s, int m0, int m, int n, i
 #undef X
 }
 
+/* Absolute vorticity at corner (i, j) of tile t from the C-grid winds
+ * (planes of the tile): f plus the circulation around the dual cell (the
+ * four C-grid faces meeting at the corner, each wind times its
+ * centre-to-centre length) over the dual-cell area.  At a cube vertex only
+ * three cells meet: the two halo faces next to the missing corner cell both
+ * cross the single face between the two neighbour cells, so each
+ * contributes half. */
+double o_corner_vort(const OGrid *g, int t, const double *ucp, const double *vcp, int i, int j)
+{
+    size_t o = (size_t)t * o_plane(g);
+    const double *dxc = g->dxc + o, *dyc = g->dyc + o, *area_c = g->area_c + o, *fB = g->fB + o;
+    double ws = 1.0, wn = 1.0, ww = 1.0, we = 1.0;
+    if (og_is_vertex(g, i, j)) {
+        if (j == 0) ws = 0.5; else wn = 0.5;
+        if (i == 0) ww = 0.5; else we = 0.5;
+    }
+    double circ = ws * ucp[IX(g, i, j - 1)] * dxc[IX(g, i, j - 1)] -
+                  wn * ucp[IX(g, i, j)] * dxc[IX(g, i, j)] -
+                  ww * vcp[IX(g, i - 1, j)] * dyc[IX(g, i - 1, j)] +
+                  we * vcp[IX(g, i, j)] * dyc[IX(g, i, j)];
+    return fB[IX(g, i, j)] + circ / area_c[IX(g, i, j)];
+}
+
 /* ------------------------------------------------------------------ c_sw */
 /*
  * Half-step C-grid update on one level of one tile.  D-grid winds are
@@ -201,23 +224,11 @@ static void c_sw_plane(const OGrid *g, int t, double dt2, const double *u, const
                                  vac * (vac > 0.0 ? vcp[c] : vcp[nn]));
         }
 
-    /* absolute vorticity at corners from the C-grid circulation.  At a cube
-     * vertex only three cells meet: the two halo faces next to the missing
-     * corner cell both cross the single face between the two neighbour
-     * cells, so each contributes half. */
+    /* absolute vorticity at corners from the C-grid circulation */
     for (int j = 0; j <= n; j++)
         for (int i = 0; i <= n; i++) {
             size_t b = IX(g, i, j);
-            double ws = 1.0, wn = 1.0, ww = 1.0, we = 1.0;
-            if (og_is_vertex(g, i, j)) {
-                if (j == 0) ws = 0.5; else wn = 0.5;
-                if (i == 0) ww = 0.5; else we = 0.5;
-            }
-            double circ = ws * ucp[IX(g, i, j - 1)] * dxc[IX(g, i, j - 1)] -
-                          wn * ucp[IX(g, i, j)] * dxc[IX(g, i, j)] -
-                          ww * vcp[IX(g, i - 1, j)] * dyc[IX(g, i - 1, j)] +
-                          we * vcp[IX(g, i, j)] * dyc[IX(g, i, j)];
-            vort[b] = fB[b] + circ / area_c[b];
+            vort[b] = o_corner_vort(g, t, ucp, vcp, i, j);
             if (vort_out) vort_out[b] = vort[b];
         }
 
@@ -857,6 +868,16 @@ static void corner_interp(const OGrid *g, const double *q, double *qB)
             qB[IX(g, i, j)] = o_interp(OI_FACE_MEAN, rows, 1, j - 2, j, n, ei);
         }
     free(qx);
+}
+
+/* c_sw's corner vorticity of one level of every tile from C-grid winds */
+void o_corner_vort_all(const OGrid *g, const double *uc, const double *vc, double *out)
+{
+    size_t P = o_plane(g);
+    for (int t = 0; t < g->T; t++)
+        for (int j = 0; j <= g->n; j++)
+            for (int i = 0; i <= g->n; i++)
+                out[(size_t)t * P + IX(g, i, j)] = o_corner_vort(g, t, uc + (size_t)t * P, vc + (size_t)t * P, i, j);
 }
 
 /* corner values of one level of every tile (halos already filled) */

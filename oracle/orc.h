@@ -83,6 +83,8 @@ static inline size_t o_plane(const OGrid *g) { return (size_t)g->N * g->N; }
 enum { OI_FACE_PT = 0, OI_CELL_PT = 1, OI_FACE_MEAN = 2 };
 double o_interp(int kind, const double *x0, ptrdiff_t s, int m0, int m, int n, int edge);
 void o_corner_values(const OGrid *g, const double *q, double *qB);
+double o_corner_vort(const OGrid *g, int t, const double *ucp, const double *vcp, int i, int j);
+void o_corner_vort_all(const OGrid *g, const double *uc, const double *vc, double *out);
 #define IX(g, i, j) ((size_t)((j) + H) * (size_t)(g)->N + (size_t)((i) + H))
 
 /* caller-owned state arrays of the substep loop */

@@ -196,3 +196,65 @@ def test_linear_flow_upwinded_kinetic_energy_closed_form(orc, comp):
     incr = DT2 * a * np.abs(w[far]).max()
     err = np.abs(got - expect)[far].max()
     assert err < 1e-9 * incr + 1e-12 * U0, (err, incr)
+
+
+def test_potential_flows_have_no_vorticity_on_the_cube(orc):
+    """The circulation weights on the cube's uneven metrics.  C-grid winds
+    that are differences of any cell-centred potential over the
+    centre-to-centre lengths (uc = (phi_E - phi_W) / dxc, vc = (phi_N -
+    phi_S) / dyc) have zero circulation around every dual cell, so c_sw's
+    corner vorticity is exactly f at every corner off the cube vertices;
+    D-grid winds that are differences of any corner potential over the edge
+    lengths (u = (phi_E - phi_W) / dx, v = (phi_N - phi_S) / dy) leave d_sw's
+    cell vorticity exactly f in every cell.  An index or weight slip in
+    either circulation breaks the telescoping sum."""
+    import fv3_inputs as fi
+
+    n, nz = 12, 1
+    g = orc.Grid(1, n, nz)
+    T, N = 6, n + 2 * H + 1
+    rng = np.random.default_rng(23)
+    dxc, dyc, dx, dy = g.metric("dxc"), g.metric("dyc"), g.metric("dx"), g.metric("dy")
+    fB, fC = g.metric("fB"), g.metric("fC")
+    # C-grid: cell potential on cells -1..n
+    phi = rng.normal(size=(T, N, N)) * 1e6
+    uc = np.zeros((T, N, N))
+    vc = np.zeros((T, N, N))
+    for j in range(-1, n + 1):
+        for i in range(0, n + 1):
+            uc[:, j + H, i + H] = (phi[:, j + H, i + H] - phi[:, j + H, i - 1 + H]) / dxc[:, j + H, i + H]
+    for j in range(0, n + 1):
+        for i in range(-1, n + 1):
+            vc[:, j + H, i + H] = (phi[:, j + H, i + H] - phi[:, j - 1 + H, i + H]) / dyc[:, j + H, i + H]
+    vort = orc.corner_vorticity(g, uc, vc)
+    scale = np.abs(uc).max() * dxc[:, H:H + n, H:H + n].max() / g.metric("area_c")[:, H:H + n, H:H + n].min()
+    for t in range(T):
+        for j in range(0, n + 1):
+            for i in range(0, n + 1):
+                if (i in (0, n)) and (j in (0, n)):
+                    continue
+                assert abs(vort[t, j + H, i + H] - fB[t, j + H, i + H]) <= 1e-12 * scale, (t, i, j)
+    # D-grid: corner potential on corners 0..n, winds on the tile's faces;
+    # the substep's halo fill supplies the rest, d_sw's vorticity is read back
+    init = fi.cube_state(n=n, nz=nz)
+    psi = rng.normal(size=(T, N, N)) * 1e6
+    u = np.zeros_like(init["u"])
+    v = np.zeros_like(init["v"])
+    for j in range(0, n + 1):
+        for i in range(0, n):
+            u[:, 0, j + H, i + H] = (psi[:, j + H, i + 1 + H] - psi[:, j + H, i + H]) / dx[:, j + H, i + H]
+    for j in range(0, n):
+        for i in range(0, n + 1):
+            v[:, 0, j + H, i + H] = (psi[:, j + 1 + H, i + H] - psi[:, j + H, i + H]) / dy[:, j + H, i + H]
+    init["u"], init["v"] = u, v
+    s = orc.new_state(g, init)
+    st, dbg = orc.acoustic_substeps(g, s, 1.0, 1, stop_stage=6, debug=True)
+    om = dbg["vortd"][:, 0, H:H + n, H:H + n]
+    scale = np.abs(u).max() * dx.max() / g.metric("area")[:, H:H + n, H:H + n].min()
+    assert np.abs(om - fC[:, H:H + n, H:H + n]).max() <= 1e-12 * scale
+    # the same winds with the metric weights taken one face off are not
+    # irrotational: the pin sees the weights
+    uc2 = uc.copy()
+    uc2[:, H:H + n, H + 1:H + n] *= dxc[:, H:H + n, H + 1:H + n] / dxc[:, H:H + n, H:H + n - 1]
+    vort2 = orc.corner_vorticity(g, uc2, vc)
+    assert np.abs(vort2 - fB)[:, H + 1:H + n, H + 1:H + n].max() > 1e-6 * scale
