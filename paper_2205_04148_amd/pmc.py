@@ -40,6 +40,11 @@ def launch_name(symbol: str):
     """Launch name of a library kernel from its mangled k_one<...> symbol."""
     m = re.search(r"k_oneITnDaXadL_ZNS_(\d+)(k_\w+)", symbol)
     if not m:
+        # plain kernels of the library (reductions, copies, the learned
+        # correction's products): their own name
+        p = re.search(r"_ZN3fv3(\d+)(k_\w+)", symbol) or re.search(r"^_Z(\d+)(k_\w+)", symbol)
+        if p:
+            return p.group(2)[:int(p.group(1))]
         return None
     ln = int(m.group(1))
     rest = m.group(2)
@@ -113,7 +118,9 @@ def counters_main(a):
     work; GRBM_GUI_ACTIVE / XCDs is the kernel's duration in cycles),
     valu_per_wave = SQ_INSTS_VALU / SQ_WAVES, lds_conflict_per_inst =
     SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (conflict cycles per LDS
-    instruction)."""
+    instruction), mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / SIMDs / duration in
+    cycles, mfma_bf16_tflops from SQ_INSTS_VALU_MFMA_MOPS_BF16 (units of 512
+    FLOPs) over the duration at 2.4 GHz."""
     dirs, out, workload = [a[0]] + a[3:], a[1], a[2]
     merged = collections.defaultdict(dict)
     for d in dirs:
@@ -132,6 +139,12 @@ def counters_main(a):
             m["valu_per_wave"] = m["SQ_INSTS_VALU"] / m["SQ_WAVES"]
         if m.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in m:
             m["lds_conflict_per_inst"] = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_INSTS_LDS"]
+        if g and "SQ_VALU_MFMA_BUSY_CYCLES" in m:
+            # share of the kernel's cycles the average SIMD's matrix core is busy
+            m["mfma_busy"] = m["SQ_VALU_MFMA_BUSY_CYCLES"] / SIMDS / (g / XCDS)
+        if g and "SQ_INSTS_VALU_MFMA_MOPS_BF16" in m:
+            # BF16 matrix FLOPs (the counter counts units of 512) per second
+            m["mfma_bf16_tflops"] = m["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512 / (g / XCDS / 2.4e9) / 1e12
         kern[name] = m
     doc = {"workload": workload, "kernel_source_sha256": source_sha256(), "kernels": kern}
     with open(out, "w") as fh:
