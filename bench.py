@@ -80,7 +80,7 @@ BYTES_MODEL = {
     "k_sim1_3.p4": (0, 3),     # thickness | phi, delz out
     "k_pgradc": (3, 4), "k_dsw_courant": (8, 0),
     "k_dsw_omke": (6, 0), "k_dsw_update": (13, 0), "k_heights": (0, 2), "k_delz_from_zh": (0, 2),
-    "k_nhpgrad": (5, 4),       # delp, u, v in, u, v out | pfull, phi at the layer's two interfaces
+    "k_nhpgrad": (5, 2),       # delp, u, v in, u, v out | pfull, phi (each interface once)
     # fused fv_tp_2d: the field, 4 Courant / area-flux arrays, weights, outputs, per epilogue
     "k_fvtp_delp": (12, 4),    # delp, crx, cry, xfx, yfx, FX, FY, dn, cx, cy (rw) | mfx, mfy (rw)
     "k_fvtp_massw": (10, 0),   # q, 4 fluxes, mx, my, delp old, delp new, q new

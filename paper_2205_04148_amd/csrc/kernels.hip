@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "fv3_internal.hpp"
+#include "flog.hpp"
 
 namespace fv3 {
 
@@ -48,6 +49,15 @@ DEVI T &at_(T *p, int i, int j, int pitch)
     return *(T *)(b + (unsigned)((j + 3) * pitch + (i + 3)) * (unsigned)sizeof(T));
 }
 #define AT(P, i, j) at_((P), (int)(i), (int)(j), (int)G.pitch)
+
+// a / b in the FP32 bulk through the hardware reciprocal (about 1 ulp, far
+// below the FP32 bulk's rounding), FP64 exact
+template <class T>
+DEVI T rdiv(T a, T b)
+{
+    if constexpr (std::is_same<T, float>::value) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
 
 DEVI int stx_(int st) { return (st == SC || st == SY) ? 1 : 0; }
 DEVI int sty_(int st) { return (st == SC || st == SX) ? 1 : 0; }
@@ -1062,11 +1072,11 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
 
     // ---- pass 1: top-down elimination; step k consumes layer k + 1
     if constexpr (PASS == 1 && PPO == 2) {
-    double lpi_k = log(ptop);
+    double lpi_k = flog(ptop);
     double dp0 = (double)dpi[base], th0 = (double)theta[base] * virt(qv, base), h0 = -delz[base], w0 = (double)w[base];
-    double pi_k1 = ptop + dp0, lpi_k1 = log(pi_k1);
+    double pi_k1 = ptop + dp0, lpi_k1 = flog(pi_k1);
     double m0 = dp0 / GRAV;
-    double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi_k1 - lpi_k);
+    double pp0 = P_REF * exp(gam * flog(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi_k1 - lpi_k);
     double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0, wprev = 0.0;
     // off-centring: coupling scaled by beta^2, the explicit part of the
     // pressure response on the right-hand side; P* kept at the interfaces
@@ -1107,9 +1117,9 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                     double pps_k1, A_k1, pi_k2 = 0, lpi_k2 = 0, m1 = 0, pp1 = 0;
                     if (k < nz - 1) {
                         pi_k2 = pi_k1 + dp1;
-                        lpi_k2 = log(pi_k2);
+                        lpi_k2 = flog(pi_k2);
                         m1 = dp1 / GRAV;
-                        pp1 = P_REF * exp(gam * log(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi_k2 - lpi_k1);
+                        pp1 = P_REF * exp(gam * flog(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi_k2 - lpi_k1);
                         pps_k1 = (dp1 * pp0 + dp0 * pp1) / (dp0 + dp1);
                         A_k1 = bb * gam * (pi_k1 + pps_k1) * dt2x / (0.5 * (h0 + h1));
                     } else {
@@ -1148,9 +1158,9 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     if constexpr (PASS == 1 && PPO == 4) {
     const double bb = OFFC ? beta * beta : 1.0, ex = (1.0 - beta) / beta;
     double dp0 = (double)dpi[base], th0 = (double)theta[base] * virt(qv, base), h0 = -delz[base], w0 = (double)w[base];
-    double pi1 = ptop + dp0, lpi1 = log(pi1);
+    double pi1 = ptop + dp0, lpi1 = flog(pi1);
     double m0 = dp0 / GRAV;
-    double pp0 = P_REF * exp(gam * log(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi1 - log(ptop));
+    double pp0 = P_REF * exp(gam * flog(RDGAS * th0 * m0 / (h0 * P_REF))) - dp0 / (lpi1 - flog(ptop));
     double dp1 = 0.0, h1 = 0.0, w1 = 0.0, pp1 = 0.0, pi2 = 0.0, lpi2 = 0.0, m1 = 0.0;
     if (nz > 1) {
         const long o = base + lev;
@@ -1159,9 +1169,9 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
         h1 = -delz[o];
         w1 = (double)w[o];
         pi2 = pi1 + dp1;
-        lpi2 = log(pi2);
+        lpi2 = flog(pi2);
         m1 = dp1 / GRAV;
-        pp1 = P_REF * exp(gam * log(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi2 - lpi1);
+        pp1 = P_REF * exp(gam * flog(RDGAS * th1 * m1 / (h1 * P_REF))) - dp1 / (lpi2 - lpi1);
     }
     double dpm = 0.0, ppm = 0.0;   // layer k - 1
     double pps_k = 0.0, A_k = 0.0, cprev = 0.0, dprev = 0.0, wprev = 0.0;
@@ -1200,9 +1210,9 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                     double pi3 = 0.0, lpi3 = 0.0, m2 = 0.0, pp2 = 0.0;
                     if (k + 2 < nz) {
                         pi3 = pi2 + dp2;
-                        lpi3 = log(pi3);
+                        lpi3 = flog(pi3);
                         m2 = dp2 / GRAV;
-                        pp2 = P_REF * exp(gam * log(RDGAS * th2 * m2 / (h2 * P_REF))) - dp2 / (lpi3 - lpi2);
+                        pp2 = P_REF * exp(gam * flog(RDGAS * th2 * m2 / (h2 * P_REF))) - dp2 / (lpi3 - lpi2);
                     }
                     double pps_k1, A_k1;
                     if (k < nz - 1) {
@@ -1275,8 +1285,8 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
     }
     // ---- pass 3: new perturbation (top down), thicknesses, interface pressure
     if constexpr (PASS == 3) {
-        const double lpref = log(P_REF);
-        double ppn = 0.0, pnk = 0.0, pik = ptop, lpik = log(ptop);
+        const double lpref = flog(P_REF);
+        double ppn = 0.0, pnk = 0.0, pik = ptop, lpik = flog(ptop);
         if (pfull) pfull[basei] = ptop;
         G4 cur, nxt;
 #pragma unroll
@@ -1310,14 +1320,14 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                 if (k < nz) {
                     double dp = cur.a[u], th = cur.b[u] * (1.0 + EPSV * cur.e[u]), wk = cur.c[u], wo = cur.d[u];
                     double m = dp / GRAV;
-                    double pik1 = pik + dp, lpik1 = log(pik1);
+                    double pik1 = pik + dp, lpik1 = flog(pik1);
                     double pib = dp / (lpik1 - lpik);
                     // the scan gives the off-centred perturbation; the new one follows
                     double ppn1 = ppn + m * (wk - wo) / dt;
                     double pnk1 = ppn1;
                     if constexpr (OFFC) pnk1 = (ppn1 - (1.0 - beta) * pfull[basei + (long)(k + 1) * lev]) / beta;
                     double pn = pib + 0.5 * (pnk + pnk1);
-                    double hn = RDGAS * th * m / P_REF * exp(rgam * (lpref - log(pn)));
+                    double hn = RDGAS * th * m / P_REF * exp(rgam * (lpref - flog(pn)));
                     cpv[base + (long)k * lev] = hn;   // reuse as the new thickness
                     if (pfull) pfull[basei + (long)(k + 1) * lev] = pik1 + pnk1;
                     if (w_out) w_out[base + (long)k * lev] = (TW)wk;
@@ -1482,15 +1492,6 @@ DEVI T ccr(const C *a, const C *a0, unsigned idx, int avg)
 {
     if (avg) return (T)(0.5 * ((double)ldo(a0, idx) + (double)ldo(a, idx)));
     return (T)ldo(a, idx);
-}
-
-// a / b for the flux-divergence updates: FP32 through the hardware
-// reciprocal (about 1 ulp, far below the FP32 bulk's rounding), FP64 exact
-template <class T>
-DEVI T rdiv(T a, T b)
-{
-    if constexpr (std::is_same<T, float>::value) return a * __builtin_amdgcn_rcpf(b);
-    else return a / b;
 }
 
 // The transport tile in LDS (one instance per block, shared by both
@@ -1866,40 +1867,63 @@ static void fvtp(const fv3_grid *g, int planes, const FvArgs<T, C, M> &a, hipStr
 // ====================================================================
 // Courant numbers and area fluxes from the contravariant half-step C-grid
 // winds (partner component: four-point mean of the other C-grid wind).
-template <class B>
-DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc, B *ut, B *vt,
-                              B *crx, B *cry, B *xfx, B *yfx, int *flags)
+// CORNER = false for blocks whose reads cannot reach a cube corner block
+// (no view checks).
+template <class B, bool CORNER>
+DEVI void dsw_courant_body(const Geo &G, const Mets<B> &M, B bdt, const B *UC, const B *VC, long o, int t, int i, int j,
+                           B *ut, B *vt, B *crx, B *cry, B *xfx, B *yfx, bool &bad)
 {
-    KBEGIN(G.nz);
-    int n = G.n;
-    long o = pidx(G, G.nz, t, k);
-    const B *UC = uc + o, *VC = vc + o;
+    const int n = G.n;
     const B *dxa = MP(M, M_DXA), *dya = MP(M, M_DYA);
-    bool bad = false;
     if (i >= 0 && i <= n && j >= -3 && j <= n + 2) {
-        B vb = (B)0.25 * (pvy(G, UC, VC, SY, i - 1, j, 0, true) + pvy(G, UC, VC, SY, i, j, 0, true) +
-                          pvy(G, UC, VC, SY, i - 1, j + 1, 0, true) + pvy(G, UC, VC, SY, i, j + 1, 0, true));
+        B vb;
+        if constexpr (CORNER)
+            vb = (B)0.25 * (pvy(G, UC, VC, SY, i - 1, j, 0, true) + pvy(G, UC, VC, SY, i, j, 0, true) +
+                            pvy(G, UC, VC, SY, i - 1, j + 1, 0, true) + pvy(G, UC, VC, SY, i, j + 1, 0, true));
+        else
+            vb = (B)0.25 * (AT(VC, i - 1, j) + AT(VC, i, j) + AT(VC, i - 1, j + 1) + AT(VC, i, j + 1));
         B su = AT(MP(M, M_SIN_U), i, j);
-        B uu = (AT(UC, i, j) - vb * AT(MP(M, M_COS_U), i, j)) / (su * su);
+        B uu = rdiv(AT(UC, i, j) - vb * AT(MP(M, M_COS_U), i, j), su * su);
         int up = uu > 0 ? i - 1 : i;
-        B cr = bdt * uu / pvx(G, dxa, dya, SC, up, j, 0, false);
+        B da = CORNER ? pvx(G, dxa, dya, SC, up, j, 0, false) : AT(dxa, up, j);
+        B cr = rdiv(bdt * uu, da);
         AT(ut + o, i, j) = uu;
         AT(crx + o, i, j) = cr;
         AT(xfx + o, i, j) = bdt * uu * su * AT(MP(M, M_DY), i, j);
         bad |= fabs((double)cr) > 1.0;
     }
     if (i >= -3 && i <= n + 2 && j >= 0 && j <= n) {
-        B ub = (B)0.25 * (pvx(G, UC, VC, SX, i, j - 1, 1, true) + pvx(G, UC, VC, SX, i + 1, j - 1, 1, true) +
-                          pvx(G, UC, VC, SX, i, j, 1, true) + pvx(G, UC, VC, SX, i + 1, j, 1, true));
+        B ub;
+        if constexpr (CORNER)
+            ub = (B)0.25 * (pvx(G, UC, VC, SX, i, j - 1, 1, true) + pvx(G, UC, VC, SX, i + 1, j - 1, 1, true) +
+                            pvx(G, UC, VC, SX, i, j, 1, true) + pvx(G, UC, VC, SX, i + 1, j, 1, true));
+        else
+            ub = (B)0.25 * (AT(UC, i, j - 1) + AT(UC, i + 1, j - 1) + AT(UC, i, j) + AT(UC, i + 1, j));
         B sv_ = AT(MP(M, M_SIN_V), i, j);
-        B vv = (AT(VC, i, j) - ub * AT(MP(M, M_COS_V), i, j)) / (sv_ * sv_);
+        B vv = rdiv(AT(VC, i, j) - ub * AT(MP(M, M_COS_V), i, j), sv_ * sv_);
         int up = vv > 0 ? j - 1 : j;
-        B cr = bdt * vv / pvy(G, dxa, dya, SC, i, up, 1, false);
+        B da = CORNER ? pvy(G, dxa, dya, SC, i, up, 1, false) : AT(dya, i, up);
+        B cr = rdiv(bdt * vv, da);
         AT(vt + o, i, j) = vv;
         AT(cry + o, i, j) = cr;
         AT(yfx + o, i, j) = bdt * vv * sv_ * AT(MP(M, M_DX), i, j);
         bad |= fabs((double)cr) > 1.0;
     }
+}
+template <class B>
+DEVI void k_dsw_courant(KARGS, Geo G, Mets<B> M, B bdt, const B *uc, const B *vc, B *ut, B *vt,
+                              B *crx, B *cry, B *xfx, B *yfx, int *flags)
+{
+    KBEGIN(G.nz);
+    long o = pidx(G, G.nz, t, k);
+    // the block's reads span its points +-1 in both directions; corner views
+    // exist only outside [0, n - 1] in both
+    const int i0 = ib + (int)(bk.x * blockDim.x) - 1, i1 = i0 + (int)blockDim.x + 1;
+    const int j0 = jlo + (int)(bk.y * blockDim.y) - 1, j1 = j0 + (int)blockDim.y + 1;
+    const bool corner = G.cube && (i0 < 0 || i1 >= G.n) && (j0 < 0 || j1 >= G.n);
+    bool bad = false;
+    if (corner) dsw_courant_body<B, true>(G, M, bdt, uc + o, vc + o, o, t, i, j, ut, vt, crx, cry, xfx, yfx, bad);
+    else dsw_courant_body<B, false>(G, M, bdt, uc + o, vc + o, o, t, i, j, ut, vt, crx, cry, xfx, yfx, bad);
     if (bad) atomicOr(flags, 1);
 }
 
@@ -1916,14 +1940,14 @@ DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const 
     const B *U = u + o, *V = v + o;
     const B *dx = MP(M, M_DX), *dy = MP(M, M_DY);
     if (!in_corner(G, SC, i, j) && i <= n + 2 && j <= n + 2)
-        AT(om + o, i, j) = AT(MP(M, M_FC), i, j) + (AT(U, i, j) * AT(dx, i, j) - AT(U, i, j + 1) * AT(dx, i, j + 1) -
-                                                    AT(V, i, j) * AT(dy, i, j) + AT(V, i + 1, j) * AT(dy, i + 1, j)) /
-                                                       AT(MP(M, M_AREA), i, j);
+        AT(om + o, i, j) = AT(MP(M, M_FC), i, j) + rdiv(AT(U, i, j) * AT(dx, i, j) - AT(U, i, j + 1) * AT(dx, i, j + 1) -
+                                                         AT(V, i, j) * AT(dy, i, j) + AT(V, i + 1, j) * AT(dy, i + 1, j),
+                                                     AT(MP(M, M_AREA), i, j));
     if (i >= 0 && i <= n && j >= 0 && j <= n) {
         B ub = (B)0.5 * bdt * (AT(ut + o, i, j - 1) + AT(ut + o, i, j));
         B vb = (B)0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
-        B cu = ub / AT(dx, ub > 0 ? i - 1 : i, j);
-        B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
+        B cu = rdiv(ub, AT(dx, ub > 0 ? i - 1 : i, j));
+        B cv = rdiv(vb, AT(dy, i, vb > 0 ? j - 1 : j));
         B uu = ppm6<ORD>(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j), AT(U, i + 2, j), cu);
         B vv = ppm6<ORD>(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1), AT(V, i, j + 2), cv);
         B kev = (B)0.5 * (ub * uu + vb * vv);
@@ -2012,7 +2036,7 @@ DEVI void k_ke_edge(Bk bk, Geo G, Mets<B> M, B bdt, const B *u, const B *v, cons
     bool west;
     if (edge_face(i, n)) {
         const B ub = (B)0.5 * bdt * (AT(ut + o, i, j - 1) + AT(ut + o, i, j));
-        const B cu = ub / AT(dx, ub > 0 ? i - 1 : i, j);
+        const B cu = rdiv(ub, AT(dx, ub > 0 ? i - 1 : i, j));
         const int pe = edge_pe(i, n, west);
         const B ue = ppm_edge<ORD>(&AT(U, i - 3, j), 1, &AT(dx, i - 3, j), 1, cu, pe, west);
         const B uc = ppm6<ORD>(AT(U, i - 3, j), AT(U, i - 2, j), AT(U, i - 1, j), AT(U, i, j), AT(U, i + 1, j),
@@ -2021,7 +2045,7 @@ DEVI void k_ke_edge(Bk bk, Geo G, Mets<B> M, B bdt, const B *u, const B *v, cons
     }
     if (edge_face(j, n)) {
         const B vb = (B)0.5 * bdt * (AT(vt + o, i - 1, j) + AT(vt + o, i, j));
-        const B cv = vb / AT(dy, i, vb > 0 ? j - 1 : j);
+        const B cv = rdiv(vb, AT(dy, i, vb > 0 ? j - 1 : j));
         const int pe = edge_pe(j, n, west);
         const B ve = ppm_edge<ORD>(&AT(V, i, j - 3), (int)G.pitch, &AT(dy, i, j - 3), (int)G.pitch, cv, pe, west);
         const B vc = ppm6<ORD>(AT(V, i, j - 3), AT(V, i, j - 2), AT(V, i, j - 1), AT(V, i, j), AT(V, i, j + 1),
@@ -2256,61 +2280,88 @@ DEVI double face_mean(double x0, double x1, double x2, double x3, int m, int n, 
     return r;
 }
 
-template <class B, bool EI = false>
-DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
-                                                 const double *phi, const B *delp, B *u, B *v)
+// Each block walks NHK consecutive layers of its corner tile: the corner
+// values of p and phi at the interface below one layer are those above the
+// next, so they are kept (two alternating LDS slots) instead of being
+// interpolated again, and per layer only p, phi at the lower interface and
+// delp are staged.  The next layer's cells and winds are loaded while the
+// current layer computes.
+#ifndef FV3_NHK
+#define FV3_NHK 8
+#endif
+constexpr int NHK = FV3_NHK;
+constexpr int NCS = (NCH * NCW + 255) / 256;    // staged cells per thread
+constexpr int NBC = (NPY + 1) * (NPX + 1);      // corners of a block
+constexpr int NPP = (NPX * NPY + 255) / 256;    // faces per thread
+struct NhLds {
+    double sc[3][NCH * NCW];   // staged cells (x-sweep view), then the x pass in place
+    double sb[5][NBC];         // corner values: p, p (alternating interfaces), phi, phi, delp
+};
+
+// cells of the block's staging window into registers: p and phi of one
+// interface and (WD) delp of one layer
+template <class B, bool CORNER, bool WD>
+DEVI void nh_load(const Geo &G, int i0, int j0, const double *Fp, const double *Fz, const B *D, double (&r)[NCS][3])
 {
-    __shared__ double sc[5][NCH * NCW];               // p0, p1, z0, z1, d at cells (x-sweep view)
-    __shared__ double sb[5][(NPY + 1) * (NPX + 1)];   // corner values
-    const int n = G.n, nz = G.nz, tid = threadIdx.x;
-    const int i0 = bk.x * NPX, j0 = bk.y * NPY;
-    const int t = bk.z / nz, k = bk.z % nz;
-    const double *F[4] = {pfull + pidx(G, nz + 1, t, k), pfull + pidx(G, nz + 1, t, k + 1),
-                          phi + pidx(G, nz + 1, t, k), phi + pidx(G, nz + 1, t, k + 1)};
-    const B *D = delp + pidx(G, nz, t, k);
-    const long o = pidx(G, nz, t, k);
-    // prefetch of the winds and edge lengths of the faces this thread updates
-    constexpr int NPP = (NPX * NPY + 255) / 256;
-    double pu[NPP], pdx[NPP], pv[NPP], pdy[NPP];
+    const int n = G.n;
 #pragma unroll
-    for (int m = 0; m < NPP; m++) {
-        int e = tid + m * 256, r = e / NPX, c = e - r * NPX;
-        int i = i0 + c, j = j0 + r;
-        bool in = e < NPX * NPY;
-        bool fu = in && i < n && j <= n, fv = in && i <= n && j < n;
-        pu[m] = fu ? (double)AT(u + o, i, j) : 0.0;
-        pdx[m] = fu ? AT(MP(M, M_DX), i, j) : 1.0;
-        pv[m] = fv ? (double)AT(v + o, i, j) : 0.0;
-        pdy[m] = fv ? AT(MP(M, M_DY), i, j) : 1.0;
+    for (int m = 0; m < NCS; m++) {
+        const int e = (int)threadIdx.x + m * 256, rr = e / NCW, c = e - rr * NCW;
+        const int i = i0 - 2 + c, j = j0 - 2 + rr;
+        double a = 0.0, b = 0.0, d = 0.0;
+        if (e < NCH * NCW && i <= n + 2 && j <= n + 2) {
+            if constexpr (CORNER) {
+                a = sv(G, Fp, SC, i, j, 0);
+                b = sv(G, Fz, SC, i, j, 0);
+                if constexpr (WD) d = (double)sv(G, D, SC, i, j, 0);
+            } else {
+                a = AT(Fp, i, j);
+                b = AT(Fz, i, j);
+                if constexpr (WD) d = (double)AT(D, i, j);
+            }
+        }
+        r[m][0] = a;
+        r[m][1] = b;
+        r[m][2] = d;
     }
-    for (int e = tid; e < NCH * NCW; e += 256) {
-        int r = e / NCW, c = e - r * NCW;
-        int i = i0 - 2 + c, j = j0 - 2 + r;
-        bool ok = i <= n + 2 && j <= n + 2;
-        for (int f = 0; f < 4; f++) sc[f][e] = ok ? sv(G, F[f], SC, i, j, 0) : 0.0;
-        sc[4][e] = ok ? (double)sv(G, D, SC, i, j, 0) : 0.0;
+}
+
+template <int NF>
+DEVI void nh_store(NhLds &L, const double (&r)[NCS][3])
+{
+#pragma unroll
+    for (int m = 0; m < NCS; m++) {
+        const int e = (int)threadIdx.x + m * 256;
+        if (e < NCH * NCW) {
+#pragma unroll
+            for (int f = 0; f < NF; f++) L.sc[f][e] = r[m][f];
+        }
     }
-    __syncthreads();
+}
+
+// The tensor interpolation of the NF staged fields to the block's corners
+// (into corner slots s0, s1, s2) in two passes: along x for every staged row
+// at every corner column (into registers), then along y at each corner.
+// Expects the staged cells to be visible (after a barrier); ends with one.
+template <bool EI, bool CORNER, int NF>
+DEVI void nh_corners(const Geo &G, int i0, int j0, NhLds &L, int s0, int s1, int s2, bool ebx, bool eby)
+{
+    const int n = G.n, tid = threadIdx.x;
+    const int slot[3] = {s0, s1, s2};
     const double w4[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
-    // with the edge rule, only blocks with corner columns (rows) within one
-    // cell of a tile edge (0, 1, n - 1, n) take the one-sided branches of
-    // the x (y) pass
-    const bool ebx = EI && (i0 <= 1 || i0 + NPX >= n - 1), eby = EI && (j0 <= 1 || j0 + NPY >= n - 1);
-    // The tensor interpolation in two passes: along x for every staged row at
-    // every corner column (into registers), then along y at each corner.
     constexpr int NRX = (NPY + 4) * (NPX + 1), NRP = (NRX + 255) / 256;
-    double xr[NRP][5];
+    double xr[NRP][NF];
 #pragma unroll
     for (int m = 0; m < NRP; m++) {
-        int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
+        const int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
         // the edge rule on rows inside the tile (row j = j0 - 2 + rr)
         const int jr = j0 - 2 + rr;
         const bool ex = EI && jr >= 0 && jr < n;
 #pragma unroll
-        for (int f = 0; f < 5; f++) {
+        for (int f = 0; f < NF; f++) {
             double rw = 0.0;
             if (e < NRX) {
-                const double *row = &sc[f][rr * NCW + c];
+                const double *row = &L.sc[f][rr * NCW + c];
                 if (EI && ebx)
                     rw = face_mean(row[0], row[1], row[2], row[3], i0 + c, n, ex, w4);
                 else
@@ -2319,68 +2370,139 @@ DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull,
             xr[m][f] = rw;
         }
     }
-    // corners at cube vertices: mean of the three cells, from the staged cells
-    for (int e = tid; e < (NPY + 1) * (NPX + 1); e += 256) {
-        int r = e / (NPX + 1), c = e - r * (NPX + 1);
-        int i = i0 + c, j = j0 + r;
-        if (i > n || j > n || !is_vertex(G, i, j)) continue;
-        int ci[4] = {i - 1, i, i, i - 1}, cj[4] = {j - 1, j - 1, j, j};
-        for (int f = 0; f < 5; f++) {
-            double sum = 0.0;
-            for (int q = 0; q < 4; q++)
-                if (!in_corner(G, SC, ci[q], cj[q])) sum += sc[f][(cj[q] - j0 + 2) * NCW + (ci[q] - i0 + 2)];
-            sb[f][e] = sum / 3.0;
+    // corners at cube vertices (corner blocks only): mean of the three
+    // cells, from the staged cells
+    if constexpr (CORNER) {
+        for (int e = tid; e < NBC; e += 256) {
+            const int r = e / (NPX + 1), c = e - r * (NPX + 1);
+            const int i = i0 + c, j = j0 + r;
+            if (i > n || j > n || !is_vertex(G, i, j)) continue;
+            const int ci[4] = {i - 1, i, i, i - 1}, cj[4] = {j - 1, j - 1, j, j};
+            for (int f = 0; f < NF; f++) {
+                double sum = 0.0;
+                for (int q = 0; q < 4; q++)
+                    if (!in_corner(G, SC, ci[q], cj[q])) sum += L.sc[f][(cj[q] - j0 + 2) * NCW + (ci[q] - i0 + 2)];
+                L.sb[slot[f]][e] = sum / 3.0;
+            }
         }
     }
     __syncthreads();
     // the x pass in place of the staged cells (row rr, corner column c)
 #pragma unroll
     for (int m = 0; m < NRP; m++) {
-        int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
+        const int e = tid + m * 256, rr = e / (NPX + 1), c = e - rr * (NPX + 1);
         if (e < NRX) {
 #pragma unroll
-            for (int f = 0; f < 5; f++) sc[f][rr * NCW + c] = xr[m][f];
+            for (int f = 0; f < NF; f++) L.sc[f][rr * NCW + c] = xr[m][f];
         }
     }
     __syncthreads();
-    for (int e = tid; e < (NPY + 1) * (NPX + 1); e += 256) {
-        int r = e / (NPX + 1), c = e - r * (NPX + 1);
-        int i = i0 + c, j = j0 + r;
-        if (i > n || j > n || is_vertex(G, i, j)) continue;
-        for (int f = 0; f < 5; f++) {
+    for (int e = tid; e < NBC; e += 256) {
+        const int r = e / (NPX + 1), c = e - r * (NPX + 1);
+        const int i = i0 + c, j = j0 + r;
+        if (i > n || j > n || (CORNER && is_vertex(G, i, j))) continue;
+#pragma unroll
+        for (int f = 0; f < NF; f++) {
             double acc = 0.0;
             if (EI && eby) {
-                const double *col = &sc[f][r * NCW + c];
+                const double *col = &L.sc[f][r * NCW + c];
                 acc = face_mean(col[0], col[NCW], col[2 * NCW], col[3 * NCW], j, n, true, w4);
             } else {
-                for (int b = 0; b < 4; b++) acc += w4[b] * sc[f][(r + b) * NCW + c];
+                for (int b = 0; b < 4; b++) acc += w4[b] * L.sc[f][(r + b) * NCW + c];
             }
-            sb[f][e] = acc;
+            L.sb[slot[f]][e] = acc;
         }
     }
     __syncthreads();
-    // Each block owns the faces of its NPX x NPY corner rows/columns: the grid
-    // spans corners 0..n, so a face row or column on a block boundary is
-    // updated by exactly one block.  u on y-faces (i, j) uses corners (i, j)
-    // and (i + 1, j); v on x-faces (i, j) corners (i, j) and (i, j + 1).
+}
+
+// CORNER: the block's staging window reaches a cube corner block, so its
+// cell reads go through the corner views and its vertex corners take the
+// three-cell mean; every other block reads the planes directly.
+template <class B, bool EI, bool CORNER>
+DEVI void nhpgrad_body(Bk bk, const Geo &G, const MetD &M, double bdt, const double *pfull, const double *phi,
+                       const B *delp, B *u, B *v, NhLds &L)
+{
+    const int n = G.n, nz = G.nz, tid = threadIdx.x;
+    const int i0 = bk.x * NPX, j0 = bk.y * NPY;
+    const int nzb = (nz + NHK - 1) / NHK;
+    const int t = (int)bk.z / nzb, k0 = ((int)bk.z % nzb) * NHK, k1 = k0 + NHK < nz ? k0 + NHK : nz;
+    // with the edge rule, only blocks with corner columns (rows) within one
+    // cell of a tile edge (0, 1, n - 1, n) take the one-sided branches of
+    // the x (y) pass
+    const bool ebx = EI && (i0 <= 1 || i0 + NPX >= n - 1), eby = EI && (j0 <= 1 || j0 + NPY >= n - 1);
+    // edge lengths of the faces this thread updates (the same on every layer)
+    double pdx[NPP], pdy[NPP];
 #pragma unroll
     for (int m = 0; m < NPP; m++) {
-        int e = tid + m * 256;
-        if (e >= NPX * NPY) break;
-        int r = e / NPX, c = e - r * NPX;
-        int i = i0 + c, j = j0 + r;
-        int W = r * (NPX + 1) + c;
-        if (i < n && j <= n) {
-            int E = W + 1;
-            AT(u + o, i, j) = (B)pu[m] + (B)pgf(bdt, pdx[m], sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
-                                                sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+        const int e = tid + m * 256, r = e / NPX, c = e - r * NPX;
+        const int i = i0 + c, j = j0 + r;
+        const bool in = e < NPX * NPY;
+        pdx[m] = (in && i < n && j <= n) ? AT(MP(M, M_DX), i, j) : 1.0;
+        pdy[m] = (in && i <= n && j < n) ? AT(MP(M, M_DY), i, j) : 1.0;
+    }
+    // the interface above the first layer
+    double rg[NCS][3];
+    nh_load<B, CORNER, false>(G, i0, j0, pfull + pidx(G, nz + 1, t, k0), phi + pidx(G, nz + 1, t, k0),
+                              (const B *)nullptr, rg);
+    nh_store<2>(L, rg);
+    __syncthreads();
+    nh_corners<EI, CORNER, 2>(G, i0, j0, L, 0, 2, 4, ebx, eby);
+    nh_load<B, CORNER, true>(G, i0, j0, pfull + pidx(G, nz + 1, t, k0 + 1), phi + pidx(G, nz + 1, t, k0 + 1),
+                             delp + pidx(G, nz, t, k0), rg);
+    for (int k = k0; k < k1; k++) {
+        const int b = 1 - ((k - k0) & 1), a = 1 - b;   // corner slots of the lower / upper interface
+        const long o = pidx(G, nz, t, k);
+        double pu[NPP], pv[NPP];
+#pragma unroll
+        for (int m = 0; m < NPP; m++) {
+            const int e = tid + m * 256, r = e / NPX, c = e - r * NPX;
+            const int i = i0 + c, j = j0 + r;
+            const bool in = e < NPX * NPY;
+            pu[m] = (in && i < n && j <= n) ? (double)AT(u + o, i, j) : 0.0;
+            pv[m] = (in && i <= n && j < n) ? (double)AT(v + o, i, j) : 0.0;
         }
-        if (i <= n && j < n) {
-            int E = W + (NPX + 1);
-            AT(v + o, i, j) = (B)pv[m] + (B)pgf(bdt, pdy[m], sb[4][W], sb[4][E], sb[2][W], sb[3][W], sb[2][E],
-                                                sb[3][E], sb[0][W], sb[1][W], sb[0][E], sb[1][E]);
+        nh_store<3>(L, rg);
+        __syncthreads();
+        if (k + 1 < k1)
+            nh_load<B, CORNER, true>(G, i0, j0, pfull + pidx(G, nz + 1, t, k + 2), phi + pidx(G, nz + 1, t, k + 2),
+                                     delp + pidx(G, nz, t, k + 1), rg);
+        nh_corners<EI, CORNER, 3>(G, i0, j0, L, b, 2 + b, 4, ebx, eby);
+        const double *P0 = L.sb[a], *P1 = L.sb[b], *Z0 = L.sb[2 + a], *Z1 = L.sb[2 + b], *DD = L.sb[4];
+        // Each block owns the faces of its NPX x NPY corner rows/columns: the
+        // grid spans corners 0..n, so a face row or column on a block boundary
+        // is updated by exactly one block.  u on y-faces (i, j) uses corners
+        // (i, j) and (i + 1, j); v on x-faces (i, j) corners (i, j) and (i, j + 1).
+#pragma unroll
+        for (int m = 0; m < NPP; m++) {
+            const int e = tid + m * 256;
+            if (e >= NPX * NPY) break;
+            const int r = e / NPX, c = e - r * NPX;
+            const int i = i0 + c, j = j0 + r;
+            const int W = r * (NPX + 1) + c;
+            if (i < n && j <= n) {
+                const int E = W + 1;
+                AT(u + o, i, j) = (B)pu[m] + (B)pgf(bdt, pdx[m], DD[W], DD[E], Z0[W], Z1[W], Z0[E], Z1[E], P0[W],
+                                                    P1[W], P0[E], P1[E]);
+            }
+            if (i <= n && j < n) {
+                const int E = W + (NPX + 1);
+                AT(v + o, i, j) = (B)pv[m] + (B)pgf(bdt, pdy[m], DD[W], DD[E], Z0[W], Z1[W], Z0[E], Z1[E], P0[W],
+                                                    P1[W], P0[E], P1[E]);
+            }
         }
     }
+}
+
+template <class B, bool EI = false>
+DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull, const double *phi, const B *delp, B *u,
+                    B *v)
+{
+    __shared__ NhLds L;
+    const int i0 = bk.x * NPX, j0 = bk.y * NPY;
+    const bool corner = G.cube && (i0 - 2 < 0 || i0 + NPX + 2 >= G.n) && (j0 - 2 < 0 || j0 + NPY + 2 >= G.n);
+    if (corner) nhpgrad_body<B, EI, true>(bk, G, M, bdt, pfull, phi, delp, u, v, L);
+    else nhpgrad_body<B, EI, false>(bk, G, M, bdt, pfull, phi, delp, u, v, L);
 }
 
 // ====================================================================
@@ -2894,7 +3016,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         STOP(9);
         // nh_p_grad
         {
-            const dim3 ngrd((n + NPX) / NPX, (n + NPY) / NPY, P);
+            const dim3 ngrd((n + NPX) / NPX, (n + NPY) / NPY, T * ((nz + NHK - 1) / NHK));
             if (g->p.edge_interp && g->p.kind == FV3_GRID_CUBED_SPHERE)
                 launch_fn<k_nhpgrad<B, true>>("k_nhpgrad", ngrd, dim3(256), st, G, Md, bdt, (const double *)s->pfull,
                                               (const double *)s->phi, (const B *)delp, u, v);
