@@ -928,6 +928,17 @@ DEVI double zs_at(const Geo &G, const double *phis, int t, int i, int j, int mod
     return sv(G, P, SC, i, j, mode) / GRAV;
 }
 
+// dz_c and the equation-of-state passes of riem_solver_c run over the
+// half-step cells i, j in [-1, n] flattened row by row (one thread per
+// column, 256 per block, grid x ceil((n + 2)^2 / 256) per tile): with
+// wavefronts aligned to the interior origin a row of n + 2 columns takes
+// ceil((n + 2) / 64) + 1 wavefronts (four at C192, two of them a third full),
+// and these walks are bound by their arithmetic, which a wavefront issues
+// whatever its active lanes.  A flattened wavefront covers at most two row
+// segments.  (The two light passes of the solve are bound by memory and keep
+// the aligned rows.)
+inline __host__ __device__ int sim1c_flat_blocks(int n) { return ((n + 2) * (n + 2) + 255) / 256; }
+
 // dz_c: half-step interface heights by first-order upwind transport of the
 // interface heights with layer-averaged area fluxes (top interface: top
 // layer), advective form, surface fixed; output the half-step thicknesses.
@@ -935,9 +946,10 @@ template <class B>
 DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, const B *ax,
                       const B *ay, double *delzc)
 {
-    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
-    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
-    if (i < ilo || i > ihi || j > jhi) return;
+    const int w = G.n + 2, p = (int)(bk.x * blockDim.x + threadIdx.x);
+    if (p >= w * w) return;
+    const int j = -1 + p / w, i = -1 + p % w;
+    (void)ib; (void)ilo; (void)ihi; (void)jlo; (void)jhi;
     int n = G.n, nz = G.nz, t = bk.z;
     if (!((i >= 0 && i < n) || (j >= 0 && j < n))) return;
     double area = AT(MP(M, M_AREA), i, j);
@@ -1046,9 +1058,17 @@ DEVI void k_sim1(KARGS, Geo G, double dt, double beta, double ptop, const B *dpi
                                               double *wnv, TW *w_out, double *delz_out,
                                               double *pfull, double *phi, int need_cross)
 {
-    int i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
-    int j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
-    if (i < ilo || i > ihi || j > jhi) return;
+    int i, j;
+    if constexpr (SITE == 0 && (PASS == 1 || PASS == 3)) {
+        const int w = G.n + 2, p = (int)(bk.x * blockDim.x + threadIdx.x);
+        if (p >= w * w) return;
+        j = -1 + p / w;
+        i = -1 + p % w;
+    } else {
+        i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+        j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+        if (i < ilo || i > ihi || j > jhi) return;
+    }
     int n = G.n, nz = G.nz, t = bk.z;
     if (need_cross && !((i >= 0 && i < n) || (j >= 0 && j < n))) return;
     const double kap = RDGAS / CP_AIR, gam = 1.0 / (1.0 - kap), rgam = 1.0 / gam;
@@ -1934,7 +1954,20 @@ template <class B, int ORD>
 DEVI void k_dsw_omke(KARGS, Geo G, Mets<B> M, B bdt, B d2, B dd, B damin, const B *u, const B *v,
                            const B *ut, const B *vt, const B *hd, B hc, B *om, B *ke)
 {
-    KBEGIN(G.nz);
+    int i, j;
+    if constexpr (sizeof(B) == 4) {
+        // FP32 (bound by its arithmetic): launched over the range flattened
+        // by rows, so that no wavefront is mostly idle at the range's ends
+        const int w = ihi - ilo + 1, p = (int)(bk.x * blockDim.x + threadIdx.x);
+        if (p >= w * (jhi - jlo + 1)) return;
+        j = jlo + p / w;
+        i = ilo + p % w;
+    } else {
+        i = ib + (int)(bk.x * blockDim.x + threadIdx.x);
+        j = jlo + (int)(bk.y * blockDim.y + threadIdx.y);
+        if (i < ilo || i > ihi || j > jhi) return;
+    }
+    const int t = (int)bk.z / G.nz, k = (int)bk.z % G.nz;
     int n = G.n;
     long o = pidx(G, G.nz, t, k);
     const B *U = u + o, *V = v + o;
@@ -2869,11 +2902,12 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         }
         STOP(2);
         // dz_c + riem_solver_c on the half-step cells
-        launch2d(k_dzc<B>, -1, n, -1, n, T, st, G, Md, (const double *)delz, phis, (const B *)W.ax,
-                 (const B *)W.ay, W.delzc);
+        launch_fn<k_dzc<B>>("k_dzc<B>", dim3((unsigned)sim1c_flat_blocks(n), 1, (unsigned)T), dim3(256), st, 0, -1, n,
+                            -1, n, G, Md, (const double *)delz, phis, (const B *)W.ax, (const B *)W.ay, W.delzc);
+        const dim3 fgrd((unsigned)sim1c_flat_blocks(n), 1, (unsigned)T);
         sim1_pass1(g, qvp != nullptr, [&](auto offc, auto ppo, auto moist) {
-            launch2d_fn<k_sim1<B, B, 1, 0, decltype(offc)::value, decltype(ppo)::value, decltype(moist)::value>>(
-                "k_sim1_c.p1", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
+            launch_fn<k_sim1<B, B, 1, 0, decltype(offc)::value, decltype(ppo)::value, decltype(moist)::value>>(
+                "k_sim1_c.p1", fgrd, dim3(256), st, 0, -1, n, -1, n, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                 (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
                 (double *)nullptr, W.pkc, W.gz, 1);
         });
@@ -2881,8 +2915,8 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
                        (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3,
                        (B *)nullptr, (double *)nullptr, W.pkc, W.gz, 1);
         sim1_pass3(g, qvp != nullptr, [&](auto offc, auto moist) {
-            launch2d_fn<k_sim1<B, B, 3, 0, decltype(offc)::value, 2, decltype(moist)::value>>(
-                "k_sim1_c.p3", -1, n, -1, n, T, st, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
+            launch_fn<k_sim1<B, B, 3, 0, decltype(offc)::value, 2, decltype(moist)::value>>(
+                "k_sim1_c.p3", fgrd, dim3(256), st, 0, -1, n, -1, n, G, dt2, g->p.beta, g->p.ptop, (const B *)W.delpc,
                 (const B *)W.ptc, qvp, (const double *)W.delzc, (const B *)W.wc, phis, W.s1, W.s2, W.s3, (B *)nullptr,
                 (double *)nullptr, W.pkc, W.gz, 1);
         });
@@ -2932,10 +2966,16 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         }
         const bool eppm = g->p.edge_ppm && g->p.kind == FV3_GRID_CUBED_SPHERE;
         auto omke = [&](auto lim) {
-            launch2d_sh<k_dsw_omke<B, decltype(lim)::value>>(
-                "k_dsw_omke<B>", (sizeof(B) == 8 ? Shape{16, 16} : SH_DEFAULT), -3, n + 2, -3, n + 2, P, st, G, M,
-                (B)bdt, (B)g->p.d2_bg, (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v,
-                (const B *)W.ut, (const B *)W.vt, (const B *)hd, (B)hc, W.om, W.ke);
+            if constexpr (sizeof(B) == 4)
+                launch_fn<k_dsw_omke<B, decltype(lim)::value>>(
+                    "k_dsw_omke<B>", dim3((unsigned)(((n + 6) * (n + 6) + 255) / 256), 1, (unsigned)P), dim3(256), st,
+                    0, -3, n + 2, -3, n + 2, G, M, (B)bdt, (B)g->p.d2_bg, (B)(g->p.dddmp * bdt), (B)g->da_min,
+                    (const B *)u, (const B *)v, (const B *)W.ut, (const B *)W.vt, (const B *)hd, (B)hc, W.om, W.ke);
+            else
+                launch2d_sh<k_dsw_omke<B, decltype(lim)::value>>(
+                    "k_dsw_omke<B>", Shape{16, 16}, -3, n + 2, -3, n + 2, P, st, G, M, (B)bdt, (B)g->p.d2_bg,
+                    (B)(g->p.dddmp * bdt), (B)g->da_min, (const B *)u, (const B *)v, (const B *)W.ut,
+                    (const B *)W.vt, (const B *)hd, (B)hc, W.om, W.ke);
         };
         if (g->p.hord == 6) omke(std::integral_constant<int, 6>{});
         else if (g->p.hord == 5) omke(std::integral_constant<int, 5>{});

@@ -99,7 +99,7 @@ def test_cube_member_and_oracle(fv3, orc):
             b = os_[k][..., H:H + nj, H:H + ni]
             e = float(np.abs(a - b).max() / np.abs(b).max())
             print(f"member {q} {k}: {e:.2e}", flush=True)
-            assert e <= (1e-10 if k == "w" else 1e-11), (q, k, e)
+            assert e <= (3e-11 if k == "w" else 1e-11), (q, k, e)
 
 
 def test_graph_replays_match_eager(fv3):
