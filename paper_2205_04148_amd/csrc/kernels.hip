@@ -769,7 +769,10 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
     };
 
     // 1. A-grid winds and cell scalars (corner cells are not stored)
-    for (int e = tid; e < HA * WA; e += CNT) {
+#pragma unroll
+    for (int m = 0; m < (HA * WA + CNT - 1) / CNT; m++) {
+        const int e = tid + m * CNT;
+        if (e >= HA * WA) break;
         int r = e / WA, c = e - r * WA;
         int i = i0 - 3 + c, j = j0 - 3 + r;
         B a = 0, b = 0;
@@ -780,7 +783,10 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         sUA[e] = a;
         sVA[e] = b;
     }
-    for (int e = tid; e < HD * WD; e += CNT) {
+#pragma unroll
+    for (int m = 0; m < (HD * WD + CNT - 1) / CNT; m++) {
+        const int e = tid + m * CNT;
+        if (e >= HD * WD) break;
         int r = e / WD, c = e - r * WD;
         int i = i0 - 2 + c, j = j0 - 2 + r;
         B a = 0, b = 0, c2 = 0;
@@ -793,20 +799,46 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         sPT[e] = b;
         sW[e] = c2;
     }
+    // The global operands of each later phase (D-grid winds at the faces and
+    // 2-D metric terms) are loaded one phase ahead, before the barrier that
+    // ends the previous phase, so that their latency overlaps it.
+    auto xface = [&](int i, int j) {
+        return (j >= -1 && j <= n) && ((j >= 0 && j < n) ? (i >= -1 && i <= n + 1) : (i >= 0 && i <= n));
+    };
+    auto yface = [&](int i, int j) {
+        return (i >= -1 && i <= n) && ((i >= 0 && i < n) ? (j >= -1 && j <= n + 1) : (j >= 0 && j <= n));
+    };
+    constexpr int N2 = (HF * WF + CNT - 1) / CNT, N3 = (HK * WK + CNT - 1) / CNT, N4 = (CTX * CTY + CNT - 1) / CNT;
+    B q2V[N2], q2cu[N2], q2su[N2], q2dy[N2], q2U[N2], q2cv[N2], q2sv[N2], q2dx[N2];
+#pragma unroll
+    for (int m = 0; m < N2; m++) {
+        const int e = tid + m * CNT, r = e / WF, c = e - r * WF;
+        const int i = i0 - 1 + c, j = j0 - 1 + r;
+        const bool in = e < HF * WF, xf = in && xface(i, j), yf = in && yface(i, j);
+        q2V[m] = xf ? AT(V, i, j) : (B)0;
+        q2cu[m] = xf ? AT(MP(M, M_COS_U), i, j) : (B)0;
+        q2su[m] = xf ? AT(MP(M, M_RSIN_U), i, j) : (B)0;
+        q2dy[m] = xf ? AT(MP(M, M_DY), i, j) : (B)0;
+        q2U[m] = yf ? AT(U, i, j) : (B)0;
+        q2cv[m] = yf ? AT(MP(M, M_COS_V), i, j) : (B)0;
+        q2sv[m] = yf ? AT(MP(M, M_RSIN_V), i, j) : (B)0;
+        q2dx[m] = yf ? AT(MP(M, M_DX), i, j) : (B)0;
+    }
     __syncthreads();
     // 2. C-grid faces: winds before the update, area fluxes, upwind fluxes
-    for (int e = tid; e < HF * WF; e += CNT) {
+#pragma unroll
+    for (int m = 0; m < (HF * WF + CNT - 1) / CNT; m++) {
+        const int e = tid + m * CNT;
+        if (e >= HF * WF) break;
         int r = e / WF, c = e - r * WF;
         int i = i0 - 1 + c, j = j0 - 1 + r;
         bool own = i >= i0 && i < i0 + CTX && j >= j0 && j < j0 + CTY;
-        bool xf = (j >= -1 && j <= n) && ((j >= 0 && j < n) ? (i >= -1 && i <= n + 1) : (i >= 0 && i <= n));
-        bool yf = (i >= -1 && i <= n) && ((i >= 0 && i < n) ? (j >= -1 && j <= n + 1) : (j >= 0 && j <= n));
+        bool xf = xface(i, j), yf = yface(i, j);
         B uc0 = 0, fm = 0, fp = 0, fw = 0;
         if (xf) {
             B a = UAx(i - 2, j, 0), b = UAx(i - 1, j, 0), c1 = UAx(i, j, 0), d = UAx(i + 1, j, 0);
             uc0 = face_pt(a, b, c1, d, i, n, EI && j >= 0 && j < n);
-            B fl = dt2 * (uc0 - AT(V, i, j) * AT(MP(M, M_COS_U), i, j)) * AT(MP(M, M_RSIN_U), i, j) *
-                   AT(MP(M, M_DY), i, j);
+            B fl = dt2 * (uc0 - q2V[m] * q2cu[m]) * q2su[m] * q2dy[m];
             int up = fl > 0 ? i - 1 : i;
             fm = fl * cv(sD, D, up, j, 0);
             fp = fm * cv(sPT, PT, up, j, 0);
@@ -821,8 +853,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         if (yf) {
             B a = VAy(i, j - 2, 1), b = VAy(i, j - 1, 1), c1 = VAy(i, j, 1), d = VAy(i, j + 1, 1);
             vc0 = face_pt(a, b, c1, d, j, n, EI && i >= 0 && i < n);
-            B fl = dt2 * (vc0 - AT(U, i, j) * AT(MP(M, M_COS_V), i, j)) * AT(MP(M, M_RSIN_V), i, j) *
-                   AT(MP(M, M_DX), i, j);
+            B fl = dt2 * (vc0 - q2U[m] * q2cv[m]) * q2sv[m] * q2dx[m];
             int up = fl > 0 ? j - 1 : j;
             gm = fl * cv(sD, D, i, up, 1);
             gp = gm * cv(sPT, PT, i, up, 1);
@@ -834,22 +865,45 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         sGp[e] = gp;
         sGw[e] = gw;
     }
+    B q3rs2[N3], q3ca[N3], q3ra[N3], q3dxs[N3], q3dxn[N3], q3dyw[N3], q3dye[N3], q3fb[N3], q3rac[N3];
+#pragma unroll
+    for (int m = 0; m < N3; m++) {
+        const int e = tid + m * CNT, r = e / WK, c = e - r * WK;
+        const bool in = e < HK * WK;
+        // cell (i0 - 1 + c, j0 - 1 + r) of the half-step update, corner (i0 + c, j0 + r)
+        const int i = i0 - 1 + c, j = j0 - 1 + r, ic = i0 + c, jc = j0 + r;
+        const bool cross = in && i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
+        const bool mine = cross && i >= i0 && j >= j0;
+        const bool corner = in && ic >= 0 && ic <= n && jc >= 0 && jc <= n;
+        q3rs2[m] = cross ? AT(MP(M, M_RSIN2_A), i, j) : (B)0;
+        q3ca[m] = cross ? AT(MP(M, M_COS_A), i, j) : (B)0;
+        q3ra[m] = mine ? AT(MP(M, M_RAREA), i, j) : (B)0;
+        q3dxs[m] = corner ? AT(MP(M, M_DXC), ic, jc - 1) : (B)0;
+        q3dxn[m] = corner ? AT(MP(M, M_DXC), ic, jc) : (B)0;
+        q3dyw[m] = corner ? AT(MP(M, M_DYC), ic - 1, jc) : (B)0;
+        q3dye[m] = corner ? AT(MP(M, M_DYC), ic, jc) : (B)0;
+        q3fb[m] = corner ? AT(MP(M, M_FB), ic, jc) : (B)0;
+        q3rac[m] = corner ? AT(MP(M, M_RAREA_C), ic, jc) : (B)0;
+    }
     __syncthreads();
     // 3. half-step cells (own points) and kinetic energy (one ring wider);
     //    absolute vorticity at the corners
-    for (int e = tid; e < HK * WK; e += CNT) {
+#pragma unroll
+    for (int m = 0; m < (HK * WK + CNT - 1) / CNT; m++) {
+        const int e = tid + m * CNT;
+        if (e >= HK * WK) break;
         int r = e / WK, c = e - r * WK;
         int i = i0 - 1 + c, j = j0 - 1 + r;
         bool cross = i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
         B kev = 0;
         if (cross) {
-            B rs2 = AT(MP(M, M_RSIN2_A), i, j), ca = AT(MP(M, M_COS_A), i, j);
+            B rs2 = q3rs2[m], ca = q3ca[m];
             B a = sUA[aA(i, j)], b = sVA[aA(i, j)];
             B uu = (a - b * ca) * rs2, vv = (b - a * ca) * rs2;
             kev = (B)0.5 * dt2 * (uu * (uu > 0 ? sUC[aF(i, j)] : sUC[aF(i + 1, j)]) +
                                   vv * (vv > 0 ? sVC[aF(i, j)] : sVC[aF(i, j + 1)]));
             if (i >= i0 && j >= j0) {
-                B rar = AT(MP(M, M_RAREA), i, j);
+                B rar = q3ra[m];
                 B dp = sD[aD(i, j)];
                 B dc = dp + (sFm[aF(i, j)] - sFm[aF(i + 1, j)] + sGm[aF(i, j)] - sGm[aF(i, j + 1)]) * rar;
                 B rdc = (B)1 / dc;
@@ -862,7 +916,10 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         }
         sKE[e] = kev;
     }
-    for (int e = tid; e < HK * WK; e += CNT) {
+#pragma unroll
+    for (int m = 0; m < (HK * WK + CNT - 1) / CNT; m++) {
+        const int e = tid + m * CNT;
+        if (e >= HK * WK) break;
         int r = e / WK, c = e - r * WK;
         int i = i0 + c, j = j0 + r;
         B vo = 0;
@@ -872,28 +929,47 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
                 if (j == 0) ws = 0.5; else wn = 0.5;
                 if (i == 0) ww = 0.5; else we = 0.5;
             }
-            B circ = ws * sUC[aF(i, j - 1)] * AT(MP(M, M_DXC), i, j - 1) - wn * sUC[aF(i, j)] * AT(MP(M, M_DXC), i, j) -
-                     ww * sVC[aF(i - 1, j)] * AT(MP(M, M_DYC), i - 1, j) + we * sVC[aF(i, j)] * AT(MP(M, M_DYC), i, j);
-            vo = AT(MP(M, M_FB), i, j) + circ * AT(MP(M, M_RAREA_C), i, j);
+            B circ = ws * sUC[aF(i, j - 1)] * q3dxs[m] - wn * sUC[aF(i, j)] * q3dxn[m] -
+                     ww * sVC[aF(i - 1, j)] * q3dyw[m] + we * sVC[aF(i, j)] * q3dye[m];
+            vo = q3fb[m] + circ * q3rac[m];
         }
         sVO[e] = vo;
     }
+    B q4V[N4], q4cu[N4], q4su[N4], q4rdx[N4], q4U[N4], q4cv[N4], q4sv[N4], q4rdy[N4];
+#pragma unroll
+    for (int m = 0; m < N4; m++) {
+        const int e = tid + m * CNT, r = e / CTX, c = e - r * CTX;
+        const int i = i0 + c, j = j0 + r;
+        const bool in = e < CTX * CTY;
+        const bool fu = in && i >= 0 && i <= n && j >= 0 && j < n, fv = in && i >= 0 && i < n && j >= 0 && j <= n;
+        q4V[m] = fu ? AT(V, i, j) : (B)0;
+        q4cu[m] = fu ? AT(MP(M, M_COS_U), i, j) : (B)0;
+        q4su[m] = fu ? AT(MP(M, M_RSIN_U), i, j) : (B)0;
+        q4rdx[m] = fu ? AT(MP(M, M_RDXC), i, j) : (B)0;
+        q4U[m] = fv ? AT(U, i, j) : (B)0;
+        q4cv[m] = fv ? AT(MP(M, M_COS_V), i, j) : (B)0;
+        q4sv[m] = fv ? AT(MP(M, M_RSIN_V), i, j) : (B)0;
+        q4rdy[m] = fv ? AT(MP(M, M_RDYC), i, j) : (B)0;
+    }
     __syncthreads();
     // 4. C-grid wind update on the interior faces of the own points
-    for (int e = tid; e < CTX * CTY; e += CNT) {
+#pragma unroll
+    for (int m = 0; m < (CTX * CTY + CNT - 1) / CNT; m++) {
+        const int e = tid + m * CNT;
+        if (e >= CTX * CTY) break;
         int r = e / CTX, c = e - r * CTX;
         int i = i0 + c, j = j0 + r;
         if (i >= 0 && i <= n && j >= 0 && j < n) {
             B u0 = sUC[aF(i, j)];
-            B fy1 = dt2 * (AT(V, i, j) - u0 * AT(MP(M, M_COS_U), i, j)) * AT(MP(M, M_RSIN_U), i, j);
+            B fy1 = dt2 * (q4V[m] - u0 * q4cu[m]) * q4su[m];
             B vt = fy1 > 0 ? sVO[aV(i, j)] : sVO[aV(i, j + 1)];
-            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * AT(MP(M, M_RDXC), i, j);
+            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * q4rdx[m];
         }
         if (i >= 0 && i < n && j >= 0 && j <= n) {
             B v0 = sVC[aF(i, j)];
-            B fx1 = dt2 * (AT(U, i, j) - v0 * AT(MP(M, M_COS_V), i, j)) * AT(MP(M, M_RSIN_V), i, j);
+            B fx1 = dt2 * (q4U[m] - v0 * q4cv[m]) * q4sv[m];
             B vt = fx1 > 0 ? sVO[aV(i, j)] : sVO[aV(i + 1, j)];
-            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * AT(MP(M, M_RDYC), i, j);
+            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * q4rdy[m];
         }
     }
 }
@@ -1552,7 +1628,7 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
     const unsigned hb = 3u * (unsigned)P + 3u;   // rebase of the staging windows
     const T *Q = A.q + pidx(G, A.Lq, t, k);
     const long oc = pidx(G, A.Lc, t, k);
-    const int avg = A.iface && k > 0;
+    const int avg = EPI == EPI_ADV && A.iface && k > 0;   // set only for the interface heights
     const long ob = avg ? pidx(G, A.Lc, t, k - 1) : oc;
     const T *AR = A.area + G.off0 + (long)t * G.lev;
     const T *DXA = EDGE ? A.dxa + G.off0 + (long)t * G.lev : nullptr;
@@ -1564,20 +1640,38 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
     using PT = typename std::conditional<EPI == EPI_TRACER, double, T>::type;
 
     // 0. per-thread prefetch of the global operands of phases 4 and 5, in
-    //    their storage types
+    //    their storage types (with the delp epilogue also the old values of
+    //    the flux accumulators that phase 4 adds to: their loads would
+    //    otherwise wait behind the previous face's stores)
     M wx[N4X], wy[N4Y];
+    constexpr int NAX = EPI == EPI_DELP ? N4X : 1, NAY = EPI == EPI_DELP ? N4Y : 1;
+    double amx[NAX], amy[NAY];
+    C acx[NAX], acy[NAY];
     PT pa[N5], pb[N5];
 #pragma unroll
     for (int m = 0; m < N4X; m++) {
         int e = tid + m * FNT, r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 + r;
-        wx[m] = (MX && e < FTY * XW && i <= n && j < n) ? ldo(MX, (unsigned)(j * P + i)) : (M)0;
+        const bool in = e < FTY * XW && i <= n && j < n;
+        wx[m] = (MX && in) ? ldo(MX, (unsigned)(j * P + i)) : (M)0;
+        if constexpr (EPI == EPI_DELP) {
+            // the faces phase 4 writes: c < FTX, or the last face i == n
+            const bool own = in && (c < FTX || i == n) && !(EDGE && edge_face(i, n));
+            amx[m] = own ? ldo(A.mfx + oc, (unsigned)(j * P + i)) : 0.0;
+            acx[m] = own ? ldo(A.cxa + oc, (unsigned)(j * P + i)) : (C)0;
+        }
     }
 #pragma unroll
     for (int m = 0; m < N4Y; m++) {
         int e = tid + m * FNT, r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 + r;
-        wy[m] = (MY && e < YH * FTX && i < n && j <= n) ? ldo(MY, (unsigned)(j * P + i)) : (M)0;
+        const bool in = e < YH * FTX && i < n && j <= n;
+        wy[m] = (MY && in) ? ldo(MY, (unsigned)(j * P + i)) : (M)0;
+        if constexpr (EPI == EPI_DELP) {
+            const bool own = in && (r < FTY || j == n) && !(EDGE && edge_face(j, n));
+            amy[m] = own ? ldo(A.mfy + oc, (unsigned)(j * P + i)) : 0.0;
+            acy[m] = own ? ldo(A.cya + oc, (unsigned)(j * P + i)) : (C)0;
+        }
     }
 #pragma unroll
     for (int m = 0; m < N5; m++) {
@@ -1600,52 +1694,91 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
         }
     }
     // 1. stage the field (both sweep views), the area, the Courant numbers and
-    //    the area fluxes of the tile and its halo
-    for (int e = tid; e < QH * QW; e += FNT) {
-        int r = e / QW, c = e - r * QW;
-        int i = i0 - 3 + c, j = j0 - 3 + r;
-        T vx = 0, vy = 0, ar = 0;
-        if (i <= n + 2 && j <= n + 2) {
-            if (CORNER && in_corner(G, SC, i, j)) {
-                vx = sv(G, Q, SC, i, j, 0);
-                vy = sv(G, Q, SC, i, j, 1);
-            } else {
+    //    the area fluxes of the tile and its halo: every load of the thread
+    //    is issued before the first LDS write, so that they are all in flight
+    //    together
+    {
+        constexpr int NSQ = (QH * QW + FNT - 1) / FNT, NSY = (YH * YW + FNT - 1) / FNT;
+        constexpr int NSX = (XH * XW + FNT - 1) / FNT;
+        T qx[NSQ], qy[NSQ], qa[NSQ], cy[NSY], fy[NSY], cx[NSX], fx[NSX];
+#pragma unroll
+        for (int m = 0; m < NSQ; m++) {
+            const int e = tid + m * FNT, r = e / QW, c = e - r * QW;
+            const int i = i0 - 3 + c, j = j0 - 3 + r;
+            T vx = 0, vy = 0, ar = 0;
+            if (e < QH * QW && i <= n + 2 && j <= n + 2) {
+                if (CORNER && in_corner(G, SC, i, j)) {
+                    vx = sv(G, Q, SC, i, j, 0);
+                    vy = sv(G, Q, SC, i, j, 1);
+                } else {
+                    const unsigned u = (unsigned)((j + 3) * P + (i + 3));
+                    vx = vy = ldo(Qh, u);
+                    ar = ldo(ARh, u);
+                }
+            }
+            qx[m] = vx;
+            qy[m] = vy;
+            qa[m] = ar;
+        }
+#pragma unroll
+        for (int m = 0; m < NSY; m++) {
+            const int e = tid + m * FNT, r = e / YW, c = e - r * YW;
+            const int i = i0 - 3 + c, j = j0 + r;
+            T cr = 0, fl = 0;
+            if (e < YH * YW && i <= n + 2 && j <= n) {
                 const unsigned u = (unsigned)((j + 3) * P + (i + 3));
-                vx = vy = ldo(Qh, u);
-                ar = ldo(ARh, u);
+                cr = ccr<T>(cryh, cry0h, u, avg);
+                fl = ccr<T>(yfxh, yfx0h, u, avg);
+            }
+            cy[m] = cr;
+            fy[m] = fl;
+        }
+#pragma unroll
+        for (int m = 0; m < NSX; m++) {
+            const int e = tid + m * FNT, r = e / XW, c = e - r * XW;
+            const int i = i0 + c, j = j0 - 3 + r;
+            T cr = 0, fl = 0;
+            if (e < XH * XW && i <= n && j <= n + 2) {
+                const unsigned u = (unsigned)((j + 3) * P + (i + 3));
+                cr = ccr<T>(crxh, crx0h, u, avg);
+                fl = ccr<T>(xfxh, xfx0h, u, avg);
+            }
+            cx[m] = cr;
+            fx[m] = fl;
+        }
+#pragma unroll
+        for (int m = 0; m < NSQ; m++) {
+            const int e = tid + m * FNT;
+            if (e < QH * QW) {
+                sQ[e] = qx[m];
+                sQy[e] = qy[m];
+                sAR[e] = qa[m];
             }
         }
-        sQ[e] = vx;
-        sQy[e] = vy;
-        sAR[e] = ar;
-    }
-    for (int e = tid; e < YH * YW; e += FNT) {
-        int r = e / YW, c = e - r * YW;
-        int i = i0 - 3 + c, j = j0 + r;
-        T cr = 0, fl = 0;
-        if (i <= n + 2 && j <= n) {
-            const unsigned u = (unsigned)((j + 3) * P + (i + 3));
-            cr = ccr<T>(cryh, cry0h, u, avg);
-            fl = ccr<T>(yfxh, yfx0h, u, avg);
+#pragma unroll
+        for (int m = 0; m < NSY; m++) {
+            const int e = tid + m * FNT;
+            if (e < YH * YW) {
+                sCY[e] = cy[m];
+                sYF[e] = fy[m];
+            }
         }
-        sCY[e] = cr;
-        sYF[e] = fl;
-    }
-    for (int e = tid; e < XH * XW; e += FNT) {
-        int r = e / XW, c = e - r * XW;
-        int i = i0 + c, j = j0 - 3 + r;
-        T cr = 0, fl = 0;
-        if (i <= n && j <= n + 2) {
-            const unsigned u = (unsigned)((j + 3) * P + (i + 3));
-            cr = ccr<T>(crxh, crx0h, u, avg);
-            fl = ccr<T>(xfxh, xfx0h, u, avg);
+#pragma unroll
+        for (int m = 0; m < NSX; m++) {
+            const int e = tid + m * FNT;
+            if (e < XH * XW) {
+                sCX[e] = cx[m];
+                sXF[e] = fx[m];
+            }
         }
-        sCX[e] = cr;
-        sXF[e] = fl;
     }
     __syncthreads();
-    // 2. outer fluxes of the field
-    for (int e = tid; e < YH * YW; e += FNT) {
+    // 2. outer fluxes of the field (unrolled: the LDS reads of the next
+    //    faces overlap the arithmetic of the current one)
+#pragma unroll
+    for (int m = 0; m < (YH * YW + FNT - 1) / FNT; m++) {
+        const int e = tid + m * FNT;
+        if (e >= YH * YW) break;
         int r = e / YW, c = e - r * YW;
         int i = i0 - 3 + c, j = j0 + r;
         T f = 0;
@@ -1655,7 +1788,10 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
         }
         sFy[e] = f;
     }
-    for (int e = tid; e < XH * XW; e += FNT) {
+#pragma unroll
+    for (int m = 0; m < (XH * XW + FNT - 1) / FNT; m++) {
+        const int e = tid + m * FNT;
+        if (e >= XH * XW) break;
         int r = e / XW, c = e - r * XW;
         int i = i0 + c, j = j0 - 3 + r;
         T f = 0;
@@ -1689,7 +1825,10 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
     }
     __syncthreads();
     // 3. inner advective half updates
-    for (int e = tid; e < FTY * QW; e += FNT) {
+#pragma unroll
+    for (int m = 0; m < (FTY * QW + FNT - 1) / FNT; m++) {
+        const int e = tid + m * FNT;
+        if (e >= FTY * QW) break;
         int r = e / QW, c = e - r * QW;
         int i = i0 - 3 + c, j = j0 + r;
         T v = 0;
@@ -1700,7 +1839,10 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
         }
         sQi[e] = v;
     }
-    for (int e = tid; e < QH * FTX; e += FNT) {
+#pragma unroll
+    for (int m = 0; m < (QH * FTX + FNT - 1) / FNT; m++) {
+        const int e = tid + m * FNT;
+        if (e >= QH * FTX) break;
         int r = e / FTX, c = e - r * FTX;
         int i = i0 + c, j = j0 - 3 + r;
         T v = 0;
@@ -1713,25 +1855,26 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
     }
     __syncthreads();
     // 4. final fluxes (in place over the outer fluxes)
-    auto put_x = [&](int i, int c, int fi, int s, T fx, T wgt) {
+    // am, ac: the old accumulator values of the face (delp epilogue)
+    auto put_x = [&](int i, int c, int fi, int s, T fx, T wgt, double am, C ac) {
         const T F = (T)0.5 * (fx + sFx[s]) * wgt;
         sFx[s] = F;
         if (c < FTX || i == n) {
             if (A.FX && (!A.edges_only || i == 0 || i == n)) sto(A.FX + oc, (unsigned)fi, F);
             if (EPI == EPI_DELP) {
-                sto(A.mfx + oc, (unsigned)fi, ldo(A.mfx + oc, (unsigned)fi) + (double)F);
-                sto(A.cxa + oc, (unsigned)fi, (C)(ldo(A.cxa + oc, (unsigned)fi) + (C)sCX[s]));
+                sto(A.mfx + oc, (unsigned)fi, am + (double)F);
+                sto(A.cxa + oc, (unsigned)fi, (C)(ac + (C)sCX[s]));
             }
         }
     };
-    auto put_y = [&](int j, int r, int fi, int s, T fy, T wgt) {
+    auto put_y = [&](int j, int r, int fi, int s, T fy, T wgt, double am, C ac) {
         const T F = (T)0.5 * (fy + sFy[s]) * wgt;
         sFy[s] = F;
         if (r < FTY || j == n) {
             if (A.FY && (!A.edges_only || j == 0 || j == n)) sto(A.FY + oc, (unsigned)fi, F);
             if (EPI == EPI_DELP) {
-                sto(A.mfy + oc, (unsigned)fi, ldo(A.mfy + oc, (unsigned)fi) + (double)F);
-                sto(A.cya + oc, (unsigned)fi, (C)(ldo(A.cya + oc, (unsigned)fi) + (C)sCY[s]));
+                sto(A.mfy + oc, (unsigned)fi, am + (double)F);
+                sto(A.cya + oc, (unsigned)fi, (C)(ac + (C)sCY[s]));
             }
         }
     };
@@ -1744,7 +1887,8 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
         if (i <= n && j < n && !(EDGE && edge_face(i, n))) {
             const int s = (r + 3) * XW + c;
             T fx = ppm_lds<1, ORD>(sQi + r * QW + c, sCX[s]);
-            put_x(i, c, j * P + i, s, fx, A.mx ? (T)wx[m] : sXF[s]);
+            put_x(i, c, j * P + i, s, fx, A.mx ? (T)wx[m] : sXF[s], amx[EPI == EPI_DELP ? m : 0],
+                  acx[EPI == EPI_DELP ? m : 0]);
         }
     }
     if constexpr (EDGE) {
@@ -1756,7 +1900,9 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
             bool west;
             const int pe = edge_pe(i, n, west);
             T fx = ppm_edge<ORD>(sQi + r * QW + c, 1, DXA + j * P + i - 3, 1, sCX[s], pe, west);
-            put_x(i, c, fi, s, fx, MX ? (T)ldo(MX, (unsigned)fi) : sXF[s]);
+            const bool own = EPI == EPI_DELP && (c < FTX || i == n);
+            put_x(i, c, fi, s, fx, MX ? (T)ldo(MX, (unsigned)fi) : sXF[s],
+                  own ? ldo(A.mfx + oc, (unsigned)fi) : 0.0, own ? ldo(A.cxa + oc, (unsigned)fi) : (C)0);
         }
     }
 #pragma unroll
@@ -1768,7 +1914,8 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
         if (i < n && j <= n && !(EDGE && edge_face(j, n))) {
             const int s = r * YW + c + 3;
             T fy = ppm_lds<FTX, ORD>(sQj + r * FTX + c, sCY[s]);
-            put_y(j, r, j * P + i, s, fy, A.my ? (T)wy[m] : sYF[s]);
+            put_y(j, r, j * P + i, s, fy, A.my ? (T)wy[m] : sYF[s], amy[EPI == EPI_DELP ? m : 0],
+                  acy[EPI == EPI_DELP ? m : 0]);
         }
     }
     if constexpr (EDGE) {
@@ -1780,7 +1927,9 @@ DEVI void fvtp_body(Bk bk, const Geo &G, const FvArgs<T, C, M> &A, FvLds<T> &L)
             bool west;
             const int pe = edge_pe(j, n, west);
             T fy = ppm_edge<ORD>(sQj + r * FTX + c, FTX, DYA + (j - 3) * P + i, P, sCY[s], pe, west);
-            put_y(j, r, fi, s, fy, MY ? (T)ldo(MY, (unsigned)fi) : sYF[s]);
+            const bool own = EPI == EPI_DELP && (r < FTY || j == n);
+            put_y(j, r, fi, s, fy, MY ? (T)ldo(MY, (unsigned)fi) : sYF[s],
+                  own ? ldo(A.mfy + oc, (unsigned)fi) : 0.0, own ? ldo(A.cya + oc, (unsigned)fi) : (C)0);
         }
     }
     if constexpr (EPI == EPI_FLUX) return;
@@ -2282,13 +2431,15 @@ DEVI void k_delz_from_zh(KARGS, Geo G, const double *zn, const double *phis, dou
 // interpolation (inner pass along x with the x-sweep corner view; mean of
 // the three cells at a cube vertex) of pfull and phi at the layer's two
 // interfaces and of delp, staged through LDS, then the finite-volume
-// pressure gradient along each D-grid edge.  Block: NPX x NPY corners.
+// pressure gradient along each D-grid edge.  Block: NPX x NPY corners; 33
+// wide so that the n + 1 corner columns of C192 take 6 tiles (32 wide took 7,
+// the last with one column), 7 rows so that its faces fit 256 threads.
 // ====================================================================
 #ifndef FV3_NHP_TX
-#define FV3_NHP_TX 32
+#define FV3_NHP_TX 33
 #endif
 #ifndef FV3_NHP_TY
-#define FV3_NHP_TY 8
+#define FV3_NHP_TY 7
 #endif
 constexpr int NPX = FV3_NHP_TX, NPY = FV3_NHP_TY;   // nh_p_grad corner tile
 constexpr int NCW = NPX + 5, NCH = NPY + 5;   // cells i0-2..i0+NPX+2, j0-2..j0+NPY+2
@@ -2430,7 +2581,10 @@ DEVI void nh_corners(const Geo &G, int i0, int j0, NhLds &L, int s0, int s1, int
         }
     }
     __syncthreads();
-    for (int e = tid; e < NBC; e += 256) {
+#pragma unroll
+    for (int m = 0; m < (NBC + 255) / 256; m++) {
+        const int e = tid + m * 256;
+        if (e >= NBC) break;
         const int r = e / (NPX + 1), c = e - r * (NPX + 1);
         const int i = i0 + c, j = j0 + r;
         if (i > n || j > n || (CORNER && is_vertex(G, i, j))) continue;
