@@ -1091,7 +1091,7 @@ DEVI void k_dzc(KARGS, Geo G, MetD M, const double *delz, const double *phis, co
 // Every pass walks the column in groups of levels and issues the next
 // group's loads before computing the current one.
 #ifndef FV3_SIM1_SU
-#define FV3_SIM1_SU 1
+#define FV3_SIM1_SU 2
 #endif
 constexpr int SU = FV3_SIM1_SU;   // levels per prefetch group, passes 1 and 3
 constexpr int SU2 = 8;            // levels per prefetch group, passes 2 and 4

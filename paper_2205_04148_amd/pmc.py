@@ -120,7 +120,11 @@ def counters_main(a):
     SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (conflict cycles per LDS
     instruction), mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / SIMDs / duration in
     cycles, mfma_bf16_tflops from SQ_INSTS_VALU_MFMA_MOPS_BF16 (units of 512
-    FLOPs) over the duration at 2.4 GHz."""
+    FLOPs) over the duration at 2.4 GHz; wait_any_share, wait_inst_any_share,
+    wait_inst_lds_share = SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_WAIT_INST_LDS over
+    SQ_WAVE_CYCLES (share of the waves' resident cycles spent waiting for
+    outstanding memory or LDS results, for any instruction to issue, for an
+    LDS instruction to issue)."""
     dirs, out, workload = [a[0]] + a[3:], a[1], a[2]
     merged = collections.defaultdict(dict)
     for d in dirs:
@@ -145,6 +149,11 @@ def counters_main(a):
         if g and "SQ_INSTS_VALU_MFMA_MOPS_BF16" in m:
             # BF16 matrix FLOPs (the counter counts units of 512) per second
             m["mfma_bf16_tflops"] = m["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512 / (g / XCDS / 2.4e9) / 1e12
+        if m.get("SQ_WAVE_CYCLES"):
+            for c, k in (("SQ_WAIT_ANY", "wait_any_share"), ("SQ_WAIT_INST_ANY", "wait_inst_any_share"),
+                         ("SQ_WAIT_INST_LDS", "wait_inst_lds_share")):
+                if c in m:
+                    m[k] = m[c] / m["SQ_WAVE_CYCLES"]
         kern[name] = m
     doc = {"workload": workload, "kernel_source_sha256": source_sha256(), "kernels": kern}
     with open(out, "w") as fh:
