@@ -632,6 +632,11 @@ static void halo_pair(const fv3_grid *g, const Plan &p, T *fx, T *fy, int L, hip
 #define FV3_CSW_CTX 33
 #endif
 constexpr int CTX = FV3_CSW_CTX, CNT = 256;
+// layers per c_sw block (the block's 2-D metric terms stay in registers)
+#ifndef FV3_CSW_LEVELS
+#define FV3_CSW_LEVELS 4
+#endif
+constexpr int CSL = FV3_CSW_LEVELS;
 // tile rows per precision: the FP64 tile is shorter so that its LDS allows
 // five blocks per CU
 template <class B>
@@ -707,8 +712,73 @@ constexpr int csw_lds()
     return 2 * (CTY + 5) * (CTX + 5) + 3 * (CTY + 3) * (CTX + 3) + 8 * (CTY + 2) * (CTX + 2) + 2 * (CTY + 1) * (CTX + 1);
 }
 
+// The 2-D metric terms a c_sw thread uses in phases 2-4, the same on every
+// layer: loaded once per block into registers and kept for all its layers
+// (the same threads own the same points on every layer).
+template <class B>
+struct CswMet {
+    static constexpr int CTY = CswRows<B>::Y, HF = CTY + 2, WF = CTX + 2, HK = CTY + 1, WK = CTX + 1;
+    static constexpr int N2 = (HF * WF + CNT - 1) / CNT, N3 = (HK * WK + CNT - 1) / CNT, N4 = (CTX * CTY + CNT - 1) / CNT;
+    B cu2[N2], su2[N2], dy2[N2], cv2[N2], sv2[N2], dx2[N2];                            // C-grid faces
+    B rs2[N3], ca[N3], ra[N3], dxs[N3], dxn[N3], dyw[N3], dye[N3], fb[N3], rac[N3];    // cells, corners
+    B cu4[N4], su4[N4], rdx4[N4], cv4[N4], sv4[N4], rdy4[N4];                          // own faces
+};
+template <class B>
+DEVI void csw_metrics(const Geo &G, const Mets<B> &M, const int t, const int i0, const int j0, CswMet<B> &Q)
+{
+    using Q_ = CswMet<B>;
+    constexpr int CTY = Q_::CTY, HF = Q_::HF, WF = Q_::WF, HK = Q_::HK, WK = Q_::WK;
+    const int n = G.n, tid = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < Q_::N2; m++) {
+        const int e = tid + m * CNT, r = e / WF, c = e - r * WF;
+        const int i = i0 - 1 + c, j = j0 - 1 + r;
+        const bool in = e < HF * WF;
+        const bool xf = in && (j >= -1 && j <= n) && ((j >= 0 && j < n) ? (i >= -1 && i <= n + 1) : (i >= 0 && i <= n));
+        const bool yf = in && (i >= -1 && i <= n) && ((i >= 0 && i < n) ? (j >= -1 && j <= n + 1) : (j >= 0 && j <= n));
+        Q.cu2[m] = xf ? AT(MP(M, M_COS_U), i, j) : (B)0;
+        Q.su2[m] = xf ? AT(MP(M, M_RSIN_U), i, j) : (B)0;
+        Q.dy2[m] = xf ? AT(MP(M, M_DY), i, j) : (B)0;
+        Q.cv2[m] = yf ? AT(MP(M, M_COS_V), i, j) : (B)0;
+        Q.sv2[m] = yf ? AT(MP(M, M_RSIN_V), i, j) : (B)0;
+        Q.dx2[m] = yf ? AT(MP(M, M_DX), i, j) : (B)0;
+    }
+#pragma unroll
+    for (int m = 0; m < Q_::N3; m++) {
+        const int e = tid + m * CNT, r = e / WK, c = e - r * WK;
+        const bool in = e < HK * WK;
+        // cell (i0 - 1 + c, j0 - 1 + r) of the half-step update, corner (i0 + c, j0 + r)
+        const int i = i0 - 1 + c, j = j0 - 1 + r, ic = i0 + c, jc = j0 + r;
+        const bool cross = in && i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
+        const bool mine = cross && i >= i0 && j >= j0;
+        const bool corner = in && ic >= 0 && ic <= n && jc >= 0 && jc <= n;
+        Q.rs2[m] = cross ? AT(MP(M, M_RSIN2_A), i, j) : (B)0;
+        Q.ca[m] = cross ? AT(MP(M, M_COS_A), i, j) : (B)0;
+        Q.ra[m] = mine ? AT(MP(M, M_RAREA), i, j) : (B)0;
+        Q.dxs[m] = corner ? AT(MP(M, M_DXC), ic, jc - 1) : (B)0;
+        Q.dxn[m] = corner ? AT(MP(M, M_DXC), ic, jc) : (B)0;
+        Q.dyw[m] = corner ? AT(MP(M, M_DYC), ic - 1, jc) : (B)0;
+        Q.dye[m] = corner ? AT(MP(M, M_DYC), ic, jc) : (B)0;
+        Q.fb[m] = corner ? AT(MP(M, M_FB), ic, jc) : (B)0;
+        Q.rac[m] = corner ? AT(MP(M, M_RAREA_C), ic, jc) : (B)0;
+    }
+#pragma unroll
+    for (int m = 0; m < Q_::N4; m++) {
+        const int e = tid + m * CNT, r = e / CTX, c = e - r * CTX;
+        const int i = i0 + c, j = j0 + r;
+        const bool in = e < CTX * CTY;
+        const bool fu = in && i >= 0 && i <= n && j >= 0 && j < n, fv = in && i >= 0 && i < n && j >= 0 && j <= n;
+        Q.cu4[m] = fu ? AT(MP(M, M_COS_U), i, j) : (B)0;
+        Q.su4[m] = fu ? AT(MP(M, M_RSIN_U), i, j) : (B)0;
+        Q.rdx4[m] = fu ? AT(MP(M, M_RDXC), i, j) : (B)0;
+        Q.cv4[m] = fv ? AT(MP(M, M_COS_V), i, j) : (B)0;
+        Q.sv4[m] = fv ? AT(MP(M, M_RSIN_V), i, j) : (B)0;
+        Q.rdy4[m] = fv ? AT(MP(M, M_RDYC), i, j) : (B)0;
+    }
+}
+
 template <class B, bool CORNER, bool EI>
-DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Mets<B> &M, B dt2, const B *u,
+DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const CswMet<B> &Q, B dt2, const B *u,
                    const B *v, const B *delp, const B *pt, const B *w, B *uc, B *vc, B *delpc, B *ptc, B *wc,
                    B *ax, B *ay)
 {
@@ -722,7 +792,12 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
     B *sUC = sW + HD * WD, *sFm = sUC + HF * WF, *sFp = sFm + HF * WF, *sFw = sFp + HF * WF;
     B *sVC = sFw + HF * WF, *sGm = sVC + HF * WF, *sGp = sGm + HF * WF, *sGw = sGp + HF * WF;
     B *sKE = sGw + HF * WF, *sVO = sKE + HK * WK;
-    const int n = G.n, tid = threadIdx.x;
+    const int n = G.n;
+    // the thread index is made opaque per layer, so that the compiler does
+    // not hoist every layer-invariant index and address of the body out of
+    // the block's layer loop into registers (it then needed all 256)
+    int tid = threadIdx.x;
+    __asm__ volatile("" : "+v"(tid));
     const int i0 = -1 + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
     const long o = pidx(G, G.nz, t, k);
     const B *U = u + o, *V = v + o, *D = delp + o, *PT = pt + o, *Wf = w + o;
@@ -799,30 +874,24 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         sPT[e] = b;
         sW[e] = c2;
     }
-    // The global operands of each later phase (D-grid winds at the faces and
-    // 2-D metric terms) are loaded one phase ahead, before the barrier that
-    // ends the previous phase, so that their latency overlaps it.
+    // The D-grid winds at the faces of phases 2 and 4 are loaded one phase
+    // ahead, before the barrier that ends the previous phase (the 2-D metric
+    // terms of every phase are in registers for all layers of the block).
     auto xface = [&](int i, int j) {
         return (j >= -1 && j <= n) && ((j >= 0 && j < n) ? (i >= -1 && i <= n + 1) : (i >= 0 && i <= n));
     };
     auto yface = [&](int i, int j) {
         return (i >= -1 && i <= n) && ((i >= 0 && i < n) ? (j >= -1 && j <= n + 1) : (j >= 0 && j <= n));
     };
-    constexpr int N2 = (HF * WF + CNT - 1) / CNT, N3 = (HK * WK + CNT - 1) / CNT, N4 = (CTX * CTY + CNT - 1) / CNT;
-    B q2V[N2], q2cu[N2], q2su[N2], q2dy[N2], q2U[N2], q2cv[N2], q2sv[N2], q2dx[N2];
+    constexpr int N2 = CswMet<B>::N2, N4 = CswMet<B>::N4;
+    B q2V[N2], q2U[N2];
 #pragma unroll
     for (int m = 0; m < N2; m++) {
         const int e = tid + m * CNT, r = e / WF, c = e - r * WF;
         const int i = i0 - 1 + c, j = j0 - 1 + r;
         const bool in = e < HF * WF, xf = in && xface(i, j), yf = in && yface(i, j);
         q2V[m] = xf ? AT(V, i, j) : (B)0;
-        q2cu[m] = xf ? AT(MP(M, M_COS_U), i, j) : (B)0;
-        q2su[m] = xf ? AT(MP(M, M_RSIN_U), i, j) : (B)0;
-        q2dy[m] = xf ? AT(MP(M, M_DY), i, j) : (B)0;
         q2U[m] = yf ? AT(U, i, j) : (B)0;
-        q2cv[m] = yf ? AT(MP(M, M_COS_V), i, j) : (B)0;
-        q2sv[m] = yf ? AT(MP(M, M_RSIN_V), i, j) : (B)0;
-        q2dx[m] = yf ? AT(MP(M, M_DX), i, j) : (B)0;
     }
     __syncthreads();
     // 2. C-grid faces: winds before the update, area fluxes, upwind fluxes
@@ -838,7 +907,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         if (xf) {
             B a = UAx(i - 2, j, 0), b = UAx(i - 1, j, 0), c1 = UAx(i, j, 0), d = UAx(i + 1, j, 0);
             uc0 = face_pt(a, b, c1, d, i, n, EI && j >= 0 && j < n);
-            B fl = dt2 * (uc0 - q2V[m] * q2cu[m]) * q2su[m] * q2dy[m];
+            B fl = dt2 * (uc0 - q2V[m] * Q.cu2[m]) * Q.su2[m] * Q.dy2[m];
             int up = fl > 0 ? i - 1 : i;
             fm = fl * cv(sD, D, up, j, 0);
             fp = fm * cv(sPT, PT, up, j, 0);
@@ -853,7 +922,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         if (yf) {
             B a = VAy(i, j - 2, 1), b = VAy(i, j - 1, 1), c1 = VAy(i, j, 1), d = VAy(i, j + 1, 1);
             vc0 = face_pt(a, b, c1, d, j, n, EI && i >= 0 && i < n);
-            B fl = dt2 * (vc0 - q2U[m] * q2cv[m]) * q2sv[m] * q2dx[m];
+            B fl = dt2 * (vc0 - q2U[m] * Q.cv2[m]) * Q.sv2[m] * Q.dx2[m];
             int up = fl > 0 ? j - 1 : j;
             gm = fl * cv(sD, D, i, up, 1);
             gp = gm * cv(sPT, PT, i, up, 1);
@@ -864,26 +933,6 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         sGm[e] = gm;
         sGp[e] = gp;
         sGw[e] = gw;
-    }
-    B q3rs2[N3], q3ca[N3], q3ra[N3], q3dxs[N3], q3dxn[N3], q3dyw[N3], q3dye[N3], q3fb[N3], q3rac[N3];
-#pragma unroll
-    for (int m = 0; m < N3; m++) {
-        const int e = tid + m * CNT, r = e / WK, c = e - r * WK;
-        const bool in = e < HK * WK;
-        // cell (i0 - 1 + c, j0 - 1 + r) of the half-step update, corner (i0 + c, j0 + r)
-        const int i = i0 - 1 + c, j = j0 - 1 + r, ic = i0 + c, jc = j0 + r;
-        const bool cross = in && i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
-        const bool mine = cross && i >= i0 && j >= j0;
-        const bool corner = in && ic >= 0 && ic <= n && jc >= 0 && jc <= n;
-        q3rs2[m] = cross ? AT(MP(M, M_RSIN2_A), i, j) : (B)0;
-        q3ca[m] = cross ? AT(MP(M, M_COS_A), i, j) : (B)0;
-        q3ra[m] = mine ? AT(MP(M, M_RAREA), i, j) : (B)0;
-        q3dxs[m] = corner ? AT(MP(M, M_DXC), ic, jc - 1) : (B)0;
-        q3dxn[m] = corner ? AT(MP(M, M_DXC), ic, jc) : (B)0;
-        q3dyw[m] = corner ? AT(MP(M, M_DYC), ic - 1, jc) : (B)0;
-        q3dye[m] = corner ? AT(MP(M, M_DYC), ic, jc) : (B)0;
-        q3fb[m] = corner ? AT(MP(M, M_FB), ic, jc) : (B)0;
-        q3rac[m] = corner ? AT(MP(M, M_RAREA_C), ic, jc) : (B)0;
     }
     __syncthreads();
     // 3. half-step cells (own points) and kinetic energy (one ring wider);
@@ -897,13 +946,13 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         bool cross = i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
         B kev = 0;
         if (cross) {
-            B rs2 = q3rs2[m], ca = q3ca[m];
+            B rs2 = Q.rs2[m], ca = Q.ca[m];
             B a = sUA[aA(i, j)], b = sVA[aA(i, j)];
             B uu = (a - b * ca) * rs2, vv = (b - a * ca) * rs2;
             kev = (B)0.5 * dt2 * (uu * (uu > 0 ? sUC[aF(i, j)] : sUC[aF(i + 1, j)]) +
                                   vv * (vv > 0 ? sVC[aF(i, j)] : sVC[aF(i, j + 1)]));
             if (i >= i0 && j >= j0) {
-                B rar = q3ra[m];
+                B rar = Q.ra[m];
                 B dp = sD[aD(i, j)];
                 B dc = dp + (sFm[aF(i, j)] - sFm[aF(i + 1, j)] + sGm[aF(i, j)] - sGm[aF(i, j + 1)]) * rar;
                 B rdc = (B)1 / dc;
@@ -929,13 +978,13 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
                 if (j == 0) ws = 0.5; else wn = 0.5;
                 if (i == 0) ww = 0.5; else we = 0.5;
             }
-            B circ = ws * sUC[aF(i, j - 1)] * q3dxs[m] - wn * sUC[aF(i, j)] * q3dxn[m] -
-                     ww * sVC[aF(i - 1, j)] * q3dyw[m] + we * sVC[aF(i, j)] * q3dye[m];
-            vo = q3fb[m] + circ * q3rac[m];
+            B circ = ws * sUC[aF(i, j - 1)] * Q.dxs[m] - wn * sUC[aF(i, j)] * Q.dxn[m] -
+                     ww * sVC[aF(i - 1, j)] * Q.dyw[m] + we * sVC[aF(i, j)] * Q.dye[m];
+            vo = Q.fb[m] + circ * Q.rac[m];
         }
         sVO[e] = vo;
     }
-    B q4V[N4], q4cu[N4], q4su[N4], q4rdx[N4], q4U[N4], q4cv[N4], q4sv[N4], q4rdy[N4];
+    B q4V[N4], q4U[N4];
 #pragma unroll
     for (int m = 0; m < N4; m++) {
         const int e = tid + m * CNT, r = e / CTX, c = e - r * CTX;
@@ -943,13 +992,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         const bool in = e < CTX * CTY;
         const bool fu = in && i >= 0 && i <= n && j >= 0 && j < n, fv = in && i >= 0 && i < n && j >= 0 && j <= n;
         q4V[m] = fu ? AT(V, i, j) : (B)0;
-        q4cu[m] = fu ? AT(MP(M, M_COS_U), i, j) : (B)0;
-        q4su[m] = fu ? AT(MP(M, M_RSIN_U), i, j) : (B)0;
-        q4rdx[m] = fu ? AT(MP(M, M_RDXC), i, j) : (B)0;
         q4U[m] = fv ? AT(U, i, j) : (B)0;
-        q4cv[m] = fv ? AT(MP(M, M_COS_V), i, j) : (B)0;
-        q4sv[m] = fv ? AT(MP(M, M_RSIN_V), i, j) : (B)0;
-        q4rdy[m] = fv ? AT(MP(M, M_RDYC), i, j) : (B)0;
     }
     __syncthreads();
     // 4. C-grid wind update on the interior faces of the own points
@@ -961,15 +1004,15 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Me
         int i = i0 + c, j = j0 + r;
         if (i >= 0 && i <= n && j >= 0 && j < n) {
             B u0 = sUC[aF(i, j)];
-            B fy1 = dt2 * (q4V[m] - u0 * q4cu[m]) * q4su[m];
+            B fy1 = dt2 * (q4V[m] - u0 * Q.cu4[m]) * Q.su4[m];
             B vt = fy1 > 0 ? sVO[aV(i, j)] : sVO[aV(i, j + 1)];
-            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * q4rdx[m];
+            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * Q.rdx4[m];
         }
         if (i >= 0 && i < n && j >= 0 && j <= n) {
             B v0 = sVC[aF(i, j)];
-            B fx1 = dt2 * (q4U[m] - v0 * q4cv[m]) * q4sv[m];
+            B fx1 = dt2 * (q4U[m] - v0 * Q.cv4[m]) * Q.sv4[m];
             B vt = fx1 > 0 ? sVO[aV(i, j)] : sVO[aV(i + 1, j)];
-            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * q4rdy[m];
+            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * Q.rdy4[m];
         }
     }
 }
@@ -985,13 +1028,23 @@ DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B 
     const int i0 = -1 + (int)bk.x * CTX, j0 = -1 + (int)bk.y * CTY;
     const bool nx = i0 - 6 < 0 || i0 + CTX + 5 > n, ny = j0 - 6 < 0 || j0 + CTY + 5 > n;
     __shared__ B L[csw_lds<CTY>()];
-    const int t = (int)bk.z / G.nz, k = (int)bk.z % G.nz;
-    if (G.cube && nx && ny)
-        csw_body<B, true, EI>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
-    else if (EI && (nx || ny))
-        csw_body<B, false, EI>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
-    else
-        csw_body<B, false, false>(bk, L, t, k, G, M, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+    const int nzb = (G.nz + CSL - 1) / CSL;
+    const int t = (int)bk.z / nzb, k0 = ((int)bk.z % nzb) * CSL, k1 = k0 + CSL < G.nz ? k0 + CSL : G.nz;
+    CswMet<B> Q;
+    csw_metrics<B>(G, M, t, i0, j0, Q);
+    if (G.cube && nx && ny) {
+#pragma clang loop unroll(disable)
+        for (int k = k0; k < k1; k++)
+            csw_body<B, true, EI>(bk, L, t, k, G, Q, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+    } else if (EI && (nx || ny)) {
+#pragma clang loop unroll(disable)
+        for (int k = k0; k < k1; k++)
+            csw_body<B, false, EI>(bk, L, t, k, G, Q, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+    } else {
+#pragma clang loop unroll(disable)
+        for (int k = k0; k < k1; k++)
+            csw_body<B, false, false>(bk, L, t, k, G, Q, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
+    }
 }
 
 // ====================================================================
@@ -3044,7 +3097,7 @@ static fv3_status substeps_t(fv3_state *s, const fv3_grid *g, double dt, int n_s
         // c_sw
         {
             const dim3 cgrd((unsigned)((n + 3 + CTX - 1) / CTX), (unsigned)((n + 3 + CswRows<B>::Y - 1) / CswRows<B>::Y),
-                            P);
+                            (unsigned)(T * ((nz + CSL - 1) / CSL)));
             if (g->p.edge_interp && g->p.kind == FV3_GRID_CUBED_SPHERE)
                 launch_fn<k_csw<B, true>>("k_csw", cgrd, dim3(CNT), st, G, M, (B)dt2, (const B *)u, (const B *)v,
                                           (const B *)delp, (const B *)pt, (const B *)w, uc, vc, W.delpc, W.ptc,
