@@ -45,7 +45,9 @@ def launch_name(symbol: str):
         p = re.search(r"_ZN3fv3(\d+)(k_\w+)", symbol) or re.search(r"^_Z(\d+)(k_\w+)", symbol)
         if p:
             return p.group(2)[:int(p.group(1))]
-        return None
+        # names stored demangled ("fv3::k_name(args)")
+        p = re.search(r"fv3::(k_\w+)\s*[(<]", symbol)
+        return p.group(1) if p else None
     ln = int(m.group(1))
     rest = m.group(2)
     name, targs = rest[:ln], rest[ln:]
