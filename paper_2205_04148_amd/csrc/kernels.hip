@@ -903,8 +903,10 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         int i = i0 - 1 + c, j = j0 - 1 + r;
         bool own = i >= i0 && i < i0 + CTX && j >= j0 && j < j0 + CTY;
         bool xf = xface(i, j), yf = yface(i, j);
+        // blocks without corner views compute every face and select (all their
+        // LDS reads stay inside the tile); only the global stores are masked
         B uc0 = 0, fm = 0, fp = 0, fw = 0;
-        if (xf) {
+        if (CORNER ? xf : true) {
             B a = UAx(i - 2, j, 0), b = UAx(i - 1, j, 0), c1 = UAx(i, j, 0), d = UAx(i + 1, j, 0);
             uc0 = face_pt(a, b, c1, d, i, n, EI && j >= 0 && j < n);
             B fl = dt2 * (uc0 - q2V[m] * Q.cu2[m]) * Q.su2[m] * Q.dy2[m];
@@ -912,14 +914,15 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
             fm = fl * cv(sD, D, up, j, 0);
             fp = fm * cv(sPT, PT, up, j, 0);
             fw = fm * cv(sW, Wf, up, j, 0);
-            if (own) AT(ax + o, i, j) = fl;
+            if (own && xf) AT(ax + o, i, j) = fl;
+            if (!xf) uc0 = fm = fp = fw = (B)0;
         }
         sUC[e] = uc0;
         sFm[e] = fm;
         sFp[e] = fp;
         sFw[e] = fw;
         B vc0 = 0, gm = 0, gp = 0, gw = 0;
-        if (yf) {
+        if (CORNER ? yf : true) {
             B a = VAy(i, j - 2, 1), b = VAy(i, j - 1, 1), c1 = VAy(i, j, 1), d = VAy(i, j + 1, 1);
             vc0 = face_pt(a, b, c1, d, j, n, EI && i >= 0 && i < n);
             B fl = dt2 * (vc0 - q2U[m] * Q.cv2[m]) * Q.sv2[m] * Q.dx2[m];
@@ -927,7 +930,8 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
             gm = fl * cv(sD, D, i, up, 1);
             gp = gm * cv(sPT, PT, i, up, 1);
             gw = gm * cv(sW, Wf, i, up, 1);
-            if (own) AT(ay + o, i, j) = fl;
+            if (own && yf) AT(ay + o, i, j) = fl;
+            if (!yf) vc0 = gm = gp = gw = (B)0;
         }
         sVC[e] = vc0;
         sGm[e] = gm;
@@ -945,13 +949,13 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         int i = i0 - 1 + c, j = j0 - 1 + r;
         bool cross = i >= -1 && i <= n && j >= -1 && j <= n && ((i >= 0 && i < n) || (j >= 0 && j < n));
         B kev = 0;
-        if (cross) {
+        if (CORNER ? cross : true) {
             B rs2 = Q.rs2[m], ca = Q.ca[m];
             B a = sUA[aA(i, j)], b = sVA[aA(i, j)];
             B uu = (a - b * ca) * rs2, vv = (b - a * ca) * rs2;
             kev = (B)0.5 * dt2 * (uu * (uu > 0 ? sUC[aF(i, j)] : sUC[aF(i + 1, j)]) +
                                   vv * (vv > 0 ? sVC[aF(i, j)] : sVC[aF(i, j + 1)]));
-            if (i >= i0 && j >= j0) {
+            if (cross && i >= i0 && j >= j0) {
                 B rar = Q.ra[m];
                 B dp = sD[aD(i, j)];
                 B dc = dp + (sFm[aF(i, j)] - sFm[aF(i + 1, j)] + sGm[aF(i, j)] - sGm[aF(i, j + 1)]) * rar;
@@ -963,7 +967,7 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
                     (sW[aD(i, j)] * dp + (sFw[aF(i, j)] - sFw[aF(i + 1, j)] + sGw[aF(i, j)] - sGw[aF(i, j + 1)]) * rar) * rdc;
             }
         }
-        sKE[e] = kev;
+        sKE[e] = cross ? kev : (B)0;
     }
 #pragma unroll
     for (int m = 0; m < (HK * WK + CNT - 1) / CNT; m++) {
@@ -972,7 +976,8 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         int r = e / WK, c = e - r * WK;
         int i = i0 + c, j = j0 + r;
         B vo = 0;
-        if (i >= 0 && i <= n && j >= 0 && j <= n) {
+        // outside [0, n]^2 the metric registers are zero, so vo is zero
+        if (CORNER ? (i >= 0 && i <= n && j >= 0 && j <= n) : true) {
             B ws = 1, wn = 1, ww = 1, we = 1;
             if (CORNER && is_vertex(G, i, j)) {
                 if (j == 0) ws = 0.5; else wn = 0.5;
@@ -1002,17 +1007,20 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         if (e >= CTX * CTY) break;
         int r = e / CTX, c = e - r * CTX;
         int i = i0 + c, j = j0 + r;
-        if (i >= 0 && i <= n && j >= 0 && j < n) {
+        const bool fu = i >= 0 && i <= n && j >= 0 && j < n, fv = i >= 0 && i < n && j >= 0 && j <= n;
+        if (CORNER ? fu : true) {
             B u0 = sUC[aF(i, j)];
             B fy1 = dt2 * (q4V[m] - u0 * Q.cu4[m]) * Q.su4[m];
             B vt = fy1 > 0 ? sVO[aV(i, j)] : sVO[aV(i, j + 1)];
-            AT(uc + o, i, j) = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * Q.rdx4[m];
+            B un = u0 + fy1 * vt + (sKE[aK(i - 1, j)] - sKE[aK(i, j)]) * Q.rdx4[m];
+            if (fu) AT(uc + o, i, j) = un;
         }
-        if (i >= 0 && i < n && j >= 0 && j <= n) {
+        if (CORNER ? fv : true) {
             B v0 = sVC[aF(i, j)];
             B fx1 = dt2 * (q4U[m] - v0 * Q.cv4[m]) * Q.sv4[m];
             B vt = fx1 > 0 ? sVO[aV(i, j)] : sVO[aV(i + 1, j)];
-            AT(vc + o, i, j) = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * Q.rdy4[m];
+            B vn = v0 - fx1 * vt + (sKE[aK(i, j - 1)] - sKE[aK(i, j)]) * Q.rdy4[m];
+            if (fv) AT(vc + o, i, j) = vn;
         }
     }
 }
