@@ -851,9 +851,21 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         int r = e / WA, c = e - r * WA;
         int i = i0 - 3 + c, j = j0 - 3 + r;
         B a = 0, b = 0;
-        if (i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2 && !(CORNER && in_corner(G, SC, i, j))) {
-            if (j >= -2 && j <= n + 1) a = ua_at<B, CORNER, EI>(G, U, V, i, j);
-            if (i >= -2 && i <= n + 1) b = va_at<B, CORNER, EI>(G, U, V, i, j);
+        const bool ok = i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2;
+        if constexpr (CORNER) {
+            if (ok && !in_corner(G, SC, i, j)) {
+                if (j >= -2 && j <= n + 1) a = ua_at<B, CORNER, EI>(G, U, V, i, j);
+                if (i >= -2 && i <= n + 1) b = va_at<B, CORNER, EI>(G, U, V, i, j);
+            }
+        } else {
+            // loads at clamped points (inside the planes), then select: no
+            // branches around the loads
+            const bool oka = ok && j >= -2 && j <= n + 1, okb = ok && i >= -2 && i <= n + 1;
+            const int ic = min(max(i, -3), n + 2), jc = min(max(j, -3), n + 2);
+            a = ua_at<B, false, EI>(G, U, V, ic, min(max(jc, -2), n + 1));
+            b = va_at<B, false, EI>(G, U, V, min(max(ic, -2), n + 1), jc);
+            a = oka ? a : (B)0;
+            b = okb ? b : (B)0;
         }
         sUA[e] = a;
         sVA[e] = b;
@@ -865,10 +877,21 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         int r = e / WD, c = e - r * WD;
         int i = i0 - 2 + c, j = j0 - 2 + r;
         B a = 0, b = 0, c2 = 0;
-        if (i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2 && !(CORNER && in_corner(G, SC, i, j))) {
-            a = AT(D, i, j);
-            b = AT(PT, i, j);
-            c2 = AT(Wf, i, j);
+        const bool ok = i >= -3 && i <= n + 2 && j >= -3 && j <= n + 2;
+        if constexpr (CORNER) {
+            if (ok && !in_corner(G, SC, i, j)) {
+                a = AT(D, i, j);
+                b = AT(PT, i, j);
+                c2 = AT(Wf, i, j);
+            }
+        } else {
+            const int ic = min(max(i, -3), n + 2), jc = min(max(j, -3), n + 2);
+            a = AT(D, ic, jc);
+            b = AT(PT, ic, jc);
+            c2 = AT(Wf, ic, jc);
+            a = ok ? a : (B)0;
+            b = ok ? b : (B)0;
+            c2 = ok ? c2 : (B)0;
         }
         sD[e] = a;
         sPT[e] = b;
@@ -890,8 +913,10 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         const int e = tid + m * CNT, r = e / WF, c = e - r * WF;
         const int i = i0 - 1 + c, j = j0 - 1 + r;
         const bool in = e < HF * WF, xf = in && xface(i, j), yf = in && yface(i, j);
-        q2V[m] = xf ? AT(V, i, j) : (B)0;
-        q2U[m] = yf ? AT(U, i, j) : (B)0;
+        const int ic = min(max(i, -3), n + 2), jc = min(max(j, -3), n + 2);   // inside the planes
+        const B vv = AT(V, ic, jc), uu = AT(U, ic, jc);
+        q2V[m] = xf ? vv : (B)0;
+        q2U[m] = yf ? uu : (B)0;
     }
     __syncthreads();
     // 2. C-grid faces: winds before the update, area fluxes, upwind fluxes
@@ -996,8 +1021,10 @@ DEVI void csw_body(Bk bk, B *L, const int t, const int k, const Geo &G, const Cs
         const int i = i0 + c, j = j0 + r;
         const bool in = e < CTX * CTY;
         const bool fu = in && i >= 0 && i <= n && j >= 0 && j < n, fv = in && i >= 0 && i < n && j >= 0 && j <= n;
-        q4V[m] = fu ? AT(V, i, j) : (B)0;
-        q4U[m] = fv ? AT(U, i, j) : (B)0;
+        const int ic = min(max(i, -3), n + 2), jc = min(max(j, -3), n + 2);
+        const B vv = AT(V, ic, jc), uu = AT(U, ic, jc);
+        q4V[m] = fu ? vv : (B)0;
+        q4U[m] = fv ? uu : (B)0;
     }
     __syncthreads();
     // 4. C-grid wind update on the interior faces of the own points
