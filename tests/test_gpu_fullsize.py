@@ -10,7 +10,8 @@ across a tile in x, so no block there is free of tile edges.  Here:
   the edge-flux fix-up the device's mass, pt-mass and tracer-mass sums stay
   exact.
 * C96 x 79, FP64, 10 substeps of 30 s plus the 4-tracer transport (the
-  C96 baroclinic-jet configuration of the paper's test case, Sec. X).
+  C96 baroclinic-jet configuration of the paper's test case, Sec. X), and
+  its full 60 substeps of 30 s.
 * C192 x 79, FP64, 2 substeps of 15 s plus the 4-tracer transport (the
   launch configuration the benchmark times, in FP64), every field compared
   over the whole interior.
@@ -81,7 +82,8 @@ def _run_pair(fv3, orc, n, nz, bdt, ns, opts, tol=1e-11, label=""):
         errs[f"q{m}"] = _relerr(_int(g.download(a, nz), n, "C"), _int(b, n, "C"))
     print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, e in errs.items():
-        assert e <= tol, (label, k, e)
+        bar = tol.get(k, tol["*"]) if isinstance(tol, dict) else tol
+        assert e <= bar, (label, k, e, bar)
     return g, s, qd, m0, m1
 
 
@@ -99,6 +101,13 @@ def test_cube_c64_multiblock(fv3, orc, edge_ppm, edge_fix):
 def test_cfg2_c96x79_fp64(fv3, orc):
     """C96 x 79 in FP64: 10 substeps of 30 s and the 4-tracer transport."""
     _run_pair(fv3, orc, 96, 79, 30.0, 10, {}, label="C96x79 fp64")
+
+
+def test_cfg2_c96x79_fp64_sixty_substeps(fv3, orc):
+    """The C96 x 79 configuration over its 60 substeps of 30 s (half an hour)
+    plus the 4-tracer transport, FP64, at the same 1e-11 bar (measured: w
+    4.2e-12, tracers <= 8.5e-13, every other field <= 2.1e-13)."""
+    _run_pair(fv3, orc, 96, 79, 30.0, 60, {}, label="C96x79 fp64 60 substeps")
 
 
 def test_c192x79_fp64_two_substeps(fv3, orc):
