@@ -227,14 +227,19 @@ DEVI Bk xcd_block()
     return Bk{lid % gx, (lid / gx) % gy, lid / (gx * gy)};
 }
 
+// Minimum wavefronts per SIMD a kernel body is compiled for (its register
+// budget: at most 512 / waves VGPRs); 1 leaves the choice to the compiler.
+template <auto F>
+constexpr int kocc = 1;
+
 template <auto F, class... A>
-__global__ void __launch_bounds__(256) k_one(A... a)
+__global__ void __launch_bounds__(256, kocc<F>) k_one(A... a)
 {
     F(xcd_block(), a...);
 }
 
 template <auto F, class... A>
-__global__ void __launch_bounds__(256) k_multi(const Tup<A...> *__restrict__ args, const MemberBlk *__restrict__ tab,
+__global__ void __launch_bounds__(256, kocc<F>) k_multi(const Tup<A...> *__restrict__ args, const MemberBlk *__restrict__ tab,
                                                int members)
 {
     // one-dimensional grid over every member's own blocks back to back (no
@@ -1081,6 +1086,12 @@ DEVI void k_csw(Bk bk, Geo G, Mets<B> M, B dt2, const B *u, const B *v, const B 
             csw_body<B, false, false>(bk, L, t, k, G, Q, dt2, u, v, delp, pt, w, uc, vc, delpc, ptc, wc, ax, ay);
     }
 }
+
+#ifndef FV3_CSW_OCC
+#define FV3_CSW_OCC 6
+#endif
+template <> constexpr int kocc<k_csw<float, false>> = FV3_CSW_OCC;
+template <> constexpr int kocc<k_csw<float, true>> = FV3_CSW_OCC;
 
 // ====================================================================
 // Vertical column work (one thread per column, k marching in FP64).
