@@ -2791,6 +2791,13 @@ DEVI void k_nhpgrad(Bk bk, Geo G, MetD M, double bdt, const double *pfull, const
     else nhpgrad_body<B, EI, false>(bk, G, M, bdt, pfull, phi, delp, u, v, L);
 }
 
+// FP32 nh_p_grad compiled for six wavefronts per SIMD (its LDS allows six,
+// its natural 95 VGPRs five; 75 VGPRs without spills)
+#ifndef FV3_NHP_OCC
+#define FV3_NHP_OCC 6
+#endif
+template <> constexpr int kocc<k_nhpgrad<float, false>> = FV3_NHP_OCC;
+
 // ====================================================================
 // utilities: fills, copies, finiteness check, tracer helpers, reductions
 // ====================================================================
