@@ -91,3 +91,36 @@ def test_pmc_launch_names():
     assert pmc.launch_name(sim1.format(p=1, s=0)) == "k_sim1_c.p1"
     assert pmc.launch_name(sim1.format(p=4, s=1)) == "k_sim1_3.p4"
     assert pmc.launch_name("_ZN2at6native18elementwise_kernelIiEEvv") is None
+    # plain library kernels, mangled or stored demangled (the learned correction's products)
+    assert pmc.launch_name("_ZN3fv311k_gemm_bf16EiiiPKtllS1_llPKfiPflPtl") == "k_gemm_bf16"
+    assert pmc.launch_name("fv3::k_gemm_bf16(int, int, int, unsigned short const*, long)") == "k_gemm_bf16"
+    assert pmc.launch_name("fv3::k_adam(float*, float const*, float*, float*, long)") == "k_adam"
+    assert pmc.launch_name("void at::native::vectorized_elementwise_kernel<4>(int)") is None
+
+
+def test_pmc_wait_shares(tmp_path):
+    """The counter summary derives the wait shares from SQ_WAIT_* over
+    SQ_WAVE_CYCLES and the VALU busy share from SQ_ACTIVE_INST_VALU over the
+    kernel's duration (GRBM_GUI_ACTIVE summed over the 8 dies)."""
+    import json
+    import sqlite3
+
+    from paper_2205_04148_amd import pmc
+
+    d = tmp_path / "run"
+    d.mkdir()
+    con = sqlite3.connect(str(d / "x.db"))
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real)")
+    sym = "fv3::k_adam(float*, float const*)"
+    rows = {"SQ_WAVE_CYCLES": 1000.0, "SQ_WAIT_ANY": 250.0, "SQ_WAIT_INST_ANY": 100.0, "SQ_WAIT_INST_LDS": 10.0,
+            "GRBM_GUI_ACTIVE": 8 * 2400.0, "SQ_ACTIVE_INST_VALU": 1024 * 2400.0 / 4 / 2}
+    for c, v in rows.items():
+        con.execute("insert into counters_collection values (?, ?, ?)", (sym, c, v))
+    con.commit()
+    con.close()
+    out = tmp_path / "o.json"
+    pmc.counters_main([str(d), str(out), "test"])
+    k = json.loads(out.read_text())["kernels"]["k_adam"]
+    assert abs(k["wait_any_share"] - 0.25) < 1e-12 and abs(k["wait_inst_any_share"] - 0.1) < 1e-12
+    assert abs(k["wait_inst_lds_share"] - 0.01) < 1e-12
+    assert abs(k["valu_busy"] - 0.5) < 1e-12 and abs(k["duration_us_at_2400MHz"] - 1.0) < 1e-12
